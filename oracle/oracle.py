@@ -1,0 +1,198 @@
+"""ctypes binding of the serial CPU oracle (``spinmc_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline use this module to obtain reference results; the product library
+never imports it.  The C file is built with plain gcc (``build()``), it
+shares no code with the HIP library.
+
+Arrays are numpy arrays in the layouts of the C functions:
+  Ising / EA spins   int8  [N]          (x fastest)
+  couplings          int8  [d][N]       (bond mu of site i joins i and i+e_mu)
+  Heisenberg spins   float64 [N][3]
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "spinmc_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(LIB)
+        i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        vp = C.c_void_p
+        I, U32, U64, D, I64 = C.c_int, C.c_uint32, C.c_uint64, C.c_double, C.c_int64
+        sig = {
+            "orc_philox4x32_10": (None, [u32p, u32p, u32p]),
+            "orc_metropolis_u32": (U32, [U64, U32, U32, I, U64]),
+            "orc_init_spins": (None, [I, I, U64, U32, i8p]),
+            "orc_init_couplings": (None, [I, I, U64, U32, i8p]),
+            "orc_init_heis": (None, [I, I, U64, U32, f64p]),
+            "orc_thresholds": (None, [D, I, u64p]),
+            "orc_half_sweep": (I64, [I, I, vp, i8p, D, U64, U32, U32, I]),
+            "orc_sweep": (I64, [I, I, vp, i8p, D, U64, U32, U32]),
+            "orc_run": (I64, [I, I, vp, i8p, D, U64, U32, U32, I]),
+            "orc_energy": (I64, [I, I, vp, i8p]),
+            "orc_magnetisation": (I64, [I, I, i8p]),
+            "orc_run_series": (None, [I, I, vp, i8p, D, U64, U32, U32, I, i64p, i64p]),
+            "orc_heis_half_sweep": (I64, [I, I, f64p, D, U64, U32, U32, I]),
+            "orc_heis_renormalise": (None, [I, I, f64p]),
+            "orc_heis_sweep": (I64, [I, I, f64p, D, U64, U32, U32, I]),
+            "orc_heis_run": (I64, [I, I, f64p, D, U64, U32, U32, I, I]),
+            "orc_heis_energy": (D, [I, I, f64p]),
+            "orc_heis_magnetisation": (None, [I, I, f64p, f64p]),
+            "orc_pt_step": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, vp]),
+            "orc_pt_run": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, I, vp]),
+            "orc_swap_u53": (D, [U64, U32, U32, U32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def n_sites(dim: int, L: int) -> int:
+    return L ** dim
+
+
+# ---------------------------------------------------------------- RNG ----
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(c, k, out)
+    return out
+
+
+def metropolis_u32(seed: int, t: int, r: int, c: int, h: int) -> int:
+    return int(lib().orc_metropolis_u32(seed, t, r, c, h))
+
+
+def swap_u53(seed: int, k: int, t: int, q: int) -> float:
+    return float(lib().orc_swap_u53(seed, k, t, q))
+
+
+# ------------------------------------------------------------ discrete ---
+def init_spins(dim: int, L: int, seed: int, r: int) -> np.ndarray:
+    s = np.zeros(n_sites(dim, L), np.int8)
+    lib().orc_init_spins(dim, L, seed, r, s)
+    return s
+
+
+def init_couplings(dim: int, L: int, seed: int, q: int) -> np.ndarray:
+    J = np.zeros(dim * n_sites(dim, L), np.int8)
+    lib().orc_init_couplings(dim, L, seed, q, J)
+    return J
+
+
+def thresholds(beta: float, dim: int) -> np.ndarray:
+    thr = np.zeros(dim + 1, np.uint64)
+    lib().orc_thresholds(beta, dim, thr)
+    return thr
+
+
+def half_sweep(dim, L, J, s, beta, seed, r, t, c) -> int:
+    return int(lib().orc_half_sweep(dim, L, _ptr(J), s, beta, seed, r, t, c))
+
+
+def sweep(dim, L, J, s, beta, seed, r, t) -> int:
+    return int(lib().orc_sweep(dim, L, _ptr(J), s, beta, seed, r, t))
+
+
+def run(dim, L, J, s, beta, seed, r, t0, n) -> int:
+    """n sweeps t0..t0+n-1 in place; returns the summed Delta E of accepted flips."""
+    return int(lib().orc_run(dim, L, _ptr(J), s, beta, seed, r, t0, n))
+
+
+def run_series(dim, L, J, s, beta, seed, r, t0, n):
+    """n sweeps in place; returns (E, M) int64 arrays recorded after each sweep."""
+    E = np.zeros(n, np.int64)
+    M = np.zeros(n, np.int64)
+    lib().orc_run_series(dim, L, _ptr(J), s, beta, seed, r, t0, n, E, M)
+    return E, M
+
+
+def energy(dim, L, J, s) -> int:
+    return int(lib().orc_energy(dim, L, _ptr(J), s))
+
+
+def magnetisation(dim, L, s) -> int:
+    return int(lib().orc_magnetisation(dim, L, s))
+
+
+# ---------------------------------------------------------- Heisenberg ---
+def init_heis(dim: int, L: int, seed: int, r: int) -> np.ndarray:
+    s = np.zeros((n_sites(dim, L), 3), np.float64)
+    lib().orc_init_heis(dim, L, seed, r, s)
+    return s
+
+
+def heis_half_sweep(dim, L, s, beta, seed, r, t, c) -> int:
+    return int(lib().orc_heis_half_sweep(dim, L, s, beta, seed, r, t, c))
+
+
+def heis_sweep(dim, L, s, beta, seed, r, t, renorm_every=16) -> int:
+    return int(lib().orc_heis_sweep(dim, L, s, beta, seed, r, t, renorm_every))
+
+
+def heis_run(dim, L, s, beta, seed, r, t0, n, renorm_every=16) -> int:
+    return int(lib().orc_heis_run(dim, L, s, beta, seed, r, t0, n, renorm_every))
+
+
+def heis_renormalise(dim, L, s) -> None:
+    lib().orc_heis_renormalise(dim, L, s)
+
+
+def heis_energy(dim, L, s) -> float:
+    return float(lib().orc_heis_energy(dim, L, s))
+
+
+def heis_magnetisation(dim, L, s) -> np.ndarray:
+    m = np.zeros(3, np.float64)
+    lib().orc_heis_magnetisation(dim, L, s, m)
+    return m
+
+
+# ---------------------------------------------------- parallel tempering --
+def pt_run(dim, L, J, spins, beta, slot_of_temp, E, seed, q, r0, t0, n_steps, swap_acc=None):
+    """n_steps PT steps of one chain in place.
+
+    spins: int8 [n_temps, N]; beta: float64 [n_temps]; slot_of_temp: int32
+    [n_temps]; E: int64 [n_temps] (energy per slot); swap_acc: uint64
+    [n_temps] or None.
+    """
+    n_temps = len(beta)
+    lib().orc_pt_run(dim, L, _ptr(J), spins.reshape(-1), n_temps, np.ascontiguousarray(beta, np.float64),
+                     slot_of_temp, E, seed, q, r0, t0, n_steps, _ptr(swap_acc))

@@ -1,0 +1,486 @@
+/*
+ * spinmc_oracle.c -- plain, serial, obviously-correct CPU reference for the
+ * checkerboard Metropolis / parallel-tempering hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  Only the tests, the smoke check and the benchmark's CPU
+ * baseline may load it; the product library never links, calls or falls back
+ * to it.  It shares no code with the HIP sources (its own Philox, indexing,
+ * thresholds and energies).
+ *
+ * Method (M. Weigel, "Performance potential for simulating spin models on
+ * GPU", J. Comput. Phys. 231 (2012)):
+ *   - Ising Hamiltonian, Sec. 3.1 Eq. (1); Metropolis acceptance Eq. (2) with
+ *     Delta E = 2 s_i sum_nn J s_j;
+ *   - two-colour checkerboard sweep: all sites of one sub-lattice are
+ *     independent and are updated, then the other sub-lattice (Sec. 3.2);
+ *   - tabulated Boltzmann factors for discrete energy changes (Sec. 3.5);
+ *   - O(n) / Heisenberg Hamiltonian Eq. (10) with uniform re-orientation
+ *     proposals (Sec. 4);
+ *   - +-J Edwards-Anderson spin glass Eq. (11), bimodal couplings (Sec. 5);
+ *   - parallel tempering, exchange probability Eq. (12), temperatures (not
+ *     configurations) are exchanged (Sec. 6);
+ *   - energies tracked incrementally from accepted flips (Sec. 3.5, Sec. 6).
+ *
+ * Readings where the paper leaves a choice open (the random-number contract,
+ * the sweep order, the threshold arithmetic, the swap schedule) are fixed
+ * here and listed in the design notes; each function states the one it uses.
+ *
+ * Everything is plain loops over sites in storage order.  Floating point is
+ * FP64; the file is compiled with -ffp-contract=off so that a*b+c is never
+ * fused.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define EXPORT __attribute__((visibility("default")))
+
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11).  One round maps (x0,x1,x2,x3) with key (k0,k1): */
+/*   (hi0,lo0) = M0*x0,  (hi1,lo1) = M1*x2                                  */
+/*   x' = (hi1^x1^k0, lo1, hi0^x3^k1, lo0)                                  */
+/* and the key is advanced by the Weyl constants between rounds.            */
+/* ------------------------------------------------------------------------ */
+static const uint32_t PHILOX_M0 = 0xD2511F53u;
+static const uint32_t PHILOX_M1 = 0xCD9E8D57u;
+static const uint32_t PHILOX_W0 = 0x9E3779B9u;
+static const uint32_t PHILOX_W1 = 0xBB67AE85u;
+
+EXPORT void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Stream tags: counter word 3 is (tag * 2 + colour). */
+enum { TAG_INIT = 1, TAG_COUP = 2, TAG_HEAD = 3, TAG_TAIL = 4, TAG_HEIS = 5, TAG_SWAP = 6 };
+
+static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t out[4])
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* The 32-bit Metropolis uniform of the colour-c site with in-colour index h
+ * at sweep t in replica r.  Its high 16 bits are half (h mod 8) of the draw
+ * (h/8, t, r, HEAD) (halves numbered low half of word 0 first), its low 16
+ * bits are the low half of word 0 of the draw (h, t, r, TAIL). */
+EXPORT uint32_t orc_metropolis_u32(uint64_t seed, uint32_t t, uint32_t r, int c, uint64_t h)
+{
+    uint32_t w[4], v[4];
+    draw(seed, (uint32_t)(h >> 3), t, r, (uint32_t)(TAG_HEAD * 2 + c), w);
+    uint32_t word = w[(h & 7) >> 1];
+    uint32_t head = (h & 1) ? (word >> 16) : (word & 0xFFFFu);
+    draw(seed, (uint32_t)h, t, r, (uint32_t)(TAG_TAIL * 2 + c), v);
+    uint32_t tail = v[0] & 0xFFFFu;
+    return (head << 16) | tail;
+}
+
+/* Uniform in (0,1) from the top 23 bits of a word: (k + 1/2) 2^-23.
+ * Every such value is exact in binary32 and in binary64. */
+static double unit23(uint32_t w)
+{
+    return ((double)(w >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+/* 53-bit uniform in [0,1) from two words (swap stream). */
+static double unit53(uint32_t w0, uint32_t w1)
+{
+    return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice geometry.  Periodic simple-cubic lattice of edge L (even), d = 2  */
+/* or 3, N = L^d sites in row-major order with x fastest:                    */
+/*   2D: i = y L + x;  3D: i = (z L + y) L + x.                              */
+/* Colour c(i) = (x + y [+ z]) mod 2; the in-colour index h(i) = i / 2       */
+/* (equal to (row index) * L/2 + x/2 because L is even).                     */
+/* ------------------------------------------------------------------------ */
+static void coords(int dim, int L, int64_t i, int x[3])
+{
+    x[0] = (int)(i % L);
+    x[1] = (int)((i / L) % L);
+    x[2] = dim == 3 ? (int)(i / ((int64_t)L * L)) : 0;
+}
+
+static int64_t index_of(int dim, int L, const int x[3])
+{
+    int64_t i = x[0] + (int64_t)L * x[1];
+    if (dim == 3) i += (int64_t)L * L * x[2];
+    return i;
+}
+
+static int colour_of(int dim, const int x[3])
+{
+    int s = x[0] + x[1] + (dim == 3 ? x[2] : 0);
+    return s & 1;
+}
+
+/* Neighbour of site x in direction mu, step +1 or -1, periodic. */
+static int64_t neighbour(int dim, int L, const int x[3], int mu, int step)
+{
+    int y[3] = {x[0], x[1], x[2]};
+    y[mu] = (y[mu] + step + L) % L;
+    return index_of(dim, L, y);
+}
+
+static int64_t n_sites(int dim, int L)
+{
+    return dim == 3 ? (int64_t)L * L * L : (int64_t)L * L;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial state.                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Random start for Ising / EA spins of replica r: site i takes word (i mod 4)
+ * of the draw (i/4, 0, r, INIT); the spin is +1 iff that word's top bit is 0. */
+EXPORT void orc_init_spins(int dim, int L, uint64_t seed, uint32_t r, int8_t *s)
+{
+    int64_t N = n_sites(dim, L);
+    for (int64_t i = 0; i < N; ++i) {
+        uint32_t w[4];
+        draw(seed, (uint32_t)(i >> 2), 0, r, TAG_INIT * 2, w);
+        s[i] = (w[i & 3] >> 31) ? -1 : +1;
+    }
+}
+
+/* Bimodal couplings of disorder sample q (Sec. 5: J = +-1 with probability
+ * 1/2 each).  Bond (i, mu) joins i and i + e_mu; its draw is word (b mod 4)
+ * of (b/4, 0, q, COUP) with b = i d + mu; J = +1 iff the top bit is 0.
+ * Storage J[mu * N + i]. */
+EXPORT void orc_init_couplings(int dim, int L, uint64_t seed, uint32_t q, int8_t *J)
+{
+    int64_t N = n_sites(dim, L);
+    for (int64_t i = 0; i < N; ++i) {
+        for (int mu = 0; mu < dim; ++mu) {
+            uint64_t b = (uint64_t)i * dim + mu;
+            uint32_t w[4];
+            draw(seed, (uint32_t)(b >> 2), 0, q, TAG_COUP * 2, w);
+            J[(int64_t)mu * N + i] = (w[b & 3] >> 31) ? -1 : +1;
+        }
+    }
+}
+
+/* Uniform point on the unit sphere from two uniforms (Archimedes: z is
+ * uniform on [-1,1], the azimuth uniform on [0, 2 pi)). */
+static void sphere_point(double u0, double u1, double out[3])
+{
+    double z = 2.0 * u0 - 1.0;
+    double phi = TWO_PI * u1;
+    double rho = sqrt(1.0 - z * z);
+    out[0] = rho * cos(phi);
+    out[1] = rho * sin(phi);
+    out[2] = z;
+}
+
+/* Random start for Heisenberg spins of replica r: words 0, 1 of (i, 0, r, INIT). */
+EXPORT void orc_init_heis(int dim, int L, uint64_t seed, uint32_t r, double *s)
+{
+    int64_t N = n_sites(dim, L);
+    for (int64_t i = 0; i < N; ++i) {
+        uint32_t w[4];
+        draw(seed, (uint32_t)i, 0, r, TAG_INIT * 2, w);
+        sphere_point(unit23(w[0]), unit23(w[1]), &s[3 * i]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Acceptance thresholds for discrete energy changes Delta E = 4m > 0        */
+/* (Sec. 3.5: tabulate exp(-beta Delta E)).  thr[m] = floor(2^32 e^{-4 m b}) */
+/* in FP64 with libm exp; a flip with Delta E = 4m > 0 is accepted iff the   */
+/* 32-bit uniform u satisfies u < thr[m]; thr[m] = 2^32 means always.        */
+/* ------------------------------------------------------------------------ */
+EXPORT void orc_thresholds(double beta, int dim, uint64_t *thr /* [dim+1] */)
+{
+    thr[0] = 4294967296ull;
+    for (int m = 1; m <= dim; ++m) {
+        double p = exp(-beta * (4.0 * m));
+        double v = floor(4294967296.0 * p);
+        thr[m] = (uint64_t)v;
+    }
+}
+
+/* Local field h_i = sum_mu [ J(i,mu) s(i+e_mu) + J(i-e_mu,mu) s(i-e_mu) ]
+ * (J == NULL: ferromagnet, all couplings +1). */
+static int local_field(int dim, int L, const int8_t *J, const int8_t *s, int64_t i)
+{
+    int64_t N = n_sites(dim, L);
+    int x[3];
+    coords(dim, L, i, x);
+    int h = 0;
+    for (int mu = 0; mu < dim; ++mu) {
+        int64_t up = neighbour(dim, L, x, mu, +1);
+        int64_t dn = neighbour(dim, L, x, mu, -1);
+        int j_up = J ? J[(int64_t)mu * N + i] : 1;
+        int j_dn = J ? J[(int64_t)mu * N + dn] : 1;
+        h += j_up * s[up] + j_dn * s[dn];
+    }
+    return h;
+}
+
+/* One half-sweep: a Metropolis attempt (Eq. 2) at every site of colour c.
+ * Sites of one colour only neighbour sites of the other colour, so their
+ * updates are independent and the visiting order is irrelevant.
+ * Returns the sum of Delta E over accepted flips. */
+EXPORT int64_t orc_half_sweep(int dim, int L, const int8_t *J, int8_t *s, double beta,
+                              uint64_t seed, uint32_t r, uint32_t t, int c)
+{
+    uint64_t thr[4];
+    orc_thresholds(beta, dim, thr);
+    int64_t N = n_sites(dim, L);
+    int64_t dE_sum = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int x[3];
+        coords(dim, L, i, x);
+        if (colour_of(dim, x) != c) continue;
+        int h = local_field(dim, L, J, s, i);
+        int dE = 2 * s[i] * h;
+        int accept;
+        if (dE <= 0) {
+            accept = 1;
+        } else {
+            uint32_t u = orc_metropolis_u32(seed, t, r, c, (uint64_t)(i >> 1));
+            accept = (uint64_t)u < thr[dE / 4];
+        }
+        if (accept) {
+            s[i] = (int8_t)(-s[i]);
+            dE_sum += dE;
+        }
+    }
+    return dE_sum;
+}
+
+/* Sweep t: colour 0, then colour 1. */
+EXPORT int64_t orc_sweep(int dim, int L, const int8_t *J, int8_t *s, double beta,
+                         uint64_t seed, uint32_t r, uint32_t t)
+{
+    int64_t dE = orc_half_sweep(dim, L, J, s, beta, seed, r, t, 0);
+    dE += orc_half_sweep(dim, L, J, s, beta, seed, r, t, 1);
+    return dE;
+}
+
+/* n sweeps t0 .. t0+n-1. */
+EXPORT int64_t orc_run(int dim, int L, const int8_t *J, int8_t *s, double beta,
+                       uint64_t seed, uint32_t r, uint32_t t0, int n)
+{
+    int64_t dE = 0;
+    for (int k = 0; k < n; ++k) dE += orc_sweep(dim, L, J, s, beta, seed, r, t0 + (uint32_t)k);
+    return dE;
+}
+
+/* E = -sum_i sum_mu J(i,mu) s_i s_{i+e_mu} (Eqs. 1 and 11), each bond once. */
+EXPORT int64_t orc_energy(int dim, int L, const int8_t *J, const int8_t *s)
+{
+    int64_t N = n_sites(dim, L);
+    int64_t E = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int x[3];
+        coords(dim, L, i, x);
+        for (int mu = 0; mu < dim; ++mu) {
+            int64_t up = neighbour(dim, L, x, mu, +1);
+            int j = J ? J[(int64_t)mu * N + i] : 1;
+            E -= (int64_t)j * s[i] * s[up];
+        }
+    }
+    return E;
+}
+
+EXPORT int64_t orc_magnetisation(int dim, int L, const int8_t *s)
+{
+    int64_t N = n_sites(dim, L);
+    int64_t M = 0;
+    for (int64_t i = 0; i < N; ++i) M += s[i];
+    return M;
+}
+
+/* n sweeps t0 .. t0+n-1 recording E and M after every sweep (for the
+ * statistical checks against exact results). */
+EXPORT void orc_run_series(int dim, int L, const int8_t *J, int8_t *s, double beta,
+                           uint64_t seed, uint32_t r, uint32_t t0, int n,
+                           int64_t *E_series, int64_t *M_series)
+{
+    for (int k = 0; k < n; ++k) {
+        orc_sweep(dim, L, J, s, beta, seed, r, t0 + (uint32_t)k);
+        E_series[k] = orc_energy(dim, L, J, s);
+        M_series[k] = orc_magnetisation(dim, L, s);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Heisenberg (O(3)) model, Eq. (10), FP64.                                  */
+/* ------------------------------------------------------------------------ */
+
+/* One half-sweep of colour c: at each site propose a fresh uniform direction
+ * s' (independent of s, Sec. 4) from words 0, 1 of (h, t, r, HEIS+c) and
+ * accept iff Delta E = -(s' - s).h <= 0 or u < exp(-beta Delta E), u from
+ * word 2.  Returns the number of accepted moves. */
+EXPORT int64_t orc_heis_half_sweep(int dim, int L, double *s, double beta,
+                                   uint64_t seed, uint32_t r, uint32_t t, int c)
+{
+    int64_t N = n_sites(dim, L);
+    int64_t n_acc = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int x[3];
+        coords(dim, L, i, x);
+        if (colour_of(dim, x) != c) continue;
+        double h[3] = {0.0, 0.0, 0.0};
+        for (int mu = 0; mu < dim; ++mu) {
+            int64_t up = neighbour(dim, L, x, mu, +1);
+            int64_t dn = neighbour(dim, L, x, mu, -1);
+            for (int a = 0; a < 3; ++a) h[a] += s[3 * up + a] + s[3 * dn + a];
+        }
+        uint32_t w[4];
+        draw(seed, (uint32_t)(i >> 1), t, r, (uint32_t)(TAG_HEIS * 2 + c), w);
+        double sp[3];
+        sphere_point(unit23(w[0]), unit23(w[1]), sp);
+        double dE = 0.0;
+        for (int a = 0; a < 3; ++a) dE -= (sp[a] - s[3 * i + a]) * h[a];
+        int accept = (dE <= 0.0) || (unit23(w[2]) < exp(-beta * dE));
+        if (accept) {
+            for (int a = 0; a < 3; ++a) s[3 * i + a] = sp[a];
+            ++n_acc;
+        }
+    }
+    return n_acc;
+}
+
+EXPORT void orc_heis_renormalise(int dim, int L, double *s)
+{
+    int64_t N = n_sites(dim, L);
+    for (int64_t i = 0; i < N; ++i) {
+        double n = sqrt(s[3 * i] * s[3 * i] + s[3 * i + 1] * s[3 * i + 1] + s[3 * i + 2] * s[3 * i + 2]);
+        for (int a = 0; a < 3; ++a) s[3 * i + a] /= n;
+    }
+}
+
+/* Sweep t (colour 0 then colour 1); spins are renormalised after the sweep
+ * when renorm_every > 0 and (t + 1) is a multiple of renorm_every. */
+EXPORT int64_t orc_heis_sweep(int dim, int L, double *s, double beta, uint64_t seed,
+                              uint32_t r, uint32_t t, int renorm_every)
+{
+    int64_t n = orc_heis_half_sweep(dim, L, s, beta, seed, r, t, 0);
+    n += orc_heis_half_sweep(dim, L, s, beta, seed, r, t, 1);
+    if (renorm_every > 0 && ((uint64_t)t + 1) % (uint64_t)renorm_every == 0)
+        orc_heis_renormalise(dim, L, s);
+    return n;
+}
+
+EXPORT int64_t orc_heis_run(int dim, int L, double *s, double beta, uint64_t seed,
+                            uint32_t r, uint32_t t0, int n, int renorm_every)
+{
+    int64_t acc = 0;
+    for (int k = 0; k < n; ++k) acc += orc_heis_sweep(dim, L, s, beta, seed, r, t0 + (uint32_t)k, renorm_every);
+    return acc;
+}
+
+/* Kahan-compensated FP64 sums of E = -sum_bonds s_i . s_j and of M. */
+EXPORT double orc_heis_energy(int dim, int L, const double *s)
+{
+    int64_t N = n_sites(dim, L);
+    double sum = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        int x[3];
+        coords(dim, L, i, x);
+        for (int mu = 0; mu < dim; ++mu) {
+            int64_t up = neighbour(dim, L, x, mu, +1);
+            double term = -(s[3 * i] * s[3 * up] + s[3 * i + 1] * s[3 * up + 1] + s[3 * i + 2] * s[3 * up + 2]);
+            double y = term - comp;
+            double tt = sum + y;
+            comp = (tt - sum) - y;
+            sum = tt;
+        }
+    }
+    return sum;
+}
+
+EXPORT void orc_heis_magnetisation(int dim, int L, const double *s, double m[3])
+{
+    int64_t N = n_sites(dim, L);
+    for (int a = 0; a < 3; ++a) {
+        double sum = 0.0, comp = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            double y = s[3 * i + a] - comp;
+            double tt = sum + y;
+            comp = (tt - sum) - y;
+            sum = tt;
+        }
+        m[a] = sum;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Parallel tempering (Sec. 6).                                              */
+/* A chain q holds n_temps replicas (storage slots 0..n_temps-1, replica     */
+/* index r = r0 + slot) that share the couplings J.  slot_of_temp[k] is the  */
+/* slot currently simulated at inverse temperature beta[k]; beta[0] is the   */
+/* coldest end of the ladder by convention.  E[slot] is the energy of the    */
+/* configuration in that slot.                                               */
+/*                                                                           */
+/* Step t: one sweep (index t) of every slot at its current temperature,     */
+/* tracking E; then for every k with k = t (mod 2), k <= n_temps - 2, the    */
+/* exchange of temperatures k and k+1 is attempted with Eq. (12):            */
+/*   x = (beta[k+1] - beta[k]) (E[B] - E[A]),  A = slot at k, B = at k+1,    */
+/*   accept iff x >= 0 or u < exp(x), u the 53-bit uniform of (k, t, q, SWAP)*/
+/* and on acceptance the two slots exchange temperatures.                    */
+/* ------------------------------------------------------------------------ */
+EXPORT void orc_pt_step(int dim, int L, const int8_t *J, int8_t *spins /* [n_temps][N] */,
+                        int n_temps, const double *beta, int32_t *slot_of_temp, int64_t *E,
+                        uint64_t seed, uint32_t q, uint32_t r0, uint32_t t, uint64_t *swap_acc)
+{
+    int64_t N = n_sites(dim, L);
+    for (int k = 0; k < n_temps; ++k) {
+        int slot = slot_of_temp[k];
+        E[slot] += orc_sweep(dim, L, J, spins + (int64_t)slot * N, beta[k], seed, r0 + (uint32_t)slot, t);
+    }
+    for (int k = (int)(t & 1u); k + 1 < n_temps; k += 2) {
+        int A = slot_of_temp[k], B = slot_of_temp[k + 1];
+        double x = (beta[k + 1] - beta[k]) * (double)(E[B] - E[A]);
+        uint32_t w[4];
+        draw(seed, (uint32_t)k, t, q, TAG_SWAP * 2, w);
+        int accept = (x >= 0.0) || (unit53(w[0], w[1]) < exp(x));
+        if (accept) {
+            slot_of_temp[k] = B;
+            slot_of_temp[k + 1] = A;
+            if (swap_acc) swap_acc[k] += 1;
+        }
+    }
+}
+
+EXPORT void orc_pt_run(int dim, int L, const int8_t *J, int8_t *spins, int n_temps,
+                       const double *beta, int32_t *slot_of_temp, int64_t *E, uint64_t seed,
+                       uint32_t q, uint32_t r0, uint32_t t0, int n_steps, uint64_t *swap_acc)
+{
+    for (int k = 0; k < n_steps; ++k)
+        orc_pt_step(dim, L, J, spins, n_temps, beta, slot_of_temp, E, seed, q, r0, t0 + (uint32_t)k, swap_acc);
+}
+
+/* The swap uniform itself, exposed for the near-tie audit of exp(x). */
+EXPORT double orc_swap_u53(uint64_t seed, uint32_t k, uint32_t t, uint32_t q)
+{
+    uint32_t w[4];
+    draw(seed, k, t, q, TAG_SWAP * 2, w);
+    return unit53(w[0], w[1]);
+}

@@ -1,0 +1,94 @@
+"""Pins of the oracle's parallel-tempering step (Sec. 6, Eq. 12)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact as X
+from oracle import oracle as O
+import workloads as W
+
+SEED = W.seed_for(44)
+
+
+def _chain(dim, L, n_temps, r0, J=None):
+    spins = np.stack([O.init_spins(dim, L, SEED, r0 + k) for k in range(n_temps)])
+    E = np.array([O.energy(dim, L, J, spins[k]) for k in range(n_temps)], np.int64)
+    return spins, E, np.arange(n_temps, dtype=np.int32)
+
+
+def test_equal_temperatures_accept_every_swap():
+    """x = 0 for equal betas: every attempt is accepted, so the permutation
+    follows the deterministic even/odd transposition walk."""
+    n = 6
+    spins, E, sot = _chain(2, 8, n, 0)
+    beta = np.full(n, 0.4)
+    acc = np.zeros(n, np.uint64)
+    expect = list(range(n))
+    for t in range(9):
+        O.pt_run(2, 8, None, spins, beta, sot, E, SEED, 0, 0, t, 1, acc)
+        for k in range(t & 1, n - 1, 2):
+            expect[k], expect[k + 1] = expect[k + 1], expect[k]
+        assert list(sot) == expect
+    assert int(acc.sum()) == sum(len(range(t & 1, n - 1, 2)) for t in range(9))
+
+
+def test_energy_tracking_and_permutation_validity():
+    J = O.init_couplings(2, 8, SEED, 3)
+    n = 8
+    spins, E, sot = _chain(2, 8, n, 16, J)
+    beta = W.geometric_ladder(0.5, 2.0, n)
+    O.pt_run(2, 8, J, spins, beta, sot, E, SEED, 2, 16, 0, 200)
+    assert sorted(sot) == list(range(n))
+    for k in range(n):
+        assert E[k] == O.energy(2, 8, J, spins[k])
+
+
+def test_swap_rate_matches_exact_double_sum():
+    """For two temperatures on the 4x4 Ising model the mean acceptance of a
+    swap attempt is sum_{E1,E2} P_b1(E1) P_b2(E2) min(1, exp((b2-b1)(E2-E1)))."""
+    b1, b2 = 0.30, 0.45
+    E_all, M_all = X.enumerate_states(2, 4)
+    lev, cnt = X.density_of_states(E_all)
+
+    def p(b):
+        w = cnt * np.exp(-b * (lev - lev.min()))
+        return w / w.sum()
+
+    P1, P2 = p(b1), p(b2)
+    x = (b2 - b1) * (lev[None, :] - lev[:, None])
+    exact = float((P1[:, None] * P2[None, :] * np.minimum(1.0, np.exp(x))).sum())
+    beta = np.array([b1, b2])
+    rates = []
+    for q in range(64):
+        spins, E, sot = _chain(2, 4, 2, 2 * q)
+        O.pt_run(2, 4, None, spins, beta, sot, E, SEED, q, 2 * q, 0, 100)   # equilibrate
+        acc = np.zeros(2, np.uint64)
+        O.pt_run(2, 4, None, spins, beta, sot, E, SEED, q, 2 * q, 100, 2000, acc)
+        rates.append(float(acc[0]) / 1000.0)   # pair 0 is attempted on even steps
+    m, err = np.mean(rates), np.std(rates, ddof=1) / math.sqrt(len(rates))
+    assert abs(m - exact) < 4.5 * err, (m, exact, err)
+
+
+def test_uniform_occupancy():
+    """The stationary law is symmetric in the slot labels: in the long run each
+    slot spends the same fraction of time at every temperature."""
+    n = 4
+    beta = np.array([0.2, 0.3, 0.4, 0.5])
+    occ = np.zeros((n, n))
+    for q in range(24):
+        spins, E, sot = _chain(2, 4, n, 4 * q)
+        for t in range(1500):
+            O.pt_run(2, 4, None, spins, beta, sot, E, SEED, q, 4 * q, t, 1)
+            if t >= 100:
+                occ[sot, np.arange(n)] += 1
+    frac = occ / occ.sum(axis=1, keepdims=True)
+    assert np.all(np.abs(frac - 1.0 / n) < 0.03), frac
+
+
+def test_swap_uniform_is_53_bit_uniform():
+    u = np.array([O.swap_u53(SEED, k % 31, k // 31, 7) for k in range(20000)])
+    assert np.all((u >= 0) & (u < 1))
+    assert abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / len(u))
+    # 53 significant bits: scaled by 2^53 every value is an integer
+    assert np.all(np.floor(u * 2.0 ** 53) == u * 2.0 ** 53)
