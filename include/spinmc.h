@@ -1,0 +1,185 @@
+/*
+ * spinmc.h -- C ABI of the MI355X checkerboard Metropolis / parallel-tempering
+ * library (libspinmc.so).
+ *
+ * Method: M. Weigel, "Performance potential for simulating spin models on
+ * GPU" (arXiv:1101.1427).  Models: Ising ferromagnet (Sec. 3.1, Eq. 1),
+ * +-J Edwards-Anderson spin glass (Sec. 5, Eq. 11), O(3) Heisenberg model
+ * with uniform re-orientation proposals (Sec. 4, Eq. 10).  Update:
+ * single-spin-flip Metropolis (Eq. 2) on the two-colour checkerboard
+ * (Sec. 3.2): one sweep updates every colour-0 site (x+y[+z] even), then
+ * every colour-1 site.  Parallel tempering exchanges temperatures of
+ * neighbouring replicas with Eq. (12) (Sec. 6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments marked DEVICE are device pointers owned by the caller
+ *   (e.g. torch tensors on the current HIP device); arrays marked HOST are
+ *   read during the call only.  The library never frees caller memory.  It
+ *   keeps internal device scratch (threshold tables, ping-pong buffers),
+ *   allocated on first use and grown as needed; SMC_ENOMEM if that fails.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *   asynchronous with respect to the host on that stream; its results are
+ *   valid once the stream has reached the call.
+ * - Arguments are validated on the host before anything is launched; on an
+ *   argument error nothing is launched and nothing is modified.
+ * - Results are a pure function of (inputs, seed, sweep/step index): they
+ *   do not depend on launch shapes, streams or the device.  Every random
+ *   number is a Philox4x32-10 draw keyed by the seed with a counter made of
+ *   (site or pair index, sweep index, replica or chain index, stream tag).
+ * - Lattices are periodic simple (hyper)cubic, d = 2 or 3, edge L even and
+ *   >= 4, N = L^d sites in row-major order with x fastest:
+ *     2D: i = y*L + x,  3D: i = (z*L + y)*L + x.
+ * - Ising / EA spins are int8 +1/-1.  Heisenberg spins are float32 triples
+ *   (x, y, z) per site.  Couplings are int8 +1/-1 laid out [sample][mu][N]:
+ *   entry (mu, i) is the bond joining i and i + e_mu.
+ * - A batch holds n_rep replicas.  Uniform batch (desc.L > 0): replica r's
+ *   spins start at element r*N (r*N*3 floats for Heisenberg) and an EA
+ *   replica r uses sample r / rep_per_sample, whose couplings start at
+ *   element (r / rep_per_sample) * d * N.  Uneven batch (desc.L == 0): the
+ *   HOST table desc.inst[n_rep] gives each replica's edge, sample and offsets.
+ * - Return value: SMC_OK (0) or a negative smc_status.
+ */
+#ifndef SPINMC_H
+#define SPINMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SMC_OK = 0,
+    SMC_EINVAL = -1,       /* invalid argument (message in smc_last_error()) */
+    SMC_EUNSUPPORTED = -2, /* valid but not supported combination           */
+    SMC_EHIP = -3,         /* a HIP runtime call failed                      */
+    SMC_ENOMEM = -4        /* internal scratch could not be allocated        */
+} smc_status;
+
+typedef enum {
+    SMC_ISING = 0,       /* ferromagnet, all couplings +1 (Eq. 1)              */
+    SMC_EA = 1,          /* +-J Edwards-Anderson spin glass (Eq. 11)           */
+    SMC_HEISENBERG = 2   /* O(3) unit vectors, ferromagnetic (Eq. 10)          */
+} smc_model;
+
+/* One replica of an uneven batch. */
+typedef struct smc_inst {
+    int32_t L;        /* even edge length >= 4                                  */
+    int32_t sample;   /* coupling sample (keys the coupling draws; EA only)     */
+    int64_t spin_off; /* first spin of the replica, in spins (x3 floats: Heis.) */
+    int64_t coup_off; /* first coupling of its sample, in int8 elements (EA)    */
+} smc_inst;
+
+typedef struct smc_desc {
+    int32_t model;          /* smc_model                                          */
+    int32_t dim;            /* 2 or 3                                             */
+    int32_t L;              /* > 0: uniform batch of edge L; 0: use inst[]        */
+    int32_t n_rep;          /* replicas in the batch, >= 1                        */
+    int32_t rep_per_sample; /* uniform EA batch: replicas per coupling sample     */
+    int32_t renorm_every;   /* Heisenberg: renormalise every spin after sweeps t
+                               with (t+1) % renorm_every == 0; 0 = never          */
+    uint64_t seed;          /* Philox key                                         */
+    const smc_inst *inst;   /* HOST [n_rep] when L == 0, otherwise NULL           */
+    int64_t spins_len;      /* elements in the caller's spin buffer (int8 spins or
+                               floats, 3 per Heisenberg site); every replica must
+                               lie inside it, else SMC_EINVAL                     */
+    int64_t coup_len;       /* int8 elements in the coupling buffer (EA), else 0  */
+} smc_desc;
+
+/* Parallel-tempering layout: replica r = chain * n_temps + slot. */
+typedef struct smc_pt_desc {
+    int32_t n_chains;       /* independent chains                                 */
+    int32_t n_temps;        /* temperatures (= replicas) per chain, >= 2          */
+    int32_t beta_per_chain; /* 0: beta is [n_temps]; 1: beta is [n_chains][n_temps] */
+    int32_t reserved;
+    const double *beta;     /* HOST inverse temperatures of the ladder, index k   */
+} smc_pt_desc;
+
+/*
+ * Random initial state (scope row "spin_init").
+ *  Ising/EA: spin i of replica r is +1 iff the top bit of word (i mod 4) of
+ *  the draw (i/4, 0, r, 2) is 0.  Heisenberg: a uniform point on the sphere
+ *  from words 0, 1 of (i, 0, r, 2).  EA couplings (Sec. 5, bimodal, p = 1/2):
+ *  bond b = i*d + mu of sample q is +1 iff the top bit of word (b mod 4) of
+ *  (b/4, 0, q, 4) is 0.
+ *  spins:     DEVICE, int8 [.. N] or float32 [.. N][3], written.
+ *  couplings: DEVICE int8, written for every sample used by the batch when
+ *             model == SMC_EA and couplings != NULL; ignored otherwise.
+ */
+int smc_spin_init(const smc_desc *desc, void *spins, int8_t *couplings, void *stream);
+
+/*
+ * n_sweeps checkerboard Metropolis sweeps with global sweep indices
+ * sweep0 .. sweep0 + n_sweeps - 1 (Eq. 2; Sec. 3.2; rows "half-sweep
+ * colour 0 / colour 1", "Heisenberg sweep", "Delta E tracking").
+ *  beta:     HOST [n_rep] inverse temperature of each replica (>= 0, finite).
+ *  Ising/EA: a flip with Delta E = 4m > 0 is accepted iff the 32-bit uniform
+ *            u < floor(2^32 exp(-4 m beta)); Delta E <= 0 is always accepted.
+ *  Heisenberg: proposal uniform on the sphere, accepted iff Delta E <= 0 or
+ *            u < exp(-beta Delta E) in float32; renormalisation per desc.
+ *  couplings: DEVICE int8 (EA), NULL otherwise.
+ *  dE_accum: DEVICE int64 [n_rep] or NULL.  Ising/EA: += the sum of Delta E
+ *            over accepted flips (so E + dE_accum is the new energy).
+ *            Heisenberg: += the number of accepted moves.
+ *  Constraint: sweep0 + n_sweeps <= 2^32 (the sweep index is 32 bits).
+ */
+int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *couplings,
+                         const double *beta, uint64_t sweep0, int32_t n_sweeps,
+                         int64_t *dE_accum, void *stream);
+
+/*
+ * n_steps parallel-tempering steps with indices step0 .. step0+n_steps-1
+ * (Sec. 6, Eq. 12).  Step t: one sweep (sweep index t) of every replica at
+ * its current temperature, energies tracked from the accepted flips; then
+ * for every pair (k, k+1) with k = t (mod 2), k <= n_temps-2, in every
+ * chain q: A = slot_of_temp[q][k], B = slot_of_temp[q][k+1],
+ * x = (beta_{k+1} - beta_k) * (E_B - E_A) in float64, accepted iff x >= 0 or
+ * u53 < exp(x) with u53 the 53-bit uniform of the draw (k, t, q, 12); on
+ * acceptance the two slots exchange temperatures.
+ *  Models: Ising and EA (the EA replicas of one chain must share a sample).
+ *  desc.n_rep must equal n_chains * n_temps.
+ *  slot_of_temp: DEVICE int32 [n_chains][n_temps], in/out (a permutation of
+ *                0..n_temps-1 per chain).
+ *  energy:       DEVICE float64 [n_rep], in/out: energy of the configuration
+ *                stored in each replica (exact integers; e.g. from
+ *                smc_measure_energy_magnetisation).
+ *  swap_accepts: DEVICE uint64 [n_chains][n_temps-1] or NULL; += accepted
+ *                exchanges of pair k.
+ *  Constraint: step0 + n_steps <= 2^32.
+ */
+int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins,
+                      const int8_t *couplings, int32_t *slot_of_temp, double *energy,
+                      uint64_t step0, int32_t n_steps, uint64_t *swap_accepts, void *stream);
+
+/*
+ * Energy and magnetisation of every replica (row "measure"):
+ *  E = -sum_i sum_mu J(i,mu) s_i . s_{i+e_mu},  M = sum_i s_i.
+ *  energy:        DEVICE float64 [n_rep] (exact integers for Ising/EA).
+ *  magnetisation: DEVICE float64 [n_rep] (Ising/EA) or [n_rep][3]
+ *                 (Heisenberg), or NULL.
+ *  Heisenberg sums are accumulated in float64 in a fixed order (the result
+ *  is reproducible run to run).
+ */
+int smc_measure_energy_magnetisation(const smc_desc *desc, const void *spins,
+                                     const int8_t *couplings, double *energy,
+                                     double *magnetisation, void *stream);
+
+/*
+ * How smc_metropolis_sweep will execute this batch: the number of kernel
+ * launches per sweep and the name of the sweep kernel (a static string).
+ * Used by benchmarks to attribute per-launch time; no device work.
+ */
+int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char **kernel_name);
+
+/* Static description of a status code. */
+const char *smc_strerror(int status);
+
+/* Detail of the last error raised on the calling host thread ("" if none). */
+const char *smc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPINMC_H */

@@ -1,0 +1,187 @@
+"""Python binding of libspinmc.so (checkerboard Metropolis / parallel tempering on MI355X).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI (``include/spinmc.h``).  Tensors are torch tensors on the
+current HIP device; calls are enqueued on ``torch.cuda.current_stream()``
+unless a stream is given.  There is no CPU fallback: if the library is
+missing, importing the binding's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspinmc.so")
+
+ISING, EA, HEISENBERG = 0, 1, 2
+OK, EINVAL, EUNSUPPORTED, EHIP, ENOMEM = 0, -1, -2, -3, -4
+
+
+class SpinMCError(RuntimeError):
+    def __init__(self, code: int, func: str, detail: str):
+        self.code = code
+        super().__init__(f"{func} failed with status {code}: {detail}")
+
+
+class Inst(C.Structure):
+    _fields_ = [("L", C.c_int32), ("sample", C.c_int32), ("spin_off", C.c_int64), ("coup_off", C.c_int64)]
+
+
+class Desc(C.Structure):
+    _fields_ = [("model", C.c_int32), ("dim", C.c_int32), ("L", C.c_int32), ("n_rep", C.c_int32),
+                ("rep_per_sample", C.c_int32), ("renorm_every", C.c_int32), ("seed", C.c_uint64),
+                ("inst", C.POINTER(Inst)), ("spins_len", C.c_int64), ("coup_len", C.c_int64)]
+
+
+class PTDesc(C.Structure):
+    _fields_ = [("n_chains", C.c_int32), ("n_temps", C.c_int32), ("beta_per_chain", C.c_int32),
+                ("reserved", C.c_int32), ("beta", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libspinmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1101_1427_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, P = C.c_void_p, C.POINTER
+        L.smc_spin_init.argtypes = [P(Desc), vp, vp, vp]
+        L.smc_metropolis_sweep.argtypes = [P(Desc), vp, vp, P(C.c_double), C.c_uint64, C.c_int32, vp, vp]
+        L.smc_pt_sweep_swap.argtypes = [P(Desc), P(PTDesc), vp, vp, vp, vp, C.c_uint64, C.c_int32, vp, vp]
+        L.smc_measure_energy_magnetisation.argtypes = [P(Desc), vp, vp, vp, vp, vp]
+        for f in (L.smc_spin_init, L.smc_metropolis_sweep, L.smc_pt_sweep_swap, L.smc_measure_energy_magnetisation):
+            f.restype = C.c_int
+        L.smc_sweep_plan.argtypes = [P(Desc), P(C.c_int32), P(C.c_char_p)]
+        L.smc_sweep_plan.restype = C.c_int
+        L.smc_strerror.argtypes = [C.c_int]
+        L.smc_strerror.restype = C.c_char_p
+        L.smc_last_error.argtypes = []
+        L.smc_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, func: str):
+    if rc != OK:
+        L = lib()
+        raise SpinMCError(rc, func, f"{L.smc_strerror(rc).decode()}: {L.smc_last_error().decode()}")
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Batch:
+    """A batch of replicas.  Uniform (L > 0) or uneven (L == 0 with ``inst``,
+    an int64 array of rows (L, sample, spin_off, coup_off))."""
+    model: int
+    dim: int
+    L: int
+    n_rep: int
+    seed: int
+    rep_per_sample: int = 1
+    renorm_every: int = 0
+    inst: np.ndarray | None = None
+
+    def sites(self, L=None):
+        L = self.L if L is None else L
+        return L ** self.dim
+
+    def spins_shape(self):
+        per = 3 if self.model == HEISENBERG else 1
+        if self.L > 0:
+            return (self.n_rep * self.sites() * per,)
+        ends = [int(r[2]) + self.sites(int(r[0])) for r in self.inst]
+        return (max(ends) * per,)
+
+    def coup_len(self):
+        if self.model != EA:
+            return 0
+        if self.L > 0:
+            n_samples = -(-self.n_rep // self.rep_per_sample)
+            return n_samples * self.dim * self.sites()
+        return max(int(r[3]) + self.dim * self.sites(int(r[0])) for r in self.inst)
+
+    def desc(self, spins_len: int, coup_len: int) -> Desc:
+        d = Desc(self.model, self.dim, self.L, self.n_rep, self.rep_per_sample, self.renorm_every,
+                 self.seed & 0xFFFFFFFFFFFFFFFF, None, spins_len, coup_len)
+        if self.L == 0:
+            rows = (Inst * self.n_rep)()
+            for k, r in enumerate(self.inst):
+                rows[k] = Inst(int(r[0]), int(r[1]), int(r[2]), int(r[3]))
+            d._inst_keep = rows  # keep alive for the call
+            d.inst = C.cast(rows, C.POINTER(Inst))
+        return d
+
+
+def _desc(batch: Batch, spins, couplings):
+    return batch.desc(spins.numel(), 0 if couplings is None else couplings.numel())
+
+
+def spin_init(batch: Batch, spins, couplings=None, stream=None):
+    """Random start (and bimodal couplings for EA); see smc_spin_init."""
+    d = _desc(batch, spins, couplings)
+    _check(lib().smc_spin_init(C.byref(d), _ptr(spins), _ptr(couplings), _stream(stream)), "smc_spin_init")
+
+
+def metropolis_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, couplings=None, dE_accum=None,
+                     stream=None):
+    """n_sweeps checkerboard Metropolis sweeps; beta is a host sequence [n_rep]."""
+    d = _desc(batch, spins, couplings)
+    b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (batch.n_rep,)))
+    _check(lib().smc_metropolis_sweep(C.byref(d), _ptr(spins), _ptr(couplings),
+                                      b.ctypes.data_as(C.POINTER(C.c_double)), sweep0, n_sweeps,
+                                      _ptr(dE_accum), _stream(stream)), "smc_metropolis_sweep")
+
+
+def pt_sweep_swap(batch: Batch, n_chains: int, n_temps: int, beta, spins, slot_of_temp, energy, step0: int,
+                  n_steps: int, couplings=None, swap_accepts=None, beta_per_chain: bool = False, stream=None):
+    """n_steps parallel-tempering steps (sweep + exchange round); beta is host [n_temps]
+    (or [n_chains, n_temps] with beta_per_chain)."""
+    d = _desc(batch, spins, couplings)
+    b = np.ascontiguousarray(np.asarray(beta, np.float64).reshape(-1))
+    pt = PTDesc(n_chains, n_temps, 1 if beta_per_chain else 0, 0, b.ctypes.data_as(C.POINTER(C.c_double)))
+    _check(lib().smc_pt_sweep_swap(C.byref(d), C.byref(pt), _ptr(spins), _ptr(couplings), _ptr(slot_of_temp),
+                                   _ptr(energy), step0, n_steps, _ptr(swap_accepts), _stream(stream)),
+           "smc_pt_sweep_swap")
+
+
+def measure_energy_magnetisation(batch: Batch, spins, energy, magnetisation=None, couplings=None, stream=None):
+    """Energy and magnetisation of every replica into float64 device tensors."""
+    d = _desc(batch, spins, couplings)
+    _check(lib().smc_measure_energy_magnetisation(C.byref(d), _ptr(spins), _ptr(couplings), _ptr(energy),
+                                                  _ptr(magnetisation), _stream(stream)),
+           "smc_measure_energy_magnetisation")
+
+
+def sweep_plan(batch: Batch):
+    """(launches per sweep, sweep kernel name) that smc_metropolis_sweep uses for this batch."""
+    spins_len = batch.spins_shape()[0]
+    d = batch.desc(spins_len, batch.coup_len())
+    n = C.c_int32(0)
+    name = C.c_char_p()
+    _check(lib().smc_sweep_plan(C.byref(d), C.byref(n), C.byref(name)), "smc_sweep_plan")
+    return int(n.value), name.value.decode()
+
+
+def launches_per_sweep(batch: Batch) -> int:
+    return sweep_plan(batch)[0]
+
+
+def sweep_kernel_name(batch: Batch) -> str:
+    return sweep_plan(batch)[1]

@@ -1,0 +1,461 @@
+// C-ABI layer of libspinmc.so: argument validation, acceptance tables,
+// per-stream scratch, and dispatch to the sweep / exchange kernels.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace smc {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define SMC_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail(SMC_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ scratch --
+// Device scratch and a pinned staging area, one set per (device, stream):
+// calls on one stream are ordered, so reusing the set between them is safe;
+// calls on different streams never share a set.
+struct Buffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+    // uploaded slots: pinned staging, the event of its last copy, and the
+    // bytes last uploaded (an identical upload is skipped)
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    std::vector<unsigned char> last;
+};
+
+enum Slot { kTables = 0, kInst, kSamples, kMeasure, kEnergy64, kRows, kBeta, kPingPong, kNumSlots };
+
+struct StreamCtx {
+    Buffer dev[kNumSlots];
+};
+
+std::mutex g_ctx_mutex;
+std::map<std::pair<int, hipStream_t>, StreamCtx> g_ctx;
+
+StreamCtx &ctx_for(hipStream_t s) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_ctx_mutex);
+    return g_ctx[std::make_pair(dev, s)];
+}
+
+// Device buffer of at least `bytes`; growing waits for the device first so
+// that no queued kernel still reads the old allocation.
+int ensure(StreamCtx &c, Slot slot, size_t bytes, void **out) {
+    Buffer &b = c.dev[slot];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            SMC_HIP(hipDeviceSynchronize());
+            SMC_HIP(hipFree(b.p));
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        b.last.clear();
+        size_t want = bytes < 256 ? 256 : bytes;
+        if (hipMalloc(&b.p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return fail(SMC_ENOMEM, "could not allocate %zu bytes of scratch", want);
+        }
+        b.bytes = want;
+    }
+    *out = b.p;
+    return SMC_OK;
+}
+
+// Copy host bytes into a device scratch slot through that slot's pinned
+// staging area.  The staging area is reused only after its previous copy has
+// completed; an upload identical to the slot's previous one is skipped (the
+// device copy is only ever written by uploads, in stream order).
+int upload(StreamCtx &c, hipStream_t s, Slot slot, const void *src, size_t bytes, void **dev_out) {
+    int rc = ensure(c, slot, bytes, dev_out);
+    if (rc) return rc;
+    Buffer &b = c.dev[slot];
+    if (b.last.size() == bytes && memcmp(b.last.data(), src, bytes) == 0) return SMC_OK;
+    if (b.staged_pending) {
+        SMC_HIP(hipEventSynchronize(b.staged));
+        b.staged_pending = false;
+    }
+    if (b.pinned_bytes < bytes) {
+        if (b.pinned) SMC_HIP(hipHostFree(b.pinned));
+        b.pinned = nullptr;
+        b.pinned_bytes = 0;
+        size_t want = bytes < 4096 ? 4096 : bytes;
+        if (hipHostMalloc(&b.pinned, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            b.pinned = nullptr;
+            return fail(SMC_ENOMEM, "could not allocate %zu bytes of pinned staging", want);
+        }
+        b.pinned_bytes = want;
+    }
+    if (!b.staged) SMC_HIP(hipEventCreateWithFlags(&b.staged, hipEventDisableTiming));
+    memcpy(b.pinned, src, bytes);
+    b.last.assign((const unsigned char *)src, (const unsigned char *)src + bytes);
+    SMC_HIP(hipMemcpyAsync(*dev_out, b.pinned, bytes, hipMemcpyHostToDevice, s));
+    SMC_HIP(hipEventRecord(b.staged, s));
+    b.staged_pending = true;
+    return SMC_OK;
+}
+
+// ----------------------------------------------------------------- tables ----
+// thr[m] = floor(2^32 exp(-4 m beta)) for Delta E = 4m > 0, computed in
+// float64 with the C library's exp and split as (thr >> 16, thr & 0xffff).
+ThrRow threshold_row(double beta, int dim) {
+    ThrRow row;
+    row.m[0] = make_uint2(65536u, 0u);
+    for (int m = 1; m <= 3; ++m) {
+        uint64_t thr = 0;
+        if (m <= dim) {
+            const double p = exp(-beta * (4.0 * m));
+            thr = (uint64_t)floor(4294967296.0 * p);
+        }
+        row.m[m] = make_uint2((uint32_t)(thr >> 16), (uint32_t)(thr & 0xFFFFu));
+    }
+    return row;
+}
+
+// --------------------------------------------------------------- validation --
+struct Plan {
+    Batch b;
+    int max_L = 0;
+    int64_t n_samples = 0;
+    std::vector<smc_inst> samples;  // distinct samples (EA): L, sample, -, coup_off
+};
+
+int64_t sites(int dim, int L) { return dim == 3 ? (int64_t)L * L * L : (int64_t)L * L; }
+
+int validate(const smc_desc *d, bool need_coup, Plan &plan) {
+    if (!d) return fail(SMC_EINVAL, "desc is NULL");
+    if (d->model < SMC_ISING || d->model > SMC_HEISENBERG) return fail(SMC_EINVAL, "unknown model %d", d->model);
+    if (d->dim != 2 && d->dim != 3) return fail(SMC_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
+    if (d->n_rep < 1) return fail(SMC_EINVAL, "n_rep must be >= 1 (got %d)", d->n_rep);
+    if (d->spins_len <= 0) return fail(SMC_EINVAL, "spins_len must be > 0");
+    if (d->model == SMC_HEISENBERG && d->renorm_every < 0) return fail(SMC_EINVAL, "renorm_every must be >= 0");
+    const bool ea = d->model == SMC_EA;
+    const int per_site = d->model == SMC_HEISENBERG ? 3 : 1;
+    Batch &b = plan.b;
+    b.dim = d->dim;
+    b.model = d->model;
+    b.n_rep = d->n_rep;
+    b.L = d->L;
+    b.rep_per_sample = 1;
+    b.inst = nullptr;
+    b.N = 0;
+    plan.samples.clear();
+    if (d->L > 0) {
+        if (d->inst) return fail(SMC_EINVAL, "inst must be NULL for a uniform batch (L > 0)");
+        if (d->L % 2 || d->L < 4) return fail(SMC_EINVAL, "L must be even and >= 4 (got %d)", d->L);
+        if (d->L > (d->dim == 3 ? 1024 : 65536)) return fail(SMC_EINVAL, "L too large (got %d)", d->L);
+        b.N = sites(d->dim, d->L);
+        if (b.N / 2 > 0xFFFFFFFFll) return fail(SMC_EINVAL, "lattice too large for 32-bit site counters");
+        plan.max_L = d->L;
+        if ((int64_t)d->n_rep * b.N * per_site > d->spins_len)
+            return fail(SMC_EINVAL, "spin buffer too small: need %lld elements, have %lld",
+                        (long long)((int64_t)d->n_rep * b.N * per_site), (long long)d->spins_len);
+        if (ea) {
+            if (d->rep_per_sample < 1) return fail(SMC_EINVAL, "rep_per_sample must be >= 1 for EA");
+            b.rep_per_sample = d->rep_per_sample;
+            plan.n_samples = (d->n_rep + d->rep_per_sample - 1) / d->rep_per_sample;
+            for (int64_t q = 0; q < plan.n_samples; ++q) {
+                smc_inst g;
+                g.L = d->L;
+                g.sample = (int32_t)q;
+                g.spin_off = 0;
+                g.coup_off = q * d->dim * b.N;
+                plan.samples.push_back(g);
+            }
+        }
+    } else {
+        if (!d->inst) return fail(SMC_EINVAL, "inst is required when L == 0");
+        std::map<int32_t, smc_inst> seen;
+        for (int r = 0; r < d->n_rep; ++r) {
+            const smc_inst &g = d->inst[r];
+            if (g.L % 2 || g.L < 4 || g.L > (d->dim == 3 ? 1024 : 65536))
+                return fail(SMC_EINVAL, "inst[%d].L must be even and in [4, limit] (got %d)", r, g.L);
+            const int64_t N = sites(d->dim, g.L);
+            if (g.spin_off < 0 || g.spin_off > d->spins_len / per_site - N)
+                return fail(SMC_EINVAL, "inst[%d] spins lie outside the spin buffer", r);
+            if (ea) {
+                if (g.sample < 0) return fail(SMC_EINVAL, "inst[%d].sample must be >= 0", r);
+                auto it = seen.find(g.sample);
+                if (it == seen.end()) {
+                    seen[g.sample] = g;
+                } else if (it->second.L != g.L || it->second.coup_off != g.coup_off) {
+                    return fail(SMC_EINVAL, "inst[%d]: sample %d used with two geometries", r, g.sample);
+                }
+            }
+            if (g.L > plan.max_L) plan.max_L = g.L;
+        }
+        for (auto &kv : seen) plan.samples.push_back(kv.second);
+        plan.n_samples = (int64_t)plan.samples.size();
+    }
+    if (ea && need_coup) {
+        if (d->coup_len <= 0) return fail(SMC_EINVAL, "coup_len must be > 0 for EA");
+        for (const smc_inst &g : plan.samples) {
+            const int64_t need = (int64_t)d->dim * sites(d->dim, g.L);
+            if (g.coup_off < 0 || g.coup_off > d->coup_len - need)
+                return fail(SMC_EINVAL, "couplings of sample %d lie outside the coupling buffer", g.sample);
+        }
+    }
+    return SMC_OK;
+}
+
+int upload_inst(StreamCtx &c, hipStream_t s, const smc_desc *d, Plan &plan) {
+    if (d->L > 0) return SMC_OK;
+    void *p = nullptr;
+    int rc = upload(c, s, kInst, d->inst, sizeof(smc_inst) * (size_t)d->n_rep, &p);
+    plan.b.inst = (const smc_inst *)p;
+    return rc;
+}
+
+}  // namespace
+}  // namespace smc
+
+using namespace smc;
+
+extern "C" {
+
+const char *smc_strerror(int status) {
+    switch (status) {
+        case SMC_OK: return "success";
+        case SMC_EINVAL: return "invalid argument";
+        case SMC_EUNSUPPORTED: return "unsupported combination of arguments";
+        case SMC_EHIP: return "HIP runtime error";
+        case SMC_ENOMEM: return "out of device memory for scratch";
+        default: return "unknown status";
+    }
+}
+
+const char *smc_last_error(void) { return g_last_error.c_str(); }
+
+int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char **kernel_name) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, false, plan);
+    if (rc) return rc;
+    if (!launches_per_sweep || !kernel_name) return fail(SMC_EINVAL, "output pointers are required");
+    if (desc->model == SMC_HEISENBERG) {
+        *launches_per_sweep = 2;
+        *kernel_name = "k_heis_half_sweep_generic";
+    } else {
+        *launches_per_sweep = 2;
+        *kernel_name = "k_half_sweep_generic";
+    }
+    return SMC_OK;
+}
+
+int smc_spin_init(const smc_desc *desc, void *spins, int8_t *couplings, void *stream) {
+    g_last_error.clear();
+    Plan plan;
+    const bool want_coup = desc && desc->model == SMC_EA && couplings;
+    int rc = validate(desc, want_coup, plan);
+    if (rc) return rc;
+    if (!spins) return fail(SMC_EINVAL, "spins is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    StreamCtx &c = ctx_for(s);
+    if ((rc = upload_inst(c, s, desc, plan))) return rc;
+    const Key key = make_key(desc->seed);
+    if (desc->model == SMC_HEISENBERG) {
+        SMC_HIP(launch_init_heis(plan.b, plan.max_L, (float *)spins, key, s));
+    } else {
+        SMC_HIP(launch_init_spins(plan.b, plan.max_L, (int8_t *)spins, key, s));
+    }
+    if (want_coup && plan.n_samples > 0) {
+        void *p = nullptr;
+        if ((rc = upload(c, s, kSamples, plan.samples.data(), sizeof(smc_inst) * plan.samples.size(), &p))) return rc;
+        int maxL = 0;
+        for (auto &g : plan.samples) maxL = g.L > maxL ? g.L : maxL;
+        SMC_HIP(launch_init_couplings(desc->dim, (int)plan.n_samples, (const smc_inst *)p, maxL, couplings, key, s));
+    }
+    return SMC_OK;
+}
+
+int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta,
+                         uint64_t sweep0, int32_t n_sweeps, int64_t *dE_accum, void *stream) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, true, plan);
+    if (rc) return rc;
+    if (!spins) return fail(SMC_EINVAL, "spins is NULL");
+    if (!beta) return fail(SMC_EINVAL, "beta is NULL");
+    if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
+    if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+    if (sweep0 + (uint64_t)n_sweeps > (1ull << 32)) return fail(SMC_EINVAL, "sweep index exceeds 32 bits");
+    for (int r = 0; r < desc->n_rep; ++r)
+        if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
+    if (n_sweeps == 0) return SMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    StreamCtx &c = ctx_for(s);
+    if ((rc = upload_inst(c, s, desc, plan))) return rc;
+
+    SweepArgs a;
+    memset(&a, 0, sizeof a);
+    a.b = plan.b;
+    a.spins = spins;
+    a.coup = desc->model == SMC_EA ? couplings : nullptr;
+    a.key = make_key(desc->seed);
+    a.dE = dE_accum;
+    a.max_L = plan.max_L;
+    a.row_of_rep = nullptr;
+    void *p = nullptr;
+    if (desc->model == SMC_HEISENBERG) {
+        std::vector<float> bf(desc->n_rep);
+        for (int r = 0; r < desc->n_rep; ++r) bf[r] = (float)beta[r];
+        if ((rc = upload(c, s, kTables, bf.data(), sizeof(float) * bf.size(), &p))) return rc;
+        a.beta_f = (const float *)p;
+        for (int32_t k = 0; k < n_sweeps; ++k) {
+            a.t = (uint32_t)(sweep0 + (uint64_t)k);
+            SMC_HIP(launch_heis_half_sweep_generic(a, 0, s));
+            SMC_HIP(launch_heis_half_sweep_generic(a, 1, s));
+            if (desc->renorm_every > 0 && ((uint64_t)a.t + 1) % (uint64_t)desc->renorm_every == 0)
+                SMC_HIP(launch_heis_renorm(plan.b, (float *)spins, plan.max_L, s));
+        }
+        return SMC_OK;
+    }
+    std::vector<ThrRow> rows(desc->n_rep);
+    for (int r = 0; r < desc->n_rep; ++r) rows[r] = threshold_row(beta[r], desc->dim);
+    if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &p))) return rc;
+    a.thr = (const ThrRow *)p;
+    for (int32_t k = 0; k < n_sweeps; ++k) {
+        a.t = (uint32_t)(sweep0 + (uint64_t)k);
+        SMC_HIP(launch_half_sweep_generic(a, 0, s));
+        SMC_HIP(launch_half_sweep_generic(a, 1, s));
+    }
+    return SMC_OK;
+}
+
+int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, const int8_t *couplings,
+                      int32_t *slot_of_temp, double *energy, uint64_t step0, int32_t n_steps,
+                      uint64_t *swap_accepts, void *stream) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, true, plan);
+    if (rc) return rc;
+    if (!pt) return fail(SMC_EINVAL, "pt desc is NULL");
+    if (desc->model == SMC_HEISENBERG)
+        return fail(SMC_EUNSUPPORTED, "parallel tempering is provided for Ising and EA models");
+    if (pt->n_chains < 1 || pt->n_temps < 2) return fail(SMC_EINVAL, "need n_chains >= 1 and n_temps >= 2");
+    if ((int64_t)pt->n_chains * pt->n_temps != desc->n_rep)
+        return fail(SMC_EINVAL, "n_rep (%d) must equal n_chains * n_temps", desc->n_rep);
+    if (!pt->beta) return fail(SMC_EINVAL, "beta is NULL");
+    if (!spins || !slot_of_temp || !energy) return fail(SMC_EINVAL, "spins, slot_of_temp and energy are required");
+    if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
+    if (n_steps < 0) return fail(SMC_EINVAL, "n_steps must be >= 0");
+    if (step0 + (uint64_t)n_steps > (1ull << 32)) return fail(SMC_EINVAL, "step index exceeds 32 bits");
+    const int n = pt->n_temps;
+    const int rows_n = pt->beta_per_chain ? pt->n_chains : 1;
+    for (int64_t k = 0; k < (int64_t)rows_n * n; ++k)
+        if (!(pt->beta[k] >= 0.0) || !isfinite(pt->beta[k])) return fail(SMC_EINVAL, "beta[%lld] invalid", (long long)k);
+    if (desc->model == SMC_EA) {
+        if (desc->L > 0) {
+            if (desc->rep_per_sample % n) return fail(SMC_EINVAL, "rep_per_sample must be a multiple of n_temps");
+        } else {
+            for (int q = 0; q < pt->n_chains; ++q)
+                for (int k = 1; k < n; ++k)
+                    if (desc->inst[q * n + k].sample != desc->inst[q * n].sample)
+                        return fail(SMC_EINVAL, "chain %d mixes coupling samples", q);
+        }
+    }
+    if (desc->L == 0) {
+        for (int q = 0; q < pt->n_chains; ++q)
+            for (int k = 1; k < n; ++k)
+                if (desc->inst[q * n + k].L != desc->inst[q * n].L)
+                    return fail(SMC_EINVAL, "chain %d mixes lattice sizes", q);
+    }
+    if (n_steps == 0) return SMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    StreamCtx &c = ctx_for(s);
+    if ((rc = upload_inst(c, s, desc, plan))) return rc;
+
+    // tables: beta per (row, k) and threshold rows (row * n + k)
+    std::vector<ThrRow> rows((size_t)rows_n * n);
+    for (size_t k = 0; k < rows.size(); ++k) rows[k] = threshold_row(pt->beta[k], desc->dim);
+    void *thr = nullptr, *bdev = nullptr, *E64 = nullptr, *rowrep = nullptr;
+    if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &thr))) return rc;
+    if ((rc = upload(c, s, kBeta, pt->beta, sizeof(double) * rows.size(), &bdev))) return rc;
+    if ((rc = ensure(c, kEnergy64, sizeof(int64_t) * desc->n_rep, &E64))) return rc;
+    if ((rc = ensure(c, kRows, sizeof(int32_t) * desc->n_rep, &rowrep))) return rc;
+
+    SwapArgs sw;
+    sw.n_chains = pt->n_chains;
+    sw.n_temps = n;
+    sw.beta_per_chain = pt->beta_per_chain ? 1 : 0;
+    sw.beta = (const double *)bdev;
+    sw.slot_of_temp = slot_of_temp;
+    sw.row_of_rep = (int32_t *)rowrep;
+    sw.E = (int64_t *)E64;
+    sw.acc = (unsigned long long *)swap_accepts;
+    sw.key = make_key(desc->seed);
+    sw.t = 0;
+
+    SweepArgs a;
+    memset(&a, 0, sizeof a);
+    a.b = plan.b;
+    a.spins = spins;
+    a.coup = desc->model == SMC_EA ? couplings : nullptr;
+    a.key = make_key(desc->seed);
+    a.dE = (int64_t *)E64;
+    a.max_L = plan.max_L;
+    a.thr = (const ThrRow *)thr;
+    a.row_of_rep = (const int32_t *)rowrep;
+
+    SMC_HIP(launch_pt_prepare(sw, energy, s));
+    for (int32_t k = 0; k < n_steps; ++k) {
+        const uint32_t t = (uint32_t)(step0 + (uint64_t)k);
+        a.t = t;
+        sw.t = t;
+        SMC_HIP(launch_half_sweep_generic(a, 0, s));
+        SMC_HIP(launch_half_sweep_generic(a, 1, s));
+        SMC_HIP(launch_pt_swap(sw, s));
+    }
+    SMC_HIP(launch_pt_finish(sw, energy, s));
+    return SMC_OK;
+}
+
+int smc_measure_energy_magnetisation(const smc_desc *desc, const void *spins, const int8_t *couplings,
+                                     double *energy, double *magnetisation, void *stream) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, true, plan);
+    if (rc) return rc;
+    if (!spins || !energy) return fail(SMC_EINVAL, "spins and energy are required");
+    if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
+    hipStream_t s = (hipStream_t)stream;
+    StreamCtx &c = ctx_for(s);
+    if ((rc = upload_inst(c, s, desc, plan))) return rc;
+    const size_t bytes = measure_scratch_bytes(plan.b, plan.max_L);
+    void *p = nullptr;
+    if ((rc = ensure(c, kMeasure, bytes, &p))) return rc;
+    SMC_HIP(launch_measure(plan.b, spins, desc->model == SMC_EA ? couplings : nullptr, plan.max_L, energy,
+                           magnetisation, p, bytes, s));
+    return SMC_OK;
+}
+
+}  // extern "C"

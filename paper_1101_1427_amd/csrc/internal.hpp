@@ -1,0 +1,86 @@
+// Internal interfaces between the C-ABI layer (api.hip) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/spinmc.h"
+#include "philox.hpp"
+
+namespace smc {
+
+// One row of the acceptance table: entry m (1..3) is the threshold of
+// Delta E = 4m split as (hi, lo); entry 0 is unused.
+struct ThrRow {
+    uint2 m[4];
+};
+
+// Geometry of a batch as the kernels see it.  Uniform batches use (L, N,
+// spin_stride, coup_stride, rep_per_sample); uneven ones the inst table.
+struct Batch {
+    int dim;
+    int model;
+    int n_rep;
+    int L;                  // > 0 uniform, 0 uneven
+    int64_t N;              // sites per replica (uniform)
+    int rep_per_sample;     // uniform EA
+    const smc_inst *inst;   // device [n_rep] (uneven) or nullptr
+};
+
+__device__ __forceinline__ smc_inst replica_geom(const Batch &b, int r) {
+    if (b.L > 0) {
+        smc_inst g;
+        g.L = b.L;
+        g.sample = r / b.rep_per_sample;
+        g.spin_off = (int64_t)r * b.N;
+        g.coup_off = (int64_t)g.sample * b.dim * b.N;
+        return g;
+    }
+    return b.inst[r];
+}
+
+struct SweepArgs {
+    Batch b;
+    void *spins;
+    const int8_t *coup;        // EA couplings or nullptr
+    const ThrRow *thr;         // discrete: rows of thresholds
+    const float *beta_f;       // Heisenberg: beta per row
+    const int32_t *row_of_rep; // nullptr: row = replica index
+    Key key;
+    uint32_t t;                // sweep index
+    int64_t *dE;               // nullable per-replica accumulator
+    int max_L;                 // largest edge in the batch
+};
+
+struct SwapArgs {
+    int n_chains, n_temps, beta_per_chain;
+    const double *beta;        // device [rows][n_temps]
+    int32_t *slot_of_temp;     // [n_chains][n_temps]
+    int32_t *row_of_rep;       // [n_rep]: threshold row of each replica
+    int64_t *E;                // [n_rep]
+    unsigned long long *acc;   // [n_chains][n_temps-1] or nullptr
+    Key key;
+    uint32_t t;
+};
+
+// ---- launchers (each returns the hipError_t of its launch) ----
+hipError_t launch_init_spins(const Batch &b, int max_L, int8_t *spins, Key key, hipStream_t s);
+hipError_t launch_init_heis(const Batch &b, int max_L, float *spins, Key key, hipStream_t s);
+hipError_t launch_init_couplings(int dim, int n_samples, const smc_inst *samples_dev, int max_L, int8_t *coup,
+                                 Key key, hipStream_t s);
+
+// Generic in-place half-sweep of colour c over every replica (any L, d).
+hipError_t launch_half_sweep_generic(const SweepArgs &a, int c, hipStream_t s);
+hipError_t launch_heis_half_sweep_generic(const SweepArgs &a, int c, hipStream_t s);
+hipError_t launch_heis_renorm(const Batch &b, float *spins, int max_L, hipStream_t s);
+
+// Measurement: partials of every replica, then a fixed-order final sum.
+hipError_t launch_measure(const Batch &b, const void *spins, const int8_t *coup, int max_L, double *energy,
+                          double *magnet, void *scratch, size_t scratch_bytes, hipStream_t s);
+size_t measure_scratch_bytes(const Batch &b, int max_L);
+
+// Parallel tempering helpers.
+hipError_t launch_pt_prepare(const SwapArgs &a, const double *energy_in, hipStream_t s);
+hipError_t launch_pt_swap(const SwapArgs &a, hipStream_t s);
+hipError_t launch_pt_finish(const SwapArgs &a, double *energy_out, hipStream_t s);
+
+}  // namespace smc

@@ -1,0 +1,81 @@
+// Device-side Philox4x32-10 and the stream layout of the random numbers.
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+//   (hi0,lo0) = M0*x0, (hi1,lo1) = M1*x2, x' = (hi1^x1^k0, lo1, hi0^x3^k1, lo0)
+// with the key advanced by the Weyl constants between rounds.  The key is
+// uniform across a launch, so its schedule lives in scalar registers; only
+// the counter word that carries the site index varies per lane.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+// Stream tags (counter word 3 = 2*tag + colour).
+constexpr uint32_t kTagInit = 1, kTagCoup = 2, kTagHead = 3, kTagTail = 4, kTagHeis = 5, kTagSwap = 6;
+
+struct Key {
+    uint32_t k0, k1;
+};
+
+__host__ __device__ inline Key make_key(uint64_t seed) { return Key{(uint32_t)seed, (uint32_t)(seed >> 32)}; }
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 x, Key key) {
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint32_t lo0 = kPhiloxM0 * x.x;
+        const uint32_t hi0 = __umulhi(kPhiloxM0, x.x);
+        const uint32_t lo1 = kPhiloxM1 * x.z;
+        const uint32_t hi1 = __umulhi(kPhiloxM1, x.z);
+        x = make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &w, uint32_t j) {
+    return j == 0 ? w.x : j == 1 ? w.y : j == 2 ? w.z : w.w;
+}
+
+// 16-bit head of the Metropolis uniform of in-colour index h: half (h & 7) of
+// the draw (h>>3, t, r, 2*HEAD + c), the low half of word 0 first.
+__device__ __forceinline__ uint32_t head16_of(const uint4 &w, uint32_t h8) {
+    const uint32_t word = word_of(w, h8 >> 1);
+    return (h8 & 1) ? (word >> 16) : (word & 0xFFFFu);
+}
+
+// 16-bit tail: low half of word 0 of the draw (h, t, r, 2*TAIL + c).
+__device__ __forceinline__ uint32_t tail16(uint32_t h, uint32_t t, uint32_t r, uint32_t c, Key key) {
+    return philox4x32_10(make_uint4(h, t, r, 2 * kTagTail + c), key).x & 0xFFFFu;
+}
+
+// Threshold of a positive energy change, split into the part compared with
+// the head (0 .. 65536) and the part compared with the tail (0 .. 65535):
+// thr = hi * 2^16 + lo = floor(2^32 exp(-beta dE)).
+// u = head*2^16 + tail < thr  <=>  head < hi  or  (head == hi and tail < lo).
+__device__ __forceinline__ bool metropolis_accept(uint32_t head, uint2 thr, uint32_t h, uint32_t t,
+                                                  uint32_t r, uint32_t c, Key key) {
+    if (head != thr.x) return head < thr.x;
+    return tail16(h, t, r, c, key) < thr.y;
+}
+
+// Uniform (k + 1/2) 2^-23 from the top 23 bits of a word: exact in float.
+__device__ __forceinline__ float unit23f(uint32_t w) {
+    return ((float)(w >> 9) + 0.5f) * (1.0f / 8388608.0f);
+}
+
+// 53-bit uniform in [0, 1) from two words.
+__device__ __forceinline__ double unit53(uint32_t w0, uint32_t w1) {
+    return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace smc

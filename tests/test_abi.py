@@ -1,0 +1,114 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function the header declares, and rejects invalid arguments before it
+touches the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1101_1427_amd as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spinmc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(smc_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for f in ("smc_spin_init", "smc_metropolis_sweep", "smc_pt_sweep_swap", "smc_measure_energy_magnetisation",
+              "smc_strerror", "smc_last_error"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(S.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror():
+    L = S.lib()
+    assert L.smc_strerror(0) == b"success"
+    assert L.smc_strerror(-1) == b"invalid argument"
+    assert L.smc_strerror(-3) == b"HIP runtime error"
+    assert L.smc_strerror(12345) == b"unknown status"
+
+
+FAKE = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def _desc(**kw):
+    base = dict(model=S.ISING, dim=2, L=16, n_rep=1, rep_per_sample=1, renorm_every=0, seed=1, inst=None,
+                spins_len=256, coup_len=0)
+    base.update(kw)
+    return S.Desc(**base)
+
+
+def _sweep(d, n=1, beta=0.4, spins=FAKE, coup=None, sweep0=0):
+    b = (C.c_double * max(1, d.n_rep))(*([beta] * max(1, d.n_rep)))
+    return S.lib().smc_metropolis_sweep(C.byref(d), spins, coup, b, sweep0, n, None, None)
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(L=15), b"even"), (dict(L=2), b"even"), (dict(dim=4), b"dim"), (dict(model=7), b"model"),
+    (dict(n_rep=0), b"n_rep"), (dict(spins_len=255), b"too small"), (dict(L=0), b"inst"),
+    (dict(model=S.EA, rep_per_sample=0, coup_len=512), b"rep_per_sample"),
+    (dict(model=S.EA, coup_len=0), b"coup_len"), (dict(model=S.EA, coup_len=511), b"outside"),
+    (dict(dim=3, L=2048, spins_len=1 << 40), b"too large"),
+])
+def test_invalid_descriptors_are_rejected(kw, frag):
+    rc = _sweep(_desc(**kw), coup=FAKE)
+    assert rc == S.EINVAL
+    assert frag in S.lib().smc_last_error()
+
+
+def test_invalid_call_arguments_are_rejected():
+    L = S.lib()
+    assert _sweep(_desc(), spins=None) == S.EINVAL
+    assert _sweep(_desc(), n=-1) == S.EINVAL
+    assert _sweep(_desc(), beta=-0.1) == S.EINVAL
+    assert _sweep(_desc(), beta=float("nan")) == S.EINVAL
+    assert _sweep(_desc(), sweep0=(1 << 32) - 1, n=2) == S.EINVAL
+    assert _sweep(_desc(model=S.EA, coup_len=512), coup=None) == S.EINVAL
+    assert L.smc_metropolis_sweep(None, FAKE, None, None, 0, 1, None, None) == S.EINVAL
+
+
+def test_uneven_batch_bounds_are_checked():
+    rows = (S.Inst * 2)(S.Inst(8, 0, 0, 0), S.Inst(6, 1, 64, 0))
+    d = _desc(L=0, n_rep=2, spins_len=64 + 35)
+    d.inst = C.cast(rows, C.POINTER(S.Inst))
+    assert _sweep(d) == S.EINVAL and b"outside" in S.lib().smc_last_error()
+    rows[1] = S.Inst(7, 1, 64, 0)
+    d.spins_len = 200
+    assert _sweep(d) == S.EINVAL and b"even" in S.lib().smc_last_error()
+
+
+def test_pt_arguments_are_validated():
+    L = S.lib()
+    beta = (C.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    d = _desc(n_rep=6, spins_len=6 * 256)
+    pt = S.PTDesc(2, 4, 0, 0, C.cast(beta, C.POINTER(C.c_double)))
+    rc = L.smc_pt_sweep_swap(C.byref(d), C.byref(pt), FAKE, None, FAKE, FAKE, 0, 1, None, None)
+    assert rc == S.EINVAL and b"n_chains * n_temps" in L.smc_last_error()
+    d = _desc(n_rep=8, spins_len=8 * 256, model=S.HEISENBERG)
+    d.spins_len = 8 * 256 * 3
+    rc = L.smc_pt_sweep_swap(C.byref(d), C.byref(pt), FAKE, None, FAKE, FAKE, 0, 1, None, None)
+    assert rc == S.EUNSUPPORTED
+    d = _desc(n_rep=8, spins_len=8 * 256, model=S.EA, rep_per_sample=2, coup_len=8 * 512)
+    rc = L.smc_pt_sweep_swap(C.byref(d), C.byref(pt), FAKE, FAKE, FAKE, FAKE, 0, 1, None, None)
+    assert rc == S.EINVAL and b"multiple of n_temps" in L.smc_last_error()
+
+
+def test_binding_has_no_cpu_fallback():
+    """The product binding does not import the oracle."""
+    src = open(os.path.join(ROOT, "paper_1101_1427_amd", "__init__.py")).read()
+    assert "oracle" not in src.replace("oracle (", "")
+    for f in os.listdir(os.path.join(ROOT, "paper_1101_1427_amd", "csrc")):
+        assert "oracle" not in open(os.path.join(ROOT, "paper_1101_1427_amd", "csrc", f)).read().lower()
