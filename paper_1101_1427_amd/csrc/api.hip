@@ -141,6 +141,17 @@ ThrRow threshold_row(double beta, int dim) {
     return row;
 }
 
+// The one-pass split-layout kernel serves uniform 2D Ising batches whose
+// edge it supports, with 16-byte aligned spins and thresholds below 2^32
+// (beta > 0 up to rounding; the generic kernels cover the rest).
+bool use_lattice2d(const smc_desc *d, const void *spins, const std::vector<ThrRow> &rows) {
+    if (d->model != SMC_ISING || d->dim != 2 || d->L <= 0 || !lattice2d_supported(d->L)) return false;
+    if (((uintptr_t)spins & 15u) != 0) return false;
+    for (const ThrRow &r : rows)
+        if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu) return false;
+    return true;
+}
+
 // --------------------------------------------------------------- validation --
 struct Plan {
     Batch b;
@@ -264,6 +275,9 @@ int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char
     if (desc->model == SMC_HEISENBERG) {
         *launches_per_sweep = 2;
         *kernel_name = "k_heis_half_sweep_generic";
+    } else if (desc->model == SMC_ISING && desc->dim == 2 && desc->L > 0 && lattice2d_supported(desc->L)) {
+        *launches_per_sweep = 1;
+        *kernel_name = "k_ising2d_split";
     } else {
         *launches_per_sweep = 2;
         *kernel_name = "k_half_sweep_generic";
@@ -343,6 +357,21 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
     for (int r = 0; r < desc->n_rep; ++r) rows[r] = threshold_row(beta[r], desc->dim);
     if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &p))) return rc;
     a.thr = (const ThrRow *)p;
+    if (use_lattice2d(desc, spins, rows)) {
+        // one-pass sweeps on the colour-split layout, ping-pong between two buffers
+        const size_t bytes = (size_t)desc->n_rep * (size_t)plan.b.N;
+        void *pp = nullptr;
+        if ((rc = ensure(c, kPingPong, 2 * bytes, &pp))) return rc;
+        uint8_t *A = (uint8_t *)pp, *B = A + bytes;
+        SMC_HIP(launch_to_split((const int8_t *)spins, A, desc->L, desc->n_rep, s));
+        for (int32_t k = 0; k < n_sweeps; ++k) {
+            const uint32_t t = (uint32_t)(sweep0 + (uint64_t)k);
+            SMC_HIP(launch_ising2d_split(k & 1 ? B : A, k & 1 ? A : B, desc->L, desc->n_rep, a.thr, dE_accum, a.key,
+                                         t, s));
+        }
+        SMC_HIP(launch_from_split(n_sweeps & 1 ? B : A, (int8_t *)spins, desc->L, desc->n_rep, s));
+        return SMC_OK;
+    }
     for (int32_t k = 0; k < n_sweeps; ++k) {
         a.t = (uint32_t)(sweep0 + (uint64_t)k);
         SMC_HIP(launch_half_sweep_generic(a, 0, s));

@@ -78,6 +78,13 @@ hipError_t launch_measure(const Batch &b, const void *spins, const int8_t *coup,
                           double *magnet, void *scratch, size_t scratch_bytes, hipStream_t s);
 size_t measure_scratch_bytes(const Batch &b, int max_L);
 
+// Large 2D Ising lattices on the colour-split layout (lattice2d.hip).
+bool lattice2d_supported(int L);
+hipError_t launch_to_split(const int8_t *src, uint8_t *dst, int L, int n_rep, hipStream_t s);
+hipError_t launch_from_split(const uint8_t *src, int8_t *dst, int L, int n_rep, hipStream_t s);
+hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_rep, const ThrRow *thr, int64_t *dE,
+                                Key key, uint32_t t, hipStream_t s);
+
 // Parallel tempering helpers.
 hipError_t launch_pt_prepare(const SwapArgs &a, const double *energy_in, hipStream_t s);
 hipError_t launch_pt_swap(const SwapArgs &a, hipStream_t s);

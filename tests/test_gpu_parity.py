@@ -158,18 +158,22 @@ def test_measure_exact(model, dim, L):
 
 
 def test_measure_heisenberg_fp64():
+    """float64 reductions of float32 spins: the oracle's own start rounded to
+    float32 is measured by both sides."""
     seed = W.seed_for(17)
-    b = S.Batch(S.HEISENBERG, 3, 16, 2, seed)
-    spins, _ = gpu_init(b)
-    E = torch.zeros(2, dtype=torch.float64, device=DEV)
-    M = torch.zeros(2, 3, dtype=torch.float64, device=DEV)
+    L, n_rep = 16, 2
+    ref, _ = refrun.init_uniform(refrun.HEIS, 3, L, n_rep, seed)
+    ref32 = ref.astype(np.float32)
+    b = S.Batch(S.HEISENBERG, 3, L, n_rep, seed)
+    spins = _dev(ref32.reshape(-1))
+    E = torch.zeros(n_rep, dtype=torch.float64, device=DEV)
+    M = torch.zeros(n_rep, 3, dtype=torch.float64, device=DEV)
     S.measure_energy_magnetisation(b, spins, E, M)
-    host = _host(spins).astype(np.float64).reshape(2, -1, 3)   # the GPU's own float32 spins, widened
-    N = 16 ** 3
-    for r in range(2):
-        # the oracle measures the same configuration exactly in float64
-        assert abs(_host(E)[r] - O.heis_energy(3, 16, np.ascontiguousarray(host[r]))) <= 2 ** -20 * N
-        assert np.allclose(_host(M)[r], O.heis_magnetisation(3, 16, np.ascontiguousarray(host[r])), atol=1e-9)
+    N = L ** 3
+    for r in range(n_rep):
+        exact = np.ascontiguousarray(ref32[r].astype(np.float64))
+        assert abs(_host(E)[r] - O.heis_energy(3, L, exact)) <= 2 ** -20 * N
+        assert np.allclose(_host(M)[r], O.heis_magnetisation(3, L, exact), atol=1e-9)
 
 
 # ------------------------------------------------------------- Heisenberg --
@@ -232,3 +236,38 @@ def test_pt_3d_bit_exact():
 
 def test_pt_ising_equal_betas_walk():
     _pt_case(S.ISING, 2, [8, 8], 4, 9, W.seed_for(21), np.full(4, 0.4))
+
+
+# ------------------------------------------- one-pass split-layout 2D kernel --
+@pytest.mark.parametrize("L,n_rep,n,sweep0", [(1024, 2, 5, 0), (2048, 1, 4, 33), (1024, 3, 1, 7)])
+def test_split_kernel_bit_exact(L, n_rep, n, sweep0):
+    """Uniform 2D Ising batches served by the one-pass kernel: odd and even
+    sweep counts, nonzero first sweep index, per-replica beta, dE tracking."""
+    seed = W.seed_for(22)
+    b = S.Batch(S.ISING, 2, L, n_rep, seed)
+    assert S.sweep_plan(b) == (1, "k_ising2d_split")
+    spins, _ = gpu_init(b)
+    betas = [0.30, W.BETA_C_2D, 0.55][:n_rep]
+    dE = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
+    S.metropolis_sweep(b, spins, betas, sweep0, n, dE_accum=dE)
+    ref_s, _ = refrun.init_uniform(S.ISING, 2, L, n_rep, seed)
+    ref_dE = refrun.sweep_uniform(S.ISING, 2, L, ref_s, None, betas, seed, sweep0, n)
+    assert np.array_equal(_host(spins).reshape(ref_s.shape), ref_s)
+    assert np.array_equal(_host(dE), ref_dE)
+
+
+def test_split_kernel_launch_shape_invariance(monkeypatch):
+    """Band height and lane width change the schedule, never the result."""
+    seed = W.seed_for(23)
+    L = 2048
+    b = S.Batch(S.ISING, 2, L, 1, seed)
+    outs = []
+    for chunks, H in [(1, 64), (2, 16), (1, 2), (2, 128)]:
+        monkeypatch.setenv("SPINMC_L2D_CHUNKS", str(chunks))
+        monkeypatch.setenv("SPINMC_L2D_H", str(H))
+        spins, _ = gpu_init(b)
+        dE = torch.zeros(1, dtype=torch.int64, device=DEV)
+        S.metropolis_sweep(b, spins, [0.42], 0, 6, dE_accum=dE)
+        outs.append((_host(spins).copy(), int(_host(dE)[0])))
+    for s, d in outs[1:]:
+        assert np.array_equal(s, outs[0][0]) and d == outs[0][1]
