@@ -359,7 +359,7 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
     a.thr = (const ThrRow *)p;
     if (use_lattice2d(desc, spins, rows)) {
         // one-pass sweeps on the colour-split layout, ping-pong between two buffers
-        const size_t bytes = (size_t)desc->n_rep * (size_t)plan.b.N;
+        const size_t bytes = (size_t)desc->n_rep * lattice2d_split_bytes(desc->L);
         void *pp = nullptr;
         if ((rc = ensure(c, kPingPong, 2 * bytes, &pp))) return rc;
         uint8_t *A = (uint8_t *)pp, *B = A + bytes;

@@ -32,20 +32,16 @@
 namespace smc {
 namespace {
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+// packed 16-bit helpers (v_pk_sub_u16 clamp, v_pk_sub_u16, v_pk_min_u16)
 __device__ __forceinline__ uint32_t pk_sub_sat_u16(uint32_t a, uint32_t b) {
-    uint32_t r;
-    asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(r) : "v"(a), "v"(b));
-    return r;
+    return as_u32(__builtin_elementwise_sub_sat(as_u16x2(a), as_u16x2(b)));
 }
-__device__ __forceinline__ uint32_t pk_sub_u16(uint32_t a, uint32_t b) {
-    uint32_t r;
-    asm("v_pk_sub_u16 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
+__device__ __forceinline__ uint32_t pk_sub_u16(uint32_t a, uint32_t b) { return as_u32(as_u16x2(a) - as_u16x2(b)); }
 __device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b) {
-    uint32_t r;
-    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
+    return as_u32(__builtin_elementwise_min(as_u16x2(a), as_u16x2(b)));
 }
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
     return __builtin_amdgcn_perm(hi, lo, sel);
@@ -59,10 +55,11 @@ struct Lut {
     uint32_t tlo_lo, tlo_hi, thi_lo, thi_hi;  // T(n): low / high bytes, selectors n = 0..7
     uint32_t de_lo, de_hi;                    // dE/4 + 2 for index n + 4F
     uint32_t one2;                            // 0x00010001
+    uint32_t four;                            // 4 (trip count of the tie loop, kept opaque)
     uint2 thr1, thr2;                         // exact thresholds of dE = 4 and dE = 8
 };
 
-__device__ __forceinline__ Lut make_lut(const ThrRow &row) {
+__device__ __forceinline__ Lut make_lut(const ThrRow &row, uint32_t one2, uint32_t four) {
     Lut k;
     const uint32_t t2 = row.m[2].x, t1 = row.m[1].x;  // both <= 0xFFFF (checked on the host)
     k.tlo_lo = (t2 & 0xFFu) | ((t1 & 0xFFu) << 8) | 0xFFFF0000u;
@@ -73,7 +70,8 @@ __device__ __forceinline__ Lut make_lut(const ThrRow &row) {
     // the sign of byte 1 (= 2 > 0), i.e. 0 = 4 - 4.
     k.de_lo = 0x02020202u;
     k.de_hi = 0x01020304u;
-    k.one2 = 0x00010001u;
+    k.one2 = one2;
+    k.four = four;
     k.thr1 = row.m[1];
     k.thr2 = row.m[2];
     return k;
@@ -145,63 +143,64 @@ __device__ __forceinline__ uint32_t decide4(uint32_t n, uint32_t wa, uint32_t wb
     return perm(rb, ra, 0x06040200u);
 }
 
-// Exact decision of site s (0..7) of a chunk: n its count, w the chunk's draw.
-__device__ __noinline__ uint32_t exact_flip(uint32_t n, uint32_t head, const Lut &K, uint32_t h, uint32_t t,
-                                            uint32_t r, uint32_t c, Key key) {
-    if (n >= 2) return 1u;
-    const uint2 th = n == 0 ? K.thr2 : K.thr1;
-    return metropolis_accept(head, th, h, t, r, c, key) ? 1u : 0u;
-}
-
 struct Lattice2dArgs {
     const uint8_t *src;  // split planes of replica 0 (read)
     uint8_t *dst;        // split planes of replica 0 (written)
-    int64_t rep_bytes;   // bytes per replica (L*L)
+    int64_t rep_bytes;   // bytes per replica (2 planes of L rows at `pitch`)
+    int64_t pitch;       // bytes between consecutive physical rows of a plane (>= L/2)
     const ThrRow *thr;   // per replica
     int64_t *dE;         // per replica or nullptr
     Key key;
     uint32_t t;
     int L, H, bands, n_rep;
+    uint32_t one2;  // 0x00010001, passed in so that the compiler keeps the packed ops
+    uint32_t four;  // 4, passed in so that the compiler keeps the tie loop rolled
 };
 
-// Update colour c of one lane-row: own (updated in place), vertical rows
-// va/vb, horizontal row hz with edge word.  Returns the summed dE/4 + 2 per
-// site via `de` (SWAR bytes) when counted.
+// Decide and apply colour c of one lane-row: own (updated in place),
+// vertical rows va / vb, horizontal row hz with the neighbouring lane's word
+// `edge`, draws w[q] of chunk q.  Adds sum(dE/4 + 2) into de_total when
+// `count`.
 template <int C>
-__device__ __forceinline__ void update_row(Row<C> &own, const Row<C> &va, const Row<C> &vb, const Row<C> &hz,
-                                           uint32_t edge, int p, uint32_t c, uint32_t row, uint32_t groups_per_row,
-                                           uint32_t lane_group0, const Lut &K, Key key, uint32_t t, uint32_t r,
-                                           bool count, uint32_t &de_total) {
+__device__ __forceinline__ void apply_row(Row<C> &own, const Row<C> &va, const Row<C> &vb, const Row<C> &hz,
+                                          uint32_t edge, int p, const uint4 (&w)[C], uint32_t g0, uint32_t c,
+                                          const Lut &K, Key key, uint32_t t, uint32_t r, bool count,
+                                          uint32_t &de_total) {
     uint32_t n[2 * C], F[2 * C];
-    uint4 w[C];
     uint32_t eq = 0xFFFFFFFFu;
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-        const uint32_t g = row * groups_per_row + lane_group0 + q;
-        w[q] = philox4x32_10(make_uint4(g, t, r, 2 * kTagHead + c), key);
-    }
 #pragma unroll
     for (int i = 0; i < 2 * C; ++i) {
         n[i] = count_anti<C>(own.d[i], va.d[i], vb.d[i], hz, i, edge, p);
         const uint4 &wq = w[i >> 1];
-        const uint32_t wa = (i & 1) ? wq.z : wq.x;
-        const uint32_t wb = (i & 1) ? wq.w : wq.y;
-        F[i] = decide4(n[i], wa, wb, K, eq);
+        F[i] = decide4(n[i], (i & 1) ? wq.z : wq.x, (i & 1) ? wq.w : wq.y, K, eq);
     }
-    // a head equal to its threshold's high part: resolve those sites exactly
+    // a head equal to the high half of its threshold: decide those sites exactly
     const bool tie = ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u);
     if (__builtin_expect(__any(tie), 0)) {
         if (tie) {
+            // Exact decisions of all 8C sites, word by word with a rolled
+            // loop over the four sites of a word (ties are rare, probability
+            // 2^-16 per site, so this path is kept compact).
 #pragma unroll
             for (int i = 0; i < 2 * C; ++i) {
-                const uint4 &wq = w[i >> 1];
+                const uint4 wq = w[i >> 1];
+                const uint32_t wlo = (i & 1) ? wq.z : wq.x, whi = (i & 1) ? wq.w : wq.y;
                 uint32_t f = 0;
-                for (int s = 0; s < 4; ++s) {
-                    const uint32_t k = 4 * (i & 1) + s;  // site within the chunk
-                    const uint32_t word = word_of(wq, k >> 1);
-                    const uint32_t head = (k & 1) ? (word >> 16) : (word & 0xFFFFu);
-                    const uint32_t h = (row * groups_per_row + lane_group0 + (i >> 1)) * 8u + k;
-                    f |= exact_flip((n[i] >> (8 * s)) & 0xFFu, head, K, h, t, r, c, key) << (8 * s);
+#pragma unroll 1
+                for (uint32_t s4 = 0; s4 < K.four; ++s4) {
+                    const uint32_t word = s4 < 2u ? wlo : whi;
+                    const uint32_t head = (s4 & 1u) ? (word >> 16) : (word & 0xFFFFu);
+                    const uint32_t ns = (n[i] >> (8u * s4)) & 0xFFu;
+                    uint32_t flip = 1u;
+                    if (ns < 2u) {
+                        const uint2 th = ns == 0u ? K.thr2 : K.thr1;
+                        flip = head < th.x ? 1u : 0u;
+                        if (head == th.x) {
+                            const uint32_t h = (g0 + (uint32_t)(i >> 1)) * 8u + 4u * (uint32_t)(i & 1) + s4;
+                            flip = tail16(h, t, r, c, key) < th.y ? 1u : 0u;
+                        }
+                    }
+                    f |= flip << (8u * s4);
                 }
                 F[i] = f;
             }
@@ -216,33 +215,252 @@ __device__ __forceinline__ void update_row(Row<C> &own, const Row<C> &va, const 
     if (count) de_total = __builtin_amdgcn_sad_u8(de, 0u, de_total);
 }
 
-// Neighbour-lane word exchange: every lane receives the last word of the
-// lane to its left (dir 0) or the first word of the lane to its right
-// (dir 1); the row wraps around through the workgroup.
-__device__ __forceinline__ void exchange2(uint32_t v1, uint32_t v0, int dir, uint32_t *xch, int par,
-                                          uint32_t &e1, uint32_t &e0) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int send_lane = dir ? 0 : 63;
-    if (lane == send_lane) {
+// Neighbour-lane words: every lane receives the last word of the lane to
+// its left (dir 0, DPP wave_shr:1) or the first word of the lane to its
+// right (dir 1, wave_shl:1); the lanes at a wave's ends take the word of the
+// neighbouring wave through LDS, and the row wraps around the workgroup.
+template <int DIR>
+__device__ __forceinline__ void exchange2(uint32_t v1, uint32_t v0, uint32_t *xch, int par, uint32_t &e1,
+                                          uint32_t &e0, int nw) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == (DIR ? 0 : 63)) {
         xch[(par * nw + wave) * 2] = v1;
         xch[(par * nw + wave) * 2 + 1] = v0;
     }
     __syncthreads();
-    uint32_t s1 = dir ? __shfl_down(v1, 1) : __shfl_up(v1, 1);
-    uint32_t s0 = dir ? __shfl_down(v0, 1) : __shfl_up(v0, 1);
-    const int recv_lane = dir ? 63 : 0;
-    if (lane == recv_lane) {
-        const int other = dir ? (wave + 1 == nw ? 0 : wave + 1) : (wave == 0 ? nw - 1 : wave - 1);
-        s1 = xch[(par * nw + other) * 2];
-        s0 = xch[(par * nw + other) * 2 + 1];
+    const int other = DIR ? (wave + 1 == nw ? 0 : wave + 1) : (wave == 0 ? nw - 1 : wave - 1);
+    const uint32_t o1 = xch[(par * nw + other) * 2];
+    const uint32_t o0 = xch[(par * nw + other) * 2 + 1];
+    constexpr int ctrl = DIR ? 0x130 : 0x138;  // wave_shl:1 : wave_shr:1
+    e1 = (uint32_t)__builtin_amdgcn_update_dpp((int)o1, (int)v1, ctrl, 0xF, 0xF, false);
+    e0 = (uint32_t)__builtin_amdgcn_update_dpp((int)o0, (int)v0, ctrl, 0xF, 0xF, false);
+}
+
+// ------------------------------------------------------------ pipeline ----
+// Warp-specialised band pipeline.  A workgroup = NCW compute waves that span
+// one full row + one loader wave.  The loader streams the rows the compute
+// waves need into an LDS ring with direct global->LDS loads, kDepth steps
+// ahead; the compute waves read new rows from LDS and only store to global
+// memory.  On this target loads and stores share one completion counter, so
+// a wave that both loads and stores must drain its stores whenever it waits
+// for data; with the roles split, the loader waits only for its own loads
+// (in issue order, so the wait count is exact) and the compute waves never
+// wait for global memory at all.
+constexpr int kDepth = 3;                // feeds in flight ahead of the consumer
+constexpr int kSlots = kDepth + 1;       // LDS ring slots per plane
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(3))) uint8_t lds_u8_t;
+
+template <int C>
+__device__ __forceinline__ Row<C> lds_row(const uint8_t *p) {
+    Row<C> r;
+    if constexpr (C == 1) {
+        const uint2 v = *(const uint2 *)p;
+        r.d[0] = v.x;
+        r.d[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < C / 2; ++i) {
+            const uint4 v = ((const uint4 *)p)[i];
+            r.d[4 * i] = v.x;
+            r.d[4 * i + 1] = v.y;
+            r.d[4 * i + 2] = v.z;
+            r.d[4 * i + 3] = v.w;
+        }
     }
-    e1 = s1;
-    e0 = s0;
+    return r;
+}
+
+// s_waitcnt for vmcnt <= N only (expcnt / lgkmcnt left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Physical row of lattice row y in the split planes: band-interleaved, so
+// that row k of every band (H rows each) is stored next to row k of the
+// other bands.  The bands are processed in lockstep, so at any time the
+// workgroups of a sweep touch one compact region instead of one region per
+// band.
+__host__ __device__ __forceinline__ int64_t split_row(int y, int H, int bands) {
+    return (int64_t)(y % H) * bands + y / H;
 }
 
 template <int C>
+struct Band {
+    const uint8_t *S0, *S1;
+    uint8_t *D0, *D1;
+    int L, half, Y0, H, bands, ncw;
+    int64_t pitch;
+    int64_t lane_off;
+    uint32_t gpr, lg0, r, t;
+    Key key;
+    Lut K;
+    __device__ __forceinline__ int64_t off(int y) const {
+        const int w = y < 0 ? y + L : (y >= L ? y - L : y);
+        return split_row(w, H, bands) * pitch;
+    }
+};
+
+// Loader waves: the feed of step s (plane-1 row s+1, plane-0 row s) goes to
+// ring slot (s - Y0 + 1) % kSlots.  A feed is NF direct-load instructions,
+// each moving 16 bytes per lane (1 KB per wave) of one plane row of L/2
+// bytes (a 512-byte row, L = 1024, uses half the lanes); loader wave lw of
+// NLW issues instructions lw, lw + NLW, ...
+template <int NF>
+struct LoaderShape {
+    static constexpr int NLW = NF >= 4 ? 4 : NF;  // loader waves
+    static constexpr int PER = NF / NLW;          // instructions per loader wave per feed
+};
+
+template <int C, int NF>
+__device__ __forceinline__ void issue_feed(const Band<C> &B, int s, uint8_t *ring, int lw) {
+    using SH = LoaderShape<NF>;
+    const int slot = (s - B.Y0 + 1) % kSlots;
+    const int lane = threadIdx.x & 63;
+    constexpr int per_plane = NF / 2;
+    const bool active = 16 * lane < B.half;
+#pragma unroll
+    for (int q = 0; q < SH::PER; ++q) {
+        const int ins = lw + q * SH::NLW;  // instruction index within the feed
+        const int pl = ins / per_plane, k = ins % per_plane;
+        const int row = pl == 0 ? s + 1 : s;  // pl 0: plane 1, pl 1: plane 0
+        const uint8_t *src = (pl == 0 ? B.S1 : B.S0) + B.off(row);
+        uint8_t *dst = ring + (size_t)(pl * kSlots + slot) * (size_t)B.half;
+        if (active)
+            __builtin_amdgcn_global_load_lds(src + 1024 * k + 16 * lane, (lds_void_t *)(lds_u8_t *)(dst + 1024 * k), 16,
+                                             0, 0);
+    }
+}
+
+// Workgroup barrier without the memory fence of __syncthreads(): the fence
+// would make the loaders drain all of their direct loads at every step.  The
+// loaders order their LDS writes explicitly (wait_vmcnt before the barrier).
+__device__ __forceinline__ void loader_barrier() { __builtin_amdgcn_s_barrier(); }
+
+template <int C, int NF>
+__device__ void loader_loop(const Band<C> &B, uint8_t *ring, int lw) {
+    using SH = LoaderShape<NF>;
+    const int first = B.Y0 - 1, last = B.Y0 + B.H;  // steps
+    // prologue: feeds of steps first .. first+kDepth-1, then the first one must land
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) issue_feed<C, NF>(B, first + d, ring, lw);
+    wait_vmcnt<SH::PER *(kDepth - 1)>();
+    loader_barrier();  // (1) prologue
+    loader_barrier();  // (2) initial edge exchange of the compute waves
+    for (int s = first; s < last; ++s) {
+        // step s is running on the compute waves; bring in step s+kDepth, make s+1 land
+        if (s + kDepth <= last) {
+            issue_feed<C, NF>(B, s + kDepth, ring, lw);
+            wait_vmcnt<SH::PER *(kDepth - 1)>();
+        } else {
+            wait_vmcnt<0>();
+        }
+        loader_barrier();  // end of step s
+    }
+}
+
+// Compute waves, step j: colour 0 of row j, colour 1 of row j-1, store row
+// j-1, exchange the edge words of step j+1.  Row y of plane 1 is kept in
+// p1[y & 3], new row y of plane 0 in n0[y & 3].
+template <int C>
+struct Pipe {
+    Row<C> p1[4], n0[4];
+    uint32_t e1, e0;
+    uint32_t de_total, counted;
+};
+
+template <int C, int PH>
+__device__ __forceinline__ void step(Pipe<C> &S, const Band<C> &B, int j, const uint8_t *ring, uint32_t *xch) {
+    constexpr int a_m1 = (PH + 3) & 3, a_0 = PH & 3, a_p1 = (PH + 1) & 3, a_m2 = (PH + 2) & 3;
+    constexpr int P = PH & 1;
+    __builtin_amdgcn_sched_barrier(0);
+    // new rows from the ring: plane-1 row j+1, plane-0 row j
+    const int slot = (j - B.Y0 + 1) % kSlots;
+    S.p1[a_p1] = lds_row<C>(ring + (size_t)slot * B.half + B.lane_off);
+    Row<C> own0 = lds_row<C>(ring + (size_t)(kSlots + slot) * B.half + B.lane_off);
+    const int jw = j < 0 ? j + B.L : (j >= B.L ? j - B.L : j);
+    const uint32_t row0 = (uint32_t)jw;
+    const uint32_t row1 = jw == 0 ? (uint32_t)B.L - 1u : (uint32_t)jw - 1u;
+    const uint32_t g0 = row0 * B.gpr + B.lg0, g1 = row1 * B.gpr + B.lg0;
+    uint4 w[2 * C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        w[q] = make_uint4(g0 + q, B.t, B.r, 2 * kTagHead + 0);
+        w[C + q] = make_uint4(g1 + q, B.t, B.r, 2 * kTagHead + 1);
+    }
+    philox4x32_10_multi<2 * C>(w, B.key);
+    uint4 w0[C], w1[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        w0[q] = w[q];
+        w1[q] = w[C + q];
+    }
+    // colour 0, row j
+    const bool in0 = j >= B.Y0 && j < B.Y0 + B.H;
+    apply_row<C>(own0, S.p1[a_m1], S.p1[a_p1], S.p1[a_0], S.e1, P, w0, g0, 0u, B.K, B.key, B.t, B.r, in0,
+                 S.de_total);
+    S.n0[a_0] = own0;
+    S.counted += in0 ? 1u : 0u;
+    if (j >= B.Y0 + 1) {
+        // colour 1, row j-1, from the new colour-0 rows j-2, j-1, j
+        apply_row<C>(S.p1[a_m1], S.n0[a_m2], S.n0[a_0], S.n0[a_m1], S.e0, P, w1, g1, 1u, B.K, B.key, B.t, B.r, true,
+                     S.de_total);
+        S.counted += 1u;
+        store_row<C>(B.D0 + B.off(j - 1) + B.lane_off, S.n0[a_m1]);
+        store_row<C>(B.D1 + B.off(j - 1) + B.lane_off, S.p1[a_m1]);
+    }
+    if (j < B.Y0 + B.H) {
+        // edges for step j+1: plane-1 old row j+1 and plane-0 new row j
+        constexpr int D = (PH + 1) & 1;
+        exchange2<D>(D ? S.p1[a_p1].d[0] : S.p1[a_p1].d[2 * C - 1], D ? S.n0[a_0].d[0] : S.n0[a_0].d[2 * C - 1], xch,
+                     PH & 1, S.e1, S.e0, B.ncw);
+    }
+}
+
+template <int C>
+__device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xch, int64_t *dE) {
+    Pipe<C> S;
+    const int Y0 = B.Y0;  // a multiple of 4: step Y0-1 has phase 3
+    // rows Y0-2 and Y0-1 of plane 1 (all later rows come through the ring)
+    S.p1[2] = load_row<C>(B.S1 + B.off(Y0 - 2) + B.lane_off);
+    S.p1[3] = load_row<C>(B.S1 + B.off(Y0 - 1) + B.lane_off);
+#pragma unroll
+    for (int i = 0; i < 2 * C; ++i) S.n0[0].d[i] = S.n0[1].d[i] = S.n0[2].d[i] = S.n0[3].d[i] = 0u;
+    S.de_total = 0;
+    S.counted = 0;
+    S.e0 = 0;
+    __syncthreads();  // (1) prologue: the first feed has landed
+    {
+        // plane-1 row Y0-1 is odd: its colour-0 sites need the right neighbour word
+        uint32_t dummy;
+        exchange2<1>(S.p1[3].d[0], 0u, xch, 0, S.e1, dummy, B.ncw);  // (2)
+    }
+    step<C, 3>(S, B, Y0 - 1, ring, xch);
+    for (int j = Y0; j < Y0 + B.H; j += 4) {
+        step<C, 0>(S, B, j, ring, xch);
+        step<C, 1>(S, B, j + 1, ring, xch);
+        step<C, 2>(S, B, j + 2, ring, xch);
+        step<C, 3>(S, B, j + 3, ring, xch);
+    }
+    step<C, 0>(S, B, Y0 + B.H, ring, xch);
+    if (dE) {
+        // sum over sites of (dE/4 + 2) minus 2 per counted site
+        long long v = ((long long)S.de_total - 2ll * (long long)S.counted * 8 * C) * 4;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd((unsigned long long *)&dE[B.r], (unsigned long long)v);
+    }
+}
+
+template <int C, int NF>
 __global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
-    __shared__ uint32_t xch[2 * 16 * 2];
+    extern __shared__ __align__(16) uint8_t smem[];  // [2 planes][kSlots][L/2] ring, then the edge words
+    const int ncw = (int)(blockDim.x >> 6) - LoaderShape<NF>::NLW;  // compute waves; the last NLW waves load
+    uint8_t *ring = smem;
+    uint32_t *xch = (uint32_t *)(smem + (size_t)2 * kSlots * (a.L >> 1));
     // XCD-aware order: consecutive bands of a replica run on the same XCD.
     const uint32_t nblk = gridDim.x;
     const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3;
@@ -250,120 +468,70 @@ __global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
     const uint32_t logical = (nblk & 7u) ? blockIdx.x : xcd * per_xcd + slot;
     const int r = (int)(logical / (uint32_t)a.bands);
     const int band = (int)(logical % (uint32_t)a.bands);
-    const int L = a.L, H = a.H, half = L >> 1;
-    const uint32_t gpr = (uint32_t)L >> 4;  // draw groups per row (8 sites each)
-    const uint32_t lg0 = threadIdx.x * C;   // this lane's first group in a row
-    const Lut K = make_lut(a.thr[r]);
-    const uint8_t *S0 = a.src + (int64_t)r * a.rep_bytes;
-    const uint8_t *S1 = S0 + (int64_t)half * L;
-    uint8_t *D0 = a.dst + (int64_t)r * a.rep_bytes;
-    uint8_t *D1 = D0 + (int64_t)half * L;
-    const int64_t lane_off = (int64_t)threadIdx.x * 8 * C;
-    auto rowp = [&](int y) { return (int64_t)((y % L + L) % L) * half + lane_off; };
-
-    const int Y0 = band * H;
-    // window for step j = Y0-1
-    Row<C> q1m = load_row<C>(S1 + rowp(Y0 - 2));
-    Row<C> q1c = load_row<C>(S1 + rowp(Y0 - 1));
-    Row<C> q1p = load_row<C>(S1 + rowp(Y0));
-    Row<C> q0c = load_row<C>(S0 + rowp(Y0 - 1));
-    Row<C> pa1 = load_row<C>(S1 + rowp(Y0 + 1));  // plane 1 row j+2
-    Row<C> pa0 = load_row<C>(S0 + rowp(Y0));      // plane 0 row j+1
-    Row<C> n0m2, n0m1;
-#pragma unroll
-    for (int i = 0; i < 2 * C; ++i) n0m2.d[i] = n0m1.d[i] = 0u;
-    uint32_t e1 = 0, e0 = 0;
-    {
-        const int dir = (Y0 - 1) & 1;
-        exchange2(dir ? q1c.d[0] : q1c.d[2 * C - 1], 0u, dir, xch, 0, e1, e0);
-    }
-    uint32_t de_total = 0;
-    uint32_t counted = 0;
-    for (int j = Y0 - 1; j <= Y0 + H; ++j) {
-        // prefetch the rows of step j+2
-        Row<C> pb1, pb0;
-#pragma unroll
-        for (int i = 0; i < 2 * C; ++i) pb1.d[i] = pb0.d[i] = 0u;
-        if (j + 3 <= Y0 + H + 1) pb1 = load_row<C>(S1 + rowp(j + 3));
-        if (j + 2 <= Y0 + H) pb0 = load_row<C>(S0 + rowp(j + 2));
-        const uint32_t jm = (uint32_t)((j % L + L) % L);
-        const int p = j & 1;
-        // colour 0 of row j
-        const bool in0 = j >= Y0 && j < Y0 + H;
-        Row<C> n0c = q0c;
-        update_row<C>(n0c, q1m, q1p, q1c, e1, p, 0u, jm, gpr, lg0, K, a.key, a.t, (uint32_t)r, in0, de_total);
-        counted += in0 ? 1u : 0u;
-        if (j >= Y0 + 1) {
-            // colour 1 of row j-1 from the new colour-0 rows j-2, j-1, j
-            const uint32_t jm1 = jm == 0 ? (uint32_t)L - 1u : jm - 1u;
-            update_row<C>(q1m, n0m2, n0c, n0m1, e0, p, 1u, jm1, gpr, lg0, K, a.key, a.t, (uint32_t)r, true,
-                          de_total);
-            counted += 1u;
-            store_row<C>(D0 + rowp(j - 1), n0m1);
-            store_row<C>(D1 + rowp(j - 1), q1m);
-        }
-        // rotate the window
-        n0m2 = n0m1;
-        n0m1 = n0c;
-        q1m = q1c;
-        q1c = q1p;
-        q1p = pa1;
-        q0c = pa0;
-        pa1 = pb1;
-        pa0 = pb0;
-        if (j < Y0 + H) {
-            const int dir = (j + 1) & 1;
-            exchange2(dir ? q1c.d[0] : q1c.d[2 * C - 1], dir ? n0m1.d[0] : n0m1.d[2 * C - 1], dir, xch, j & 1,
-                      e1, e0);
-        }
-    }
-    if (a.dE) {
-        // sum over sites of (dE/4 + 2) minus 2 per counted site
-        long long v = ((long long)de_total - 2ll * (long long)counted * 8 * C) * 4;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd((unsigned long long *)&a.dE[r], (unsigned long long)v);
+    Band<C> B;
+    B.L = a.L;
+    B.half = a.L >> 1;
+    B.H = a.H;
+    B.Y0 = band * a.H;
+    B.pitch = a.pitch;
+    B.bands = a.bands;
+    B.ncw = ncw;
+    B.S0 = a.src + (int64_t)r * a.rep_bytes;
+    B.S1 = B.S0 + B.pitch * a.L;
+    B.D0 = a.dst + (int64_t)r * a.rep_bytes;
+    B.D1 = B.D0 + B.pitch * a.L;
+    B.lane_off = (int64_t)threadIdx.x * 8 * C;
+    B.gpr = (uint32_t)a.L >> 4;  // draw groups per row (8 sites each)
+    B.lg0 = threadIdx.x * C;     // this lane's first group in a row
+    B.r = (uint32_t)r;
+    B.t = a.t;
+    B.key = a.key;
+    if ((int)(threadIdx.x >> 6) >= ncw) {
+        loader_loop<C, NF>(B, ring, (int)(threadIdx.x >> 6) - ncw);
+    } else {
+        B.K = make_lut(a.thr[r], a.one2, a.four);
+        compute_loop<C>(B, ring, xch, a.dE);
     }
 }
 
 // ----------------------------------------------------- layout conversion ----
 // ABI row-major int8 +-1  <->  split planes of 0/1 bytes (x even -> plane
 // (y&1), x odd -> plane ((y+1)&1), plane index x/2).
-__global__ __launch_bounds__(256) void k_to_split(const int8_t *src, uint8_t *dst, int L, int64_t chunks_per_rep,
-                                                  int64_t total) {
+__global__ __launch_bounds__(256) void k_to_split(const int8_t *src, uint8_t *dst, int L, int64_t pitch, int H,
+                                                  int64_t chunks_per_rep, int64_t total) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= total) return;
     const int64_t r = gid / chunks_per_rep, cidx = gid % chunks_per_rep;
     const int cpr = L >> 4;  // 16-site chunks per row
     const int y = (int)(cidx / cpr), xc = (int)(cidx % cpr);
-    const int64_t N = (int64_t)L * L;
+    const int64_t N = (int64_t)L * L, P = (int64_t)L * pitch;  // sites, bytes per plane
     const uint4 v = *(const uint4 *)(src + r * N + (int64_t)y * L + 16 * xc);
     const uint32_t m = 0x01010101u;
     const uint32_t b0 = (v.x >> 1) & m, b1 = (v.y >> 1) & m, b2 = (v.z >> 1) & m, b3 = (v.w >> 1) & m;
     const uint2 ev = make_uint2(perm(b1, b0, 0x06040200u), perm(b3, b2, 0x06040200u));
     const uint2 od = make_uint2(perm(b1, b0, 0x07050301u), perm(b3, b2, 0x07050301u));
-    uint8_t *base = dst + r * N;
-    const int64_t off = (int64_t)y * (L >> 1) + 8 * xc;
+    uint8_t *base = dst + r * 2 * P;
+    const int64_t off = split_row(y, H, L / H) * pitch + 8 * xc;
     const int pe = y & 1, po = (y + 1) & 1;
-    *(uint2 *)(base + (int64_t)pe * (N >> 1) + off) = ev;
-    *(uint2 *)(base + (int64_t)po * (N >> 1) + off) = od;
+    *(uint2 *)(base + pe * P + off) = ev;
+    *(uint2 *)(base + po * P + off) = od;
 }
 
 __device__ __forceinline__ uint32_t pm1(uint32_t b) { return ((b << 8) - b) | 0x01010101u; }
 
-__global__ __launch_bounds__(256) void k_from_split(const uint8_t *src, int8_t *dst, int L, int64_t chunks_per_rep,
-                                                    int64_t total) {
+__global__ __launch_bounds__(256) void k_from_split(const uint8_t *src, int8_t *dst, int L, int64_t pitch, int H,
+                                                    int64_t chunks_per_rep, int64_t total) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= total) return;
     const int64_t r = gid / chunks_per_rep, cidx = gid % chunks_per_rep;
     const int cpr = L >> 4;
     const int y = (int)(cidx / cpr), xc = (int)(cidx % cpr);
-    const int64_t N = (int64_t)L * L;
-    const uint8_t *base = src + r * N;
-    const int64_t off = (int64_t)y * (L >> 1) + 8 * xc;
+    const int64_t N = (int64_t)L * L, P = (int64_t)L * pitch;
+    const uint8_t *base = src + r * 2 * P;
+    const int64_t off = split_row(y, H, L / H) * pitch + 8 * xc;
     const int pe = y & 1, po = (y + 1) & 1;
-    const uint2 ev = *(const uint2 *)(base + (int64_t)pe * (N >> 1) + off);
-    const uint2 od = *(const uint2 *)(base + (int64_t)po * (N >> 1) + off);
+    const uint2 ev = *(const uint2 *)(base + pe * P + off);
+    const uint2 od = *(const uint2 *)(base + po * P + off);
     const uint32_t e0 = pm1(ev.x), e1 = pm1(ev.y), o0 = pm1(od.x), o1 = pm1(od.y);
     uint4 v;
     v.x = perm(o0, e0, 0x05010400u);
@@ -385,35 +553,47 @@ int env_int(const char *name, int dflt) {
 }
 
 int lattice2d_chunks(int L) {
-    if (L % 1024 != 0 || L < 1024) return 0;
-    const int lanes16 = L / 16;  // lanes at one chunk each
+    // supported edges: 1024, 2048, 4096, 8192, 16384 (feeds of L/1024 direct loads)
+    if (L < 1024 || L > 16384 || (L & (L - 1))) return 0;
     const int want = env_int("SPINMC_L2D_CHUNKS", 0);
-    if (want == 1 || want == 2 || want == 4)
-        if (lanes16 / want <= 1024 && lanes16 % (want * 64) == 0) return want;
-    for (int C = 1; C <= 4; C *= 2)
-        if (lanes16 / C <= 1024 && lanes16 % (C * 64) == 0) return C;
-    return 0;
+    if (want == 2 && L >= 8192) return 2;
+    if (want == 1 && L <= 8192) return 1;
+    return L <= 4096 ? 1 : 2;  // at most 512 compute lanes per row
 }
 
 bool lattice2d_supported(int L) { return lattice2d_chunks(L) > 0; }
 
 int lattice2d_band_height(int L, int n_rep) {
     (void)n_rep;
-    int H = env_int("SPINMC_L2D_H", 64);
-    if (H < 2 || H % 2 || L % H) H = 64;
-    while (H > 2 && L % H) H >>= 1;
-    return L % H ? 0 : H;
+    int H = env_int("SPINMC_L2D_H", 32);
+    if (H < 4 || H % 4 || L % H) H = 32;
+    while (H > 4 && L % H) H >>= 1;
+    return (L % H || H % 4) ? 0 : H;
 }
+
+// Row pitch of the split planes: L/2 bytes plus padding, so that the rows
+// that concurrently running bands touch (H rows apart) do not all fall on
+// the same memory channels.  SPINMC_L2D_PAD overrides the padding (bytes, a
+// multiple of 16).
+int64_t lattice2d_pitch(int L) {
+    int pad = env_int("SPINMC_L2D_PAD", 256);
+    if (pad < 0 || pad % 16) pad = 256;
+    return (int64_t)(L / 2) + pad;
+}
+
+size_t lattice2d_split_bytes(int L) { return (size_t)(2 * (int64_t)L * lattice2d_pitch(L)); }
 
 hipError_t launch_to_split(const int8_t *src, uint8_t *dst, int L, int n_rep, hipStream_t s) {
     const int64_t cpr = (int64_t)L * L / 16, total = cpr * n_rep;
-    hipLaunchKernelGGL(k_to_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L, cpr, total);
+    hipLaunchKernelGGL(k_to_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L,
+                       lattice2d_pitch(L), lattice2d_band_height(L, n_rep), cpr, total);
     return hipGetLastError();
 }
 
 hipError_t launch_from_split(const uint8_t *src, int8_t *dst, int L, int n_rep, hipStream_t s) {
     const int64_t cpr = (int64_t)L * L / 16, total = cpr * n_rep;
-    hipLaunchKernelGGL(k_from_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L, cpr, total);
+    hipLaunchKernelGGL(k_from_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L,
+                       lattice2d_pitch(L), lattice2d_band_height(L, n_rep), cpr, total);
     return hipGetLastError();
 }
 
@@ -425,7 +605,8 @@ hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_r
     Lattice2dArgs a;
     a.src = src;
     a.dst = dst;
-    a.rep_bytes = (int64_t)L * L;
+    a.pitch = lattice2d_pitch(L);
+    a.rep_bytes = 2 * (int64_t)L * a.pitch;
     a.thr = thr;
     a.dE = dE;
     a.key = key;
@@ -434,15 +615,27 @@ hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_r
     a.H = H;
     a.bands = L / H;
     a.n_rep = n_rep;
-    const unsigned threads = (unsigned)(L / (16 * C));
+    a.one2 = 0x00010001u;
+    a.four = 4u;
+    const unsigned compute_threads = (unsigned)(L / (16 * C));
     const unsigned blocks = (unsigned)(a.bands * n_rep);
-    switch (C) {
-        case 1: hipLaunchKernelGGL(k_ising2d_split<1>, dim3(blocks), dim3(threads), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_ising2d_split<2>, dim3(blocks), dim3(threads), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_ising2d_split<4>, dim3(blocks), dim3(threads), 0, s, a); break;
-        default: return hipErrorInvalidValue;
+    const size_t lds = (size_t)2 * kSlots * (L / 2) + 2 * 16 * 2 * sizeof(uint32_t);
+    const int NF = L >= 2048 ? L / 1024 : 2;  // direct-load instructions per feed (two planes of L/2 bytes)
+#define SMC_L2D(CC, NFF)                                                                                   \
+    if (C == CC && NF == NFF) {                                                                            \
+        (void)hipFuncSetAttribute((const void *)k_ising2d_split<CC, NFF>,                                  \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
+        const unsigned threads = compute_threads + 64u * LoaderShape<NFF>::NLW;                           \
+        hipLaunchKernelGGL((k_ising2d_split<CC, NFF>), dim3(blocks), dim3(threads), lds, s, a);            \
+        return hipGetLastError();                                                                          \
     }
-    return hipGetLastError();
+    SMC_L2D(1, 2)
+    SMC_L2D(1, 4)
+    SMC_L2D(1, 8)
+    SMC_L2D(2, 8)
+    SMC_L2D(2, 16)
+#undef SMC_L2D
+    return hipErrorInvalidValue;
 }
 
 }  // namespace smc

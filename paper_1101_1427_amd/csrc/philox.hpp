@@ -25,21 +25,70 @@ struct Key {
 
 __host__ __device__ inline Key make_key(uint64_t seed) { return Key{(uint32_t)seed, (uint32_t)(seed >> 32)}; }
 
+// Three-input XOR in one VALU instruction (gfx950 v_bitop3_b32, truth table
+// 0x96 = odd parity of the three inputs).
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+    return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+}
+
+// One Philox round: the two 32x32 -> 64-bit products are single
+// v_mad_u64_u32 instructions.
+__device__ __forceinline__ uint4 philox_round(uint4 x, uint32_t k0, uint32_t k1) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * x.x;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * x.z;
+    return make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ x.w ^ k1, (uint32_t)p0);
+}
+
+__device__ __forceinline__ uint4 philox_round_x3(uint4 x, uint32_t k0, uint32_t k1) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * x.x;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * x.z;
+    return make_uint4(xor3_key((uint32_t)(p1 >> 32), x.y, k0), (uint32_t)p1, xor3_key((uint32_t)(p0 >> 32), x.w, k1),
+                      (uint32_t)p0);
+}
+
+// Philox4x32-10 of counter x.  Counter words 1..3 are wave-uniform in every
+// use here, so the first three rounds are left to the compiler (it keeps the
+// uniform parts in scalar registers); the remaining rounds are all-vector
+// and use the three-input XOR.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 x, Key key) {
     uint32_t k0 = key.k0, k1 = key.k1;
+    x = philox_round(x, k0, k1);
 #pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        if (round) {
-            k0 += kPhiloxW0;
-            k1 += kPhiloxW1;
-        }
-        const uint32_t lo0 = kPhiloxM0 * x.x;
-        const uint32_t hi0 = __umulhi(kPhiloxM0, x.x);
-        const uint32_t lo1 = kPhiloxM1 * x.z;
-        const uint32_t hi1 = __umulhi(kPhiloxM1, x.z);
-        x = make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+    for (int round = 1; round < 3; ++round) {
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+        x = philox_round(x, k0, k1);
+    }
+#pragma unroll
+    for (int round = 3; round < 10; ++round) {
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+        x = philox_round_x3(x, k0, k1);
     }
     return x;
+}
+
+// N independent draws advanced round by round together (independent
+// dependency chains interleave in the instruction stream).
+template <int NC>
+__device__ __forceinline__ void philox4x32_10_multi(uint4 (&x)[NC], Key key) {
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) x[c] = philox_round(x[c], k0, k1);
+#pragma unroll
+    for (int round = 1; round < 3; ++round) {
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = philox_round(x[c], k0, k1);
+    }
+#pragma unroll
+    for (int round = 3; round < 10; ++round) {
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = philox_round_x3(x[c], k0, k1);
+    }
 }
 
 __device__ __forceinline__ uint32_t word_of(const uint4 &w, uint32_t j) {

@@ -259,10 +259,10 @@ def test_split_kernel_bit_exact(L, n_rep, n, sweep0):
 def test_split_kernel_launch_shape_invariance(monkeypatch):
     """Band height and lane width change the schedule, never the result."""
     seed = W.seed_for(23)
-    L = 2048
+    L = 8192
     b = S.Batch(S.ISING, 2, L, 1, seed)
     outs = []
-    for chunks, H in [(1, 64), (2, 16), (1, 2), (2, 128)]:
+    for chunks, H in [(1, 64), (2, 16), (1, 4), (2, 128)]:
         monkeypatch.setenv("SPINMC_L2D_CHUNKS", str(chunks))
         monkeypatch.setenv("SPINMC_L2D_H", str(H))
         spins, _ = gpu_init(b)
