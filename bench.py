@@ -23,6 +23,151 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLIP = 2.0  # int8 spin read once and written once per sweep
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ("lattice2d.hip", "philox.hpp", "internal.hpp")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources the 2D sweep kernel is compiled from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1101_1427_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_file(kernel: str, L: int) -> str:
+    return os.path.join(PROFILES, f"{kernel}_L{L}_traffic.txt")
+
+
+def traffic_per_launch(kernel: str, L: int):
+    """HBM bytes per launch of the sweep kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size);
+    None if there is none or the kernel sources changed since it was taken."""
+    path = traffic_file(kernel, L)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 4):
+    """A plain device-to-device copy of nbytes, reps times (for the counter scale)."""
+    import torch
+
+    src = torch.ones(nbytes, dtype=torch.int8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
+
+
+def kt_summary(db: str, log: str, kernel: str, L: int, command: str):
+    """Per-kernel totals of a rocprofv3 --kernel-trace --stats run, beside the
+    bench line the same run printed; written next to the traffic summary."""
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    bench_line = ""
+    with open(log) as fh:
+        for line in fh:
+            if line.startswith("{") and '"metric"' in line:
+                bench_line = line.strip()
+    lines = [f"# rocprofv3 --kernel-trace --stats summary: {kernel}, 2D Ising {L}x{L}",
+             f"# command: {command}",
+             "# durations in microseconds (top_kernels view of the results database)",
+             f"kernel_source_sha256: {kernel_source_hash()}",
+             f"{'kernel':40s} {'calls':>7s} {'total_us':>12s} {'avg_us':>10s} {'pct':>7s}"]
+    for name, calls, total, avg, pct in rows:
+        lines.append(f"{short_name(name):40s} {calls:7d} {total:12.1f} {avg:10.3f} {pct:7.2f}")
+    if bench_line:
+        import json
+
+        d = json.loads(bench_line)
+        r = d["roofline"]
+        lines.append(f"bench_line_kernel_us_per_launch: {r['kernel_us_per_launch']}")
+        lines.append(f"bench_line_roofline_frac: {r['frac']}")
+        lines.append(f"bench_line_ns_per_flip: {d['value']}")
+    os.makedirs(PROFILES, exist_ok=True)
+    path = os.path.join(PROFILES, f"{kernel}_L{L}_kernel_trace.txt")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def short_name(name: str) -> str:
+    import re
+
+    m = re.search(r"(k_\w+|__amd_\w+|\w*[Cc]opy\w*)", name)
+    return m.group(1) if m else name[:60]
+
+
+def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, kernel: str, L: int,
+                commands: list[str]):
+    """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the sweep kernel and
+    of the copy kernel, from rocprofv3 result databases; writes the summary
+    that traffic_per_launch reads."""
+    import sqlite3
+
+    def per_kernel(db, counter):
+        con = sqlite3.connect(db)
+        acc = {}
+        for name, val in con.execute("select kernel_name, value from counters_collection where counter_name=?",
+                                     (counter,)):
+            acc.setdefault(name, []).append(val)
+        return acc
+
+    def mean_of(acc, key):
+        name = max((n for n in acc if key in n), key=lambda n: sum(acc[n]) / len(acc[n]))
+        return name, sum(acc[name]) / len(acc[name])
+
+    kf, kfv = mean_of(per_kernel(fetch_db, "FETCH_SIZE"), kernel)
+    kw, kwv = mean_of(per_kernel(write_db, "WRITE_SIZE"), kernel)
+    # the copy kernel: the one that fetched the most; its sums over the run
+    # divided by the number of 1 GiB copies
+    cf_all, cw_all = per_kernel(cfetch_db, "FETCH_SIZE"), per_kernel(cwrite_db, "WRITE_SIZE")
+    copy_name = max(cf_all, key=lambda n: sum(cf_all[n]))
+    reps = 4
+    cfv, cwv = sum(cf_all[copy_name]) / reps, sum(cw_all[copy_name]) / reps
+    copy_kib = (1 << 30) / 1024.0
+    fetch_scale = copy_kib / cfv
+    write_scale = copy_kib / cwv
+    traffic = (kfv * fetch_scale + kwv * write_scale) * 1024.0
+    algorithmic = BYTES_PER_FLIP * L * L
+    lines = [f"# rocprofv3 --pmc summary: {kernel}, one launch = one sweep of the 2D Ising {L}x{L} lattice",
+             "# figures are means per dispatch of the counter over every dispatch of the kernel in the run"]
+    lines += [f"# command: {c}" for c in commands]
+    lines += [f"kernel_source_sha256: {kernel_source_hash()}",
+              f"kernel_FETCH_SIZE_KiB_per_dispatch: {kfv:.1f}",
+              f"kernel_WRITE_SIZE_KiB_per_dispatch: {kwv:.1f}",
+              f"copy_kernel: {short_name(copy_name)}",
+              "copy_bytes_read_and_written_per_copy: 1073741824",
+              f"copy_FETCH_SIZE_KiB_per_copy: {cfv:.1f}",
+              f"copy_WRITE_SIZE_KiB_per_copy: {cwv:.1f}",
+              f"fetch_scale: {fetch_scale:.4f}",
+              f"write_scale: {write_scale:.4f}",
+              f"fetch_bytes_per_launch: {kfv * fetch_scale * 1024:.0f}",
+              f"write_bytes_per_launch: {kwv * write_scale * 1024:.0f}",
+              f"traffic_bytes_per_launch: {traffic:.0f}",
+              f"algorithmic_bytes_per_launch: {algorithmic:.0f}",
+              f"traffic_over_algorithmic: {traffic / algorithmic:.4f}"]
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(traffic_file(kernel, L), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cpu_baseline(cfg, seconds: float = 12.0):
     """The oracle (serial C, 1 thread) on a 1024^2 lattice of the same workload."""
     from oracle import oracle as O
@@ -54,7 +199,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--L", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter scale for the traffic figure)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="write the traffic summary of the sweep kernel from rocprofv3 counter databases")
+    ap.add_argument("--pmc-command", action="append", default=[],
+                    help="command line recorded in the traffic summary (repeatable)")
+    ap.add_argument("--kt-summary", nargs=2, metavar=("KT_DB", "KT_LOG"),
+                    help="write the kernel-trace summary from a rocprofv3 database and the run's output")
+    ap.add_argument("--kt-command", default="", help="command line recorded in the kernel-trace summary")
     args = ap.parse_args()
+    if args.kt_summary:
+        kt_summary(*args.kt_summary, kernel="k_ising2d_split", L=args.L, command=args.kt_command)
+        return
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, kernel="k_ising2d_split", L=args.L, commands=args.pmc_command)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -62,6 +222,9 @@ def main():
 
     import torch
 
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import paper_1101_1427_amd as S
     import workloads as W
 
@@ -84,8 +247,13 @@ def main():
         S.metropolis_sweep(b, s, [beta], 0, warm, dE_accum=dE)
     torch.cuda.synchronize()
 
+    # Timed region: one call per lattice.  The library brackets the sweep
+    # kernels of each call with HIP events on the stream they run on, which
+    # gives the kernel's own time apart from the layout conversions.
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    S.kernel_timing_read()  # drop anything recorded before
+    S.kernel_timing_enable(True)
     t_wall = time.perf_counter()
     ev0.record(stream)
     for beta, s, dE in lattices:
@@ -93,14 +261,18 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
+    kernel_ms, launches = S.kernel_timing_read()
+    S.kernel_timing_enable(False)
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = gpu_ms / steps
     ns_per_flip = gpu_ms * 1e6 / (steps * N)
 
-    launches_per_sweep = int(os.environ.get("SPINMC_LAUNCHES_PER_SWEEP", S.launches_per_sweep(b)))
-    launch_ms = ms_per_step / launches_per_sweep
+    launches_per_sweep, kernel = S.sweep_plan(b)
+    launch_ms = kernel_ms / launches
     bytes_per_launch = BYTES_PER_FLIP * N / launches_per_sweep
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    conversion_ms = (gpu_ms - kernel_ms) / nb
+    traffic = traffic_per_launch(kernel, L)
 
     out = {
         "metric": "ns per spin flip (+% HBM roofline); batched PT sweeps/s vs per-instance",
@@ -119,9 +291,11 @@ def main():
                                f"{{0.30, ln(1+sqrt2)/2, 0.50}}, {per} sweeps each, Delta E tracked",
                    "L": L, "betas": cfg.betas, "sweeps_per_beta": per, "seed": cfg.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": S.sweep_kernel_name(b), "launches_per_sweep": launches_per_sweep,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": kernel, "launches_per_sweep": launches_per_sweep,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "kernel_us_per_launch": round(launch_ms * 1e3, 3),
+                     "conversion_us_per_call": round(conversion_ms * 1e3, 3)},
         "wall_s": round(wall, 4),
     }
     if not args.no_cpu_baseline:

@@ -140,7 +140,8 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
  *  Models: Ising and EA (the EA replicas of one chain must share a sample).
  *  desc.n_rep must equal n_chains * n_temps.
  *  slot_of_temp: DEVICE int32 [n_chains][n_temps], in/out (a permutation of
- *                0..n_temps-1 per chain).
+ *                0..n_temps-1 per chain; a chain whose row is not one is
+ *                left unchanged: spins, energies, slots and counts).
  *  energy:       DEVICE float64 [n_rep], in/out: energy of the configuration
  *                stored in each replica (exact integers; e.g. from
  *                smc_measure_energy_magnetisation).
@@ -171,6 +172,29 @@ int smc_measure_energy_magnetisation(const smc_desc *desc, const void *spins,
  * Used by benchmarks to attribute per-launch time; no device work.
  */
 int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char **kernel_name);
+
+/*
+ * Profiling aid.  While enabled (enable != 0), smc_metropolis_sweep records a
+ * pair of HIP events on the call's stream around the sweep kernels of each
+ * call (the layout conversions of the 2D Ising path are outside the pair).
+ * smc_kernel_timing_read waits for the recorded events, returns the summed
+ * elapsed milliseconds and the number of sweep-kernel launches they cover,
+ * and forgets them.  Disabling also forgets unread events.  Returns
+ * SMC_EHIP if an event call fails.
+ */
+int smc_kernel_timing_enable(int enable);
+int smc_kernel_timing_read(double *elapsed_ms, int64_t *launches);
+
+/*
+ * How smc_pt_sweep_swap will execute: the number of kernel launches for a
+ * call of n_steps steps and the name of the sweep kernel (a static string).
+ * 3D lattices of edge 16 with n_temps <= 32 (EA: rep_per_sample a multiple
+ * of n_temps) run all steps of a call in one launch, one workgroup per chain
+ * with the chain resident in LDS; other shapes take three launches per step
+ * (two half-sweeps and the exchange round) plus two.  No device work.
+ */
+int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, int32_t *launches,
+                const char **kernel_name);
 
 /* Static description of a status code. */
 const char *smc_strerror(int status);

@@ -61,6 +61,12 @@ def lib():
             f.restype = C.c_int
         L.smc_sweep_plan.argtypes = [P(Desc), P(C.c_int32), P(C.c_char_p)]
         L.smc_sweep_plan.restype = C.c_int
+        L.smc_pt_plan.argtypes = [P(Desc), P(PTDesc), C.c_int32, P(C.c_int32), P(C.c_char_p)]
+        L.smc_pt_plan.restype = C.c_int
+        L.smc_kernel_timing_enable.argtypes = [C.c_int]
+        L.smc_kernel_timing_enable.restype = C.c_int
+        L.smc_kernel_timing_read.argtypes = [P(C.c_double), P(C.c_int64)]
+        L.smc_kernel_timing_read.restype = C.c_int
         L.smc_strerror.argtypes = [C.c_int]
         L.smc_strerror.restype = C.c_char_p
         L.smc_last_error.argtypes = []
@@ -179,9 +185,34 @@ def sweep_plan(batch: Batch):
     return int(n.value), name.value.decode()
 
 
+def pt_plan(batch: Batch, n_chains: int, n_temps: int, beta, n_steps: int, beta_per_chain: bool = False):
+    """(kernel launches, sweep kernel name) that smc_pt_sweep_swap uses for a call of n_steps steps."""
+    spins_len = batch.spins_shape()[0]
+    d = batch.desc(spins_len, batch.coup_len())
+    b = np.ascontiguousarray(np.asarray(beta, np.float64).reshape(-1))
+    pt = PTDesc(n_chains, n_temps, 1 if beta_per_chain else 0, 0, b.ctypes.data_as(C.POINTER(C.c_double)))
+    n = C.c_int32(0)
+    name = C.c_char_p()
+    _check(lib().smc_pt_plan(C.byref(d), C.byref(pt), n_steps, C.byref(n), C.byref(name)), "smc_pt_plan")
+    return int(n.value), name.value.decode()
+
+
 def launches_per_sweep(batch: Batch) -> int:
     return sweep_plan(batch)[0]
 
 
 def sweep_kernel_name(batch: Batch) -> str:
     return sweep_plan(batch)[1]
+
+
+def kernel_timing_enable(on: bool = True):
+    """Bracket the sweep kernels of each smc_metropolis_sweep call with HIP events (profiling aid)."""
+    _check(lib().smc_kernel_timing_enable(1 if on else 0), "smc_kernel_timing_enable")
+
+
+def kernel_timing_read():
+    """(elapsed ms, sweep-kernel launches) summed over the calls since the last read."""
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    _check(lib().smc_kernel_timing_read(C.byref(ms), C.byref(n)), "smc_kernel_timing_read")
+    return float(ms.value), int(n.value)

@@ -141,6 +141,16 @@ ThrRow threshold_row(double beta, int dim) {
     return row;
 }
 
+// The chain-resident tempering kernel serves 3D edge-16 batches of at most
+// 32 temperatures with 16-byte aligned spins and thresholds below 2^32.
+bool use_pt3d(const smc_desc *d, const smc_pt_desc *pt, const void *spins, const std::vector<ThrRow> &rows) {
+    if (!pt3d_supported(d, pt->n_temps)) return false;
+    if (((uintptr_t)spins & 15u) != 0) return false;
+    for (const ThrRow &r : rows)
+        if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu || r.m[3].x > 0xFFFFu) return false;
+    return true;
+}
+
 // The one-pass split-layout kernel serves uniform 2D Ising batches whose
 // edge it supports, with 16-byte aligned spins and thresholds below 2^32
 // (beta > 0 up to rounding; the generic kernels cover the rest).
@@ -246,6 +256,57 @@ int upload_inst(StreamCtx &c, hipStream_t s, const smc_desc *d, Plan &plan) {
     return rc;
 }
 
+// Event pairs around the sweep kernels of each call (profiling aid).
+struct TimedCall {
+    hipEvent_t start, stop;
+    int64_t launches;
+};
+std::mutex g_timing_mutex;
+bool g_timing_on = false;
+std::vector<TimedCall> g_timed;
+
+void forget_timed() {
+    for (TimedCall &c : g_timed) {
+        (void)hipEventDestroy(c.start);
+        (void)hipEventDestroy(c.stop);
+    }
+    g_timed.clear();
+}
+
+// Records the start event on construction and the stop event on finish().
+struct SweepTimer {
+    hipStream_t s;
+    TimedCall call{nullptr, nullptr, 0};
+    bool on = false;
+    SweepTimer(hipStream_t stream, int64_t launches) : s(stream) {
+        std::lock_guard<std::mutex> lk(g_timing_mutex);
+        if (!g_timing_on) return;
+        call.launches = launches;
+        if (hipEventCreate(&call.start) != hipSuccess) return;
+        if (hipEventCreate(&call.stop) != hipSuccess) {
+            (void)hipEventDestroy(call.start);
+            return;
+        }
+        on = hipEventRecord(call.start, s) == hipSuccess;
+        if (!on) {
+            (void)hipEventDestroy(call.start);
+            (void)hipEventDestroy(call.stop);
+        }
+    }
+    void finish() {
+        if (!on) return;
+        on = false;
+        std::lock_guard<std::mutex> lk(g_timing_mutex);
+        if (hipEventRecord(call.stop, s) == hipSuccess && g_timing_on) {
+            g_timed.push_back(call);
+        } else {
+            (void)hipEventDestroy(call.start);
+            (void)hipEventDestroy(call.stop);
+        }
+    }
+    ~SweepTimer() { finish(); }
+};
+
 }  // namespace
 }  // namespace smc
 
@@ -266,6 +327,37 @@ const char *smc_strerror(int status) {
 
 const char *smc_last_error(void) { return g_last_error.c_str(); }
 
+int smc_kernel_timing_enable(int enable) {
+    std::lock_guard<std::mutex> lk(g_timing_mutex);
+    g_timing_on = enable != 0;
+    if (!g_timing_on) forget_timed();
+    return SMC_OK;
+}
+
+int smc_kernel_timing_read(double *elapsed_ms, int64_t *launches) {
+    g_last_error.clear();
+    if (!elapsed_ms || !launches) return fail(SMC_EINVAL, "output pointers are required");
+    std::lock_guard<std::mutex> lk(g_timing_mutex);
+    double ms = 0.0;
+    int64_t n = 0;
+    int rc = SMC_OK;
+    for (TimedCall &c : g_timed) {
+        float part = 0.0f;
+        hipError_t e = hipEventSynchronize(c.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&part, c.start, c.stop);
+        if (e != hipSuccess) {
+            rc = fail(SMC_EHIP, "%s", hipGetErrorString(e));
+            break;
+        }
+        ms += part;
+        n += c.launches;
+    }
+    forget_timed();
+    *elapsed_ms = ms;
+    *launches = n;
+    return rc;
+}
+
 int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char **kernel_name) {
     g_last_error.clear();
     Plan plan;
@@ -280,6 +372,31 @@ int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char
         *kernel_name = "k_ising2d_split";
     } else {
         *launches_per_sweep = 2;
+        *kernel_name = "k_half_sweep_generic";
+    }
+    return SMC_OK;
+}
+
+int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, int32_t *launches,
+                const char **kernel_name) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, false, plan);
+    if (rc) return rc;
+    if (!pt || !launches || !kernel_name) return fail(SMC_EINVAL, "pt desc and output pointers are required");
+    if (n_steps < 0) return fail(SMC_EINVAL, "n_steps must be >= 0");
+    if (pt->n_temps < 2 || !pt->beta) return fail(SMC_EINVAL, "need n_temps >= 2 and beta");
+    const int rows_n = pt->beta_per_chain ? pt->n_chains : 1;
+    bool fits = pt3d_supported(desc, pt->n_temps);
+    for (int64_t k = 0; fits && k < (int64_t)rows_n * pt->n_temps; ++k) {
+        const ThrRow r = threshold_row(pt->beta[k], desc->dim);
+        fits = r.m[1].x <= 0xFFFFu && r.m[2].x <= 0xFFFFu && r.m[3].x <= 0xFFFFu;
+    }
+    if (fits) {
+        *launches = n_steps > 0 ? 1 : 0;
+        *kernel_name = "k_pt3d_chain";
+    } else {
+        *launches = n_steps > 0 ? 3 * n_steps + 2 : 0;
         *kernel_name = "k_half_sweep_generic";
     }
     return SMC_OK;
@@ -344,6 +461,7 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         for (int r = 0; r < desc->n_rep; ++r) bf[r] = (float)beta[r];
         if ((rc = upload(c, s, kTables, bf.data(), sizeof(float) * bf.size(), &p))) return rc;
         a.beta_f = (const float *)p;
+        SweepTimer timer(s, 2 * (int64_t)n_sweeps);  // the renormalisations run inside the same pair
         for (int32_t k = 0; k < n_sweeps; ++k) {
             a.t = (uint32_t)(sweep0 + (uint64_t)k);
             SMC_HIP(launch_heis_half_sweep_generic(a, 0, s));
@@ -364,14 +482,17 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         if ((rc = ensure(c, kPingPong, 2 * bytes, &pp))) return rc;
         uint8_t *A = (uint8_t *)pp, *B = A + bytes;
         SMC_HIP(launch_to_split((const int8_t *)spins, A, desc->L, desc->n_rep, s));
+        SweepTimer timer(s, n_sweeps);
         for (int32_t k = 0; k < n_sweeps; ++k) {
             const uint32_t t = (uint32_t)(sweep0 + (uint64_t)k);
             SMC_HIP(launch_ising2d_split(k & 1 ? B : A, k & 1 ? A : B, desc->L, desc->n_rep, a.thr, dE_accum, a.key,
                                          t, s));
         }
+        timer.finish();
         SMC_HIP(launch_from_split(n_sweeps & 1 ? B : A, (int8_t *)spins, desc->L, desc->n_rep, s));
         return SMC_OK;
     }
+    SweepTimer timer(s, 2 * (int64_t)n_sweeps);
     for (int32_t k = 0; k < n_sweeps; ++k) {
         a.t = (uint32_t)(sweep0 + (uint64_t)k);
         SMC_HIP(launch_half_sweep_generic(a, 0, s));
@@ -429,6 +550,13 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, 
     void *thr = nullptr, *bdev = nullptr, *E64 = nullptr, *rowrep = nullptr;
     if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &thr))) return rc;
     if ((rc = upload(c, s, kBeta, pt->beta, sizeof(double) * rows.size(), &bdev))) return rc;
+    if (use_pt3d(desc, pt, spins, rows)) {
+        SMC_HIP(launch_pt3d(desc->model, (int8_t *)spins, desc->model == SMC_EA ? couplings : nullptr,
+                            desc->rep_per_sample, pt->n_chains, n, pt->beta_per_chain ? 1 : 0, (const double *)bdev,
+                            (const ThrRow *)thr, slot_of_temp, energy, (unsigned long long *)swap_accepts,
+                            make_key(desc->seed), (uint32_t)step0, n_steps, s));
+        return SMC_OK;
+    }
     if ((rc = ensure(c, kEnergy64, sizeof(int64_t) * desc->n_rep, &E64))) return rc;
     if ((rc = ensure(c, kRows, sizeof(int32_t) * desc->n_rep, &rowrep))) return rc;
 

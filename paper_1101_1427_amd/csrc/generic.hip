@@ -1,7 +1,7 @@
 // Generic kernels: initial state, per-site half-sweeps for any edge L and
 // dimension, Heisenberg renormalisation, measurements and the
-// parallel-tempering exchange.  The optimised sweep kernels (lattice.hip,
-// batched.hip) produce the same results; these serve every shape.
+// parallel-tempering exchange.  The optimised kernels (lattice2d.hip,
+// pt3d.hip) produce the same results; these serve every shape.
 #include "internal.hpp"
 
 namespace smc {
@@ -123,8 +123,11 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_generic(SweepArgs a, int 
     const int L = g.L, dim = a.b.dim;
     const int64_t N = n_sites(dim, L);
     const int64_t h = (int64_t)(blockIdx.x % bpr) * blockDim.x + threadIdx.x;
+    // a replica without a threshold row (its tempering chain is not a valid
+    // permutation) is left unchanged
+    const int row = a.row_of_rep ? a.row_of_rep[r] : r;
     int dE = 0;
-    if (h < N / 2) {
+    if (h < N / 2 && row >= 0) {
         int8_t *s = (int8_t *)a.spins + g.spin_off;
         const int8_t *J = a.coup ? a.coup + g.coup_off : nullptr;
         const Site st = site_of_pair(dim, L, h, c);
@@ -150,7 +153,6 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_generic(SweepArgs a, int 
         const int d = 2 * si * hf;
         bool acc = d <= 0;
         if (!acc) {
-            const int row = a.row_of_rep ? a.row_of_rep[r] : r;
             const uint2 th = a.thr[row].m[d >> 2];
             const uint4 w = philox4x32_10(make_uint4((uint32_t)(h >> 3), a.t, (uint32_t)r, 2 * kTagHead + c), a.key);
             acc = metropolis_accept(head16_of(w, (uint32_t)(h & 7)), th, (uint32_t)h, a.t, (uint32_t)r, c, a.key);
@@ -335,17 +337,29 @@ int measure_blocks(const Batch &b, int max_L) {
 }
 
 // -------------------------------------------------------- parallel tempering --
+// Energies in, and the threshold row of every replica from the chain's
+// permutation; a chain whose slot_of_temp row is not a permutation gets row
+// -1 for all its replicas, and the sweeps and exchanges leave it unchanged.
 __global__ void k_pt_prepare(SwapArgs a, const double *energy_in) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.n_chains) return;
     const int n = a.n_temps;
     const int base = a.beta_per_chain ? q * n : 0;
     for (int k = 0; k < n; ++k) {
-        const int r = q * n + k;
-        a.E[r] = (int64_t)energy_in[r];
-        const int slot = a.slot_of_temp[q * n + k];
-        if ((unsigned)slot < (unsigned)n) a.row_of_rep[q * n + slot] = base + k;  // a bad permutation is ignored
+        a.E[q * n + k] = (int64_t)energy_in[q * n + k];
+        a.row_of_rep[q * n + k] = -1;
     }
+    bool ok = true;
+    for (int k = 0; k < n; ++k) {
+        const int slot = a.slot_of_temp[q * n + k];
+        if ((unsigned)slot >= (unsigned)n || a.row_of_rep[q * n + slot] >= 0) {
+            ok = false;
+            break;
+        }
+        a.row_of_rep[q * n + slot] = base + k;
+    }
+    if (!ok)
+        for (int k = 0; k < n; ++k) a.row_of_rep[q * n + k] = -1;
 }
 
 __global__ void k_pt_swap(SwapArgs a) {
@@ -355,9 +369,9 @@ __global__ void k_pt_swap(SwapArgs a) {
     const int n = a.n_temps;
     const int base = a.beta_per_chain ? q * n : 0;
     int32_t *sot = a.slot_of_temp + (int64_t)q * n;
+    if (a.row_of_rep[q * n] < 0) return;  // not a permutation: chain left unchanged
     for (int k = (int)(a.t & 1u); k + 1 < n; k += 2) {
         const int A = sot[k], B = sot[k + 1];
-        if ((unsigned)A >= (unsigned)n || (unsigned)B >= (unsigned)n) continue;  // not a permutation
         const double x = (a.beta[base + k + 1] - a.beta[base + k]) * (double)(a.E[q * n + B] - a.E[q * n + A]);
         bool accept = x >= 0.0;
         if (!accept) {

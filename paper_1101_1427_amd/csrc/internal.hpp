@@ -73,6 +73,13 @@ hipError_t launch_half_sweep_generic(const SweepArgs &a, int c, hipStream_t s);
 hipError_t launch_heis_half_sweep_generic(const SweepArgs &a, int c, hipStream_t s);
 hipError_t launch_heis_renorm(const Batch &b, float *spins, int max_L, hipStream_t s);
 
+// Parallel tempering of 3D edge-16 chains, all steps in one launch.
+bool pt3d_supported(const smc_desc *d, int n_temps);
+size_t pt3d_lds_bytes(int model, int n_temps);
+hipError_t launch_pt3d(int model, int8_t *spins, const int8_t *coup, int rep_per_sample, int n_chains, int n_temps,
+                       int beta_per_chain, const double *beta, const ThrRow *thr, int32_t *slot_of_temp,
+                       double *energy, unsigned long long *acc, Key key, uint32_t t0, int n_steps, hipStream_t s);
+
 // Measurement: partials of every replica, then a fixed-order final sum.
 hipError_t launch_measure(const Batch &b, const void *spins, const int8_t *coup, int max_L, double *energy,
                           double *magnet, void *scratch, size_t scratch_bytes, hipStream_t s);

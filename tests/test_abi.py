@@ -112,3 +112,10 @@ def test_binding_has_no_cpu_fallback():
     assert "oracle" not in src.replace("oracle (", "")
     for f in os.listdir(os.path.join(ROOT, "paper_1101_1427_amd", "csrc")):
         assert "oracle" not in open(os.path.join(ROOT, "paper_1101_1427_amd", "csrc", f)).read().lower()
+
+
+def test_kernel_timing_without_calls_reads_zero():
+    S.kernel_timing_enable(True)
+    assert S.kernel_timing_read() == (0.0, 0)
+    S.kernel_timing_enable(False)
+    assert S.kernel_timing_read() == (0.0, 0)

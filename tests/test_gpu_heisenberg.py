@@ -1,0 +1,84 @@
+"""Heisenberg model: float32 GPU sweeps against the float64 oracle.
+
+The two sides use the same random numbers but round differently, so their
+configurations part after a while; the checks are (i) the first sweep site by
+site at the full 256^3 size, (ii) the long-run mean energy within three
+combined standard errors.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1101_1427_amd as S
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _binned_mean_err(x, n_bins=20):
+    """Mean and its standard error from n_bins consecutive bins (autocorrelation-safe)."""
+    x = np.asarray(x, np.float64)
+    m = len(x) // n_bins
+    bins = x[:m * n_bins].reshape(n_bins, m).mean(axis=1)
+    return bins.mean(), bins.std(ddof=1) / np.sqrt(n_bins)
+
+
+def test_heisenberg_256_first_sweep_sitewise():
+    """256^3 at beta = 0.693 (the Heisenberg workload): one sweep from each
+    side's own start; every component within 1e-5 except where an accept
+    decision sits within float32 rounding of exp(-beta dE)."""
+    cfg = W.heisenberg_3d()
+    L, beta = cfg.L, cfg.betas[0]
+    N = L ** 3
+    b = S.Batch(S.HEISENBERG, 3, L, 1, cfg.seed, renorm_every=cfg.renorm_every)
+    spins = torch.zeros(3 * N, dtype=torch.float32, device=DEV)
+    S.spin_init(b, spins)
+    n_acc = torch.zeros(1, dtype=torch.int64, device=DEV)
+    S.metropolis_sweep(b, spins, [beta], 0, 1, dE_accum=n_acc)
+    ref = O.init_heis(3, L, cfg.seed, 0)
+    ref_acc = O.heis_sweep(3, L, ref, beta, cfg.seed, 0, 0, cfg.renorm_every)
+    got = _host(spins).astype(np.float64).reshape(-1, 3)
+    dev = np.abs(got - ref).max(axis=1)
+    mismatches = int((dev > 1e-5).sum())
+    # a decision differs only where u is within ~2^-23 of exp(-beta dE): expected count ~ N * 2^-21
+    assert mismatches <= max(8, int(8 * N * 2.0 ** -21)), mismatches
+    assert abs(int(_host(n_acc)[0]) - ref_acc) <= mismatches
+    assert np.abs(np.linalg.norm(got, axis=1) - 1).max() < 2e-6
+
+
+def test_heisenberg_long_run_energy_within_three_sigma():
+    """16^3 at beta = 0.693, 500 sweeps burn-in then 3000 sweeps measured every
+    10: the float32 GPU chain and the float64 oracle chain agree on <e> within
+    three combined standard errors."""
+    L, beta, seed = 16, 0.693, W.seed_for(30)
+    N = L ** 3
+    b = S.Batch(S.HEISENBERG, 3, L, 1, seed, renorm_every=16)
+    spins = torch.zeros(3 * N, dtype=torch.float32, device=DEV)
+    S.spin_init(b, spins)
+    ref = O.init_heis(3, L, seed, 0)
+    E = torch.zeros(1, dtype=torch.float64, device=DEV)
+    burn, total, every = 500, 3500, 10
+    S.metropolis_sweep(b, spins, [beta], 0, burn)
+    O.heis_run(3, L, ref, beta, seed, 0, 0, burn, 16)
+    e_gpu, e_ref = [], []
+    for t in range(burn, total, every):
+        S.metropolis_sweep(b, spins, [beta], t, every)
+        S.measure_energy_magnetisation(b, spins, E)
+        e_gpu.append(float(_host(E)[0]) / N)
+        O.heis_run(3, L, ref, beta, seed, 0, t, every, 16)
+        e_ref.append(O.heis_energy(3, L, ref) / N)
+    mg, sg = _binned_mean_err(e_gpu)
+    mr, sr = _binned_mean_err(e_ref)
+    assert abs(mg - mr) <= 3.0 * np.hypot(sg, sr), (mg, sg, mr, sr)
+    # beta = 0.693 is close to the 3D critical point: about one third of the
+    # maximal bond energy, e in (-1.5, -0.5)
+    assert -1.5 < mg < -0.5 and -1.5 < mr < -0.5

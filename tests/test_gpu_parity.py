@@ -262,7 +262,7 @@ def test_split_kernel_launch_shape_invariance(monkeypatch):
     L = 8192
     b = S.Batch(S.ISING, 2, L, 1, seed)
     outs = []
-    for chunks, H in [(1, 64), (2, 16), (1, 4), (2, 128)]:
+    for chunks, H in [(1, 64), (2, 16), (1, 4), (2, 128), (2, 32)]:
         monkeypatch.setenv("SPINMC_L2D_CHUNKS", str(chunks))
         monkeypatch.setenv("SPINMC_L2D_H", str(H))
         spins, _ = gpu_init(b)
