@@ -3,8 +3,10 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -50,10 +52,32 @@ struct Buffer {
     std::vector<unsigned char> last;
 };
 
-enum Slot { kTables = 0, kInst, kSamples, kMeasure, kEnergy64, kRows, kBeta, kPingPong, kNumSlots };
+enum Slot {
+    kTables = 0,
+    kInst,
+    kSamples,
+    kMeasure,
+    kEnergy64,
+    kRows,
+    kBeta,
+    kPingPong,
+    kCoupSplit,
+    kChunks,
+    kWork,
+    kStep,
+    kNumSlots
+};
+
+// An instantiated tempering graph of `steps` steps and the launch arguments
+// it was built from (rebuilt when they change).
+struct GraphCache {
+    std::vector<uint64_t> sig;
+    hipGraphExec_t exec = nullptr;
+};
 
 struct StreamCtx {
     Buffer dev[kNumSlots];
+    GraphCache graphs[2];  // full chunk of steps, remainder
 };
 
 std::mutex g_ctx_mutex;
@@ -256,6 +280,189 @@ int upload_inst(StreamCtx &c, hipStream_t s, const smc_desc *d, Plan &plan) {
     return rc;
 }
 
+// ------------------------------------------------ uneven 2D tempering ----
+// Batches of 2D lattices with edges in {16, 32, ..., 256} (uniform or uneven)
+// go to the per-replica LDS kernel; the replicas of one edge form a class
+// with its own launch shape.
+struct EdgeClass {
+    int L = 0, mode = 0, threads = 0;
+    int32_t first = 0, count = 0;  // range of the work list
+};
+
+bool use_uneven2d(const smc_desc *d, const void *spins, const int8_t *coup, const std::vector<ThrRow> &rows) {
+    if (d->dim != 2 || (d->model != SMC_ISING && d->model != SMC_EA)) return false;
+    const char *env = getenv("SPINMC_UNEVEN2D");
+    if (env && env[0] == '0') return false;
+    if (((uintptr_t)spins & 15u) != 0) return false;
+    if (d->model == SMC_EA && ((uintptr_t)coup & 15u) != 0) return false;
+    for (const ThrRow &r : rows)
+        if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu) return false;
+    if (d->L > 0) return uneven2d_edge_supported(d->L);
+    for (int r = 0; r < d->n_rep; ++r) {
+        const smc_inst &g = d->inst[r];
+        if (!uneven2d_edge_supported(g.L) || g.spin_off % 16) return false;
+        if (d->model == SMC_EA && g.coup_off % 16) return false;
+    }
+    return true;
+}
+
+// Threads per workgroup for an edge: about four draw groups per thread and
+// colour, between one and eight waves.
+int uneven2d_threads(int L) {
+    const int groups = L * L / 16;
+    int t = 64;
+    while (t < 512 && 4 * t < groups) t <<= 1;
+    return t;
+}
+
+std::vector<smc_inst> inst_rows(const smc_desc *d) {
+    std::vector<smc_inst> rows(d->n_rep);
+    const int64_t N = (int64_t)d->L * d->L;
+    for (int r = 0; r < d->n_rep; ++r) {
+        if (d->L > 0) {
+            rows[r].L = d->L;
+            rows[r].sample = d->model == SMC_EA ? r / d->rep_per_sample : 0;
+            rows[r].spin_off = (int64_t)r * N;
+            rows[r].coup_off = (int64_t)rows[r].sample * 2 * N;
+        } else {
+            rows[r] = d->inst[r];
+        }
+    }
+    return rows;
+}
+
+int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &plan, const smc_pt_desc *pt,
+                 void *spins, const int8_t *couplings, SwapArgs &sw, const ThrRow *thr, double *energy,
+                 uint64_t step0, int32_t n_steps) {
+    int rc;
+    // instance table, classes by edge (largest first), work list in replica order within a class
+    const std::vector<smc_inst> rows = inst_rows(desc);
+    void *inst_dev = nullptr;
+    if ((rc = upload(c, s, kInst, rows.data(), sizeof(smc_inst) * rows.size(), &inst_dev))) return rc;
+    std::map<int, std::vector<int32_t>, std::greater<int>> by_edge;
+    for (int r = 0; r < desc->n_rep; ++r) by_edge[rows[r].L].push_back(r);
+    std::vector<EdgeClass> classes;
+    std::vector<int32_t> work;
+    for (auto &kv : by_edge) {
+        EdgeClass e;
+        e.L = kv.first;
+        e.mode = uneven2d_coup_mode(desc->model, e.L);
+        e.threads = uneven2d_threads(e.L);
+        e.first = (int32_t)work.size();
+        e.count = (int32_t)kv.second.size();
+        work.insert(work.end(), kv.second.begin(), kv.second.end());
+        classes.push_back(e);
+        SMC_HIP(uneven2d_prepare_kernel(e.mode, uneven2d_lds_bytes(e.L, e.mode)));
+    }
+    void *work_dev = nullptr;
+    if ((rc = upload(c, s, kWork, work.data(), sizeof(int32_t) * work.size(), &work_dev))) return rc;
+
+    // colour-split couplings of every sample
+    uint8_t *csplit = nullptr;
+    if (desc->model == SMC_EA) {
+        std::vector<smc_inst> samples;
+        if (desc->L > 0) {
+            samples = plan.samples;
+            for (smc_inst &g : samples) g.coup_off = (int64_t)g.sample * 2 * (int64_t)desc->L * desc->L;
+        } else {
+            std::map<int32_t, smc_inst> seen;
+            for (const smc_inst &g : rows) seen.emplace(g.sample, g);
+            for (auto &kv : seen) samples.push_back(kv.second);
+        }
+        std::vector<int64_t> start(samples.size());
+        int64_t total = 0;
+        for (size_t k = 0; k < samples.size(); ++k) {
+            start[k] = total;
+            total += 2 * (int64_t)samples[k].L * samples[k].L / 16;
+        }
+        void *samp_dev = nullptr, *start_dev = nullptr, *cs = nullptr;
+        if ((rc = upload(c, s, kSamples, samples.data(), sizeof(smc_inst) * samples.size(), &samp_dev))) return rc;
+        if ((rc = upload(c, s, kChunks, start.data(), sizeof(int64_t) * start.size(), &start_dev))) return rc;
+        if ((rc = ensure(c, kCoupSplit, (size_t)desc->coup_len, &cs))) return rc;
+        csplit = (uint8_t *)cs;
+        SMC_HIP(launch_coup_split2d(couplings, csplit, (const smc_inst *)samp_dev, (int)samples.size(), total,
+                                    (const int64_t *)start_dev, s));
+    }
+    void *tp = nullptr;
+    if ((rc = ensure(c, kStep, sizeof(uint32_t), &tp))) return rc;
+    uint32_t *t_dev = (uint32_t *)tp;
+    SMC_HIP(launch_set_step(t_dev, (uint32_t)step0, s));
+    sw.t_dev = t_dev;
+    SMC_HIP(launch_pt_prepare(sw, energy, s));
+    const Uneven2dArgs a = make_uneven2d_args((int8_t *)spins, (const smc_inst *)inst_dev, csplit, sw.row_of_rep,
+                                              thr, sw.E, t_dev, make_key(desc->seed));
+    const int32_t *wl = (const int32_t *)work_dev;
+
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    SMC_HIP(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone || n_steps < 4) {
+        // inside a caller's capture (or a few steps): plain launches in step order
+        for (int32_t k = 0; k < n_steps; ++k) {
+            for (const EdgeClass &e : classes)
+                SMC_HIP(launch_uneven2d_sweep(a, wl + e.first, e.count, e.L, e.mode, e.threads, s));
+            SMC_HIP(launch_pt_swap(sw, s));
+            SMC_HIP(launch_advance_step(t_dev, s));
+        }
+    } else {
+        // a graph of K steps: per step the edge classes run as parallel
+        // branches, then the exchange round, then the step counter
+        const int32_t K = n_steps < 32 ? n_steps : 32;
+        const int32_t reps = n_steps / K, rest = n_steps % K;
+        for (int which = 0; which < 2; ++which) {
+            const int32_t steps = which == 0 ? K : rest;
+            if (steps == 0) continue;
+            std::vector<uint64_t> sig = {(uint64_t)steps, (uint64_t)(uintptr_t)a.spins, (uint64_t)(uintptr_t)a.inst,
+                                         (uint64_t)(uintptr_t)a.csplit, (uint64_t)(uintptr_t)a.row_of_rep,
+                                         (uint64_t)(uintptr_t)a.thr, (uint64_t)(uintptr_t)a.E,
+                                         (uint64_t)(uintptr_t)t_dev, a.key.k0, a.key.k1, (uint64_t)(uintptr_t)wl,
+                                         (uint64_t)(uintptr_t)sw.beta, (uint64_t)(uintptr_t)sw.slot_of_temp,
+                                         (uint64_t)(uintptr_t)sw.acc, (uint64_t)sw.n_chains, (uint64_t)sw.n_temps,
+                                         (uint64_t)sw.beta_per_chain};
+            for (const EdgeClass &e : classes) {
+                sig.push_back((uint64_t)e.L);
+                sig.push_back((uint64_t)e.mode);
+                sig.push_back((uint64_t)e.threads);
+                sig.push_back((uint64_t)e.first);
+                sig.push_back((uint64_t)e.count);
+            }
+            GraphCache &gc = c.graphs[which];
+            if (gc.exec == nullptr || gc.sig != sig) {
+                if (gc.exec) {
+                    SMC_HIP(hipStreamSynchronize(s));  // the old executable may still be in flight
+                    SMC_HIP(hipGraphExecDestroy(gc.exec));
+                    gc.exec = nullptr;
+                }
+                hipGraph_t g = nullptr;
+                SMC_HIP(hipGraphCreate(&g, 0));
+                hipError_t e = hipSuccess;
+                hipGraphNode_t prev = nullptr;
+                std::vector<hipGraphNode_t> sweeps(classes.size());
+                for (int32_t k = 0; k < steps && e == hipSuccess; ++k) {
+                    for (size_t q = 0; q < classes.size() && e == hipSuccess; ++q) {
+                        const EdgeClass &ec = classes[q];
+                        e = add_uneven2d_sweep_node(g, &sweeps[q], prev ? &prev : nullptr, prev ? 1 : 0, a,
+                                                    wl + ec.first, ec.count, ec.L, ec.mode, ec.threads);
+                    }
+                    hipGraphNode_t swap = nullptr;
+                    if (e == hipSuccess) e = add_pt_swap_node(g, &swap, sweeps.data(), sweeps.size(), sw);
+                    if (e == hipSuccess) e = add_advance_node(g, &prev, &swap, 1, t_dev);
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    gc.exec = nullptr;
+                    return fail(SMC_EHIP, "building the tempering graph: %s", hipGetErrorString(e));
+                }
+                gc.sig = sig;
+            }
+            const int32_t launches = which == 0 ? reps : 1;
+            for (int32_t k = 0; k < launches; ++k) SMC_HIP(hipGraphLaunch(gc.exec, s));
+        }
+    }
+    SMC_HIP(launch_pt_finish(sw, energy, s));
+    return SMC_OK;
+}
+
 // Event pairs around the sweep kernels of each call (profiling aid).
 struct TimedCall {
     hipEvent_t start, stop;
@@ -392,9 +599,29 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
         const ThrRow r = threshold_row(pt->beta[k], desc->dim);
         fits = r.m[1].x <= 0xFFFFu && r.m[2].x <= 0xFFFFu && r.m[3].x <= 0xFFFFu;
     }
+    bool fits2d = !fits && desc->dim == 2 && (desc->model == SMC_ISING || desc->model == SMC_EA);
+    if (fits2d) {
+        const char *env = getenv("SPINMC_UNEVEN2D");
+        if (env && env[0] == '0') fits2d = false;
+        for (int r = 0; fits2d && desc->L == 0 && r < desc->n_rep; ++r)
+            fits2d = uneven2d_edge_supported(desc->inst[r].L) && desc->inst[r].spin_off % 16 == 0 &&
+                     (desc->model != SMC_EA || desc->inst[r].coup_off % 16 == 0);
+        if (desc->L > 0) fits2d = uneven2d_edge_supported(desc->L);
+        for (int64_t k = 0; fits2d && k < (int64_t)rows_n * pt->n_temps; ++k) {
+            const ThrRow r = threshold_row(pt->beta[k], desc->dim);
+            fits2d = r.m[1].x <= 0xFFFFu && r.m[2].x <= 0xFFFFu;
+        }
+    }
     if (fits) {
         *launches = n_steps > 0 ? 1 : 0;
         *kernel_name = "k_pt3d_chain";
+    } else if (fits2d) {
+        // set step, prepare, (coupling split), graph launches of up to 32 steps, finish
+        const int32_t K = n_steps < 32 ? n_steps : 32;
+        const int32_t graphs = n_steps < 4 ? 0 : n_steps / K + (n_steps % K ? 1 : 0);
+        const int32_t direct = n_steps < 4 ? n_steps * (int32_t)(2 + 7) : 0;
+        *launches = n_steps > 0 ? 3 + (desc->model == SMC_EA ? 1 : 0) + graphs + direct : 0;
+        *kernel_name = "k_uneven2d_sweep";
     } else {
         *launches = n_steps > 0 ? 3 * n_steps + 2 : 0;
         *kernel_name = "k_half_sweep_generic";
@@ -561,6 +788,7 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, 
     if ((rc = ensure(c, kRows, sizeof(int32_t) * desc->n_rep, &rowrep))) return rc;
 
     SwapArgs sw;
+    sw.t_dev = nullptr;
     sw.n_chains = pt->n_chains;
     sw.n_temps = n;
     sw.beta_per_chain = pt->beta_per_chain ? 1 : 0;
@@ -583,6 +811,8 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, 
     a.thr = (const ThrRow *)thr;
     a.row_of_rep = (const int32_t *)rowrep;
 
+    if (use_uneven2d(desc, spins, couplings, rows))
+        return run_uneven2d(c, s, desc, plan, pt, spins, couplings, sw, (const ThrRow *)thr, energy, step0, n_steps);
     SMC_HIP(launch_pt_prepare(sw, energy, s));
     for (int32_t k = 0; k < n_steps; ++k) {
         const uint32_t t = (uint32_t)(step0 + (uint64_t)k);

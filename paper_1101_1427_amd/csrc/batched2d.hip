@@ -1,0 +1,367 @@
+// Parallel tempering of uneven batches of 2D lattices (Sec. 6, Eq. 12; many
+// independent instances at once, Sec. 5.2).
+//
+// A sweep of the batch is one launch per lattice size: one workgroup per
+// replica holds the replica in LDS, runs colour 0 then colour 1 and writes it
+// back, tracking the replica's energy.  Couplings are read from a
+// colour-split copy made once per call (in LDS next to the spins when they
+// fit, else from the L2-resident copy).  Results equal those of the generic
+// per-site kernels step for step.
+//
+// LDS layout of a replica of edge L (L^2 bytes): row y holds the L/2 sites
+// with even x (array E, x = 2i) and then the L/2 sites with odd x (array O),
+// one byte per site, (1 - s)/2.  E sites of row y have colour y & 1.  The
+// coupling copy has the same shape twice: plane X holds the bond from each
+// site to its +x neighbour, plane Y the bond to its +y neighbour, as bytes
+// (1 - J)/2.
+#include <string.h>
+
+#include "internal.hpp"
+
+namespace smc {
+namespace {
+
+constexpr int kMaxThreads = 512;
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) {
+    return __builtin_amdgcn_alignbyte(hi, lo, s);
+}
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ uint32_t sub_sat16(uint32_t a, uint32_t b) {
+    return as_u32(__builtin_elementwise_sub_sat(as_u16x2(a), as_u16x2(b)));
+}
+__device__ __forceinline__ uint32_t sub16(uint32_t a, uint32_t b) { return as_u32(as_u16x2(a) - as_u16x2(b)); }
+__device__ __forceinline__ uint32_t min16(uint32_t a, uint32_t b) {
+    return as_u32(__builtin_elementwise_min(as_u16x2(a), as_u16x2(b)));
+}
+
+// Thresholds by the number n of unsatisfied bonds (Delta E = 8 - 4n): n = 0
+// and 1 take the high halves of thr[2] and thr[1]; n >= 2 is always accepted
+// (0xFFFF, a head of 0xFFFF goes through the exact path).
+struct Lut2 {
+    uint32_t lo, hi;
+};
+
+__device__ __forceinline__ Lut2 lut2(const ThrRow &row) {
+    const uint32_t t2 = row.m[2].x, t1 = row.m[1].x;  // <= 0xFFFF (checked on the host)
+    Lut2 k;
+    k.lo = (t2 & 0xFFu) | ((t1 & 0xFFu) << 8) | 0xFFFF0000u;
+    k.hi = (t2 >> 8) | ((t1 >> 8) << 8) | 0xFFFF0000u;
+    return k;
+}
+
+// Flip flags of four sites from counts n (bytes) and heads wa (sites 0, 1),
+// wb (sites 2, 3); eq collects threshold - head per 16-bit lane.
+__device__ __forceinline__ uint32_t decide4(uint32_t n, uint32_t wa, uint32_t wb, Lut2 k, uint32_t one2,
+                                            uint32_t &eq) {
+    const uint32_t tl = perm(0xFFFFFFFFu, k.lo, n);
+    const uint32_t th = perm(0xFFFFFFFFu, k.hi, n);
+    const uint32_t ta = perm(th, tl, 0x05010400u);
+    const uint32_t tb = perm(th, tl, 0x07030602u);
+    const uint32_t ra = min16(sub_sat16(ta, wa), one2);
+    const uint32_t rb = min16(sub_sat16(tb, wb), one2);
+    eq = min16(eq, min16(sub16(ta, wa), sub16(tb, wb)));
+    return perm(rb, ra, 0x06040200u);
+}
+
+// One colour-c group: the eight colour-c sites of row y with in-array
+// indices 8k .. 8k+7 (one Philox draw).  S: spins, X/Y: coupling planes
+// (either in LDS or in global memory), all with the row layout above.
+template <bool EA>
+__device__ __forceinline__ void group(uint8_t *S, const uint8_t *X, const uint8_t *Yp, int L, int y, int k, int c,
+                                      uint32_t t, uint32_t r, Key key, Lut2 K, const ThrRow &th, uint32_t one2,
+                                      uint32_t four, uint32_t &cnt, uint32_t &nsum) {
+    const int half = L >> 1;
+    const int a = (y & 1) == c ? 0 : 1;
+    const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+    const int o_own = y * L + a * half + 8 * k;
+    const int o_oth = y * L + (1 - a) * half + 8 * k;
+    // the extra word of the other array: the word before (a = 0) or after (a = 1), wrapping in the row
+    const int o_ext = y * L + (1 - a) * half + (a == 0 ? (k == 0 ? half - 4 : 8 * k - 4) : (8 * k + 8 == half ? 0 : 8 * k + 8));
+    const uint2 own = *(const uint2 *)(S + o_own);
+    const uint2 oth = *(const uint2 *)(S + o_oth);
+    const uint32_t ext = *(const uint32_t *)(S + o_ext);
+    const uint2 vm = *(const uint2 *)(S + ym * L + a * half + 8 * k);
+    const uint2 vp = *(const uint2 *)(S + yp * L + a * half + 8 * k);
+    uint2 jxo = make_uint2(0u, 0u), jxt = jxo, jyo = jxo, jym = jxo;
+    uint32_t jxe = 0u;
+    if constexpr (EA) {
+        jxo = *(const uint2 *)(X + o_own);                        // +x bonds of the own sites
+        jxt = *(const uint2 *)(X + o_oth);                        // +x bonds of the other array
+        jxe = *(const uint32_t *)(X + o_ext);
+        jyo = *(const uint2 *)(Yp + o_own);                       // +y bonds of the own sites
+        jym = *(const uint2 *)(Yp + ym * L + a * half + 8 * k);   // +y bonds of the sites below
+    }
+    uint32_t xm0, xm1, xp0, xp1;  // unsatisfied flags of the -x and +x bonds
+    if (a == 0) {
+        // E site 2i: -x neighbour O[i-1] over its +x bond, +x neighbour O[i] over the own +x bond
+        const uint32_t t0 = oth.x ^ jxt.x, t1 = oth.y ^ jxt.y, te = ext ^ jxe;
+        xm0 = own.x ^ alignbyte(t0, te, 3);
+        xm1 = own.y ^ alignbyte(t1, t0, 3);
+        xp0 = own.x ^ oth.x ^ jxo.x;
+        xp1 = own.y ^ oth.y ^ jxo.y;
+    } else {
+        // O site 2i+1: -x neighbour E[i] over its +x bond, +x neighbour E[i+1] over the own +x bond
+        xm0 = own.x ^ oth.x ^ jxt.x;
+        xm1 = own.y ^ oth.y ^ jxt.y;
+        xp0 = own.x ^ alignbyte(oth.y, oth.x, 1) ^ jxo.x;
+        xp1 = own.y ^ alignbyte(ext, oth.y, 1) ^ jxo.y;
+    }
+    const uint32_t n0 = (xm0 + xp0) + ((own.x ^ vm.x ^ jym.x) + (own.x ^ vp.x ^ jyo.x));
+    const uint32_t n1 = (xm1 + xp1) + ((own.y ^ vm.y ^ jym.y) + (own.y ^ vp.y ^ jyo.y));
+    const uint32_t g = (uint32_t)(y * (L >> 4) + k);
+    const uint4 w = philox4x32_10(make_uint4(g, t, r, 2 * kTagHead + (uint32_t)c), key);
+    uint32_t eq = 0xFFFFFFFFu;
+    uint32_t F0 = decide4(n0, w.x, w.y, K, one2, eq);
+    uint32_t F1 = decide4(n1, w.z, w.w, K, one2, eq);
+    const bool tie = ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u);
+    if (__builtin_expect(__any(tie), 0)) {
+        if (tie) {
+            uint32_t f0 = 0u, f1 = 0u;
+#pragma unroll 1
+            for (uint32_t i = 0; i < 2u * four; ++i) {
+                const uint32_t nw = i < 4u ? n0 : n1;
+                const uint32_t ns = (nw >> (8u * (i & 3u))) & 0xFFu;
+                const uint32_t j = i >> 1;
+                const uint32_t word = (j & 2u) ? ((j & 1u) ? w.w : w.z) : ((j & 1u) ? w.y : w.x);
+                const uint32_t head = (i & 1u) ? (word >> 16) : (word & 0xFFFFu);
+                uint32_t flip = 1u;
+                if (ns < 2u) {
+                    const uint2 tv = th.m[2u - ns];
+                    flip = head < tv.x ? 1u : 0u;
+                    if (head == tv.x) flip = tail16(g * 8u + i, t, r, (uint32_t)c, key) < tv.y ? 1u : 0u;
+                }
+                if (i < 4u)
+                    f0 |= flip << (8u * (i & 3u));
+                else
+                    f1 |= flip << (8u * (i & 3u));
+            }
+            F0 = f0;
+            F1 = f1;
+        }
+    }
+    *(uint2 *)(S + o_own) = make_uint2(own.x ^ F0, own.y ^ F1);
+    // Delta E of a flip with n unsatisfied bonds is 4 (2 - n)
+    const uint32_t m0 = (F0 << 8) - F0, m1 = (F1 << 8) - F1;
+    cnt = __builtin_amdgcn_sad_u8(F0, 0u, __builtin_amdgcn_sad_u8(F1, 0u, cnt));
+    nsum = __builtin_amdgcn_sad_u8(n0 & m0, 0u, __builtin_amdgcn_sad_u8(n1 & m1, 0u, nsum));
+}
+
+// One workgroup per replica of the work list; COUP: 0 Ising, 1 couplings in
+// LDS, 2 couplings read from the global copy.
+template <int COUP>
+__global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, const int32_t *work, int L) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ long long red[kMaxThreads / 64];
+    const uint32_t nblk = gridDim.x, b = blockIdx.x;
+    // consecutive work items (the replicas of one chain) on one XCD, sharing its L2
+    const uint32_t logical = (nblk & 7u) ? b : (b & 7u) * (nblk >> 3) + (b >> 3);
+    const int r = work[logical];
+    const int row = a.row_of_rep[r];
+    if (row < 0) return;  // chain without a valid permutation: unchanged
+    const smc_inst g = a.inst[r];
+    const int N = L * L, half = L >> 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    uint8_t *S = smem;
+    const uint8_t *X = nullptr, *Yp = nullptr;
+    int8_t *gs = a.spins + g.spin_off;
+
+    // row-major +-1 -> split 0/1 bytes
+    for (int i = tid; i < N / 16; i += nt) {
+        const int y = i / (L >> 4), m = i % (L >> 4);
+        const uint4 v = *(const uint4 *)(gs + (int64_t)i * 16);
+        const uint32_t mm = 0x01010101u;
+        const uint32_t b0 = (v.x >> 1) & mm, b1 = (v.y >> 1) & mm, b2 = (v.z >> 1) & mm, b3 = (v.w >> 1) & mm;
+        *(uint2 *)(S + y * L + 8 * m) = make_uint2(perm(b1, b0, 0x06040200u), perm(b3, b2, 0x06040200u));
+        *(uint2 *)(S + y * L + half + 8 * m) = make_uint2(perm(b1, b0, 0x07050301u), perm(b3, b2, 0x07050301u));
+    }
+    if constexpr (COUP == 1) {
+        uint8_t *C = smem + N;
+        const uint4 *src = (const uint4 *)(a.csplit + g.coup_off);
+        for (int i = tid; i < 2 * N / 16; i += nt) ((uint4 *)C)[i] = src[i];
+        X = C;
+        Yp = C + N;
+    } else if constexpr (COUP == 2) {
+        X = a.csplit + g.coup_off;
+        Yp = X + N;
+    }
+    const ThrRow &th = a.thr[row];
+    const Lut2 K = lut2(th);
+    const uint32_t t = *a.t_dev;
+    __syncthreads();
+
+    uint32_t cnt = 0u, nsum = 0u;
+    const int groups = N >> 4;  // per colour
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll 1
+        for (int q = tid; q < groups; q += nt) {
+            const int y = q / (L >> 4), k = q % (L >> 4);
+            group<COUP != 0>(S, X, Yp, L, y, k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+        }
+        __syncthreads();
+    }
+
+    // split 0/1 bytes -> row-major +-1
+    for (int i = tid; i < N / 16; i += nt) {
+        const int y = i / (L >> 4), m = i % (L >> 4);
+        const uint2 e = *(const uint2 *)(S + y * L + 8 * m);
+        const uint2 o = *(const uint2 *)(S + y * L + half + 8 * m);
+        const uint32_t w0 = perm(o.x, e.x, 0x05010400u), w1 = perm(o.x, e.x, 0x07030602u);
+        const uint32_t w2 = perm(o.y, e.y, 0x05010400u), w3 = perm(o.y, e.y, 0x07030602u);
+        auto pm1 = [](uint32_t v) { return ((v << 8) - v) | 0x01010101u; };
+        *(uint4 *)(gs + (int64_t)i * 16) = make_uint4(pm1(w0), pm1(w1), pm1(w2), pm1(w3));
+    }
+    // energy: sum over flips of 4 (2 - n)
+    long long v = 2ll * (long long)cnt - (long long)nsum;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        long long tot = 0;
+        for (int w = 0; w < (nt >> 6); ++w) tot += red[w];
+        a.E[r] += 4 * tot;
+    }
+}
+
+// Couplings of every sample into the colour-split planes (one thread per 16
+// sites of a row): X[y][a][i] = (1 - J_x(site))/2, Y likewise.
+__global__ __launch_bounds__(256) void k_coup_split2d(const int8_t *coup, uint8_t *out, const smc_inst *samples,
+                                                     int n_samples, int64_t chunks_total, const int64_t *chunk_start) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= chunks_total) return;
+    // sample by binary search over its first chunk
+    int lo = 0, hi = n_samples - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chunk_start[mid] <= gid) lo = mid; else hi = mid - 1;
+    }
+    const smc_inst g = samples[lo];
+    const int L = g.L, half = L >> 1;
+    const int64_t N = (int64_t)L * L;
+    const int64_t i = gid - chunk_start[lo];  // chunk within the sample: plane, row, 16-site piece
+    const int per_plane = (int)(N / 16);
+    const int plane = (int)(i / per_plane), rem = (int)(i % per_plane);
+    const int y = rem / (L >> 4), m = rem % (L >> 4);
+    const uint4 v = *(const uint4 *)(coup + g.coup_off + plane * N + (int64_t)y * L + 16 * m);
+    const uint32_t mm = 0x01010101u;
+    const uint32_t b0 = (v.x >> 1) & mm, b1 = (v.y >> 1) & mm, b2 = (v.z >> 1) & mm, b3 = (v.w >> 1) & mm;
+    uint8_t *o = out + g.coup_off + plane * N + (int64_t)y * L;
+    *(uint2 *)(o + 8 * m) = make_uint2(perm(b1, b0, 0x06040200u), perm(b3, b2, 0x06040200u));
+    *(uint2 *)(o + half + 8 * m) = make_uint2(perm(b1, b0, 0x07050301u), perm(b3, b2, 0x07050301u));
+}
+
+__global__ void k_set_step(uint32_t *t_dev, uint32_t t) { *t_dev = t; }
+__global__ void k_advance_step(uint32_t *t_dev) { *t_dev += 1u; }
+
+}  // namespace
+
+bool uneven2d_edge_supported(int L) { return L >= 16 && L <= 256 && L % 16 == 0; }
+
+size_t uneven2d_lds_bytes(int L, int coup_mode) {
+    const size_t N = (size_t)L * L;
+    return coup_mode == 1 ? 3 * N : N;
+}
+
+// Couplings in LDS when spins and both planes fit next to each other.
+int uneven2d_coup_mode(int model, int L) {
+    if (model != SMC_EA) return 0;
+    return 3 * (size_t)L * L <= 150 * 1024 ? 1 : 2;
+}
+
+const void *uneven2d_kernel(int coup_mode) {
+    switch (coup_mode) {
+        case 0: return (const void *)k_uneven2d_sweep<0>;
+        case 1: return (const void *)k_uneven2d_sweep<1>;
+        default: return (const void *)k_uneven2d_sweep<2>;
+    }
+}
+
+hipError_t uneven2d_prepare_kernel(int coup_mode, size_t lds) {
+    return hipFuncSetAttribute(uneven2d_kernel(coup_mode), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+Uneven2dArgs make_uneven2d_args(int8_t *spins, const smc_inst *inst, const uint8_t *csplit, const int32_t *row_of_rep,
+                                const ThrRow *thr, int64_t *E, const uint32_t *t_dev, Key key) {
+    Uneven2dArgs a;
+    a.spins = spins;
+    a.inst = inst;
+    a.csplit = csplit;
+    a.row_of_rep = row_of_rep;
+    a.thr = thr;
+    a.E = E;
+    a.t_dev = t_dev;
+    a.key = key;
+    a.one2 = 0x00010001u;
+    a.four = 4u;
+    return a;
+}
+
+hipError_t launch_coup_split2d(const int8_t *coup, uint8_t *out, const smc_inst *samples, int n_samples,
+                               int64_t chunks_total, const int64_t *chunk_start, hipStream_t s) {
+    if (chunks_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coup_split2d, dim3((unsigned)((chunks_total + 255) / 256)), dim3(256), 0, s, coup, out,
+                       samples, n_samples, chunks_total, chunk_start);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(uint32_t *t_dev, uint32_t t, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, t_dev, t);
+    return hipGetLastError();
+}
+
+// ---- graph nodes ----
+hipError_t add_uneven2d_sweep_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
+                                   const Uneven2dArgs &a, const int32_t *work, int n_work, int L, int coup_mode,
+                                   int threads) {
+    Uneven2dArgs args = a;
+    const int32_t *w = work;
+    int edge = L;
+    void *params[] = {&args, &w, &edge};
+    hipKernelNodeParams p;
+    memset(&p, 0, sizeof p);
+    p.func = const_cast<void *>(uneven2d_kernel(coup_mode));
+    p.gridDim = dim3((unsigned)n_work);
+    p.blockDim = dim3((unsigned)threads);
+    p.sharedMemBytes = (unsigned)uneven2d_lds_bytes(L, coup_mode);
+    p.kernelParams = params;
+    p.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
+}
+
+hipError_t add_advance_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
+                            uint32_t *t_dev) {
+    uint32_t *tp = t_dev;
+    void *params[] = {&tp};
+    hipKernelNodeParams p;
+    memset(&p, 0, sizeof p);
+    p.func = (void *)k_advance_step;
+    p.gridDim = dim3(1);
+    p.blockDim = dim3(1);
+    p.kernelParams = params;
+    return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
+}
+
+hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int n_work, int L, int coup_mode,
+                                 int threads, hipStream_t s) {
+    const size_t lds = uneven2d_lds_bytes(L, coup_mode);
+    switch (coup_mode) {
+        case 0: hipLaunchKernelGGL(k_uneven2d_sweep<0>, dim3(n_work), dim3(threads), lds, s, a, work, L); break;
+        case 1: hipLaunchKernelGGL(k_uneven2d_sweep<1>, dim3(n_work), dim3(threads), lds, s, a, work, L); break;
+        default: hipLaunchKernelGGL(k_uneven2d_sweep<2>, dim3(n_work), dim3(threads), lds, s, a, work, L); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_step(uint32_t *t_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, s, t_dev);
+    return hipGetLastError();
+}
+
+}  // namespace smc

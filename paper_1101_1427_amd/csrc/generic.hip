@@ -2,6 +2,8 @@
 // dimension, Heisenberg renormalisation, measurements and the
 // parallel-tempering exchange.  The optimised kernels (lattice2d.hip,
 // pt3d.hip) produce the same results; these serve every shape.
+#include <string.h>
+
 #include "internal.hpp"
 
 namespace smc {
@@ -366,6 +368,7 @@ __global__ void k_pt_swap(SwapArgs a) {
 #pragma clang fp contract(off)
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.n_chains) return;
+    a.t = a.t_dev ? *a.t_dev : a.t;
     const int n = a.n_temps;
     const int base = a.beta_per_chain ? q * n : 0;
     int32_t *sot = a.slot_of_temp + (int64_t)q * n;
@@ -465,6 +468,19 @@ hipError_t launch_pt_prepare(const SwapArgs &a, const double *energy_in, hipStre
 hipError_t launch_pt_swap(const SwapArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_pt_swap, dim3((a.n_chains + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t add_pt_swap_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
+                            const SwapArgs &a) {
+    SwapArgs args = a;
+    void *params[] = {&args};
+    hipKernelNodeParams p;
+    memset(&p, 0, sizeof p);
+    p.func = (void *)k_pt_swap;
+    p.gridDim = dim3((unsigned)((a.n_chains + 255) / 256));
+    p.blockDim = dim3(256);
+    p.kernelParams = params;
+    return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
 }
 
 hipError_t launch_pt_finish(const SwapArgs &a, double *energy_out, hipStream_t s) {

@@ -52,6 +52,7 @@ struct SweepArgs {
 };
 
 struct SwapArgs {
+    const uint32_t *t_dev;     // step index in device memory, or nullptr: use t
     int n_chains, n_temps, beta_per_chain;
     const double *beta;        // device [rows][n_temps]
     int32_t *slot_of_temp;     // [n_chains][n_temps]
@@ -79,6 +80,39 @@ size_t pt3d_lds_bytes(int model, int n_temps);
 hipError_t launch_pt3d(int model, int8_t *spins, const int8_t *coup, int rep_per_sample, int n_chains, int n_temps,
                        int beta_per_chain, const double *beta, const ThrRow *thr, int32_t *slot_of_temp,
                        double *energy, unsigned long long *acc, Key key, uint32_t t0, int n_steps, hipStream_t s);
+
+// Uneven 2D batches: one workgroup per replica with the replica in LDS.
+struct Uneven2dArgs {
+    int8_t *spins;             // caller's spins (row-major int8 +-1 per replica)
+    const smc_inst *inst;      // device [n_rep]
+    const uint8_t *csplit;     // colour-split coupling planes at each sample's coup_off, or nullptr (Ising)
+    const int32_t *row_of_rep; // threshold row per replica; -1 leaves the replica unchanged
+    const ThrRow *thr;
+    int64_t *E;                // tracked energy per replica
+    const uint32_t *t_dev;     // step index (device), read by every sweep of the step
+    Key key;
+    uint32_t one2;  // 0x00010001 (opaque to the compiler)
+    uint32_t four;  // 4 (opaque trip count of the exact-decision loop)
+};
+bool uneven2d_edge_supported(int L);
+size_t uneven2d_lds_bytes(int L, int coup_mode);
+int uneven2d_coup_mode(int model, int L);
+hipError_t uneven2d_prepare_kernel(int coup_mode, size_t lds);
+Uneven2dArgs make_uneven2d_args(int8_t *spins, const smc_inst *inst, const uint8_t *csplit, const int32_t *row_of_rep,
+                                const ThrRow *thr, int64_t *E, const uint32_t *t_dev, Key key);
+hipError_t launch_coup_split2d(const int8_t *coup, uint8_t *out, const smc_inst *samples, int n_samples,
+                               int64_t chunks_total, const int64_t *chunk_start, hipStream_t s);
+hipError_t launch_set_step(uint32_t *t_dev, uint32_t t, hipStream_t s);
+hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int n_work, int L, int coup_mode,
+                                 int threads, hipStream_t s);
+hipError_t launch_advance_step(uint32_t *t_dev, hipStream_t s);
+hipError_t add_uneven2d_sweep_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
+                                   const Uneven2dArgs &a, const int32_t *work, int n_work, int L, int coup_mode,
+                                   int threads);
+hipError_t add_advance_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
+                            uint32_t *t_dev);
+hipError_t add_pt_swap_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
+                            const SwapArgs &a);
 
 // Measurement: partials of every replica, then a fixed-order final sum.
 hipError_t launch_measure(const Batch &b, const void *spins, const int8_t *coup, int max_L, double *energy,

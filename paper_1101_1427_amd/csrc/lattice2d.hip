@@ -102,14 +102,21 @@ __device__ __forceinline__ Row<C> load_row(const uint8_t *p) {
     return r;
 }
 
+// Rows are written once per sweep and read again only by the next sweep, so
+// the stores are non-temporal (streamed past the caches).
 template <int C>
 __device__ __forceinline__ void store_row(uint8_t *p, const Row<C> &r) {
+    typedef uint32_t v2 __attribute__((ext_vector_type(2)));
+    typedef uint32_t v4 __attribute__((ext_vector_type(4)));
     if constexpr (C == 1) {
-        *(uint2 *)p = make_uint2(r.d[0], r.d[1]);
+        const v2 x = {r.d[0], r.d[1]};
+        __builtin_nontemporal_store(x, (v2 *)p);
     } else {
 #pragma unroll
-        for (int i = 0; i < C / 2; ++i)
-            ((uint4 *)p)[i] = make_uint4(r.d[4 * i], r.d[4 * i + 1], r.d[4 * i + 2], r.d[4 * i + 3]);
+        for (int i = 0; i < C / 2; ++i) {
+            const v4 x = {r.d[4 * i], r.d[4 * i + 1], r.d[4 * i + 2], r.d[4 * i + 3]};
+            __builtin_nontemporal_store(x, (v4 *)p + i);
+        }
     }
 }
 
