@@ -24,7 +24,7 @@ BYTES_PER_FLIP = 2.0  # int8 spin read once and written once per sweep
 
 
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ("lattice2d.hip", "philox.hpp", "internal.hpp")
+KERNEL_SOURCES = ("lattice2d.hip", "lattice2d.hpp", "philox.hpp", "tables.hpp")
 
 
 def kernel_source_hash() -> str:
@@ -192,6 +192,136 @@ def cpu_baseline(cfg, seconds: float = 12.0):
                       f"{'/'.join(f'{b:.4f}' for b in cfg.betas)}, serial C oracle"}
 
 
+def _events():
+    import torch
+
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _timed(fn):
+    """GPU milliseconds of fn() between events on the current stream."""
+    import torch
+
+    e0, e1 = _events()
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def _pt_batch(S, model, dim, L, n_chains, n_temps, seed, rps=1, inst=None):
+    """Spins, couplings, energies and permutations of a tempering batch, on the device."""
+    import torch
+
+    n_rep = n_chains * n_temps
+    b = S.Batch(model, dim, L, n_rep, seed, rep_per_sample=rps, inst=inst)
+    spins = torch.zeros(b.spins_shape()[0], dtype=torch.int8, device="cuda")
+    coup = torch.zeros(b.coup_len(), dtype=torch.int8, device="cuda") if model == S.EA else None
+    S.spin_init(b, spins, coup)
+    E = torch.zeros(n_rep, dtype=torch.float64, device="cuda")
+    S.measure_energy_magnetisation(b, spins, E, couplings=coup)
+    sot = torch.arange(n_temps, dtype=torch.int32, device="cuda").repeat(n_chains)
+    return b, spins, coup, E, sot
+
+
+def tempering_ea3d(S, W, steps, per_inst_chains=16, per_inst_steps=50, per_step_steps=3):
+    """3D EA, L = 16, 512 samples x 2 replicas x 32 temperatures: the whole
+    batch in one call (one launch), against one call per chain and against
+    the generic path's per-step launches over the whole batch."""
+    import torch
+
+    cfg = W.ea3d_tempering(steps=steps)
+    nc, nt = cfg.n_chains, cfg.n_temps
+    rps = cfg.chains_per_sample * nt
+    b, spins, coup, E, sot = _pt_batch(S, S.EA, 3, cfg.L, nc, nt, cfg.seed, rps)
+    N = cfg.L ** 3
+    _, kernel = S.pt_plan(b, nc, nt, cfg.betas, cfg.steps)
+    S.pt_sweep_swap(b, nc, nt, cfg.betas, spins, sot, E, 0, 2, couplings=coup)  # warm-up
+    ms = _timed(lambda: S.pt_sweep_swap(b, nc, nt, cfg.betas, spins, sot, E, 2, cfg.steps, couplings=coup))
+    rate = cfg.steps * nc * nt / (ms * 1e-3)
+    # one call per chain: views of the chain's replicas and its sample's couplings
+    one = S.Batch(S.EA, 3, cfg.L, nt, cfg.seed, rep_per_sample=nt)
+
+    def per_chain():
+        for q in range(per_inst_chains):
+            sp = spins[q * nt * N:(q + 1) * nt * N]
+            cp = coup[(q * nt // rps) * 3 * N:(q * nt // rps + 1) * 3 * N]
+            S.pt_sweep_swap(one, 1, nt, cfg.betas, sp, sot[q * nt:(q + 1) * nt], E[q * nt:(q + 1) * nt], 0,
+                            per_inst_steps, couplings=cp)
+
+    per_chain()
+    ms_pi = _timed(per_chain)
+    rate_pi = per_inst_chains * per_inst_steps * nt / (ms_pi * 1e-3)
+    # the generic per-step launches (three per step) over the whole batch
+    os.environ["SPINMC_PT3D"] = "0"
+    try:
+        ms_ps = _timed(lambda: S.pt_sweep_swap(b, nc, nt, cfg.betas, spins, sot, E, 0, per_step_steps,
+                                               couplings=coup))
+    finally:
+        del os.environ["SPINMC_PT3D"]
+    rate_ps = per_step_steps * nc * nt / (ms_ps * 1e-3)
+    del spins, coup, E, sot
+    torch.cuda.empty_cache()
+    return {"workload": f"3D +-J EA L=16, {cfg.n_chains // cfg.chains_per_sample} samples x "
+                        f"{cfg.chains_per_sample} replicas x {nt} temperatures (T geometric 0.8..2.0), "
+                        f"{cfg.steps} steps of sweep + exchange",
+            "kernel": kernel, "steps": cfg.steps, "ms": round(ms, 3),
+            "replica_sweeps_per_s": round(rate, 1), "ns_per_flip": round(1e9 / (rate * N), 6),
+            "per_instance": {"replica_sweeps_per_s": round(rate_pi, 1),
+                             "sample": f"{per_inst_chains} chains, {per_inst_steps} steps, one call per chain"},
+            "speedup_vs_per_instance": round(rate / rate_pi, 2),
+            "per_step_launches": {"replica_sweeps_per_s": round(rate_ps, 1),
+                                  "sample": f"whole batch, {per_step_steps} steps, generic kernels"},
+            "speedup_vs_per_step_launches": round(rate / rate_ps, 2)}
+
+
+def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):
+    """Uneven 2D EA batch, 4096 instances x 16 temperatures, edges from
+    {32, ..., 256}: the batch in one call (a graph of steps), against one call
+    per instance on a sample of instances (weighted to the batch's edge mix)."""
+    import numpy as np
+    import torch
+
+    cfg = W.ea2d_uneven(steps=steps)
+    nc, nt = cfg.n_chains, cfg.n_temps
+    inst = W.uneven_table(2, cfg.sizes, nt, S.EA)
+    b, spins, coup, E, sot = _pt_batch(S, S.EA, 2, 0, nc, nt, cfg.seed, inst=inst)
+    sites = int(sum(int(r[0]) ** 2 for r in inst))
+    _, kernel = S.pt_plan(b, nc, nt, cfg.betas, cfg.steps)
+    S.pt_sweep_swap(b, nc, nt, cfg.betas, spins, sot, E, 0, cfg.steps, couplings=coup)  # builds the graph
+    ms = _timed(lambda: S.pt_sweep_swap(b, nc, nt, cfg.betas, spins, sot, E, cfg.steps, cfg.steps, couplings=coup))
+    rate = cfg.steps * nc * nt / (ms * 1e-3)
+    # one call per instance, sampled evenly over the batch
+    picks = np.linspace(0, nc - 1, per_inst_chains).astype(int)
+
+    def per_instance():
+        for q in picks:
+            L = int(cfg.sizes[q])
+            N = L * L
+            so, co = int(inst[q * nt][2]), int(inst[q * nt][3])
+            one = S.Batch(S.EA, 2, L, nt, cfg.seed, rep_per_sample=nt)
+            S.pt_sweep_swap(one, 1, nt, cfg.betas, spins[so:so + nt * N], sot[q * nt:(q + 1) * nt],
+                            E[q * nt:(q + 1) * nt], 0, per_inst_steps, couplings=coup[co:co + 2 * N])
+
+    per_instance()
+    ms_pi = _timed(per_instance)
+    # time per replica-sweep of the sample, scaled to the batch's mean lattice size
+    sample_sites = sum(int(cfg.sizes[q]) ** 2 for q in picks) * nt
+    rate_pi_sites = per_inst_steps * sample_sites / (ms_pi * 1e-3)
+    rate_pi = rate_pi_sites / (sites / (nc * nt))
+    del spins, coup, E, sot
+    torch.cuda.empty_cache()
+    return {"workload": f"uneven 2D +-J EA, {nc} instances (L from {{32,48,64,96,128,192,256}}) x {nt} "
+                        f"temperatures (T geometric 0.5..2.0), {cfg.steps} steps of sweep + exchange",
+            "kernel": kernel, "steps": cfg.steps, "ms": round(ms, 3),
+            "replica_sweeps_per_s": round(rate, 1), "ns_per_flip": round(ms * 1e6 / (cfg.steps * sites), 6),
+            "per_instance": {"replica_sweeps_per_s": round(rate_pi, 1),
+                             "sample": f"{per_inst_chains} instances spread over the batch, {per_inst_steps} "
+                                       "steps, one call per instance, rate scaled by lattice size"},
+            "speedup_vs_per_instance": round(rate / rate_pi, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +329,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--L", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tempering", action="store_true", help="skip the parallel-tempering measurements")
+    ap.add_argument("--pt3d-steps", type=int, default=10_000)
+    ap.add_argument("--uneven-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter scale for the traffic figure)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
@@ -298,6 +431,9 @@ def main():
                      "conversion_us_per_call": round(conversion_ms * 1e3, 3)},
         "wall_s": round(wall, 4),
     }
+    if not args.no_tempering:
+        out["tempering"] = {"ea3d_L16": tempering_ea3d(S, W, args.pt3d_steps),
+                            "ea2d_uneven": tempering_ea2d_uneven(S, W, args.uneven_steps)}
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg)
         out["cpu_baseline"] = cb

@@ -39,6 +39,17 @@
  *   element (r / rep_per_sample) * d * N.  Uneven batch (desc.L == 0): the
  *   HOST table desc.inst[n_rep] gives each replica's edge, sample and offsets.
  * - Return value: SMC_OK (0) or a negative smc_status.
+ * - Execution paths.  Uniform 2D Ising batches with L a power of two in
+ *   [1024, 16384] sweep on a colour-split copy of the lattice in one launch
+ *   per sweep; 3D edge-16 tempering runs all steps of a call in one launch;
+ *   2D tempering with edges in {16, 32, ..., 256} runs one workgroup per
+ *   replica per step (a graph of steps); everything else takes generic
+ *   per-site kernels.  All paths give identical results.  Environment
+ *   variables for comparisons and tuning (read at each call):
+ *   SPINMC_PT3D=0 and SPINMC_UNEVEN2D=0 send tempering to the generic
+ *   kernels; SPINMC_L2D_CHUNKS (1 or 2), SPINMC_L2D_H (band height, a
+ *   multiple of 4) and SPINMC_L2D_PAD (row padding in bytes) set the launch
+ *   shape of the 2D Ising sweep.
  */
 #ifndef SPINMC_H
 #define SPINMC_H

@@ -167,8 +167,13 @@ ThrRow threshold_row(double beta, int dim) {
 
 // The chain-resident tempering kernel serves 3D edge-16 batches of at most
 // 32 temperatures with 16-byte aligned spins and thresholds below 2^32.
+bool pt3d_enabled() {
+    const char *env = getenv("SPINMC_PT3D");
+    return !(env && env[0] == '0');
+}
+
 bool use_pt3d(const smc_desc *d, const smc_pt_desc *pt, const void *spins, const std::vector<ThrRow> &rows) {
-    if (!pt3d_supported(d, pt->n_temps)) return false;
+    if (!pt3d_enabled() || !pt3d_supported(d, pt->n_temps)) return false;
     if (((uintptr_t)spins & 15u) != 0) return false;
     for (const ThrRow &r : rows)
         if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu || r.m[3].x > 0xFFFFu) return false;
@@ -285,7 +290,7 @@ int upload_inst(StreamCtx &c, hipStream_t s, const smc_desc *d, Plan &plan) {
 // go to the per-replica LDS kernel; the replicas of one edge form a class
 // with its own launch shape.
 struct EdgeClass {
-    int L = 0, mode = 0, threads = 0;
+    int L = 0, threads = 0;
     int32_t first = 0, count = 0;  // range of the work list
 };
 
@@ -346,13 +351,12 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
     for (auto &kv : by_edge) {
         EdgeClass e;
         e.L = kv.first;
-        e.mode = uneven2d_coup_mode(desc->model, e.L);
         e.threads = uneven2d_threads(e.L);
         e.first = (int32_t)work.size();
         e.count = (int32_t)kv.second.size();
         work.insert(work.end(), kv.second.begin(), kv.second.end());
         classes.push_back(e);
-        SMC_HIP(uneven2d_prepare_kernel(e.mode, uneven2d_lds_bytes(e.L, e.mode)));
+        SMC_HIP(uneven2d_prepare_kernel(desc->model == SMC_EA, e.L));
     }
     void *work_dev = nullptr;
     if ((rc = upload(c, s, kWork, work.data(), sizeof(int32_t) * work.size(), &work_dev))) return rc;
@@ -392,6 +396,7 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
     const Uneven2dArgs a = make_uneven2d_args((int8_t *)spins, (const smc_inst *)inst_dev, csplit, sw.row_of_rep,
                                               thr, sw.E, t_dev, make_key(desc->seed));
     const int32_t *wl = (const int32_t *)work_dev;
+    const bool ea = desc->model == SMC_EA;
 
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     SMC_HIP(hipStreamIsCapturing(s, &cap));
@@ -399,7 +404,7 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
         // inside a caller's capture (or a few steps): plain launches in step order
         for (int32_t k = 0; k < n_steps; ++k) {
             for (const EdgeClass &e : classes)
-                SMC_HIP(launch_uneven2d_sweep(a, wl + e.first, e.count, e.L, e.mode, e.threads, s));
+                SMC_HIP(launch_uneven2d_sweep(a, wl + e.first, e.count, e.L, ea, e.threads, s));
             SMC_HIP(launch_pt_swap(sw, s));
             SMC_HIP(launch_advance_step(t_dev, s));
         }
@@ -420,7 +425,6 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
                                          (uint64_t)sw.beta_per_chain};
             for (const EdgeClass &e : classes) {
                 sig.push_back((uint64_t)e.L);
-                sig.push_back((uint64_t)e.mode);
                 sig.push_back((uint64_t)e.threads);
                 sig.push_back((uint64_t)e.first);
                 sig.push_back((uint64_t)e.count);
@@ -441,7 +445,7 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
                     for (size_t q = 0; q < classes.size() && e == hipSuccess; ++q) {
                         const EdgeClass &ec = classes[q];
                         e = add_uneven2d_sweep_node(g, &sweeps[q], prev ? &prev : nullptr, prev ? 1 : 0, a,
-                                                    wl + ec.first, ec.count, ec.L, ec.mode, ec.threads);
+                                                    wl + ec.first, ec.count, ec.L, ea, ec.threads);
                     }
                     hipGraphNode_t swap = nullptr;
                     if (e == hipSuccess) e = add_pt_swap_node(g, &swap, sweeps.data(), sweeps.size(), sw);
@@ -594,7 +598,7 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
     if (n_steps < 0) return fail(SMC_EINVAL, "n_steps must be >= 0");
     if (pt->n_temps < 2 || !pt->beta) return fail(SMC_EINVAL, "need n_temps >= 2 and beta");
     const int rows_n = pt->beta_per_chain ? pt->n_chains : 1;
-    bool fits = pt3d_supported(desc, pt->n_temps);
+    bool fits = pt3d_enabled() && pt3d_supported(desc, pt->n_temps);
     for (int64_t k = 0; fits && k < (int64_t)rows_n * pt->n_temps; ++k) {
         const ThrRow r = threshold_row(pt->beta[k], desc->dim);
         fits = r.m[1].x <= 0xFFFFu && r.m[2].x <= 0xFFFFu && r.m[3].x <= 0xFFFFu;

@@ -4,8 +4,10 @@
 // A sweep of the batch is one launch per lattice size: one workgroup per
 // replica holds the replica in LDS, runs colour 0 then colour 1 and writes it
 // back, tracking the replica's energy.  Couplings are read from a
-// colour-split copy made once per call (in LDS next to the spins when they
-// fit, else from the L2-resident copy).  Results equal those of the generic
+// colour-split copy made once per call; the replicas of one instance run
+// next to each other on one XCD, so the copy is served from its L2 (keeping
+// the couplings out of LDS leaves room for more workgroups per CU, which
+// measured faster than staging them).  Results equal those of the generic
 // per-site kernels step for step.
 //
 // LDS layout of a replica of edge L (L^2 bytes): row y holds the L/2 sites
@@ -152,9 +154,8 @@ __device__ __forceinline__ void group(uint8_t *S, const uint8_t *X, const uint8_
     nsum = __builtin_amdgcn_sad_u8(n0 & m0, 0u, __builtin_amdgcn_sad_u8(n1 & m1, 0u, nsum));
 }
 
-// One workgroup per replica of the work list; COUP: 0 Ising, 1 couplings in
-// LDS, 2 couplings read from the global copy.
-template <int COUP>
+// One workgroup per replica of the work list (EA: with couplings).
+template <bool EA>
 __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, const int32_t *work, int L) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ long long red[kMaxThreads / 64];
@@ -171,22 +172,26 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
     const uint8_t *X = nullptr, *Yp = nullptr;
     int8_t *gs = a.spins + g.spin_off;
 
+    // (row, 16-byte piece) of index i = tid + j*nt, advanced without divisions
+    const int G = L >> 4;  // pieces per row = draw groups per row and colour
+    const int dy = nt / G, dk = nt % G;
+    const int y0 = tid / G, k0 = tid % G;
+
     // row-major +-1 -> split 0/1 bytes
-    for (int i = tid; i < N / 16; i += nt) {
-        const int y = i / (L >> 4), m = i % (L >> 4);
+    for (int i = tid, y = y0, m = k0; i < N / 16; i += nt) {
         const uint4 v = *(const uint4 *)(gs + (int64_t)i * 16);
         const uint32_t mm = 0x01010101u;
         const uint32_t b0 = (v.x >> 1) & mm, b1 = (v.y >> 1) & mm, b2 = (v.z >> 1) & mm, b3 = (v.w >> 1) & mm;
         *(uint2 *)(S + y * L + 8 * m) = make_uint2(perm(b1, b0, 0x06040200u), perm(b3, b2, 0x06040200u));
         *(uint2 *)(S + y * L + half + 8 * m) = make_uint2(perm(b1, b0, 0x07050301u), perm(b3, b2, 0x07050301u));
+        y += dy;
+        m += dk;
+        if (m >= G) {
+            m -= G;
+            ++y;
+        }
     }
-    if constexpr (COUP == 1) {
-        uint8_t *C = smem + N;
-        const uint4 *src = (const uint4 *)(a.csplit + g.coup_off);
-        for (int i = tid; i < 2 * N / 16; i += nt) ((uint4 *)C)[i] = src[i];
-        X = C;
-        Yp = C + N;
-    } else if constexpr (COUP == 2) {
+    if constexpr (EA) {
         X = a.csplit + g.coup_off;
         Yp = X + N;
     }
@@ -200,22 +205,32 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
 #pragma unroll 1
     for (int c = 0; c < 2; ++c) {
 #pragma unroll 1
-        for (int q = tid; q < groups; q += nt) {
-            const int y = q / (L >> 4), k = q % (L >> 4);
-            group<COUP != 0>(S, X, Yp, L, y, k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+        for (int q = tid, y = y0, k = k0; q < groups; q += nt) {
+            group<EA>(S, X, Yp, L, y, k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+            y += dy;
+            k += dk;
+            if (k >= G) {
+                k -= G;
+                ++y;
+            }
         }
         __syncthreads();
     }
 
     // split 0/1 bytes -> row-major +-1
-    for (int i = tid; i < N / 16; i += nt) {
-        const int y = i / (L >> 4), m = i % (L >> 4);
+    for (int i = tid, y = y0, m = k0; i < N / 16; i += nt) {
         const uint2 e = *(const uint2 *)(S + y * L + 8 * m);
         const uint2 o = *(const uint2 *)(S + y * L + half + 8 * m);
         const uint32_t w0 = perm(o.x, e.x, 0x05010400u), w1 = perm(o.x, e.x, 0x07030602u);
         const uint32_t w2 = perm(o.y, e.y, 0x05010400u), w3 = perm(o.y, e.y, 0x07030602u);
         auto pm1 = [](uint32_t v) { return ((v << 8) - v) | 0x01010101u; };
         *(uint4 *)(gs + (int64_t)i * 16) = make_uint4(pm1(w0), pm1(w1), pm1(w2), pm1(w3));
+        y += dy;
+        m += dk;
+        if (m >= G) {
+            m -= G;
+            ++y;
+        }
     }
     // energy: sum over flips of 4 (2 - n)
     long long v = 2ll * (long long)cnt - (long long)nsum;
@@ -264,27 +279,15 @@ __global__ void k_advance_step(uint32_t *t_dev) { *t_dev += 1u; }
 
 bool uneven2d_edge_supported(int L) { return L >= 16 && L <= 256 && L % 16 == 0; }
 
-size_t uneven2d_lds_bytes(int L, int coup_mode) {
-    const size_t N = (size_t)L * L;
-    return coup_mode == 1 ? 3 * N : N;
+size_t uneven2d_lds_bytes(int L) { return (size_t)L * L; }
+
+const void *uneven2d_kernel(bool ea) {
+    return ea ? (const void *)k_uneven2d_sweep<true> : (const void *)k_uneven2d_sweep<false>;
 }
 
-// Couplings in LDS when spins and both planes fit next to each other.
-int uneven2d_coup_mode(int model, int L) {
-    if (model != SMC_EA) return 0;
-    return 3 * (size_t)L * L <= 150 * 1024 ? 1 : 2;
-}
-
-const void *uneven2d_kernel(int coup_mode) {
-    switch (coup_mode) {
-        case 0: return (const void *)k_uneven2d_sweep<0>;
-        case 1: return (const void *)k_uneven2d_sweep<1>;
-        default: return (const void *)k_uneven2d_sweep<2>;
-    }
-}
-
-hipError_t uneven2d_prepare_kernel(int coup_mode, size_t lds) {
-    return hipFuncSetAttribute(uneven2d_kernel(coup_mode), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+hipError_t uneven2d_prepare_kernel(bool ea, int L) {
+    return hipFuncSetAttribute(uneven2d_kernel(ea), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)uneven2d_lds_bytes(L));
 }
 
 Uneven2dArgs make_uneven2d_args(int8_t *spins, const smc_inst *inst, const uint8_t *csplit, const int32_t *row_of_rep,
@@ -318,7 +321,7 @@ hipError_t launch_set_step(uint32_t *t_dev, uint32_t t, hipStream_t s) {
 
 // ---- graph nodes ----
 hipError_t add_uneven2d_sweep_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
-                                   const Uneven2dArgs &a, const int32_t *work, int n_work, int L, int coup_mode,
+                                   const Uneven2dArgs &a, const int32_t *work, int n_work, int L, bool ea,
                                    int threads) {
     Uneven2dArgs args = a;
     const int32_t *w = work;
@@ -326,10 +329,10 @@ hipError_t add_uneven2d_sweep_node(hipGraph_t g, hipGraphNode_t *node, const hip
     void *params[] = {&args, &w, &edge};
     hipKernelNodeParams p;
     memset(&p, 0, sizeof p);
-    p.func = const_cast<void *>(uneven2d_kernel(coup_mode));
+    p.func = const_cast<void *>(uneven2d_kernel(ea));
     p.gridDim = dim3((unsigned)n_work);
     p.blockDim = dim3((unsigned)threads);
-    p.sharedMemBytes = (unsigned)uneven2d_lds_bytes(L, coup_mode);
+    p.sharedMemBytes = (unsigned)uneven2d_lds_bytes(L);
     p.kernelParams = params;
     p.extra = nullptr;
     return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
@@ -348,14 +351,13 @@ hipError_t add_advance_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNo
     return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
 }
 
-hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int n_work, int L, int coup_mode,
-                                 int threads, hipStream_t s) {
-    const size_t lds = uneven2d_lds_bytes(L, coup_mode);
-    switch (coup_mode) {
-        case 0: hipLaunchKernelGGL(k_uneven2d_sweep<0>, dim3(n_work), dim3(threads), lds, s, a, work, L); break;
-        case 1: hipLaunchKernelGGL(k_uneven2d_sweep<1>, dim3(n_work), dim3(threads), lds, s, a, work, L); break;
-        default: hipLaunchKernelGGL(k_uneven2d_sweep<2>, dim3(n_work), dim3(threads), lds, s, a, work, L); break;
-    }
+hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int n_work, int L, bool ea, int threads,
+                                 hipStream_t s) {
+    const size_t lds = uneven2d_lds_bytes(L);
+    if (ea)
+        hipLaunchKernelGGL(k_uneven2d_sweep<true>, dim3(n_work), dim3(threads), lds, s, a, work, L);
+    else
+        hipLaunchKernelGGL(k_uneven2d_sweep<false>, dim3(n_work), dim3(threads), lds, s, a, work, L);
     return hipGetLastError();
 }
 

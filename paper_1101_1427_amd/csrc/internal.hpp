@@ -4,15 +4,11 @@
 #include <stdint.h>
 
 #include "../../include/spinmc.h"
+#include "lattice2d.hpp"
 #include "philox.hpp"
+#include "tables.hpp"
 
 namespace smc {
-
-// One row of the acceptance table: entry m (1..3) is the threshold of
-// Delta E = 4m split as (hi, lo); entry 0 is unused.
-struct ThrRow {
-    uint2 m[4];
-};
 
 // Geometry of a batch as the kernels see it.  Uniform batches use (L, N,
 // spin_stride, coup_stride, rep_per_sample); uneven ones the inst table.
@@ -95,19 +91,18 @@ struct Uneven2dArgs {
     uint32_t four;  // 4 (opaque trip count of the exact-decision loop)
 };
 bool uneven2d_edge_supported(int L);
-size_t uneven2d_lds_bytes(int L, int coup_mode);
-int uneven2d_coup_mode(int model, int L);
-hipError_t uneven2d_prepare_kernel(int coup_mode, size_t lds);
+size_t uneven2d_lds_bytes(int L);
+hipError_t uneven2d_prepare_kernel(bool ea, int L);
 Uneven2dArgs make_uneven2d_args(int8_t *spins, const smc_inst *inst, const uint8_t *csplit, const int32_t *row_of_rep,
                                 const ThrRow *thr, int64_t *E, const uint32_t *t_dev, Key key);
 hipError_t launch_coup_split2d(const int8_t *coup, uint8_t *out, const smc_inst *samples, int n_samples,
                                int64_t chunks_total, const int64_t *chunk_start, hipStream_t s);
 hipError_t launch_set_step(uint32_t *t_dev, uint32_t t, hipStream_t s);
-hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int n_work, int L, int coup_mode,
-                                 int threads, hipStream_t s);
+hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int n_work, int L, bool ea, int threads,
+                                 hipStream_t s);
 hipError_t launch_advance_step(uint32_t *t_dev, hipStream_t s);
 hipError_t add_uneven2d_sweep_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
-                                   const Uneven2dArgs &a, const int32_t *work, int n_work, int L, int coup_mode,
+                                   const Uneven2dArgs &a, const int32_t *work, int n_work, int L, bool ea,
                                    int threads);
 hipError_t add_advance_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
                             uint32_t *t_dev);
@@ -118,14 +113,6 @@ hipError_t add_pt_swap_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNo
 hipError_t launch_measure(const Batch &b, const void *spins, const int8_t *coup, int max_L, double *energy,
                           double *magnet, void *scratch, size_t scratch_bytes, hipStream_t s);
 size_t measure_scratch_bytes(const Batch &b, int max_L);
-
-// Large 2D Ising lattices on the colour-split layout (lattice2d.hip).
-bool lattice2d_supported(int L);
-size_t lattice2d_split_bytes(int L);  // bytes of one replica in the split layout
-hipError_t launch_to_split(const int8_t *src, uint8_t *dst, int L, int n_rep, hipStream_t s);
-hipError_t launch_from_split(const uint8_t *src, int8_t *dst, int L, int n_rep, hipStream_t s);
-hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_rep, const ThrRow *thr, int64_t *dE,
-                                Key key, uint32_t t, hipStream_t s);
 
 // Parallel tempering helpers.
 hipError_t launch_pt_prepare(const SwapArgs &a, const double *energy_in, hipStream_t s);

@@ -27,7 +27,7 @@
 // that draws the 16-bit tail.
 #include <stdlib.h>
 
-#include "internal.hpp"
+#include "lattice2d.hpp"
 
 namespace smc {
 namespace {

@@ -2,6 +2,7 @@
 import numpy as np
 
 from oracle import oracle as O
+from workloads import uneven_table  # noqa: F401  (re-exported for the tests)
 
 ISING, EA, HEIS = 0, 1, 2
 
@@ -42,17 +43,3 @@ def init_uneven(model, dim, inst, seed):
         if coup is not None:
             coup[co:co + dim * N] = O.init_couplings(dim, L, seed, q)
     return spins, coup
-
-
-def uneven_table(dim, sizes, reps_per_instance, model=EA):
-    """Rows (L, sample, spin_off, coup_off): instance k has reps_per_instance
-    replicas sharing sample k; spins and couplings packed back to back."""
-    rows = []
-    so = co = 0
-    for k, L in enumerate(sizes):
-        N = int(L) ** dim
-        for _ in range(reps_per_instance):
-            rows.append((int(L), k, so, co))
-            so += N
-        co += dim * N if model == EA else 0
-    return np.array(rows, np.int64)

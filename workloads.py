@@ -101,3 +101,17 @@ def ea2d_uneven(n_instances: int = 4096, steps: int = 5000) -> Tempering:
     return Tempering("ea2d_uneven_pt", MODEL_EA, 2, 0, n_chains=n_instances, n_temps=16,
                      betas=geometric_ladder(0.5, 2.0, 16), steps=steps, seed=seed,
                      chains_per_sample=1, sizes=uneven_sizes(n_instances, seed))
+
+
+def uneven_table(dim, sizes, reps_per_instance, model=MODEL_EA):
+    """Rows (L, sample, spin_off, coup_off): instance k has reps_per_instance
+    replicas sharing sample k; spins and couplings packed back to back."""
+    rows = []
+    so = co = 0
+    for k, L in enumerate(sizes):
+        N = int(L) ** dim
+        for _ in range(reps_per_instance):
+            rows.append((int(L), k, so, co))
+            so += N
+        co += dim * N if model == MODEL_EA else 0
+    return np.array(rows, np.int64)
