@@ -322,6 +322,39 @@ def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):
             "speedup_vs_per_instance": round(rate / rate_pi, 2)}
 
 
+def heisenberg3d(S, W, sweeps):
+    """3D Heisenberg 256^3 at beta = 0.693, float32 spins, renormalised every
+    16 sweeps: ns per attempted flip and the HBM roof at 24 B/flip (float32
+    3-vector read and written once per sweep)."""
+    import torch
+
+    cfg = W.heisenberg_3d()
+    L = cfg.L
+    N = L ** 3
+    b = S.Batch(S.HEISENBERG, 3, L, 1, cfg.seed, renorm_every=cfg.renorm_every)
+    spins = torch.zeros(3 * N, dtype=torch.float32, device="cuda")
+    S.spin_init(b, spins)
+    S.metropolis_sweep(b, spins, [cfg.betas[0]], 0, 2)
+    S.kernel_timing_read()
+    S.kernel_timing_enable(True)
+    ms = _timed(lambda: S.metropolis_sweep(b, spins, cfg.betas, 2, sweeps))
+    kernel_ms, launches = S.kernel_timing_read()
+    S.kernel_timing_enable(False)
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    S.measure_energy_magnetisation(b, spins, E)
+    torch.cuda.synchronize()
+    _, kernel = S.sweep_plan(b)
+    ps = ms * 1e9 / (sweeps * N)
+    achieved = 24.0 * N * sweeps / (kernel_ms * 1e-3) / 1e9
+    del spins
+    torch.cuda.empty_cache()
+    return {"workload": f"3D Heisenberg {L}^3, beta={cfg.betas[0]}, float32 spins, renormalised every "
+                        f"{cfg.renorm_every} sweeps, {sweeps} sweeps",
+            "kernel": kernel, "sweeps": sweeps, "ms": round(ms, 3), "ns_per_flip": round(ps / 1e3, 6),
+            "energy_per_spin": round(float(E.item()) / N, 6),
+            "hbm_roof_at_24B_per_flip": {"achieved_GBps": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +365,7 @@ def main():
     ap.add_argument("--no-tempering", action="store_true", help="skip the parallel-tempering measurements")
     ap.add_argument("--pt3d-steps", type=int, default=10_000)
     ap.add_argument("--uneven-steps", type=int, default=100)
+    ap.add_argument("--heis-sweeps", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter scale for the traffic figure)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
@@ -432,6 +466,7 @@ def main():
         "wall_s": round(wall, 4),
     }
     if not args.no_tempering:
+        out["heisenberg"] = heisenberg3d(S, W, args.heis_sweeps)
         out["tempering"] = {"ea3d_L16": tempering_ea3d(S, W, args.pt3d_steps),
                             "ea2d_uneven": tempering_ea2d_uneven(S, W, args.uneven_steps)}
     if not args.no_cpu_baseline:

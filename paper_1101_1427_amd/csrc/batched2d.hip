@@ -24,6 +24,7 @@ namespace smc {
 namespace {
 
 constexpr int kMaxThreads = 512;
+constexpr int kBatch = 8;  // 16-byte spin loads in flight per thread while staging a replica
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
     return __builtin_amdgcn_perm(hi, lo, sel);
@@ -74,30 +75,62 @@ __device__ __forceinline__ uint32_t decide4(uint32_t n, uint32_t wa, uint32_t wb
 // One colour-c group: the eight colour-c sites of row y with in-array
 // indices 8k .. 8k+7 (one Philox draw).  S: spins, X/Y: coupling planes
 // (either in LDS or in global memory), all with the row layout above.
-template <bool EA>
-__device__ __forceinline__ void group(uint8_t *S, const uint8_t *X, const uint8_t *Yp, int L, int y, int k, int c,
-                                      uint32_t t, uint32_t r, Key key, Lut2 K, const ThrRow &th, uint32_t one2,
-                                      uint32_t four, uint32_t &cnt, uint32_t &nsum) {
+// Offsets (in a row-layout plane) of the words a colour-c group reads.
+struct GroupAt {
+    int own, oth, ext, below, above;
+};
+
+__device__ __forceinline__ GroupAt group_at(int L, int y, int k, int c) {
     const int half = L >> 1;
     const int a = (y & 1) == c ? 0 : 1;
     const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-    const int o_own = y * L + a * half + 8 * k;
-    const int o_oth = y * L + (1 - a) * half + 8 * k;
+    GroupAt o;
+    o.own = y * L + a * half + 8 * k;
+    o.oth = y * L + (1 - a) * half + 8 * k;
     // the extra word of the other array: the word before (a = 0) or after (a = 1), wrapping in the row
-    const int o_ext = y * L + (1 - a) * half + (a == 0 ? (k == 0 ? half - 4 : 8 * k - 4) : (8 * k + 8 == half ? 0 : 8 * k + 8));
-    const uint2 own = *(const uint2 *)(S + o_own);
-    const uint2 oth = *(const uint2 *)(S + o_oth);
-    const uint32_t ext = *(const uint32_t *)(S + o_ext);
-    const uint2 vm = *(const uint2 *)(S + ym * L + a * half + 8 * k);
-    const uint2 vp = *(const uint2 *)(S + yp * L + a * half + 8 * k);
+    o.ext = y * L + (1 - a) * half + (a == 0 ? (k == 0 ? half - 4 : 8 * k - 4) : (8 * k + 8 == half ? 0 : 8 * k + 8));
+    o.below = ym * L + a * half + 8 * k;
+    o.above = yp * L + a * half + 8 * k;
+    return o;
+}
+
+// Coupling bytes of a group: +x bonds of the own sites (xo), of the other
+// array (xt, with its extra word xe), +y bonds of the own sites (yo) and of
+// the sites below (ym).
+struct GroupCoup {
+    uint2 xo, xt, yo, ym;
+    uint32_t xe;
+};
+
+__device__ __forceinline__ GroupCoup group_coup(const uint8_t *X, const uint8_t *Yp, const GroupAt &o) {
+    GroupCoup j;
+    j.xo = *(const uint2 *)(X + o.own);
+    j.xt = *(const uint2 *)(X + o.oth);
+    j.xe = *(const uint32_t *)(X + o.ext);
+    j.yo = *(const uint2 *)(Yp + o.own);
+    j.ym = *(const uint2 *)(Yp + o.below);
+    return j;
+}
+
+template <bool EA>
+__device__ __forceinline__ void group(uint8_t *S, const GroupAt &o, const GroupCoup &J, int L, int y, int k, int c,
+                                      uint32_t t, uint32_t r, Key key, Lut2 K, const ThrRow &th, uint32_t one2,
+                                      uint32_t four, uint32_t &cnt, uint32_t &nsum) {
+    const int a = (y & 1) == c ? 0 : 1;
+    const int o_own = o.own;
+    const uint2 own = *(const uint2 *)(S + o.own);
+    const uint2 oth = *(const uint2 *)(S + o.oth);
+    const uint32_t ext = *(const uint32_t *)(S + o.ext);
+    const uint2 vm = *(const uint2 *)(S + o.below);
+    const uint2 vp = *(const uint2 *)(S + o.above);
     uint2 jxo = make_uint2(0u, 0u), jxt = jxo, jyo = jxo, jym = jxo;
     uint32_t jxe = 0u;
     if constexpr (EA) {
-        jxo = *(const uint2 *)(X + o_own);                        // +x bonds of the own sites
-        jxt = *(const uint2 *)(X + o_oth);                        // +x bonds of the other array
-        jxe = *(const uint32_t *)(X + o_ext);
-        jyo = *(const uint2 *)(Yp + o_own);                       // +y bonds of the own sites
-        jym = *(const uint2 *)(Yp + ym * L + a * half + 8 * k);   // +y bonds of the sites below
+        jxo = J.xo;
+        jxt = J.xt;
+        jxe = J.xe;
+        jyo = J.yo;
+        jym = J.ym;
     }
     uint32_t xm0, xm1, xp0, xp1;  // unsatisfied flags of the -x and +x bonds
     if (a == 0) {
@@ -177,18 +210,31 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
     const int dy = nt / G, dk = nt % G;
     const int y0 = tid / G, k0 = tid % G;
 
-    // row-major +-1 -> split 0/1 bytes
-    for (int i = tid, y = y0, m = k0; i < N / 16; i += nt) {
-        const uint4 v = *(const uint4 *)(gs + (int64_t)i * 16);
-        const uint32_t mm = 0x01010101u;
-        const uint32_t b0 = (v.x >> 1) & mm, b1 = (v.y >> 1) & mm, b2 = (v.z >> 1) & mm, b3 = (v.w >> 1) & mm;
-        *(uint2 *)(S + y * L + 8 * m) = make_uint2(perm(b1, b0, 0x06040200u), perm(b3, b2, 0x06040200u));
-        *(uint2 *)(S + y * L + half + 8 * m) = make_uint2(perm(b1, b0, 0x07050301u), perm(b3, b2, 0x07050301u));
-        y += dy;
-        m += dk;
-        if (m >= G) {
-            m -= G;
-            ++y;
+    // row-major +-1 -> split 0/1 bytes; up to kBatch 16-byte loads per
+    // thread are in flight before the first is converted
+    for (int i0 = tid, y = y0, m = k0; i0 < N / 16; i0 += kBatch * nt) {
+        uint4 v[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int i = i0 + j * nt;
+            if (i < N / 16) v[j] = *(const uint4 *)(gs + (int64_t)i * 16);
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            if (i0 + j * nt < N / 16) {
+                const uint32_t mm = 0x01010101u;
+                const uint32_t b0 = (v[j].x >> 1) & mm, b1 = (v[j].y >> 1) & mm, b2 = (v[j].z >> 1) & mm,
+                               b3 = (v[j].w >> 1) & mm;
+                *(uint2 *)(S + y * L + 8 * m) = make_uint2(perm(b1, b0, 0x06040200u), perm(b3, b2, 0x06040200u));
+                *(uint2 *)(S + y * L + half + 8 * m) =
+                    make_uint2(perm(b1, b0, 0x07050301u), perm(b3, b2, 0x07050301u));
+            }
+            y += dy;
+            m += dk;
+            if (m >= G) {
+                m -= G;
+                ++y;
+            }
         }
     }
     if constexpr (EA) {
@@ -204,15 +250,25 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
     const int groups = N >> 4;  // per colour
 #pragma unroll 1
     for (int c = 0; c < 2; ++c) {
+        // the couplings of the next group are requested before this one is computed
+        GroupAt at = group_at(L, y0, k0, c);
+        GroupCoup J{};
+        if (EA && tid < groups) J = group_coup(X, Yp, at);
 #pragma unroll 1
         for (int q = tid, y = y0, k = k0; q < groups; q += nt) {
-            group<EA>(S, X, Yp, L, y, k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
-            y += dy;
-            k += dk;
-            if (k >= G) {
-                k -= G;
-                ++y;
+            int yn = y + dy, kn = k + dk;
+            if (kn >= G) {
+                kn -= G;
+                ++yn;
             }
+            const GroupAt atn = group_at(L, yn < L ? yn : 0, kn, c);
+            GroupCoup Jn = J;
+            if (EA && q + nt < groups) Jn = group_coup(X, Yp, atn);
+            group<EA>(S, at, J, L, y, k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+            y = yn;
+            k = kn;
+            at = atn;
+            J = Jn;
         }
         __syncthreads();
     }
