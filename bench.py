@@ -106,6 +106,45 @@ def kt_summary(db: str, log: str, kernel: str, L: int, command: str):
     print("\n".join(lines))
 
 
+def valu_summary(db: str, command: str):
+    """VALU issue utilisation of the hot kernels from a rocprofv3 --pmc run
+    with SQ_INSTS_VALU and GRBM_GUI_ACTIVE: wave-instructions per dispatch over
+    (GPU-busy cycles per XCD x 256 CUs x one wave64 VALU instruction per CU
+    per cycle)."""
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    # per kernel, the dispatches of its largest grid (the batched launch, not
+    # the one-chain launches of the per-instance comparison)
+    rows = con.execute("select kernel_name, counter_name, value, grid_size from counters_collection").fetchall()
+    biggest = {}
+    for name, _, _, grid in rows:
+        k = short_name(name)
+        biggest[k] = max(biggest.get(k, 0), grid)
+    acc = {}
+    for name, cname, val, grid in rows:
+        k = short_name(name)
+        if grid == biggest[k]:
+            acc.setdefault(k, {}).setdefault(cname, []).append(val)
+    lines = ["# VALU issue utilisation per dispatch of each kernel's largest grid (rocprofv3 --pmc)",
+             f"# command: {command}",
+             "# util = SQ_INSTS_VALU / (GRBM_GUI_ACTIVE / 8 XCDs * 256 CUs); peak is one wave64 VALU",
+             "# instruction per CU per cycle (four SIMD16 units, four cycles each)",
+             f"{'kernel':28s} {'dispatches':>10s} {'VALU_insts':>14s} {'busy_cycles':>12s} {'util':>6s}"]
+    for k in ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_half", "k_half_sweep_generic",
+              "k_to_split", "k_from_split"):
+        if k not in acc or "SQ_INSTS_VALU" not in acc[k] or "GRBM_GUI_ACTIVE" not in acc[k]:
+            continue
+        v = acc[k]["SQ_INSTS_VALU"]
+        g = acc[k]["GRBM_GUI_ACTIVE"]
+        vi, gi = sum(v) / len(v), sum(g) / len(g) / 8.0
+        lines.append(f"{k:28s} {len(v):10d} {vi:14.4g} {gi:12.4g} {vi / (gi * 256):6.3f}")
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, "valu_utilisation.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def short_name(name: str) -> str:
     import re
 
@@ -375,7 +414,11 @@ def main():
     ap.add_argument("--kt-summary", nargs=2, metavar=("KT_DB", "KT_LOG"),
                     help="write the kernel-trace summary from a rocprofv3 database and the run's output")
     ap.add_argument("--kt-command", default="", help="command line recorded in the kernel-trace summary")
+    ap.add_argument("--valu-summary", metavar="DB", help="write the VALU utilisation summary from a --pmc database")
     args = ap.parse_args()
+    if args.valu_summary:
+        valu_summary(args.valu_summary, args.pmc_command[0] if args.pmc_command else "")
+        return
     if args.kt_summary:
         kt_summary(*args.kt_summary, kernel="k_ising2d_split", L=args.L, command=args.kt_command)
         return

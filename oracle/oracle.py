@@ -70,6 +70,7 @@ def lib():
             "orc_pt_step": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, vp]),
             "orc_pt_run": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, I, vp]),
             "orc_swap_u53": (D, [U64, U32, U32, U32]),
+            "orc_window_run": (None, [I, I, I, I, i8p, D, U64, U32, U32, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -196,3 +197,12 @@ def pt_run(dim, L, J, spins, beta, slot_of_temp, E, seed, q, r0, t0, n_steps, sw
     n_temps = len(beta)
     lib().orc_pt_run(dim, L, _ptr(J), spins.reshape(-1), n_temps, np.ascontiguousarray(beta, np.float64),
                      slot_of_temp, E, seed, q, r0, t0, n_steps, _ptr(swap_acc))
+
+
+def window_run(L, x0, y0, win, beta, seed, r, t0, n):
+    """n sweeps of a W x W window (site (x0+u, y0+v) mod L at win[v, u]) of a
+    2D Ising lattice of edge L, its outer ring held fixed; sites farther than
+    2n from the ring end as in the full lattice (orc_window_run)."""
+    W = win.shape[0]
+    assert win.shape == (W, W) and win.dtype == np.int8 and win.flags.c_contiguous
+    lib().orc_window_run(L, W, x0, y0, win.reshape(-1), beta, seed & 0xFFFFFFFFFFFFFFFF, r, t0, n)

@@ -291,6 +291,43 @@ EXPORT int64_t orc_run(int dim, int L, const int8_t *J, int8_t *s, double beta,
     return dE;
 }
 
+/* n sweeps t0 .. t0+n-1 of a W x W window of a 2D Ising lattice of edge L
+ * (no couplings), for checking sampled sites of lattices too large to sweep
+ * here.  win[v*W + u] is the site (x0 + u, y0 + v) mod L; every interior
+ * window site is updated exactly as in orc_sweep (same colour order, same
+ * uniform keyed by the site's index in the whole lattice), the outermost ring
+ * of the window is held fixed.  A wrong value can only enter from that ring
+ * and moves at most two sites per sweep (colour 0 then colour 1), so after
+ * n sweeps every site at distance > 2n from the ring equals the full
+ * lattice's. */
+EXPORT void orc_window_run(int L, int W, int x0, int y0, int8_t *win, double beta, uint64_t seed,
+                           uint32_t r, uint32_t t0, int n)
+{
+    uint64_t thr[4];
+    orc_thresholds(beta, 2, thr);
+    for (int k = 0; k < n; ++k) {
+        uint32_t t = t0 + (uint32_t)k;
+        for (int c = 0; c < 2; ++c) {
+            for (int v = 1; v < W - 1; ++v) {
+                for (int u = 1; u < W - 1; ++u) {
+                    int gx = (x0 + u) % L, gy = (y0 + v) % L;
+                    if (((gx + gy) & 1) != c) continue;
+                    int8_t *si = &win[v * W + u];
+                    int h = win[v * W + u + 1] + win[v * W + u - 1] + win[(v + 1) * W + u] + win[(v - 1) * W + u];
+                    int dE = 2 * (*si) * h;
+                    int accept = 1;
+                    if (dE > 0) {
+                        int64_t i = (int64_t)gy * L + gx;
+                        uint32_t uu = orc_metropolis_u32(seed, t, r, c, (uint64_t)(i >> 1));
+                        accept = (uint64_t)uu < thr[dE / 4];
+                    }
+                    if (accept) *si = (int8_t)(-(*si));
+                }
+            }
+        }
+    }
+}
+
 /* E = -sum_i sum_mu J(i,mu) s_i s_{i+e_mu} (Eqs. 1 and 11), each bond once. */
 EXPORT int64_t orc_energy(int dim, int L, const int8_t *J, const int8_t *s)
 {

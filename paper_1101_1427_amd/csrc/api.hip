@@ -167,6 +167,14 @@ ThrRow threshold_row(double beta, int dim) {
 
 // The chain-resident tempering kernel serves 3D edge-16 batches of at most
 // 32 temperatures with 16-byte aligned spins and thresholds below 2^32.
+// Uniform 3D Heisenberg batches with a power-of-two edge take the indexed
+// kernel (SPINMC_HEIS3D=0 sends them to the generic one).
+bool use_heis3d(const smc_desc *d) {
+    const char *env = getenv("SPINMC_HEIS3D");
+    if (env && env[0] == '0') return false;
+    return d->model == SMC_HEISENBERG && d->L > 0 && heis3d_supported(d->dim, d->L);
+}
+
 bool pt3d_enabled() {
     const char *env = getenv("SPINMC_PT3D");
     return !(env && env[0] == '0');
@@ -577,7 +585,7 @@ int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char
     if (!launches_per_sweep || !kernel_name) return fail(SMC_EINVAL, "output pointers are required");
     if (desc->model == SMC_HEISENBERG) {
         *launches_per_sweep = 2;
-        *kernel_name = "k_heis_half_sweep_generic";
+        *kernel_name = use_heis3d(desc) ? "k_heis3d_half" : "k_heis_half_sweep_generic";
     } else if (desc->model == SMC_ISING && desc->dim == 2 && desc->L > 0 && lattice2d_supported(desc->L)) {
         *launches_per_sweep = 1;
         *kernel_name = "k_ising2d_split";
@@ -693,10 +701,16 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         if ((rc = upload(c, s, kTables, bf.data(), sizeof(float) * bf.size(), &p))) return rc;
         a.beta_f = (const float *)p;
         SweepTimer timer(s, 2 * (int64_t)n_sweeps);  // the renormalisations run inside the same pair
+        const bool fast = use_heis3d(desc);
         for (int32_t k = 0; k < n_sweeps; ++k) {
             a.t = (uint32_t)(sweep0 + (uint64_t)k);
-            SMC_HIP(launch_heis_half_sweep_generic(a, 0, s));
-            SMC_HIP(launch_heis_half_sweep_generic(a, 1, s));
+            for (int col = 0; col < 2; ++col) {
+                if (fast)
+                    SMC_HIP(launch_heis3d_half((float *)spins, a.beta_f, dE_accum, desc->n_rep, desc->L, a.key, a.t,
+                                               col, s));
+                else
+                    SMC_HIP(launch_heis_half_sweep_generic(a, col, s));
+            }
             if (desc->renorm_every > 0 && ((uint64_t)a.t + 1) % (uint64_t)desc->renorm_every == 0)
                 SMC_HIP(launch_heis_renorm(plan.b, (float *)spins, plan.max_L, s));
         }

@@ -4,6 +4,7 @@
 // pt3d.hip) produce the same results; these serve every shape.
 #include <string.h>
 
+#include "heis_math.hpp"
 #include "internal.hpp"
 
 namespace smc {
@@ -206,12 +207,12 @@ __global__ __launch_bounds__(kBlock) void k_heis_half_sweep_generic(SweepArgs a,
             add(i - (st.z == 0 ? (1 - LL) * P : P));
         }
         const uint4 w = philox4x32_10(make_uint4((uint32_t)h, a.t, (uint32_t)r, 2 * kTagHeis + c), a.key);
-        const float3 sp = sphere_point(unit23f(w.x), unit23f(w.y));
+        const float3 sp = heis_proposal(unit23f(w.x), unit23f(w.y));
         const float3 so = ld3(s, i);
         const float dE = -((sp.x - so.x) * hf.x + (sp.y - so.y) * hf.y + (sp.z - so.z) * hf.z);
         const int row = a.row_of_rep ? a.row_of_rep[r] : r;
         const float beta = a.beta_f[row];
-        if (dE <= 0.0f || unit23f(w.z) < expf(-beta * dE)) {
+        if (dE <= 0.0f || unit23f(w.z) < heis_boltzmann(beta, dE)) {
             s[3 * i] = sp.x;
             s[3 * i + 1] = sp.y;
             s[3 * i + 2] = sp.z;

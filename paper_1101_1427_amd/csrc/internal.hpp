@@ -70,6 +70,11 @@ hipError_t launch_half_sweep_generic(const SweepArgs &a, int c, hipStream_t s);
 hipError_t launch_heis_half_sweep_generic(const SweepArgs &a, int c, hipStream_t s);
 hipError_t launch_heis_renorm(const Batch &b, float *spins, int max_L, hipStream_t s);
 
+// Heisenberg half-sweeps of uniform 3D batches with a power-of-two edge.
+bool heis3d_supported(int dim, int L);
+hipError_t launch_heis3d_half(float *spins, const float *beta, int64_t *acc, int n_rep, int L, Key key, uint32_t t,
+                              int c, hipStream_t s);
+
 // Parallel tempering of 3D edge-16 chains, all steps in one launch.
 bool pt3d_supported(const smc_desc *d, int n_temps);
 size_t pt3d_lds_bytes(int model, int n_temps);

@@ -82,3 +82,23 @@ def test_heisenberg_long_run_energy_within_three_sigma():
     # beta = 0.693 is close to the 3D critical point: about one third of the
     # maximal bond energy, e in (-1.5, -0.5)
     assert -1.5 < mg < -0.5 and -1.5 < mr < -0.5
+
+
+@pytest.mark.parametrize("L,n_rep", [(16, 3), (32, 1)])
+def test_indexed_kernel_equals_generic_kernel(monkeypatch, L, n_rep):
+    """The power-of-two 3D kernel performs the generic kernel's float32
+    arithmetic in the same order: identical spins and acceptance counts over
+    20 sweeps (one renormalisation included)."""
+    seed = W.seed_for(31)
+    b = S.Batch(S.HEISENBERG, 3, L, n_rep, seed, renorm_every=16)
+    assert S.sweep_plan(b)[1] == "k_heis3d_half"
+    out = []
+    for env in ("1", "0"):
+        monkeypatch.setenv("SPINMC_HEIS3D", env)
+        spins = torch.zeros(3 * n_rep * L ** 3, dtype=torch.float32, device=DEV)
+        S.spin_init(b, spins)
+        acc = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
+        S.metropolis_sweep(b, spins, [0.693, 0.5, 1.2][:n_rep], 3, 20, dE_accum=acc)
+        out.append((_host(spins).copy(), _host(acc).copy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
