@@ -48,8 +48,10 @@
  *   variables for comparisons and tuning (read at each call):
  *   SPINMC_PT3D=0 and SPINMC_UNEVEN2D=0 send tempering to the generic
  *   kernels; SPINMC_L2D_CHUNKS (1 or 2), SPINMC_L2D_H (band height, a
- *   multiple of 4) and SPINMC_L2D_PAD (row padding in bytes) set the launch
- *   shape of the 2D Ising sweep.
+ *   multiple of 4), SPINMC_L2D_H1 / SPINMC_L2D_H2 (heights of the bands of
+ *   the first and second half of the grid) and SPINMC_L2D_PAD (row padding
+ *   in bytes) set the launch shape of the 2D Ising sweep.  SPINMC_HEIS3D=0
+ *   sends uniform 3D Heisenberg batches to the generic kernel.
  */
 #ifndef SPINMC_H
 #define SPINMC_H

@@ -16,7 +16,8 @@
 // site), then colour 1 of row j-1 from the new colour-0 rows j-2, j-1, j.
 // Reads come from one buffer and writes go to the other (ping-pong), so
 // bands never see each other's new values.  HBM traffic per sweep: each
-// spin read once and written once (plus 4 halo rows per band from L2).
+// spin read once and written once (plus 4 halo rows per band).  Rows are
+// stored in lattice order with a padded pitch.
 //
 // Decision (Eq. 2 with integer thresholds).  Per site the number n of
 // antiparallel neighbours gives dE = 8 - 4n; n >= 2 always flips.  The
@@ -160,6 +161,7 @@ struct Lattice2dArgs {
     Key key;
     uint32_t t;
     int L, H, bands, n_rep;
+    int H2, nb1;    // bands 0 .. nb1-1 of a replica have H rows, the others H2 rows
     uint32_t one2;  // 0x00010001, passed in so that the compiler keeps the packed ops
     uint32_t four;  // 4, passed in so that the compiler keeps the tie loop rolled
 };
@@ -286,20 +288,12 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-// Physical row of lattice row y in the split planes: band-interleaved, so
-// that row k of every band (H rows each) is stored next to row k of the
-// other bands.  The bands are processed in lockstep, so at any time the
-// workgroups of a sweep touch one compact region instead of one region per
-// band.
-__host__ __device__ __forceinline__ int64_t split_row(int y, int H, int bands) {
-    return (int64_t)(y % H) * bands + y / H;
-}
 
 template <int C>
 struct Band {
     const uint8_t *S0, *S1;
     uint8_t *D0, *D1;
-    int L, half, Y0, H, bands, ncw;
+    int L, half, Y0, H, ncw;
     int64_t pitch;
     int64_t lane_off;
     uint32_t gpr, lg0, r, t;
@@ -307,7 +301,7 @@ struct Band {
     Lut K;
     __device__ __forceinline__ int64_t off(int y) const {
         const int w = y < 0 ? y + L : (y >= L ? y - L : y);
-        return split_row(w, H, bands) * pitch;
+        return (int64_t)w * pitch;
     }
 };
 
@@ -468,20 +462,14 @@ __global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
     const int ncw = (int)(blockDim.x >> 6) - LoaderShape<NF>::NLW;  // compute waves; the last NLW waves load
     uint8_t *ring = smem;
     uint32_t *xch = (uint32_t *)(smem + (size_t)2 * kSlots * (a.L >> 1));
-    // XCD-aware order: consecutive bands of a replica run on the same XCD.
-    const uint32_t nblk = gridDim.x;
-    const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3;
-    const uint32_t per_xcd = nblk >> 3;
-    const uint32_t logical = (nblk & 7u) ? blockIdx.x : xcd * per_xcd + slot;
-    const int r = (int)(logical / (uint32_t)a.bands);
-    const int band = (int)(logical % (uint32_t)a.bands);
+    const int r = (int)(blockIdx.x / (uint32_t)a.bands);
+    const int band = (int)(blockIdx.x % (uint32_t)a.bands);
     Band<C> B;
     B.L = a.L;
     B.half = a.L >> 1;
-    B.H = a.H;
-    B.Y0 = band * a.H;
+    B.H = band < a.nb1 ? a.H : a.H2;
+    B.Y0 = band < a.nb1 ? band * a.H : a.nb1 * a.H + (band - a.nb1) * a.H2;
     B.pitch = a.pitch;
-    B.bands = a.bands;
     B.ncw = ncw;
     B.S0 = a.src + (int64_t)r * a.rep_bytes;
     B.S1 = B.S0 + B.pitch * a.L;
@@ -504,7 +492,7 @@ __global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
 // ----------------------------------------------------- layout conversion ----
 // ABI row-major int8 +-1  <->  split planes of 0/1 bytes (x even -> plane
 // (y&1), x odd -> plane ((y+1)&1), plane index x/2).
-__global__ __launch_bounds__(256) void k_to_split(const int8_t *src, uint8_t *dst, int L, int64_t pitch, int H,
+__global__ __launch_bounds__(256) void k_to_split(const int8_t *src, uint8_t *dst, int L, int64_t pitch,
                                                   int64_t chunks_per_rep, int64_t total) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= total) return;
@@ -518,7 +506,7 @@ __global__ __launch_bounds__(256) void k_to_split(const int8_t *src, uint8_t *ds
     const uint2 ev = make_uint2(perm(b1, b0, 0x06040200u), perm(b3, b2, 0x06040200u));
     const uint2 od = make_uint2(perm(b1, b0, 0x07050301u), perm(b3, b2, 0x07050301u));
     uint8_t *base = dst + r * 2 * P;
-    const int64_t off = split_row(y, H, L / H) * pitch + 8 * xc;
+    const int64_t off = (int64_t)y * pitch + 8 * xc;
     const int pe = y & 1, po = (y + 1) & 1;
     *(uint2 *)(base + pe * P + off) = ev;
     *(uint2 *)(base + po * P + off) = od;
@@ -526,7 +514,7 @@ __global__ __launch_bounds__(256) void k_to_split(const int8_t *src, uint8_t *ds
 
 __device__ __forceinline__ uint32_t pm1(uint32_t b) { return ((b << 8) - b) | 0x01010101u; }
 
-__global__ __launch_bounds__(256) void k_from_split(const uint8_t *src, int8_t *dst, int L, int64_t pitch, int H,
+__global__ __launch_bounds__(256) void k_from_split(const uint8_t *src, int8_t *dst, int L, int64_t pitch,
                                                     int64_t chunks_per_rep, int64_t total) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= total) return;
@@ -535,7 +523,7 @@ __global__ __launch_bounds__(256) void k_from_split(const uint8_t *src, int8_t *
     const int y = (int)(cidx / cpr), xc = (int)(cidx % cpr);
     const int64_t N = (int64_t)L * L, P = (int64_t)L * pitch;
     const uint8_t *base = src + r * 2 * P;
-    const int64_t off = split_row(y, H, L / H) * pitch + 8 * xc;
+    const int64_t off = (int64_t)y * pitch + 8 * xc;
     const int pe = y & 1, po = (y + 1) & 1;
     const uint2 ev = *(const uint2 *)(base + pe * P + off);
     const uint2 od = *(const uint2 *)(base + po * P + off);
@@ -593,14 +581,14 @@ size_t lattice2d_split_bytes(int L) { return (size_t)(2 * (int64_t)L * lattice2d
 hipError_t launch_to_split(const int8_t *src, uint8_t *dst, int L, int n_rep, hipStream_t s) {
     const int64_t cpr = (int64_t)L * L / 16, total = cpr * n_rep;
     hipLaunchKernelGGL(k_to_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L,
-                       lattice2d_pitch(L), lattice2d_band_height(L, n_rep), cpr, total);
+                       lattice2d_pitch(L), cpr, total);
     return hipGetLastError();
 }
 
 hipError_t launch_from_split(const uint8_t *src, int8_t *dst, int L, int n_rep, hipStream_t s) {
     const int64_t cpr = (int64_t)L * L / 16, total = cpr * n_rep;
     hipLaunchKernelGGL(k_from_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L,
-                       lattice2d_pitch(L), lattice2d_band_height(L, n_rep), cpr, total);
+                       lattice2d_pitch(L), cpr, total);
     return hipGetLastError();
 }
 
@@ -620,7 +608,33 @@ hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_r
     a.t = t;
     a.L = L;
     a.H = H;
+    a.H2 = H;
     a.bands = L / H;
+    a.nb1 = a.bands;
+    // With exactly two bands per compute unit (one replica), the workgroups
+    // dispatched first (one per CU) win issue arbitration against the second
+    // ones and finish far ahead of them; giving the first ones bands of
+    // 9/8 H rows and the second ones 7/8 H lets both finish together.
+    // SPINMC_L2D_H1 / SPINMC_L2D_H2 set the two heights (multiples of 4).
+    {
+        int cus = 0;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        int h1 = 0, h2 = 0;
+        if (n_rep == 1 && cus > 0 && L / H == 2 * cus && H % 32 == 0) {
+            h1 = H + H / 8;
+            h2 = H - H / 8;
+        }
+        h1 = env_int("SPINMC_L2D_H1", h1);
+        h2 = env_int("SPINMC_L2D_H2", h2);
+        if (h1 > 0 && h2 > 0 && h1 % 4 == 0 && h2 % 4 == 0 && L % (h1 + h2) == 0) {
+            a.H = h1;
+            a.H2 = h2;
+            a.nb1 = L / (h1 + h2);
+            a.bands = 2 * a.nb1;
+        }
+    }
     a.n_rep = n_rep;
     a.one2 = 0x00010001u;
     a.four = 4u;

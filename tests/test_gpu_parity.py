@@ -257,14 +257,18 @@ def test_split_kernel_bit_exact(L, n_rep, n, sweep0):
 
 
 def test_split_kernel_launch_shape_invariance(monkeypatch):
-    """Band height and lane width change the schedule, never the result."""
+    """Band heights (equal or split between the two halves of the grid) and
+    lane width change the schedule, never the result."""
     seed = W.seed_for(23)
     L = 8192
     b = S.Batch(S.ISING, 2, L, 1, seed)
     outs = []
-    for chunks, H in [(1, 64), (2, 16), (1, 4), (2, 128), (2, 32)]:
+    for chunks, H, h1, h2 in [(1, 64, 0, 0), (2, 16, 0, 0), (1, 4, 0, 0), (2, 128, 0, 0), (2, 32, 0, 0),
+                              (2, 32, 36, 28), (1, 16, 20, 12), (2, 32, 8, 56)]:
         monkeypatch.setenv("SPINMC_L2D_CHUNKS", str(chunks))
         monkeypatch.setenv("SPINMC_L2D_H", str(H))
+        monkeypatch.setenv("SPINMC_L2D_H1", str(h1))
+        monkeypatch.setenv("SPINMC_L2D_H2", str(h2))
         spins, _ = gpu_init(b)
         dE = torch.zeros(1, dtype=torch.int64, device=DEV)
         S.metropolis_sweep(b, spins, [0.42], 0, 6, dE_accum=dE)
