@@ -47,6 +47,12 @@ __device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b) {
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
     return __builtin_amdgcn_perm(hi, lo, sel);
 }
+// (a ^ b) + c in one v_xad_u32 (register operands only, no memory access).
+__device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_xad_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
 __device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) {
     return __builtin_amdgcn_alignbyte(hi, lo, s);
 }
@@ -135,7 +141,12 @@ __device__ __forceinline__ uint32_t count_anti(uint32_t own, uint32_t va, uint32
         const uint32_t hi = i == 2 * C - 1 ? edge : hz.d[i + 1];
         sh = alignbyte(hi, hz.d[i], 1);
     }
-    return ((own ^ va) + (own ^ vb)) + ((own ^ hz.d[i]) + (own ^ sh));
+    // one xor and three xor-adds (the compiler otherwise rebalances the sum
+    // into four xors and two adds)
+    uint32_t n = own ^ sh;
+    n = xad(own, hz.d[i], n);
+    n = xad(own, vb, n);
+    return xad(own, va, n);
 }
 
 // Flip flags (bit 0 of each byte) of the four sites with counts n and heads

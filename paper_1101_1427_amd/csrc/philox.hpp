@@ -32,11 +32,14 @@ __device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
 }
 
 // One Philox round: the two 32x32 -> 64-bit products are single
-// v_mad_u64_u32 instructions.
+// v_mad_u64_u32 instructions.  The key is xored into the counter word first:
+// in the early rounds that word is uniform across the wave, so the pair
+// costs one scalar and one vector xor.
 __device__ __forceinline__ uint4 philox_round(uint4 x, uint32_t k0, uint32_t k1) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * x.x;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * x.z;
-    return make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ x.w ^ k1, (uint32_t)p0);
+    return make_uint4((uint32_t)(p1 >> 32) ^ (x.y ^ k0), (uint32_t)p1, (uint32_t)(p0 >> 32) ^ (x.w ^ k1),
+                      (uint32_t)p0);
 }
 
 __device__ __forceinline__ uint4 philox_round_x3(uint4 x, uint32_t k0, uint32_t k1) {
@@ -47,20 +50,21 @@ __device__ __forceinline__ uint4 philox_round_x3(uint4 x, uint32_t k0, uint32_t 
 }
 
 // Philox4x32-10 of counter x.  Counter words 1..3 are wave-uniform in every
-// use here, so the first three rounds are left to the compiler (it keeps the
-// uniform parts in scalar registers); the remaining rounds are all-vector
-// and use the three-input XOR.
+// use here, so the first two rounds are left to the compiler (it keeps the
+// uniform parts in scalar registers); from the third round on two of the
+// xored words vary per lane and the three-input XOR takes the place of two
+// instructions.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 x, Key key) {
     uint32_t k0 = key.k0, k1 = key.k1;
     x = philox_round(x, k0, k1);
 #pragma unroll
-    for (int round = 1; round < 3; ++round) {
+    for (int round = 1; round < 2; ++round) {
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
         x = philox_round(x, k0, k1);
     }
 #pragma unroll
-    for (int round = 3; round < 10; ++round) {
+    for (int round = 2; round < 10; ++round) {
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
         x = philox_round_x3(x, k0, k1);
@@ -76,14 +80,14 @@ __device__ __forceinline__ void philox4x32_10_multi(uint4 (&x)[NC], Key key) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) x[c] = philox_round(x[c], k0, k1);
 #pragma unroll
-    for (int round = 1; round < 3; ++round) {
+    for (int round = 1; round < 2; ++round) {
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
 #pragma unroll
         for (int c = 0; c < NC; ++c) x[c] = philox_round(x[c], k0, k1);
     }
 #pragma unroll
-    for (int round = 3; round < 10; ++round) {
+    for (int round = 2; round < 10; ++round) {
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
 #pragma unroll
