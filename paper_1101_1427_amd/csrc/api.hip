@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -65,6 +66,11 @@ enum Slot {
     kChunks,
     kWork,
     kStep,
+    kTuneSpins,
+    kTuneInst,
+    kTuneWork,
+    kTuneRows,
+    kTuneE,
     kNumSlots
 };
 
@@ -319,13 +325,103 @@ bool use_uneven2d(const smc_desc *d, const void *spins, const int8_t *coup, cons
     return true;
 }
 
-// Threads per workgroup for an edge: about four draw groups per thread and
-// colour, between one and eight waves.
-int uneven2d_threads(int L) {
+// Threads per workgroup for an edge, without measurement: about four draw
+// groups per thread and colour, between one and eight waves.
+int uneven2d_threads_default(int L) {
     const int groups = L * L / 16;
     int t = 64;
     while (t < 512 && 4 * t < groups) t <<= 1;
     return t;
+}
+
+// Autotuned workgroup size per (device, edge, model), measured once per
+// process: the sweep kernel runs on scratch copies of up to 4096 replicas of
+// the edge (enough workgroups to fill the chip) with every candidate size and
+// the fastest is kept.  The choice changes
+// the schedule only, never the results.  SPINMC_U2D_THREADS=n forces n;
+// SPINMC_AUTOTUNE=0 takes the default without measuring.
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int, int>, int> g_tuned;
+
+int uneven2d_threads(StreamCtx &c, hipStream_t s, const Uneven2dArgs &a, int L, bool ea,
+                     const std::vector<int32_t> &reps, const std::vector<smc_inst> &rows, int *out) {
+    if (const char *f = getenv("SPINMC_U2D_THREADS")) {
+        const int v = atoi(f);
+        if (v == 64 || v == 128 || v == 256 || v == 512) {
+            *out = v;
+            return SMC_OK;
+        }
+    }
+    const char *env = getenv("SPINMC_AUTOTUNE");
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    SMC_HIP(hipStreamIsCapturing(s, &cap));
+    if ((env && env[0] == '0') || cap != hipStreamCaptureStatusNone) {
+        *out = uneven2d_threads_default(L);
+        return SMC_OK;
+    }
+    int dev = 0;
+    SMC_HIP(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, L, ea ? 1 : 0);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            *out = it->second;
+            return SMC_OK;
+        }
+    }
+    // scratch copies of the first replicas of the edge (couplings are read in place)
+    int rc;
+    const int M = (int)std::min<size_t>(reps.size(), 4096);
+    const int64_t N = (int64_t)L * L;
+    void *sp = nullptr, *ip = nullptr, *wp = nullptr, *rp = nullptr, *ep = nullptr;
+    if ((rc = ensure(c, kTuneSpins, (size_t)(M * N), &sp))) return rc;
+    std::vector<smc_inst> tinst(M);
+    std::vector<int32_t> twork(M), trows(M, 0);
+    for (int m = 0; m < M; ++m) {
+        tinst[m] = rows[reps[m]];
+        tinst[m].spin_off = (int64_t)m * N;
+        twork[m] = m;
+        SMC_HIP(hipMemcpyAsync((int8_t *)sp + (int64_t)m * N, a.spins + rows[reps[m]].spin_off, (size_t)N,
+                               hipMemcpyDeviceToDevice, s));
+    }
+    if ((rc = upload(c, s, kTuneInst, tinst.data(), sizeof(smc_inst) * M, &ip))) return rc;
+    if ((rc = upload(c, s, kTuneWork, twork.data(), sizeof(int32_t) * M, &wp))) return rc;
+    if ((rc = upload(c, s, kTuneRows, trows.data(), sizeof(int32_t) * M, &rp))) return rc;
+    if ((rc = ensure(c, kTuneE, sizeof(int64_t) * M, &ep))) return rc;
+    Uneven2dArgs t = a;
+    t.spins = (int8_t *)sp;
+    t.inst = (const smc_inst *)ip;
+    t.row_of_rep = (const int32_t *)rp;
+    t.E = (int64_t *)ep;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SMC_HIP(hipEventCreate(&e0));
+    SMC_HIP(hipEventCreate(&e1));
+    int best = uneven2d_threads_default(L);
+    float best_ms = 1e30f;
+    hipError_t err = hipSuccess;
+    for (int th = 64; th <= 512 && err == hipSuccess; th <<= 1) {
+        err = launch_uneven2d_sweep(t, (const int32_t *)wp, M, L, ea, th, s);  // warm-up
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int k = 0; k < 3 && err == hipSuccess; ++k) err = launch_uneven2d_sweep(t, (const int32_t *)wp, M, L, ea, th, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = th;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(SMC_EHIP, "autotuning the 2D sweep: %s", hipGetErrorString(err));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tuned[key] = best;
+    }
+    *out = best;
+    return SMC_OK;
 }
 
 std::vector<smc_inst> inst_rows(const smc_desc *d) {
@@ -359,7 +455,7 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
     for (auto &kv : by_edge) {
         EdgeClass e;
         e.L = kv.first;
-        e.threads = uneven2d_threads(e.L);
+        e.threads = 0;  // chosen below
         e.first = (int32_t)work.size();
         e.count = (int32_t)kv.second.size();
         work.insert(work.end(), kv.second.begin(), kv.second.end());
@@ -405,6 +501,10 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
                                               thr, sw.E, t_dev, make_key(desc->seed));
     const int32_t *wl = (const int32_t *)work_dev;
     const bool ea = desc->model == SMC_EA;
+    for (auto &e : classes) {
+        const std::vector<int32_t> reps(work.begin() + e.first, work.begin() + e.first + e.count);
+        if ((rc = uneven2d_threads(c, s, a, e.L, ea, reps, rows, &e.threads))) return rc;
+    }
 
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     SMC_HIP(hipStreamIsCapturing(s, &cap));

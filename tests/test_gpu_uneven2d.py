@@ -63,8 +63,7 @@ def _check_chain(model, inst, q, n_temps, beta, seed, t0, steps, got, perms):
 @pytest.mark.parametrize("model", [S.EA, S.ISING])
 def test_uneven2d_every_edge_graph_and_remainder(model):
     """One chain per edge, 37 steps in two calls: a 32-step graph, a 5-step
-    graph and a plain 2-step call; the couplings of edge 256 are read from
-    global memory, the others from LDS."""
+    graph and a plain 2-step call."""
     sizes = [16, 32, 48, 256, 64, 96, 128, 192]
     n_temps, seed = 4, W.seed_for(50 + model)
     beta = W.geometric_ladder(0.5, 2.0, n_temps) if model == S.EA else W.geometric_ladder(1.8, 3.2, n_temps)
@@ -143,3 +142,47 @@ def test_uneven2d_full_workload_sampled_chains():
         picked += [int(idx[0]), int(idx[-1])]
     for q in picked:
         _check_chain(S.EA, inst, q, n_temps, cfg.betas, cfg.seed, 0, cfg.steps, got, perms)
+
+
+def test_invalid_chain_next_to_a_valid_one():
+    """Edge 32, two chains in one launch: the one whose slot_of_temp row
+    repeats a slot is left unchanged, the other matches the oracle."""
+    sizes, n_temps, seed = [32, 32], 4, W.seed_for(56)
+    beta = W.geometric_ladder(0.5, 2.0, n_temps)
+    perms = np.array([0, 1, 2, 3, 2, 2, 0, 1], np.int32)
+    inst = refrun.uneven_table(2, sizes, n_temps, S.EA)
+    b = S.Batch(S.EA, 2, 0, len(inst), seed, inst=inst)
+    spins = torch.zeros(b.spins_shape()[0], dtype=torch.int8, device=DEV)
+    coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV)
+    S.spin_init(b, spins, coup)
+    E = torch.zeros(len(inst), dtype=torch.float64, device=DEV)
+    S.measure_energy_magnetisation(b, spins, E, couplings=coup)
+    s0, E0 = _host(spins).copy(), _host(E).copy()
+    sot = torch.from_numpy(perms.copy()).to(DEV)
+    acc = torch.zeros(2 * (n_temps - 1), dtype=torch.int64, device=DEV)
+    S.pt_sweep_swap(b, 2, n_temps, beta, spins, sot, E, 0, 9, couplings=coup, swap_accepts=acc)
+    got = (_host(spins), _host(sot), _host(E), _host(acc))
+    N = 32 * 32
+    assert np.array_equal(got[0][n_temps * N:], s0[n_temps * N:])
+    assert np.array_equal(got[1][n_temps:], perms[n_temps:])
+    assert np.array_equal(got[2][n_temps:], E0[n_temps:])
+    assert not got[3][n_temps - 1:].any()
+    _check_chain(S.EA, inst, 0, n_temps, beta, seed, 0, 9, got, perms)
+
+
+def test_workgroup_size_never_changes_results(monkeypatch):
+    """Forced workgroup sizes 64 and 512, and the autotuner's choice: identical
+    spins, energies and permutations."""
+    sizes, n_temps, seed = [48, 128, 32], 4, W.seed_for(57)
+    beta = W.geometric_ladder(0.5, 2.0, n_temps)
+    outs = []
+    for env in ("64", "512", None):
+        if env is None:
+            monkeypatch.delenv("SPINMC_U2D_THREADS", raising=False)
+        else:
+            monkeypatch.setenv("SPINMC_U2D_THREADS", env)
+        inst, *got = _run(S.EA, sizes, n_temps, beta, seed, [(0, 6)])
+        outs.append(got[:4])
+    for o in outs[1:]:
+        for x, y in zip(o, outs[0]):
+            assert np.array_equal(x, y)
