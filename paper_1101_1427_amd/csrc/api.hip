@@ -71,6 +71,7 @@ enum Slot {
     kTuneWork,
     kTuneRows,
     kTuneE,
+    kHeisPing,
     kNumSlots
 };
 
@@ -179,6 +180,14 @@ bool use_heis3d(const smc_desc *d) {
     const char *env = getenv("SPINMC_HEIS3D");
     if (env && env[0] == '0') return false;
     return d->model == SMC_HEISENBERG && d->L > 0 && heis3d_supported(d->dim, d->L);
+}
+
+// ... and with an edge of at least 32 the one-pass tiled kernel
+// (SPINMC_HEIS_TILED=0 keeps the two half-sweep launches).
+bool use_heis3d_tiled(const smc_desc *d) {
+    const char *env = getenv("SPINMC_HEIS_TILED");
+    if (env && env[0] == '0') return false;
+    return use_heis3d(d) && heis3d_tiled_supported(d->dim, d->L);
 }
 
 bool pt3d_enabled() {
@@ -685,7 +694,12 @@ int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char
     if (!launches_per_sweep || !kernel_name) return fail(SMC_EINVAL, "output pointers are required");
     if (desc->model == SMC_HEISENBERG) {
         *launches_per_sweep = 2;
-        *kernel_name = use_heis3d(desc) ? "k_heis3d_half" : "k_heis_half_sweep_generic";
+        if (use_heis3d_tiled(desc)) {
+            *launches_per_sweep = 1;
+            *kernel_name = "k_heis3d_tiled";
+        } else {
+            *kernel_name = use_heis3d(desc) ? "k_heis3d_half" : "k_heis_half_sweep_generic";
+        }
     } else if (desc->model == SMC_ISING && desc->dim == 2 && desc->L > 0 && lattice2d_supported(desc->L)) {
         *launches_per_sweep = 1;
         *kernel_name = "k_ising2d_split";
@@ -800,6 +814,24 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         for (int r = 0; r < desc->n_rep; ++r) bf[r] = (float)beta[r];
         if ((rc = upload(c, s, kTables, bf.data(), sizeof(float) * bf.size(), &p))) return rc;
         a.beta_f = (const float *)p;
+        if (use_heis3d_tiled(desc)) {
+            // one-pass sweeps, ping-pong between the caller's buffer and a scratch copy
+            const size_t bytes = (size_t)desc->n_rep * 3 * sizeof(float) * (size_t)plan.b.N;
+            void *pp = nullptr;
+            if ((rc = ensure(c, kHeisPing, bytes, &pp))) return rc;
+            float *A = (float *)spins, *B = (float *)pp;
+            SweepTimer timer(s, n_sweeps);  // the renormalisations run inside the same pair
+            for (int32_t k = 0; k < n_sweeps; ++k) {
+                a.t = (uint32_t)(sweep0 + (uint64_t)k);
+                float *src = k & 1 ? B : A, *dst = k & 1 ? A : B;
+                SMC_HIP(launch_heis3d_tiled(src, dst, a.beta_f, dE_accum, desc->n_rep, desc->L, a.key, a.t, s));
+                if (desc->renorm_every > 0 && ((uint64_t)a.t + 1) % (uint64_t)desc->renorm_every == 0)
+                    SMC_HIP(launch_heis_renorm(plan.b, dst, plan.max_L, s));
+            }
+            timer.finish();
+            if (n_sweeps & 1) SMC_HIP(hipMemcpyAsync(A, B, bytes, hipMemcpyDeviceToDevice, s));
+            return SMC_OK;
+        }
         SweepTimer timer(s, 2 * (int64_t)n_sweeps);  // the renormalisations run inside the same pair
         const bool fast = use_heis3d(desc);
         for (int32_t k = 0; k < n_sweeps; ++k) {

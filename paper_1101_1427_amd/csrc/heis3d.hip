@@ -112,6 +112,186 @@ __global__ __launch_bounds__(kThreads) void k_heis3d_half(Heis3dArgs a, int c) {
     }
 }
 
+// ----------------------------------------------------------------------
+// One-pass sweep (colour 0 then colour 1 in a single pass over the
+// lattice).  A workgroup owns a tile of kTile x kTile sites in (x, y) over a
+// segment of kSeg planes in z and streams down the planes: at step z it
+// updates colour 0 of plane z on the tile plus a one-site ring, then colour 1
+// of plane z-1 on the tile (its neighbours are then final), and writes plane
+// z-1 of the tile.  The ring's colour-0 values are recomputed identically by
+// the neighbouring tiles (every draw is keyed by the site), so tiles never
+// exchange data; reads come from one buffer and writes go to the other.
+// Planes live in LDS as structure-of-arrays float planes of
+// (kTile+4) x (kTile+4) sites (two-site halo), four planes in a ring.
+constexpr int kTile = 32;
+constexpr int kSeg = 32;
+constexpr int kW = kTile + 4;       // staged width with the halo
+constexpr int kPlane = kW * kW;     // sites per staged plane
+constexpr int kRing = 4;
+constexpr int kTiledThreads = 512;
+constexpr int kLoadsPerThread = (kPlane + kTiledThreads - 1) / kTiledThreads;
+
+struct TiledArgs {
+    const float *src;  // [n_rep][N][3]
+    float *dst;
+    const float *beta;
+    int64_t *acc;
+    Key key;
+    uint32_t t;
+    int lgL;
+    int64_t N;
+    int tiles, segs;   // tiles per row of tiles, segments per replica
+};
+
+struct PlaneRegs {
+    F3 v[kLoadsPerThread];
+};
+
+__device__ __forceinline__ void load_plane(const float *src, int L, int lgL, int x0, int y0, int z, PlaneRegs &pr) {
+    const uint32_t m = (uint32_t)L - 1u;
+    const uint32_t zz = (uint32_t)z & m;
+#pragma unroll
+    for (int j = 0; j < kLoadsPerThread; ++j) {
+        const int q = (int)threadIdx.x + j * kTiledThreads;
+        if (q < kPlane) {
+            const int v = q / kW, u = q - v * kW;
+            const uint32_t x = (uint32_t)(x0 - 2 + u) & m, y = (uint32_t)(y0 - 2 + v) & m;
+            pr.v[j] = ld(src, (((zz << lgL) + y) << lgL) + x);
+        }
+    }
+}
+
+__device__ __forceinline__ void store_plane(float *ring, int slot, const PlaneRegs &pr) {
+    float *P = ring + slot * 3 * kPlane;
+#pragma unroll
+    for (int j = 0; j < kLoadsPerThread; ++j) {
+        const int q = (int)threadIdx.x + j * kTiledThreads;
+        if (q < kPlane) {
+            P[q] = pr.v[j].x;
+            P[kPlane + q] = pr.v[j].y;
+            P[2 * kPlane + q] = pr.v[j].z;
+        }
+    }
+}
+
+__device__ __forceinline__ F3 lds3(const float *ring, int slot, int q) {
+    const float *P = ring + slot * 3 * kPlane;
+    F3 r;
+    r.x = P[q];
+    r.y = P[kPlane + q];
+    r.z = P[2 * kPlane + q];
+    return r;
+}
+
+// Update the colour-c sites of plane z (ring slot sz) within staged rows and
+// columns [lo, hi); planes z-1 and z+1 sit in slots sm and sp.  Counts the
+// accepted moves of sites inside the tile when `count`.
+__device__ __forceinline__ int update_plane(float *ring, int sm, int sz, int sp, int lo, int hi, int c, int x0, int y0,
+                                            int z, const TiledArgs &a, int r, float beta, bool count) {
+    const int L = 1 << a.lgL;
+    const uint32_t m = (uint32_t)L - 1u;
+    const uint32_t zz = (uint32_t)z & m;
+    const int n = hi - lo;           // staged cells per row
+    const int per_row = n >> 1;      // colour-c cells per row (n even)
+    int n_acc = 0;
+    for (int k = threadIdx.x; k < n * per_row; k += kTiledThreads) {
+        const int vv = k / per_row, j = k - vv * per_row;
+        const int v = lo + vv;
+        const uint32_t y = (uint32_t)(y0 - 2 + v) & m;
+        // first column of colour c in this row: global x parity = c - y - z
+        const int u0 = lo + (((c - (int)y - (int)zz - (x0 - 2 + lo)) % 2) + 2) % 2;
+        const int u = u0 + 2 * j;
+        const uint32_t x = (uint32_t)(x0 - 2 + u) & m;
+        const int q = v * kW + u;
+        const F3 nx1 = lds3(ring, sz, q + 1), nx0 = lds3(ring, sz, q - 1);
+        const F3 ny1 = lds3(ring, sz, q + kW), ny0 = lds3(ring, sz, q - kW);
+        const F3 nz1 = lds3(ring, sp, q), nz0 = lds3(ring, sm, q);
+        const F3 so = lds3(ring, sz, q);
+        float3 hf = make_float3(0.f, 0.f, 0.f);
+        hf.x += nx1.x; hf.y += nx1.y; hf.z += nx1.z;
+        hf.x += nx0.x; hf.y += nx0.y; hf.z += nx0.z;
+        hf.x += ny1.x; hf.y += ny1.y; hf.z += ny1.z;
+        hf.x += ny0.x; hf.y += ny0.y; hf.z += ny0.z;
+        hf.x += nz1.x; hf.y += nz1.y; hf.z += nz1.z;
+        hf.x += nz0.x; hf.y += nz0.y; hf.z += nz0.z;
+        const uint32_t i = (((zz << a.lgL) + y) << a.lgL) + x;
+        const uint4 w = philox4x32_10(make_uint4(i >> 1, a.t, (uint32_t)r, 2 * kTagHeis + (uint32_t)c), a.key);
+        const float3 sp3 = heis_proposal(unit23f(w.x), unit23f(w.y));
+        const float dE = -((sp3.x - so.x) * hf.x + (sp3.y - so.y) * hf.y + (sp3.z - so.z) * hf.z);
+        if (dE <= 0.0f || unit23f(w.z) < heis_boltzmann(beta, dE)) {
+            float *P = ring + sz * 3 * kPlane;
+            P[q] = sp3.x;
+            P[kPlane + q] = sp3.y;
+            P[2 * kPlane + q] = sp3.z;
+            if (count && u >= 2 && u < 2 + kTile && v >= 2 && v < 2 + kTile) ++n_acc;
+        }
+    }
+    return n_acc;
+}
+
+__global__ __launch_bounds__(kTiledThreads) void k_heis3d_tiled(TiledArgs a) {
+    extern __shared__ __align__(16) float ring[];  // [kRing][3][kPlane]
+    __shared__ int red[kTiledThreads / 64];
+    const int L = 1 << a.lgL;
+    const int per_rep = a.tiles * a.tiles * a.segs;
+    const int r = blockIdx.x / per_rep;
+    const int rem = blockIdx.x % per_rep;
+    const int seg = rem / (a.tiles * a.tiles), tile = rem % (a.tiles * a.tiles);
+    const int x0 = (tile % a.tiles) * kTile, y0 = (tile / a.tiles) * kTile;
+    const int z0 = seg * kSeg, z1 = z0 + (kSeg < L ? kSeg : L);
+    const float *src = a.src + (size_t)r * 3 * (size_t)a.N;
+    float *dst = a.dst + (size_t)r * 3 * (size_t)a.N;
+    const float beta = a.beta[r];
+    const uint32_t m = (uint32_t)L - 1u;
+
+    // planes z0-2 .. z0 into slots (plane & 3); plane z0+1 requested
+    PlaneRegs pr;
+    for (int z = z0 - 2; z <= z0; ++z) {
+        load_plane(src, L, a.lgL, x0, y0, z, pr);
+        store_plane(ring, z & 3, pr);
+    }
+    load_plane(src, L, a.lgL, x0, y0, z0 + 1, pr);
+    __syncthreads();
+    int n_acc = 0;
+    for (int z = z0 - 1; z < z1 + 1; ++z) {
+        // plane z+1 (requested one step ago) into its slot, plane z+2 requested
+        if (z >= z0) {
+            store_plane(ring, (z + 1) & 3, pr);
+            if (z + 2 <= z1 + 1) load_plane(src, L, a.lgL, x0, y0, z + 2, pr);
+            __syncthreads();
+        }
+        // colour 0 of plane z on the tile and a one-site ring
+        n_acc += update_plane(ring, (z - 1) & 3, z & 3, (z + 1) & 3, 1, kW - 1, 0, x0, y0, z, a, r, beta,
+                              z >= z0 && z < z1);
+        __syncthreads();
+        if (z >= z0 + 1) {
+            // colour 1 of plane z-1 on the tile, then the tile's plane z-1 out
+            const int zc = z - 1;
+            n_acc += update_plane(ring, (zc - 1) & 3, zc & 3, z & 3, 2, 2 + kTile, 1, x0, y0, zc, a, r, beta, true);
+            __syncthreads();
+            const uint32_t zz = (uint32_t)zc & m;
+            for (int k = threadIdx.x; k < kTile * kTile; k += kTiledThreads) {
+                const int v = 2 + k / kTile, u = 2 + k % kTile;
+                const F3 val = lds3(ring, zc & 3, v * kW + u);
+                const uint32_t x = (uint32_t)(x0 + u - 2) & m, y = (uint32_t)(y0 + v - 2) & m;
+                *(F3 *)(dst + 3 * (size_t)((((zz << a.lgL) + y) << a.lgL) + x)) = val;
+            }
+        }
+    }
+    if (a.acc) {
+        int v = n_acc;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < kTiledThreads / 64; ++w) tot += red[w];
+            if (tot) atomicAdd((unsigned long long *)&a.acc[r], (unsigned long long)tot);
+        }
+    }
+}
+
 }  // namespace
 
 bool heis3d_supported(int dim, int L) { return dim == 3 && L >= 4 && L <= 1024 && (L & (L - 1)) == 0; }
@@ -129,6 +309,31 @@ hipError_t launch_heis3d_half(float *spins, const float *beta, int64_t *acc, int
     a.N = (int64_t)L * L * L;
     a.bpr = (int)((a.N / 2 + kThreads * kSitesPerThread - 1) / (kThreads * kSitesPerThread));
     hipLaunchKernelGGL(k_heis3d_half, dim3((unsigned)(a.bpr * n_rep)), dim3(kThreads), 0, s, a, c);
+    return hipGetLastError();
+}
+
+bool heis3d_tiled_supported(int dim, int L) { return heis3d_supported(dim, L) && L >= kTile; }
+
+size_t heis3d_tiled_lds_bytes() { return (size_t)kRing * 3 * kPlane * sizeof(float); }
+
+hipError_t launch_heis3d_tiled(const float *src, float *dst, const float *beta, int64_t *acc, int n_rep, int L, Key key,
+                               uint32_t t, hipStream_t s) {
+    TiledArgs a;
+    a.src = src;
+    a.dst = dst;
+    a.beta = beta;
+    a.acc = acc;
+    a.key = key;
+    a.t = t;
+    a.lgL = 0;
+    while ((1 << a.lgL) < L) ++a.lgL;
+    a.N = (int64_t)L * L * L;
+    a.tiles = L / kTile;
+    a.segs = L > kSeg ? L / kSeg : 1;
+    const size_t lds = heis3d_tiled_lds_bytes();
+    (void)hipFuncSetAttribute((const void *)k_heis3d_tiled, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const unsigned blocks = (unsigned)(a.tiles * a.tiles * a.segs * n_rep);
+    hipLaunchKernelGGL(k_heis3d_tiled, dim3(blocks), dim3(kTiledThreads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -84,21 +84,25 @@ def test_heisenberg_long_run_energy_within_three_sigma():
     assert -1.5 < mg < -0.5 and -1.5 < mr < -0.5
 
 
-@pytest.mark.parametrize("L,n_rep", [(16, 3), (32, 1)])
-def test_indexed_kernel_equals_generic_kernel(monkeypatch, L, n_rep):
-    """The power-of-two 3D kernel performs the generic kernel's float32
-    arithmetic in the same order: identical spins and acceptance counts over
-    20 sweeps (one renormalisation included)."""
+@pytest.mark.parametrize("L,n_rep,n", [(16, 3, 20), (32, 2, 19), (64, 1, 20)])
+def test_gpu_heisenberg_kernels_agree(monkeypatch, L, n_rep, n):
+    """The one-pass tiled kernel (edge >= 32), the two-launch indexed kernel
+    and the generic kernel perform the same float32 arithmetic in the same
+    order: identical spins and acceptance counts after n sweeps (one
+    renormalisation included; an odd count ends in the scratch buffer and is
+    copied back)."""
     seed = W.seed_for(31)
     b = S.Batch(S.HEISENBERG, 3, L, n_rep, seed, renorm_every=16)
-    assert S.sweep_plan(b)[1] == "k_heis3d_half"
+    assert S.sweep_plan(b)[1] == ("k_heis3d_tiled" if L >= 32 else "k_heis3d_half")
     out = []
-    for env in ("1", "0"):
-        monkeypatch.setenv("SPINMC_HEIS3D", env)
+    for tiled, indexed in (("1", "1"), ("0", "1"), ("0", "0")):
+        monkeypatch.setenv("SPINMC_HEIS_TILED", tiled)
+        monkeypatch.setenv("SPINMC_HEIS3D", indexed)
         spins = torch.zeros(3 * n_rep * L ** 3, dtype=torch.float32, device=DEV)
         S.spin_init(b, spins)
         acc = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
-        S.metropolis_sweep(b, spins, [0.693, 0.5, 1.2][:n_rep], 3, 20, dE_accum=acc)
+        S.metropolis_sweep(b, spins, [0.693, 0.5, 1.2][:n_rep], 3, n, dE_accum=acc)
         out.append((_host(spins).copy(), _host(acc).copy()))
-    assert np.array_equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0])
+        assert np.array_equal(out[0][1], o[1])
