@@ -1,12 +1,15 @@
-"""Benchmark: checkerboard Metropolis on the 16384^2 2D Ising lattice.
+"""Benchmark: checkerboard Metropolis on 16384^2 2D Ising lattices, plus the
+tempering and Heisenberg workloads.
 
-A step is one full sweep (colour 0 then colour 1, with Delta E tracking) of
-the 16384 x 16384 periodic Ising lattice; the K timed steps are split evenly
-over the three inverse temperatures beta in {0.30, beta_c, 0.50}, each on its
-own lattice from the seeded random start.  Spins are resident in HBM before
-the timed region.  Prints one JSON line: ns per spin flip (lower is better),
-the HBM roofline of the sweep kernel and the CPU oracle timed on a bounded
-sample (1024^2 lattice) of the same workload.
+The headline workload is three 16384 x 16384 periodic Ising lattices, one at
+each inverse temperature beta in {0.30, beta_c, 0.50}, from seeded random
+starts, swept as one batch of three replicas: a step is one sweep (colour 0
+then colour 1, with Delta E tracking) of all three, one kernel launch.
+Spins are resident in HBM before the timed region.  Prints one JSON line:
+ns per spin flip (lower is better), the HBM roofline of the sweep kernel
+(and the same kernel on one lattice alone), the batched tempering
+workloads against per-instance launches, the 3D Heisenberg workload, and
+the CPU oracle timed on a bounded sample (1024^2 lattice) of the workload.
 """
 from __future__ import annotations
 
@@ -91,6 +94,13 @@ def kt_summary(db: str, log: str, kernel: str, L: int, command: str):
              f"{'kernel':40s} {'calls':>7s} {'total_us':>12s} {'avg_us':>10s} {'pct':>7s}"]
     for name, calls, total, avg, pct in rows:
         lines.append(f"{short_name(name):40s} {calls:7d} {total:12.1f} {avg:10.3f} {pct:7.2f}")
+    # the same run times the batched launch and then single-lattice launches:
+    # the kernel's dispatches per grid size, from the kernels view
+    lines.append(f"# {kernel} per grid size (work-items): dispatches, mean duration in microseconds")
+    for grid, calls, avg in con.execute("select grid_x, count(*), avg(duration) / 1000.0 from kernels "
+                                        "where name like ? group by grid_x order by grid_x desc",
+                                        (f"%{kernel}%",)):
+        lines.append(f"grid_{grid}: {calls} {avg:.3f}")
     if bench_line:
         import json
 
@@ -159,20 +169,27 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
     that traffic_per_launch reads."""
     import sqlite3
 
-    def per_kernel(db, counter):
+    def per_kernel(db, counter, largest_grid=False):
         con = sqlite3.connect(db)
+        rows = con.execute("select kernel_name, value, grid_size from counters_collection where counter_name=?",
+                           (counter,)).fetchall()
+        biggest = {}
+        for name, _, grid in rows:
+            biggest[name] = max(biggest.get(name, 0), grid)
         acc = {}
-        for name, val in con.execute("select kernel_name, value from counters_collection where counter_name=?",
-                                     (counter,)):
-            acc.setdefault(name, []).append(val)
+        for name, val, grid in rows:
+            # the batched launch only, not the single-lattice launches the
+            # same run makes afterwards
+            if not largest_grid or grid == biggest[name]:
+                acc.setdefault(name, []).append(val)
         return acc
 
     def mean_of(acc, key):
         name = max((n for n in acc if key in n), key=lambda n: sum(acc[n]) / len(acc[n]))
         return name, sum(acc[name]) / len(acc[name])
 
-    kf, kfv = mean_of(per_kernel(fetch_db, "FETCH_SIZE"), kernel)
-    kw, kwv = mean_of(per_kernel(write_db, "WRITE_SIZE"), kernel)
+    kf, kfv = mean_of(per_kernel(fetch_db, "FETCH_SIZE", True), kernel)
+    kw, kwv = mean_of(per_kernel(write_db, "WRITE_SIZE", True), kernel)
     # the copy kernel: the one that fetched the most; its sums over the run
     # divided by the number of 1 GiB copies
     cf_all, cw_all = per_kernel(cfetch_db, "FETCH_SIZE"), per_kernel(cwrite_db, "WRITE_SIZE")
@@ -183,9 +200,11 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
     fetch_scale = copy_kib / cfv
     write_scale = copy_kib / cwv
     traffic = (kfv * fetch_scale + kwv * write_scale) * 1024.0
-    algorithmic = BYTES_PER_FLIP * L * L
-    lines = [f"# rocprofv3 --pmc summary: {kernel}, one launch = one sweep of the 2D Ising {L}x{L} lattice",
-             "# figures are means per dispatch of the counter over every dispatch of the kernel in the run"]
+    algorithmic = BYTES_PER_FLIP * L * L * 3
+    lines = [f"# rocprofv3 --pmc summary: {kernel}, one launch = one sweep of a batch of three 2D Ising {L}x{L} "
+             "lattices",
+             "# figures are means per dispatch of the counter over the kernel's dispatches of its largest grid "
+             "(the batched launch) in the run"]
     lines += [f"# command: {c}" for c in commands]
     lines += [f"kernel_source_sha256: {kernel_source_hash()}",
               f"kernel_FETCH_SIZE_KiB_per_dispatch: {kfv:.1f}",
@@ -396,6 +415,30 @@ def heisenberg3d(S, W, sweeps):
             "hbm_roof_at_24B_per_flip": {"achieved_GBps": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4)}}
 
 
+def single_lattice(S, cfg, sweeps):
+    """The sweep kernel on one lattice alone (beta_c): its time per launch and
+    HBM fraction, for comparison with the batched launch."""
+    import torch
+
+    L = cfg.L
+    N = L * L
+    b = S.Batch(S.ISING, 2, L, 1, cfg.seed)
+    s = torch.empty(N, dtype=torch.int8, device="cuda")
+    S.spin_init(b, s)
+    S.metropolis_sweep(b, s, [cfg.betas[1]], 0, 3)
+    S.kernel_timing_read()
+    S.kernel_timing_enable(True)
+    S.metropolis_sweep(b, s, [cfg.betas[1]], 3, sweeps)
+    torch.cuda.synchronize()
+    kernel_ms, launches = S.kernel_timing_read()
+    S.kernel_timing_enable(False)
+    us = kernel_ms * 1e3 / launches
+    del s
+    torch.cuda.empty_cache()
+    return {"sweeps": sweeps, "kernel_us_per_launch": round(us, 3),
+            "frac": round(BYTES_PER_FLIP * N / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,31 +488,28 @@ def main():
     N = L * L
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    b = S.Batch(S.ISING, 2, L, 1, cfg.seed)
-    lattices = []
-    for beta in cfg.betas:
-        s = torch.empty(N, dtype=torch.int8, device=dev)
-        S.spin_init(b, s)
-        lattices.append((beta, s, torch.zeros(1, dtype=torch.int64, device=dev)))
-    nb = len(lattices)
-    steps = max(nb, args.steps - args.steps % nb)
-    per = steps // nb
-    warm = max(1, args.warmup // nb)
-    for beta, s, dE in lattices:
-        S.metropolis_sweep(b, s, [beta], 0, warm, dE_accum=dE)
+    # The workload's three lattices (one per beta) are one batch of three
+    # replicas: a step is one sweep of all three (one launch).
+    nb = len(cfg.betas)
+    b = S.Batch(S.ISING, 2, L, nb, cfg.seed)
+    spins = torch.empty(nb * N, dtype=torch.int8, device=dev)
+    S.spin_init(b, spins)
+    dE = torch.zeros(nb, dtype=torch.int64, device=dev)
+    steps = max(1, args.steps)
+    warm = max(1, args.warmup)
+    S.metropolis_sweep(b, spins, cfg.betas, 0, warm, dE_accum=dE)
     torch.cuda.synchronize()
 
-    # Timed region: one call per lattice.  The library brackets the sweep
-    # kernels of each call with HIP events on the stream they run on, which
-    # gives the kernel's own time apart from the layout conversions.
+    # Timed region: one call.  The library brackets the sweep kernels of the
+    # call with HIP events on the stream they run on, which gives the
+    # kernel's own time apart from the layout conversions.
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     S.kernel_timing_read()  # drop anything recorded before
     S.kernel_timing_enable(True)
     t_wall = time.perf_counter()
     ev0.record(stream)
-    for beta, s, dE in lattices:
-        S.metropolis_sweep(b, s, [beta], warm, per, dE_accum=dE)
+    S.metropolis_sweep(b, spins, cfg.betas, warm, steps, dE_accum=dE)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
@@ -477,14 +517,17 @@ def main():
     S.kernel_timing_enable(False)
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = gpu_ms / steps
-    ns_per_flip = gpu_ms * 1e6 / (steps * N)
+    ns_per_flip = gpu_ms * 1e6 / (steps * nb * N)
 
     launches_per_sweep, kernel = S.sweep_plan(b)
     launch_ms = kernel_ms / launches
-    bytes_per_launch = BYTES_PER_FLIP * N / launches_per_sweep
+    bytes_per_launch = BYTES_PER_FLIP * nb * N / launches_per_sweep
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    conversion_ms = (gpu_ms - kernel_ms) / nb
+    conversion_ms = gpu_ms - kernel_ms
     traffic = traffic_per_launch(kernel, L)
+    del spins
+    torch.cuda.empty_cache()
+    single = single_lattice(S, cfg, min(steps, 200))
 
     out = {
         "metric": "ns per spin flip (+% HBM roofline); batched PT sweeps/s vs per-instance",
@@ -492,22 +535,24 @@ def main():
         "unit": "ns/flip",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": warm * nb,
+        "warmup": warm,
         "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int8",
         "data": "synthetic",
-        "config": {"workload": f"2D Ising {L}x{L} periodic, int8 spins, random start, beta in "
-                               f"{{0.30, ln(1+sqrt2)/2, 0.50}}, {per} sweeps each, Delta E tracked",
-                   "L": L, "betas": cfg.betas, "sweeps_per_beta": per, "seed": cfg.seed},
+        "config": {"workload": f"2D Ising {L}x{L} periodic, int8 spins, random start, three lattices at beta "
+                               f"{{0.30, ln(1+sqrt2)/2, 0.50}} swept together as one batch of three replicas "
+                               f"(one launch per sweep), {steps} sweeps, Delta E tracked",
+                   "L": L, "betas": cfg.betas, "replicas": nb, "sweeps": steps, "seed": cfg.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kernel, "launches_per_sweep": launches_per_sweep,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel_us_per_launch": round(launch_ms * 1e3, 3),
-                     "conversion_us_per_call": round(conversion_ms * 1e3, 3)},
+                     "conversion_us_per_call": round(conversion_ms * 1e3, 3),
+                     "single_lattice": single},
         "wall_s": round(wall, 4),
     }
     if not args.no_tempering:
