@@ -72,6 +72,7 @@ enum Slot {
     kTuneRows,
     kTuneE,
     kHeisPing,
+    kL2dPart,
     kNumSlots
 };
 
@@ -391,8 +392,15 @@ int uneven2d_threads(StreamCtx &c, hipStream_t s, const Uneven2dArgs &a, int L, 
         tinst[m] = rows[reps[m]];
         tinst[m].spin_off = (int64_t)m * N;
         twork[m] = m;
-        SMC_HIP(hipMemcpyAsync((int8_t *)sp + (int64_t)m * N, a.spins + rows[reps[m]].spin_off, (size_t)N,
-                               hipMemcpyDeviceToDevice, s));
+    }
+    // one copy per run of replicas that sit back to back in the caller's
+    // array (the temperatures of a chain usually do)
+    for (int m = 0; m < M;) {
+        int e = m + 1;
+        while (e < M && rows[reps[e]].spin_off == rows[reps[e - 1]].spin_off + N) ++e;
+        SMC_HIP(hipMemcpyAsync((int8_t *)sp + (int64_t)m * N, a.spins + rows[reps[m]].spin_off,
+                               (size_t)((int64_t)(e - m) * N), hipMemcpyDeviceToDevice, s));
+        m = e;
     }
     if ((rc = upload(c, s, kTuneInst, tinst.data(), sizeof(smc_inst) * M, &ip))) return rc;
     if ((rc = upload(c, s, kTuneWork, twork.data(), sizeof(int32_t) * M, &wp))) return rc;
@@ -858,14 +866,24 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         void *pp = nullptr;
         if ((rc = ensure(c, kPingPong, 2 * bytes, &pp))) return rc;
         uint8_t *A = (uint8_t *)pp, *B = A + bytes;
+        // energy changes: per-wave partial sums over the call, collected once at the end
+        int64_t *part = nullptr;
+        if (dE_accum) {
+            void *q = nullptr;
+            const size_t slots = lattice2d_de_slots(desc->L, desc->n_rep);
+            if (slots == 0) return fail(SMC_EINVAL, "no band shape for L=%d", desc->L);
+            if ((rc = ensure(c, kL2dPart, slots * sizeof(int64_t), &q))) return rc;
+            part = (int64_t *)q;
+        }
         SMC_HIP(launch_to_split((const int8_t *)spins, A, desc->L, desc->n_rep, s));
         SweepTimer timer(s, n_sweeps);
         for (int32_t k = 0; k < n_sweeps; ++k) {
             const uint32_t t = (uint32_t)(sweep0 + (uint64_t)k);
-            SMC_HIP(launch_ising2d_split(k & 1 ? B : A, k & 1 ? A : B, desc->L, desc->n_rep, a.thr, dE_accum, a.key,
-                                         t, s));
+            SMC_HIP(launch_ising2d_split(k & 1 ? B : A, k & 1 ? A : B, desc->L, desc->n_rep, a.thr, part, k == 0,
+                                         a.key, t, s));
         }
         timer.finish();
+        if (part) SMC_HIP(launch_lattice2d_de_collect(part, dE_accum, desc->L, desc->n_rep, s));
         SMC_HIP(launch_from_split(n_sweeps & 1 ? B : A, (int8_t *)spins, desc->L, desc->n_rep, s));
         return SMC_OK;
     }

@@ -168,7 +168,8 @@ struct Lattice2dArgs {
     int64_t rep_bytes;   // bytes per replica (2 planes of L rows at `pitch`)
     int64_t pitch;       // bytes between consecutive physical rows of a plane (>= L/2)
     const ThrRow *thr;   // per replica
-    int64_t *dE;         // per replica or nullptr
+    int64_t *dE_part;    // per compute wave of every workgroup (workgroup-major), or nullptr
+    int dE_first;        // 1: this launch writes the partial sums, 0: adds to them
     Key key;
     uint32_t t;
     int L, H, bands, n_rep;
@@ -433,7 +434,7 @@ __device__ __forceinline__ void step(Pipe<C> &S, const Band<C> &B, int j, const 
 }
 
 template <int C>
-__device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xch, int64_t *dE) {
+__device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xch, int64_t *dE_part, bool first) {
     Pipe<C> S;
     const int Y0 = B.Y0;  // a multiple of 4: step Y0-1 has phase 3
     // rows Y0-2 and Y0-1 of plane 1 (all later rows come through the ring)
@@ -458,12 +459,16 @@ __device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xc
         step<C, 3>(S, B, j + 3, ring, xch);
     }
     step<C, 0>(S, B, Y0 + B.H, ring, xch);
-    if (dE) {
-        // sum over sites of (dE/4 + 2) minus 2 per counted site
+    if (dE_part) {
+        // sum over sites of (dE/4 + 2) minus 2 per counted site, into this
+        // wave's own slot (no other wave touches it, so no atomics)
         long long v = ((long long)S.de_total - 2ll * (long long)S.counted * 8 * C) * 4;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd((unsigned long long *)&dE[B.r], (unsigned long long)v);
+        if ((threadIdx.x & 63) == 0) {
+            int64_t *slot = dE_part + (int64_t)blockIdx.x * B.ncw + (threadIdx.x >> 6);
+            *slot = first ? v : *slot + v;
+        }
     }
 }
 
@@ -496,7 +501,7 @@ __global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
         loader_loop<C, NF>(B, ring, (int)(threadIdx.x >> 6) - ncw);
     } else {
         B.K = make_lut(a.thr[r], a.one2, a.four);
-        compute_loop<C>(B, ring, xch, a.dE);
+        compute_loop<C>(B, ring, xch, a.dE_part, a.dE_first != 0);
     }
 }
 
@@ -545,6 +550,21 @@ __global__ __launch_bounds__(256) void k_from_split(const uint8_t *src, int8_t *
     v.z = perm(o1, e1, 0x05010400u);
     v.w = perm(o1, e1, 0x07030602u);
     *(uint4 *)(dst + r * N + (int64_t)y * L + 16 * xc) = v;
+}
+
+// Energy changes of a call: replica r adds the partial sums of its
+// workgroups' compute waves (slots [r * per_rep, (r + 1) * per_rep)).  One
+// workgroup per replica, so the update of dE[r] needs no atomics.
+__global__ __launch_bounds__(256) void k_de_collect(const int64_t *part, int64_t *dE, int per_rep) {
+    __shared__ long long red[4];
+    const int r = (int)blockIdx.x;
+    long long v = 0;
+    for (int i = (int)threadIdx.x; i < per_rep; i += 256) v += part[(int64_t)r * per_rep + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) dE[r] += red[0] + red[1] + red[2] + red[3];
 }
 
 }  // namespace
@@ -603,25 +623,19 @@ hipError_t launch_from_split(const uint8_t *src, int8_t *dst, int L, int n_rep, 
     return hipGetLastError();
 }
 
-hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_rep, const ThrRow *thr, int64_t *dE,
-                                Key key, uint32_t t, hipStream_t s) {
-    const int C = lattice2d_chunks(L);
-    const int H = lattice2d_band_height(L, n_rep);
-    if (C == 0 || H == 0) return hipErrorInvalidValue;
-    Lattice2dArgs a;
-    a.src = src;
-    a.dst = dst;
-    a.pitch = lattice2d_pitch(L);
-    a.rep_bytes = 2 * (int64_t)L * a.pitch;
-    a.thr = thr;
-    a.dE = dE;
-    a.key = key;
-    a.t = t;
-    a.L = L;
-    a.H = H;
-    a.H2 = H;
-    a.bands = L / H;
-    a.nb1 = a.bands;
+// Bands of one replica: nb1 of H rows, then bands - nb1 of H2 rows.
+struct BandShape {
+    int C, H, H2, nb1, bands, ncw;
+};
+
+static bool band_shape(int L, int n_rep, BandShape &g) {
+    g.C = lattice2d_chunks(L);
+    g.H = lattice2d_band_height(L, n_rep);
+    if (g.C == 0 || g.H == 0) return false;
+    g.H2 = g.H;
+    g.bands = L / g.H;
+    g.nb1 = g.bands;
+    g.ncw = L / (16 * g.C) / 64;
     // With exactly two bands per compute unit (one replica), the workgroups
     // dispatched first (one per CU) win issue arbitration against the second
     // ones and finish far ahead of them; giving the first ones bands of
@@ -633,19 +647,55 @@ hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_r
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         int h1 = 0, h2 = 0;
-        if (n_rep == 1 && cus > 0 && L / H == 2 * cus && H % 32 == 0) {
-            h1 = H + H / 8;
-            h2 = H - H / 8;
+        if (n_rep == 1 && cus > 0 && L / g.H == 2 * cus && g.H % 32 == 0) {
+            h1 = g.H + g.H / 8;
+            h2 = g.H - g.H / 8;
         }
         h1 = env_int("SPINMC_L2D_H1", h1);
         h2 = env_int("SPINMC_L2D_H2", h2);
         if (h1 > 0 && h2 > 0 && h1 % 4 == 0 && h2 % 4 == 0 && L % (h1 + h2) == 0) {
-            a.H = h1;
-            a.H2 = h2;
-            a.nb1 = L / (h1 + h2);
-            a.bands = 2 * a.nb1;
+            g.H = h1;
+            g.H2 = h2;
+            g.nb1 = L / (h1 + h2);
+            g.bands = 2 * g.nb1;
         }
     }
+    return true;
+}
+
+size_t lattice2d_de_slots(int L, int n_rep) {
+    BandShape g;
+    if (!band_shape(L, n_rep, g)) return 0;
+    return (size_t)g.bands * (size_t)n_rep * (size_t)g.ncw;
+}
+
+hipError_t launch_lattice2d_de_collect(const int64_t *part, int64_t *dE, int L, int n_rep, hipStream_t s) {
+    const size_t slots = lattice2d_de_slots(L, n_rep);
+    if (slots == 0 || n_rep <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_de_collect, dim3((unsigned)n_rep), dim3(256), 0, s, part, dE, (int)(slots / n_rep));
+    return hipGetLastError();
+}
+
+hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_rep, const ThrRow *thr,
+                                int64_t *dE_part, bool dE_first, Key key, uint32_t t, hipStream_t s) {
+    BandShape g;
+    if (!band_shape(L, n_rep, g)) return hipErrorInvalidValue;
+    const int C = g.C;
+    Lattice2dArgs a;
+    a.src = src;
+    a.dst = dst;
+    a.pitch = lattice2d_pitch(L);
+    a.rep_bytes = 2 * (int64_t)L * a.pitch;
+    a.thr = thr;
+    a.dE_part = dE_part;
+    a.dE_first = dE_first ? 1 : 0;
+    a.key = key;
+    a.t = t;
+    a.L = L;
+    a.H = g.H;
+    a.H2 = g.H2;
+    a.bands = g.bands;
+    a.nb1 = g.nb1;
     a.n_rep = n_rep;
     a.one2 = 0x00010001u;
     a.four = 4u;
