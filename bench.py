@@ -141,8 +141,8 @@ def valu_summary(db: str, command: str):
              "# util = SQ_INSTS_VALU / (GRBM_GUI_ACTIVE / 8 XCDs * 256 CUs); peak is one wave64 VALU",
              "# instruction per CU per cycle (four SIMD16 units, four cycles each)",
              f"{'kernel':28s} {'dispatches':>10s} {'VALU_insts':>14s} {'busy_cycles':>12s} {'util':>6s}"]
-    for k in ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_half", "k_half_sweep_generic",
-              "k_to_split", "k_from_split"):
+    for k in ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_tiled", "k_heis3d_half",
+              "k_half_sweep_generic", "k_philox_bench", "k_to_split", "k_from_split"):
         if k not in acc or "SQ_INSTS_VALU" not in acc[k] or "GRBM_GUI_ACTIVE" not in acc[k]:
             continue
         v = acc[k]["SQ_INSTS_VALU"]
@@ -415,6 +415,25 @@ def heisenberg3d(S, W, sweeps):
             "hbm_roof_at_24B_per_flip": {"achieved_GBps": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4)}}
 
 
+def rng_floor(S, n_threads=1 << 20, per_thread=128, reps=5):
+    """Philox4x32-10 alone (the generator throughput probe): time per block
+    and what it implies for the sweeps, which draw one block per 8 sites
+    (Ising/EA heads) or per site (Heisenberg)."""
+    import torch
+
+    out = torch.empty(n_threads, dtype=torch.int32, device="cuda")
+    S.philox_bench(1, 0, 0, 6, out, per_thread)  # warm-up
+    torch.cuda.synchronize()
+    best = min(_timed(lambda: S.philox_bench(1, 0, 0, 6, out, per_thread)) for _ in range(reps))
+    blocks = n_threads * per_thread
+    ps_per_block = best * 1e9 / blocks
+    del out
+    return {"kernel": "k_philox_bench", "blocks": blocks, "ms": round(best, 4),
+            "ps_per_block": round(ps_per_block, 4),
+            "ising_sweep_rng_ps_per_flip": round(ps_per_block / 8, 4),
+            "heisenberg_sweep_rng_ps_per_flip": round(ps_per_block, 4)}
+
+
 def single_lattice(S, cfg, sweeps):
     """The sweep kernel on one lattice alone (beta_c): its time per launch and
     HBM fraction, for comparison with the batched launch."""
@@ -528,6 +547,8 @@ def main():
     del spins
     torch.cuda.empty_cache()
     single = single_lattice(S, cfg, min(steps, 200))
+    rng = rng_floor(S)
+    rng["share_of_ising_sweep"] = round(rng["ising_sweep_rng_ps_per_flip"] / (launch_ms * 1e9 / (nb * N)), 4)
 
     out = {
         "metric": "ns per spin flip (+% HBM roofline); batched PT sweeps/s vs per-instance",
@@ -552,7 +573,7 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel_us_per_launch": round(launch_ms * 1e3, 3),
                      "conversion_us_per_call": round(conversion_ms * 1e3, 3),
-                     "single_lattice": single},
+                     "single_lattice": single, "rng_floor": rng},
         "wall_s": round(wall, 4),
     }
     if not args.no_tempering:

@@ -209,6 +209,21 @@ int smc_kernel_timing_read(double *elapsed_ms, int64_t *launches);
 int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, int32_t *launches,
                 const char **kernel_name);
 
+/*
+ * Throughput probe of the random-number generator (Sec. 3.3, Fig. 4
+ * measure generators on their own): thread i of n_threads draws the
+ * Philox4x32-10 blocks with counters (i + k * n_threads, t, r, tag) for
+ * k = 0 .. per_thread-1 under the key of `seed`, and writes the XOR of all
+ * their words to out[i] (device, n_threads words, owned by the caller).
+ * Not part of the method: it gives the generator's cost per block on its
+ * own, against which the sweep kernels' times are read.  SMC_EINVAL if out
+ * is NULL, n_threads or per_thread is not positive, or
+ * n_threads * per_thread exceeds 2^32 (the block index is one 32-bit word).
+ * Asynchronous on `stream`.
+ */
+int smc_philox_bench(uint64_t seed, uint32_t t, uint32_t r, uint32_t tag, int32_t n_threads, int32_t per_thread,
+                     uint32_t *out, void *stream);
+
 /* Static description of a status code. */
 const char *smc_strerror(int status);
 

@@ -67,6 +67,9 @@ def lib():
         L.smc_kernel_timing_enable.restype = C.c_int
         L.smc_kernel_timing_read.argtypes = [P(C.c_double), P(C.c_int64)]
         L.smc_kernel_timing_read.restype = C.c_int
+        L.smc_philox_bench.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
+                                       C.c_void_p, C.c_void_p]
+        L.smc_philox_bench.restype = C.c_int
         L.smc_strerror.argtypes = [C.c_int]
         L.smc_strerror.restype = C.c_char_p
         L.smc_last_error.argtypes = []
@@ -208,6 +211,17 @@ def sweep_kernel_name(batch: Batch) -> str:
 def kernel_timing_enable(on: bool = True):
     """Bracket the sweep kernels of each smc_metropolis_sweep call with HIP events (profiling aid)."""
     _check(lib().smc_kernel_timing_enable(1 if on else 0), "smc_kernel_timing_enable")
+
+
+def philox_bench(seed: int, t: int, r: int, tag: int, out, per_thread: int, stream=None):
+    """Generator throughput probe: out[i] (uint32 tensor, n_threads entries, given
+    as int32) = XOR of the words of blocks (i + k*n_threads, t, r, tag), k < per_thread."""
+    import torch
+
+    if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous():
+        raise TypeError("out must be a contiguous int32 device tensor")
+    _check(lib().smc_philox_bench(seed, t, r, tag, out.numel(), per_thread, _ptr(out), _stream(stream)),
+           "smc_philox_bench")
 
 
 def kernel_timing_read():

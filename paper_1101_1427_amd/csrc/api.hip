@@ -670,6 +670,18 @@ int smc_kernel_timing_enable(int enable) {
     return SMC_OK;
 }
 
+int smc_philox_bench(uint64_t seed, uint32_t t, uint32_t r, uint32_t tag, int32_t n_threads, int32_t per_thread,
+                     uint32_t *out, void *stream) {
+    g_last_error.clear();
+    if (!out) return fail(SMC_EINVAL, "out is NULL");
+    if (n_threads <= 0 || per_thread <= 0) return fail(SMC_EINVAL, "n_threads and per_thread must be positive");
+    if ((int64_t)n_threads * per_thread > (int64_t)1 << 32)
+        return fail(SMC_EINVAL, "n_threads * per_thread exceeds 2^32");
+    SMC_HIP(launch_philox_bench(make_key(seed), t, r, tag, (uint32_t)n_threads, per_thread, out,
+                                (hipStream_t)stream));
+    return SMC_OK;
+}
+
 int smc_kernel_timing_read(double *elapsed_ms, int64_t *launches) {
     g_last_error.clear();
     if (!elapsed_ms || !launches) return fail(SMC_EINVAL, "output pointers are required");

@@ -118,6 +118,11 @@ hipError_t add_advance_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNo
 hipError_t add_pt_swap_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
                             const SwapArgs &a);
 
+// Generator throughput: out[i] = XOR of the four words of the blocks with
+// counters (i + k * n_threads, t, r, tag), k < per_thread.
+hipError_t launch_philox_bench(Key key, uint32_t t, uint32_t r, uint32_t tag, uint32_t n_threads, int per_thread,
+                               uint32_t *out, hipStream_t s);
+
 // Measurement: partials of every replica, then a fixed-order final sum.
 hipError_t launch_measure(const Batch &b, const void *spins, const int8_t *coup, int max_L, double *energy,
                           double *magnet, void *scratch, size_t scratch_bytes, hipStream_t s);

@@ -119,3 +119,12 @@ def test_kernel_timing_without_calls_reads_zero():
     assert S.kernel_timing_read() == (0.0, 0)
     S.kernel_timing_enable(False)
     assert S.kernel_timing_read() == (0.0, 0)
+
+
+def test_philox_bench_arguments_are_validated():
+    L = S.lib()
+    assert L.smc_philox_bench(1, 0, 0, 0, 16, 4, None, None) == S.EINVAL
+    assert L.smc_philox_bench(1, 0, 0, 0, 0, 4, FAKE, None) == S.EINVAL
+    assert L.smc_philox_bench(1, 0, 0, 0, 16, 0, FAKE, None) == S.EINVAL
+    rc = L.smc_philox_bench(1, 0, 0, 0, 1 << 20, 1 << 13, FAKE, None)
+    assert rc == S.EINVAL and b"2^32" in L.smc_last_error()
