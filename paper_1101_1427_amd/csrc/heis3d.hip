@@ -128,7 +128,7 @@ constexpr int kSeg = 32;
 constexpr int kW = kTile + 4;       // staged width with the halo
 constexpr int kPlane = kW * kW;     // sites per staged plane
 constexpr int kRing = 4;
-constexpr int kTiledThreads = 512;
+constexpr int kTiledThreads = 576;  // one colour-0 cell per thread (see update_colour0)
 constexpr int kLoadsPerThread = (kPlane + kTiledThreads - 1) / kTiledThreads;
 
 struct TiledArgs {
@@ -183,50 +183,79 @@ __device__ __forceinline__ F3 lds3(const float *ring, int slot, int q) {
     return r;
 }
 
-// Update the colour-c sites of plane z (ring slot sz) within staged rows and
-// columns [lo, hi); planes z-1 and z+1 sit in slots sm and sp.  Counts the
-// accepted moves of sites inside the tile when `count`.
-__device__ __forceinline__ int update_plane(float *ring, int sm, int sz, int sp, int lo, int hi, int c, int x0, int y0,
-                                            int z, const TiledArgs &a, int r, float beta, bool count) {
-    const int L = 1 << a.lgL;
-    const uint32_t m = (uint32_t)L - 1u;
+// Update the colour-c site at staged cell (u, v) of plane z (ring slot sz);
+// planes z-1 and z+1 sit in slots sm and sp.  Returns whether it moved.
+__device__ __forceinline__ bool update_cell(float *ring, int sm, int sz, int sp, int u, int v, int c, int x0, int y0,
+                                            int z, const TiledArgs &a, int r, float beta) {
+    const uint32_t m = (1u << a.lgL) - 1u;
     const uint32_t zz = (uint32_t)z & m;
-    const int n = hi - lo;           // staged cells per row
-    const int per_row = n >> 1;      // colour-c cells per row (n even)
-    int n_acc = 0;
-    for (int k = threadIdx.x; k < n * per_row; k += kTiledThreads) {
-        const int vv = k / per_row, j = k - vv * per_row;
-        const int v = lo + vv;
-        const uint32_t y = (uint32_t)(y0 - 2 + v) & m;
-        // first column of colour c in this row: global x parity = c - y - z
-        const int u0 = lo + (((c - (int)y - (int)zz - (x0 - 2 + lo)) % 2) + 2) % 2;
-        const int u = u0 + 2 * j;
-        const uint32_t x = (uint32_t)(x0 - 2 + u) & m;
-        const int q = v * kW + u;
-        const F3 nx1 = lds3(ring, sz, q + 1), nx0 = lds3(ring, sz, q - 1);
-        const F3 ny1 = lds3(ring, sz, q + kW), ny0 = lds3(ring, sz, q - kW);
-        const F3 nz1 = lds3(ring, sp, q), nz0 = lds3(ring, sm, q);
-        const F3 so = lds3(ring, sz, q);
-        float3 hf = make_float3(0.f, 0.f, 0.f);
-        hf.x += nx1.x; hf.y += nx1.y; hf.z += nx1.z;
-        hf.x += nx0.x; hf.y += nx0.y; hf.z += nx0.z;
-        hf.x += ny1.x; hf.y += ny1.y; hf.z += ny1.z;
-        hf.x += ny0.x; hf.y += ny0.y; hf.z += ny0.z;
-        hf.x += nz1.x; hf.y += nz1.y; hf.z += nz1.z;
-        hf.x += nz0.x; hf.y += nz0.y; hf.z += nz0.z;
-        const uint32_t i = (((zz << a.lgL) + y) << a.lgL) + x;
-        const uint4 w = philox4x32_10(make_uint4(i >> 1, a.t, (uint32_t)r, 2 * kTagHeis + (uint32_t)c), a.key);
-        const float3 sp3 = heis_proposal(unit23f(w.x), unit23f(w.y));
-        const float dE = -((sp3.x - so.x) * hf.x + (sp3.y - so.y) * hf.y + (sp3.z - so.z) * hf.z);
-        if (dE <= 0.0f || unit23f(w.z) < heis_boltzmann(beta, dE)) {
-            float *P = ring + sz * 3 * kPlane;
-            P[q] = sp3.x;
-            P[kPlane + q] = sp3.y;
-            P[2 * kPlane + q] = sp3.z;
-            if (count && u >= 2 && u < 2 + kTile && v >= 2 && v < 2 + kTile) ++n_acc;
-        }
+    const uint32_t x = (uint32_t)(x0 - 2 + u) & m, y = (uint32_t)(y0 - 2 + v) & m;
+    const int q = v * kW + u;
+    const F3 nx1 = lds3(ring, sz, q + 1), nx0 = lds3(ring, sz, q - 1);
+    const F3 ny1 = lds3(ring, sz, q + kW), ny0 = lds3(ring, sz, q - kW);
+    const F3 nz1 = lds3(ring, sp, q), nz0 = lds3(ring, sm, q);
+    const F3 so = lds3(ring, sz, q);
+    float3 hf = make_float3(0.f, 0.f, 0.f);
+    hf.x += nx1.x; hf.y += nx1.y; hf.z += nx1.z;
+    hf.x += nx0.x; hf.y += nx0.y; hf.z += nx0.z;
+    hf.x += ny1.x; hf.y += ny1.y; hf.z += ny1.z;
+    hf.x += ny0.x; hf.y += ny0.y; hf.z += ny0.z;
+    hf.x += nz1.x; hf.y += nz1.y; hf.z += nz1.z;
+    hf.x += nz0.x; hf.y += nz0.y; hf.z += nz0.z;
+    const uint32_t i = (((zz << a.lgL) + y) << a.lgL) + x;
+    const uint4 w = philox4x32_10(make_uint4(i >> 1, a.t, (uint32_t)r, 2 * kTagHeis + (uint32_t)c), a.key);
+    const float3 sp3 = heis_proposal(unit23f(w.x), unit23f(w.y));
+    const float dE = -((sp3.x - so.x) * hf.x + (sp3.y - so.y) * hf.y + (sp3.z - so.z) * hf.z);
+    if (dE <= 0.0f || unit23f(w.z) < heis_boltzmann(beta, dE)) {
+        float *P = ring + sz * 3 * kPlane;
+        P[q] = sp3.x;
+        P[kPlane + q] = sp3.y;
+        P[2 * kPlane + q] = sp3.z;
+        return true;
     }
-    return n_acc;
+    return false;
+}
+
+// First staged column u >= lo of staged row v whose site has colour c in plane z.
+__device__ __forceinline__ int first_cell(int lo, int v, int c, int x0, int y0, int z) {
+    return lo + ((c - (x0 - 2 + lo) - (y0 - 2 + v) - z) & 1);
+}
+
+// Colour 0 of plane z on the tile and on the one-site ring around it without
+// the ring's corners (no tile site neighbours them): staged rows 1 and kW-2
+// over columns [2, kW-2), rows 2 .. kW-3 over columns [1, kW-1).  That is
+// kTile/2 + kTile*(kTile/2 + 1) + kTile/2 cells, one per thread.
+constexpr int kRingRowCells = kTile / 2;
+constexpr int kMidRowCells = kTile / 2 + 1;
+constexpr int kColour0Cells = 2 * kRingRowCells + kTile * kMidRowCells;
+static_assert(kColour0Cells == kTiledThreads, "one colour-0 cell per thread");
+
+__device__ __forceinline__ int update_colour0(float *ring, int sm, int sz, int sp, int x0, int y0, int z,
+                                              const TiledArgs &a, int r, float beta, bool count) {
+    const int k = (int)threadIdx.x;
+    int v, lo, j;
+    if (k < kRingRowCells) {
+        v = 1, lo = 2, j = k;
+    } else if (k < kRingRowCells + kTile * kMidRowCells) {
+        const int kk = k - kRingRowCells;
+        v = 2 + kk / kMidRowCells, lo = 1, j = kk % kMidRowCells;
+    } else {
+        v = kW - 2, lo = 2, j = k - kRingRowCells - kTile * kMidRowCells;
+    }
+    const int u = first_cell(lo, v, 0, x0, y0, z) + 2 * j;
+    const bool moved = update_cell(ring, sm, sz, sp, u, v, 0, x0, y0, z, a, r, beta);
+    return moved && count && u >= 2 && u < 2 + kTile && v >= 2 && v < 2 + kTile ? 1 : 0;
+}
+
+// Colour 1 of plane z on the tile: kTile * kTile / 2 cells, one per thread
+// of the first kTile * kTile / 2.
+__device__ __forceinline__ int update_colour1(float *ring, int sm, int sz, int sp, int x0, int y0, int z,
+                                              const TiledArgs &a, int r, float beta) {
+    const int k = (int)threadIdx.x;
+    if (k >= kTile * kTile / 2) return 0;
+    const int v = 2 + k / (kTile / 2), j = k % (kTile / 2);
+    const int u = first_cell(2, v, 1, x0, y0, z) + 2 * j;
+    return update_cell(ring, sm, sz, sp, u, v, 1, x0, y0, z, a, r, beta) ? 1 : 0;
 }
 
 __global__ __launch_bounds__(kTiledThreads) void k_heis3d_tiled(TiledArgs a) {
@@ -261,13 +290,12 @@ __global__ __launch_bounds__(kTiledThreads) void k_heis3d_tiled(TiledArgs a) {
             __syncthreads();
         }
         // colour 0 of plane z on the tile and a one-site ring
-        n_acc += update_plane(ring, (z - 1) & 3, z & 3, (z + 1) & 3, 1, kW - 1, 0, x0, y0, z, a, r, beta,
-                              z >= z0 && z < z1);
+        n_acc += update_colour0(ring, (z - 1) & 3, z & 3, (z + 1) & 3, x0, y0, z, a, r, beta, z >= z0 && z < z1);
         __syncthreads();
         if (z >= z0 + 1) {
             // colour 1 of plane z-1 on the tile, then the tile's plane z-1 out
             const int zc = z - 1;
-            n_acc += update_plane(ring, (zc - 1) & 3, zc & 3, z & 3, 2, 2 + kTile, 1, x0, y0, zc, a, r, beta, true);
+            n_acc += update_colour1(ring, (zc - 1) & 3, zc & 3, z & 3, x0, y0, zc, a, r, beta);
             __syncthreads();
             const uint32_t zz = (uint32_t)zc & m;
             for (int k = threadIdx.x; k < kTile * kTile; k += kTiledThreads) {
