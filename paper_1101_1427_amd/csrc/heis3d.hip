@@ -4,6 +4,8 @@
 // random numbers), with 32-bit shift/mask indexing instead of 64-bit
 // divisions and one 12-byte load per neighbour.  A thread handles the
 // colour-c sites of site pairs (2p, 2p+1), whose in-colour index is p.
+#include <stdlib.h>
+
 #include "heis_math.hpp"
 #include "internal.hpp"
 
@@ -141,6 +143,7 @@ struct TiledArgs {
     int lgL;
     int64_t N;
     int tiles, segs;   // tiles per row of tiles, segments per replica
+    int xcd_remap;     // 1: consecutive tiles of a segment on one XCD (shared halo lines in its L2)
 };
 
 struct PlaneRegs {
@@ -263,8 +266,13 @@ __global__ __launch_bounds__(kTiledThreads) void k_heis3d_tiled(TiledArgs a) {
     __shared__ int red[kTiledThreads / 64];
     const int L = 1 << a.lgL;
     const int per_rep = a.tiles * a.tiles * a.segs;
-    const int r = blockIdx.x / per_rep;
-    const int rem = blockIdx.x % per_rep;
+    // Workgroups go to the XCDs round-robin; with the remap, XCD k runs a
+    // contiguous range of logical blocks (whole segments), so the halo rows
+    // and columns that neighbouring tiles share are fetched once into its L2.
+    const uint32_t nblk = gridDim.x, b = blockIdx.x;
+    const int lb = (int)((a.xcd_remap && (nblk & 7u) == 0) ? (b & 7u) * (nblk >> 3) + (b >> 3) : b);
+    const int r = lb / per_rep;
+    const int rem = lb % per_rep;
     const int seg = rem / (a.tiles * a.tiles), tile = rem % (a.tiles * a.tiles);
     const int x0 = (tile % a.tiles) * kTile, y0 = (tile / a.tiles) * kTile;
     const int z0 = seg * kSeg, z1 = z0 + (kSeg < L ? kSeg : L);
@@ -358,6 +366,10 @@ hipError_t launch_heis3d_tiled(const float *src, float *dst, const float *beta, 
     a.N = (int64_t)L * L * L;
     a.tiles = L / kTile;
     a.segs = L > kSeg ? L / kSeg : 1;
+    {
+        const char *e = getenv("SPINMC_XCD_REMAP");
+        a.xcd_remap = (e && e[0] == '0') ? 0 : 1;
+    }
     const size_t lds = heis3d_tiled_lds_bytes();
     (void)hipFuncSetAttribute((const void *)k_heis3d_tiled, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const unsigned blocks = (unsigned)(a.tiles * a.tiles * a.segs * n_rep);

@@ -84,7 +84,7 @@ def test_heisenberg_long_run_energy_within_three_sigma():
     assert -1.5 < mg < -0.5 and -1.5 < mr < -0.5
 
 
-@pytest.mark.parametrize("L,n_rep,n", [(16, 3, 20), (32, 2, 19), (64, 1, 20)])
+@pytest.mark.parametrize("L,n_rep,n", [(16, 3, 20), (32, 2, 19), (64, 1, 20), (128, 1, 5)])
 def test_gpu_heisenberg_kernels_agree(monkeypatch, L, n_rep, n):
     """The one-pass tiled kernel (edge >= 32), the two-launch indexed kernel
     and the generic kernel perform the same float32 arithmetic in the same
@@ -95,7 +95,8 @@ def test_gpu_heisenberg_kernels_agree(monkeypatch, L, n_rep, n):
     b = S.Batch(S.HEISENBERG, 3, L, n_rep, seed, renorm_every=16)
     assert S.sweep_plan(b)[1] == ("k_heis3d_tiled" if L >= 32 else "k_heis3d_half")
     out = []
-    for tiled, indexed in (("1", "1"), ("0", "1"), ("0", "0")):
+    for tiled, indexed, remap in (("1", "1", "1"), ("1", "1", "0"), ("0", "1", "1"), ("0", "0", "1")):
+        monkeypatch.setenv("SPINMC_XCD_REMAP", remap)
         monkeypatch.setenv("SPINMC_HEIS_TILED", tiled)
         monkeypatch.setenv("SPINMC_HEIS3D", indexed)
         spins = torch.zeros(3 * n_rep * L ** 3, dtype=torch.float32, device=DEV)
