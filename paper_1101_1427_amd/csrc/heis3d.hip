@@ -124,12 +124,20 @@ __global__ __launch_bounds__(kThreads) void k_heis3d_half(Heis3dArgs a, int c) {
 // the neighbouring tiles (every draw is keyed by the site), so tiles never
 // exchange data; reads come from one buffer and writes go to the other.
 // Planes live in LDS as structure-of-arrays float planes of
-// (kTile+4) x (kTile+4) sites (two-site halo), four planes in a ring.
+// (kTile+4) x (kTile+4) sites (two-site halo), five planes in a ring.
+//
+// Order within step z: request plane z+2 from global memory into
+// registers, colour 0 of plane z, colour 1 of plane z-1, then wait for the
+// requested plane, put it into the slot of plane z-3, and only then store
+// the tile's plane z-1 to global memory.  Loads and stores share one
+// completion counter on this target, so a wait for data also waits for
+// every store issued before it; in this order the stores a wait covers were
+// issued two update phases earlier and have completed.
 constexpr int kTile = 32;
 constexpr int kSeg = 32;
 constexpr int kW = kTile + 4;       // staged width with the halo
 constexpr int kPlane = kW * kW;     // sites per staged plane
-constexpr int kRing = 4;
+constexpr int kRing = 5;
 constexpr int kTiledThreads = 576;  // one colour-0 cell per thread (see update_colour0)
 constexpr int kLoadsPerThread = (kPlane + kTiledThreads - 1) / kTiledThreads;
 
@@ -163,6 +171,8 @@ __device__ __forceinline__ void load_plane(const float *src, int L, int lgL, int
         }
     }
 }
+
+__device__ __forceinline__ int slot_of(int z) { return (z + 2 * kRing) % kRing; }  // z >= -2 * kRing
 
 __device__ __forceinline__ void store_plane(float *ring, int slot, const PlaneRegs &pr) {
     float *P = ring + slot * 3 * kPlane;
@@ -281,34 +291,37 @@ __global__ __launch_bounds__(kTiledThreads) void k_heis3d_tiled(TiledArgs a) {
     const float beta = a.beta[r];
     const uint32_t m = (uint32_t)L - 1u;
 
-    // planes z0-2 .. z0 into slots (plane & 3); plane z0+1 requested
+    // planes z0-2 .. z0 into their slots
     PlaneRegs pr;
     for (int z = z0 - 2; z <= z0; ++z) {
         load_plane(src, L, a.lgL, x0, y0, z, pr);
-        store_plane(ring, z & 3, pr);
+        store_plane(ring, slot_of(z), pr);
     }
-    load_plane(src, L, a.lgL, x0, y0, z0 + 1, pr);
     __syncthreads();
     int n_acc = 0;
-    for (int z = z0 - 1; z < z1 + 1; ++z) {
-        // plane z+1 (requested one step ago) into its slot, plane z+2 requested
-        if (z >= z0) {
-            store_plane(ring, (z + 1) & 3, pr);
-            if (z + 2 <= z1 + 1) load_plane(src, L, a.lgL, x0, y0, z + 2, pr);
-            __syncthreads();
-        }
-        // colour 0 of plane z on the tile and a one-site ring
-        n_acc += update_colour0(ring, (z - 1) & 3, z & 3, (z + 1) & 3, x0, y0, z, a, r, beta, z >= z0 && z < z1);
+    for (int z = z0 - 1; z <= z1; ++z) {
+        const bool fetch = z + 2 <= z1 + 1;
+        if (fetch) load_plane(src, L, a.lgL, x0, y0, z + 2, pr);
+        // colour 0 of plane z on the tile and a one-site ring (planes z-1 .. z+1)
+        n_acc += update_colour0(ring, slot_of(z - 1), slot_of(z), slot_of(z + 1), x0, y0, z, a, r, beta,
+                                z >= z0 && z < z1);
+        __syncthreads();
+        // colour 1 of plane z-1 on the tile (planes z-2 .. z)
+        if (z >= z0 + 1) n_acc += update_colour1(ring, slot_of(z - 2), slot_of(z - 1), slot_of(z), x0, y0, z - 1, a,
+                                                 r, beta);
+        // plane z+2 into the slot of plane z-3.  The wait is explicit and on
+        // every path, so that no load is left pending across the loop (the
+        // next step's request would otherwise wait behind this step's stores).
+        __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));  // vmcnt(0)
+        if (fetch) store_plane(ring, slot_of(z + 2), pr);
         __syncthreads();
         if (z >= z0 + 1) {
-            // colour 1 of plane z-1 on the tile, then the tile's plane z-1 out
+            // the tile's plane z-1 out
             const int zc = z - 1;
-            n_acc += update_colour1(ring, (zc - 1) & 3, zc & 3, z & 3, x0, y0, zc, a, r, beta);
-            __syncthreads();
             const uint32_t zz = (uint32_t)zc & m;
             for (int k = threadIdx.x; k < kTile * kTile; k += kTiledThreads) {
                 const int v = 2 + k / kTile, u = 2 + k % kTile;
-                const F3 val = lds3(ring, zc & 3, v * kW + u);
+                const F3 val = lds3(ring, slot_of(zc), v * kW + u);
                 const uint32_t x = (uint32_t)(x0 + u - 2) & m, y = (uint32_t)(y0 + v - 2) & m;
                 *(F3 *)(dst + 3 * (size_t)((((zz << a.lgL) + y) << a.lgL) + x)) = val;
             }
