@@ -27,15 +27,18 @@ BYTES_PER_FLIP = 2.0  # int8 spin read once and written once per sweep
 
 
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ("lattice2d.hip", "lattice2d.hpp", "philox.hpp", "tables.hpp")
+KERNEL_SOURCES = {
+    "k_ising2d_split": ("lattice2d.hip", "lattice2d.hpp", "philox.hpp", "tables.hpp"),
+    "k_heis3d_tiled": ("heis3d.hip", "heis_math.hpp", "philox.hpp"),
+}
 
 
-def kernel_source_hash() -> str:
-    """sha256 over the sources the 2D sweep kernel is compiled from."""
+def kernel_source_hash(kernel: str = "k_ising2d_split") -> str:
+    """sha256 over the sources a sweep kernel is compiled from."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1101_1427_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -58,7 +61,7 @@ def traffic_per_launch(kernel: str, L: int):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
+    if kv.get("kernel_source_sha256") != kernel_source_hash(kernel):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -164,6 +167,8 @@ def short_name(name: str) -> str:
 
 def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, kernel: str, L: int,
                 commands: list[str]):
+    """kernel k_ising2d_split: one launch sweeps the bench's batch of three
+    L x L lattices; k_heis3d_tiled: one launch sweeps one L^3 lattice."""
     """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the sweep kernel and
     of the copy kernel, from rocprofv3 result databases; writes the summary
     that traffic_per_launch reads."""
@@ -200,13 +205,17 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
     fetch_scale = copy_kib / cfv
     write_scale = copy_kib / cwv
     traffic = (kfv * fetch_scale + kwv * write_scale) * 1024.0
-    algorithmic = BYTES_PER_FLIP * L * L * 3
-    lines = [f"# rocprofv3 --pmc summary: {kernel}, one launch = one sweep of a batch of three 2D Ising {L}x{L} "
-             "lattices",
+    if kernel == "k_heis3d_tiled":
+        algorithmic = 24.0 * L ** 3
+        what = f"one launch = one sweep of a 3D Heisenberg {L}^3 lattice (24 B per site)"
+    else:
+        algorithmic = BYTES_PER_FLIP * L * L * 3
+        what = f"one launch = one sweep of a batch of three 2D Ising {L}x{L} lattices"
+    lines = [f"# rocprofv3 --pmc summary: {kernel}, {what}",
              "# figures are means per dispatch of the counter over the kernel's dispatches of its largest grid "
              "(the batched launch) in the run"]
     lines += [f"# command: {c}" for c in commands]
-    lines += [f"kernel_source_sha256: {kernel_source_hash()}",
+    lines += [f"kernel_source_sha256: {kernel_source_hash(kernel)}",
               f"kernel_FETCH_SIZE_KiB_per_dispatch: {kfv:.1f}",
               f"kernel_WRITE_SIZE_KiB_per_dispatch: {kwv:.1f}",
               f"copy_kernel: {short_name(copy_name)}",
@@ -412,7 +421,9 @@ def heisenberg3d(S, W, sweeps):
                         f"{cfg.renorm_every} sweeps, {sweeps} sweeps",
             "kernel": kernel, "sweeps": sweeps, "ms": round(ms, 3), "ns_per_flip": round(ps / 1e3, 6),
             "energy_per_spin": round(float(E.item()) / N, 6),
-            "hbm_roof_at_24B_per_flip": {"achieved_GBps": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+            "hbm_roof_at_24B_per_flip": {"achieved_GBps": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                         "kernel_us_per_sweep": round(kernel_ms * 1e3 / sweeps, 3),
+                                         "traffic": traffic_per_launch(kernel, L)}}
 
 
 def rng_floor(S, n_threads=1 << 20, per_thread=128, reps=5):
@@ -469,6 +480,9 @@ def main():
     ap.add_argument("--pt3d-steps", type=int, default=10_000)
     ap.add_argument("--uneven-steps", type=int, default=5000)
     ap.add_argument("--heis-sweeps", type=int, default=1000)
+    ap.add_argument("--heis-only", action="store_true", help="only the Heisenberg measurement (for profiling)")
+    ap.add_argument("--pmc-kernel", default="k_ising2d_split", choices=sorted(KERNEL_SOURCES),
+                    help="kernel of the --pmc-summary")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter scale for the traffic figure)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
@@ -487,7 +501,8 @@ def main():
         kt_summary(*args.kt_summary, kernel="k_ising2d_split", L=args.L, command=args.kt_command)
         return
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, kernel="k_ising2d_split", L=args.L, commands=args.pmc_command)
+        pmc_summary(*args.pmc_summary, kernel=args.pmc_kernel, L=256 if args.pmc_kernel == "k_heis3d_tiled" else args.L,
+                    commands=args.pmc_command)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -502,6 +517,9 @@ def main():
     import paper_1101_1427_amd as S
     import workloads as W
 
+    if args.heis_only:
+        print(json.dumps({"heisenberg": heisenberg3d(S, W, args.heis_sweeps)}))
+        return
     cfg = W.ising_large(args.L)
     L = cfg.L
     N = L * L

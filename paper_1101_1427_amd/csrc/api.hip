@@ -840,13 +840,15 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
             void *pp = nullptr;
             if ((rc = ensure(c, kHeisPing, bytes, &pp))) return rc;
             float *A = (float *)spins, *B = (float *)pp;
-            SweepTimer timer(s, n_sweeps);  // the renormalisations run inside the same pair
+            SweepTimer timer(s, n_sweeps);
             for (int32_t k = 0; k < n_sweeps; ++k) {
                 a.t = (uint32_t)(sweep0 + (uint64_t)k);
                 float *src = k & 1 ? B : A, *dst = k & 1 ? A : B;
-                SMC_HIP(launch_heis3d_tiled(src, dst, a.beta_f, dE_accum, desc->n_rep, desc->L, a.key, a.t, s));
-                if (desc->renorm_every > 0 && ((uint64_t)a.t + 1) % (uint64_t)desc->renorm_every == 0)
-                    SMC_HIP(launch_heis_renorm(plan.b, dst, plan.max_L, s));
+                // the renormalisation is applied as the sweep stores its spins
+                const bool renorm =
+                    desc->renorm_every > 0 && ((uint64_t)a.t + 1) % (uint64_t)desc->renorm_every == 0;
+                SMC_HIP(launch_heis3d_tiled(src, dst, a.beta_f, dE_accum, desc->n_rep, desc->L, a.key, a.t, renorm,
+                                            s));
             }
             timer.finish();
             if (n_sweeps & 1) SMC_HIP(hipMemcpyAsync(A, B, bytes, hipMemcpyDeviceToDevice, s));

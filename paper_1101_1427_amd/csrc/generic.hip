@@ -233,11 +233,10 @@ __global__ __launch_bounds__(kBlock) void k_heis_renorm(Batch b, float *spins, i
     const int64_t i = (int64_t)(blockIdx.x % bpr) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     float *s = spins + 3 * (g.spin_off + i);
-    const float x = s[0], y = s[1], z = s[2];
-    const float n = sqrtf(x * x + y * y + z * z);
-    s[0] = x / n;
-    s[1] = y / n;
-    s[2] = z / n;
+    const float3 u = heis_unit(s[0], s[1], s[2]);
+    s[0] = u.x;
+    s[1] = u.y;
+    s[2] = u.z;
 }
 
 // ------------------------------------------------------------ measurement ----

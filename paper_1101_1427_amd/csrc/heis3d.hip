@@ -152,6 +152,7 @@ struct TiledArgs {
     int64_t N;
     int tiles, segs;   // tiles per row of tiles, segments per replica
     int xcd_remap;     // 1: consecutive tiles of a segment on one XCD (shared halo lines in its L2)
+    int renorm;        // 1: the stored spins are renormalised (this sweep ends a renormalisation period)
 };
 
 struct PlaneRegs {
@@ -321,7 +322,13 @@ __global__ __launch_bounds__(kTiledThreads) void k_heis3d_tiled(TiledArgs a) {
             const uint32_t zz = (uint32_t)zc & m;
             for (int k = threadIdx.x; k < kTile * kTile; k += kTiledThreads) {
                 const int v = 2 + k / kTile, u = 2 + k % kTile;
-                const F3 val = lds3(ring, slot_of(zc), v * kW + u);
+                F3 val = lds3(ring, slot_of(zc), v * kW + u);
+                if (a.renorm) {
+                    const float3 n = heis_unit(val.x, val.y, val.z);
+                    val.x = n.x;
+                    val.y = n.y;
+                    val.z = n.z;
+                }
                 const uint32_t x = (uint32_t)(x0 + u - 2) & m, y = (uint32_t)(y0 + v - 2) & m;
                 *(F3 *)(dst + 3 * (size_t)((((zz << a.lgL) + y) << a.lgL) + x)) = val;
             }
@@ -366,8 +373,9 @@ bool heis3d_tiled_supported(int dim, int L) { return heis3d_supported(dim, L) &&
 size_t heis3d_tiled_lds_bytes() { return (size_t)kRing * 3 * kPlane * sizeof(float); }
 
 hipError_t launch_heis3d_tiled(const float *src, float *dst, const float *beta, int64_t *acc, int n_rep, int L, Key key,
-                               uint32_t t, hipStream_t s) {
+                               uint32_t t, bool renorm, hipStream_t s) {
     TiledArgs a;
+    a.renorm = renorm ? 1 : 0;
     a.src = src;
     a.dst = dst;
     a.beta = beta;

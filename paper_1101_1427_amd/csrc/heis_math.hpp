@@ -25,4 +25,12 @@ __device__ __forceinline__ float heis_boltzmann(float beta, float dE) {
     return __builtin_amdgcn_exp2f(-beta * dE * 1.4426950408889634f);
 }
 
+// s / |s|: the renormalisation of a spin (after every 16th sweep).  The
+// separate renormalisation kernel and the one-pass sweep, which applies it
+// as it stores the sweep's last plane, share this function.
+__device__ __forceinline__ float3 heis_unit(float x, float y, float z) {
+    const float n = sqrtf(__builtin_fmaf(x, x, __builtin_fmaf(y, y, z * z)));
+    return make_float3(x / n, y / n, z / n);
+}
+
 }  // namespace smc

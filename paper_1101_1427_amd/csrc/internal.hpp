@@ -74,10 +74,11 @@ hipError_t launch_heis_renorm(const Batch &b, float *spins, int max_L, hipStream
 bool heis3d_supported(int dim, int L);
 hipError_t launch_heis3d_half(float *spins, const float *beta, int64_t *acc, int n_rep, int L, Key key, uint32_t t,
                               int c, hipStream_t s);
-// One-pass (tiled, colour 0 then colour 1 in one launch) sweep from src to dst, L >= 32.
+// One-pass (tiled, colour 0 then colour 1 in one launch) sweep from src to dst, L >= 32;
+// with renorm the spins written to dst are renormalised.
 bool heis3d_tiled_supported(int dim, int L);
 hipError_t launch_heis3d_tiled(const float *src, float *dst, const float *beta, int64_t *acc, int n_rep, int L, Key key,
-                               uint32_t t, hipStream_t s);
+                               uint32_t t, bool renorm, hipStream_t s);
 
 // Parallel tempering of 3D edge-16 chains, all steps in one launch.
 bool pt3d_supported(const smc_desc *d, int n_temps);
