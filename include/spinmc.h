@@ -210,6 +210,37 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
                 const char **kernel_name);
 
 /*
+ * Asynchronous multi-spin coding (Sec. 5): the same sweeps as
+ * smc_metropolis_sweep for a uniform Ising or EA batch whose replicas come
+ * in groups of 32 (replicas 32g .. 32g+31 form group g) that share their
+ * Metropolis random numbers: the draws of every site of replica r are made
+ * with the group index r / 32 in the place of the replica index (counters
+ * (h/8, t, r/32, 6 + c) and (h, t, r/32, 8 + c)), as the paper uses one
+ * random number per site for all replicas coded in one word.  Each replica
+ * keeps its own spins and couplings (EA: rep_per_sample must be 1).
+ *  desc:     uniform batch (L > 0), model SMC_ISING or SMC_EA, n_rep a
+ *            multiple of 32.
+ *  spins, couplings, sweep0, n_sweeps, dE_accum, stream: as for
+ *            smc_metropolis_sweep (dE_accum: DEVICE int64 [n_rep], += the
+ *            energy change of each replica).
+ *  beta:     HOST [n_rep]; equal within each group of 32, else SMC_EINVAL.
+ * 2D batches of edge 16, 32 or 64 run with 32 replicas packed per 32-bit
+ * word, every sweep of the call in one launch, the lattices held on chip
+ * (SPINMC_MSC2D=0 sends them to the generic kernels); other shapes take the
+ * generic kernels.  Results are identical either way.  SMC_EUNSUPPORTED for
+ * the Heisenberg model.
+ */
+int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
+                  int32_t n_sweeps, int64_t *dE_accum, void *stream);
+
+/*
+ * How smc_msc_sweep will execute: the number of sweep-kernel launches for a
+ * call of n_sweeps sweeps and the sweep kernel's name (a static string).
+ * The same argument checks as smc_msc_sweep on desc; no device work.
+ */
+int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, const char **kernel_name);
+
+/*
  * Throughput probe of the random-number generator (Sec. 3.3, Fig. 4
  * measure generators on their own): thread i of n_threads draws the
  * Philox4x32-10 blocks with counters (i + k * n_threads, t, r, tag) for

@@ -73,6 +73,9 @@ enum Slot {
     kTuneE,
     kHeisPing,
     kL2dPart,
+    kMscSpins,
+    kMscCoup,
+    kMscEnergy,
     kNumSlots
 };
 
@@ -801,6 +804,26 @@ int smc_spin_init(const smc_desc *desc, void *spins, int8_t *couplings, void *st
     return SMC_OK;
 }
 
+// ------------------------------------- asynchronous multi-spin coding ----
+// Replicas 32g .. 32g+31 form group g and share its Metropolis draws.
+int msc_check(const smc_desc *d) {
+    if (d->model != SMC_ISING && d->model != SMC_EA)
+        return fail(SMC_EUNSUPPORTED, "multi-spin coding is provided for the Ising and EA models");
+    if (d->L <= 0) return fail(SMC_EINVAL, "multi-spin coding needs a uniform batch (L > 0)");
+    if (d->n_rep % 32 != 0) return fail(SMC_EINVAL, "n_rep (%d) must be a multiple of 32", d->n_rep);
+    if (d->model == SMC_EA && d->rep_per_sample != 1)
+        return fail(SMC_EINVAL, "multi-spin coding needs one coupling sample per replica (rep_per_sample = 1)");
+    return SMC_OK;
+}
+
+// The packed kernel serves 2D batches of edge 16, 32 or 64 (SPINMC_MSC2D=0
+// sends them to the generic kernels, which give the same results).
+bool use_msc2d(const smc_desc *d) {
+    const char *env = getenv("SPINMC_MSC2D");
+    if (env && env[0] == '0') return false;
+    return msc2d_supported(d->dim, d->L);
+}
+
 int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta,
                          uint64_t sweep0, int32_t n_sweeps, int64_t *dE_accum, void *stream) {
     g_last_error.clear();
@@ -906,6 +929,101 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         a.t = (uint32_t)(sweep0 + (uint64_t)k);
         SMC_HIP(launch_half_sweep_generic(a, 0, s));
         SMC_HIP(launch_half_sweep_generic(a, 1, s));
+    }
+    return SMC_OK;
+}
+
+int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
+                  int32_t n_sweeps, int64_t *dE_accum, void *stream) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, true, plan);
+    if (rc) return rc;
+    if ((rc = msc_check(desc))) return rc;
+    if (!spins) return fail(SMC_EINVAL, "spins is NULL");
+    if (!beta) return fail(SMC_EINVAL, "beta is NULL");
+    if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
+    if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+    if (sweep0 + (uint64_t)n_sweeps > (1ull << 32)) return fail(SMC_EINVAL, "sweep index exceeds 32 bits");
+    for (int r = 0; r < desc->n_rep; ++r) {
+        if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
+        if (beta[r] != beta[r - r % 32])
+            return fail(SMC_EINVAL, "beta[%d] differs from the rest of its group of 32", r);
+    }
+    if (n_sweeps == 0) return SMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    StreamCtx &c = ctx_for(s);
+    if ((rc = upload_inst(c, s, desc, plan))) return rc;
+    const int G = desc->n_rep / 32;
+    const bool ea = desc->model == SMC_EA;
+    if (use_msc2d(desc)) {
+        const int64_t N = (int64_t)desc->L * desc->L;
+        std::vector<ThrRow> rows(G);
+        for (int g = 0; g < G; ++g) rows[g] = threshold_row(beta[32 * g], desc->dim);
+        void *tp = nullptr, *sp = nullptr, *cp = nullptr, *ep = nullptr, *mp = nullptr;
+        if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &tp))) return rc;
+        if ((rc = ensure(c, kMscSpins, sizeof(uint32_t) * (size_t)(G * N), &sp))) return rc;
+        if ((rc = ensure(c, kMscCoup, sizeof(uint32_t) * (size_t)(G * 2 * N), &cp))) return rc;
+        const size_t mbytes = measure_scratch_bytes(plan.b, plan.max_L);
+        if (dE_accum) {
+            if ((rc = ensure(c, kMscEnergy, 2 * sizeof(double) * (size_t)desc->n_rep, &ep))) return rc;
+            if ((rc = ensure(c, kMeasure, mbytes, &mp))) return rc;
+            SMC_HIP(launch_measure(plan.b, spins, ea ? couplings : nullptr, plan.max_L, (double *)ep, nullptr, mp,
+                                   mbytes, s));
+        }
+        SMC_HIP(launch_msc_pack((const int8_t *)spins, (uint32_t *)sp, N, G, s));
+        SMC_HIP(launch_msc_pack_coup(ea ? couplings : nullptr, (uint32_t *)cp, 2 * N, G, s));
+        SweepTimer timer(s, 1);  // all sweeps in one launch
+        SMC_HIP(launch_msc2d((uint32_t *)sp, (const uint32_t *)cp, (const ThrRow *)tp, G, desc->L,
+                             make_key(desc->seed), (uint32_t)sweep0, n_sweeps, s));
+        timer.finish();
+        SMC_HIP(launch_msc_unpack((const uint32_t *)sp, (int8_t *)spins, N, G, s));
+        if (dE_accum) {
+            double *E0 = (double *)ep, *E1 = E0 + desc->n_rep;
+            SMC_HIP(launch_measure(plan.b, spins, ea ? couplings : nullptr, plan.max_L, E1, nullptr, mp, mbytes, s));
+            SMC_HIP(launch_msc_energy_diff(E0, E1, dE_accum, desc->n_rep, s));
+        }
+        return SMC_OK;
+    }
+    // generic per-site kernels with the group index in the draws' counters
+    std::vector<ThrRow> rows(desc->n_rep);
+    for (int r = 0; r < desc->n_rep; ++r) rows[r] = threshold_row(beta[r], desc->dim);
+    void *p = nullptr;
+    if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &p))) return rc;
+    SweepArgs a;
+    memset(&a, 0, sizeof a);
+    a.b = plan.b;
+    a.spins = spins;
+    a.coup = ea ? couplings : nullptr;
+    a.thr = (const ThrRow *)p;
+    a.key = make_key(desc->seed);
+    a.dE = dE_accum;
+    a.max_L = plan.max_L;
+    a.row_of_rep = nullptr;
+    a.rng_shift = 5;
+    SweepTimer timer(s, 2 * (int64_t)n_sweeps);
+    for (int32_t k = 0; k < n_sweeps; ++k) {
+        a.t = (uint32_t)(sweep0 + (uint64_t)k);
+        SMC_HIP(launch_half_sweep_generic(a, 0, s));
+        SMC_HIP(launch_half_sweep_generic(a, 1, s));
+    }
+    return SMC_OK;
+}
+
+int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, const char **kernel_name) {
+    g_last_error.clear();
+    if (!launches || !kernel_name) return fail(SMC_EINVAL, "output pointers are required");
+    Plan plan;
+    int rc = validate(desc, false, plan);
+    if (rc) return rc;
+    if ((rc = msc_check(desc))) return rc;
+    if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+    if (use_msc2d(desc)) {
+        *kernel_name = "k_msc2d";
+        *launches = n_sweeps > 0 ? 1 : 0;
+    } else {
+        *kernel_name = "k_half_sweep_generic";
+        *launches = 2 * n_sweeps;
     }
     return SMC_OK;
 }

@@ -157,8 +157,9 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_generic(SweepArgs a, int 
         bool acc = d <= 0;
         if (!acc) {
             const uint2 th = a.thr[row].m[d >> 2];
-            const uint4 w = philox4x32_10(make_uint4((uint32_t)(h >> 3), a.t, (uint32_t)r, 2 * kTagHead + c), a.key);
-            acc = metropolis_accept(head16_of(w, (uint32_t)(h & 7)), th, (uint32_t)h, a.t, (uint32_t)r, c, a.key);
+            const uint32_t rr = (uint32_t)r >> a.rng_shift;
+            const uint4 w = philox4x32_10(make_uint4((uint32_t)(h >> 3), a.t, rr, 2 * kTagHead + c), a.key);
+            acc = metropolis_accept(head16_of(w, (uint32_t)(h & 7)), th, (uint32_t)h, a.t, rr, c, a.key);
         }
         if (acc) {
             s[i] = (int8_t)(-si);

@@ -45,6 +45,7 @@ struct SweepArgs {
     uint32_t t;                // sweep index
     int64_t *dE;               // nullable per-replica accumulator
     int max_L;                 // largest edge in the batch
+    int rng_shift;             // the Metropolis draws of replica r use index r >> rng_shift
 };
 
 struct SwapArgs {
@@ -118,6 +119,16 @@ hipError_t add_advance_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNo
                             uint32_t *t_dev);
 hipError_t add_pt_swap_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
                             const SwapArgs &a);
+
+// Asynchronous multi-spin coding (2D EA/Ising, L in {16, 32, 64}): replicas
+// 32g .. 32g+31 packed into one word per site, all sweeps in one launch.
+bool msc2d_supported(int dim, int L);
+hipError_t launch_msc_pack(const int8_t *spins, uint32_t *packed, int64_t N, int n_groups, hipStream_t s);
+hipError_t launch_msc_pack_coup(const int8_t *coup, uint32_t *packed, int64_t dN, int n_groups, hipStream_t s);
+hipError_t launch_msc_unpack(const uint32_t *packed, int8_t *spins, int64_t N, int n_groups, hipStream_t s);
+hipError_t launch_msc_energy_diff(const double *E0, const double *E1, int64_t *dE, int n, hipStream_t s);
+hipError_t launch_msc2d(uint32_t *spins, const uint32_t *coup, const ThrRow *thr, int n_groups, int L, Key key,
+                        uint32_t t0, int n_sweeps, hipStream_t s);
 
 // Generator throughput: out[i] = XOR of the four words of the blocks with
 // counters (i + k * n_threads, t, r, tag), k < per_thread.

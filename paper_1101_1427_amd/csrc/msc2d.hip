@@ -1,0 +1,269 @@
+// Asynchronous multi-spin coding of the 2D +-J spin glass (Sec. 5): bit k of
+// a 32-bit word holds replica 32g + k of group g, so one word operation
+// updates the same site of 32 independent lattices, each with its own
+// couplings.  The 32 replicas of a group share the Metropolis uniform of
+// each site and sweep (the paper draws one random number per word); their
+// counters carry the group index g where the single-replica sweep carries
+// the replica index.
+//
+// Decision for one site of the 32 replicas: with a_j = s ^ s_j ^ J_j the
+// unsatisfied-bond bits of the four bonds, n = a_1 + .. + a_4 per replica
+// and dE = 8 - 4n.  n >= 2 always flips; n = 1 flips iff u < thr(dE = 4);
+// n = 0 iff u < thr(dE = 8).  Since thr(8) < thr(4), with the per-site
+// booleans D1 = [u < thr(4)] and D2 = [u < thr(8)] the flip mask is
+//   D2 ? all : D1 ? (n >= 1) : (n >= 2),
+// computed with a bit-sliced adder on the four words.  u is compared in
+// two 16-bit halves as in the other kernels: the head (one Philox block
+// serves 8 sites) decides unless it equals the high half of a threshold.
+//
+// Layout: a workgroup holds whole groups; each group's lattice of words
+// lives in LDS (padded so that the lanes of a wave read 64 different banks)
+// and in registers: a thread owns 16 consecutive sites of one row (8 of
+// each colour, one Philox block per colour) with their spins and the
+// couplings of all their bonds.  A half-sweep reads the four neighbours'
+// words from LDS, updates the owned words of one colour in registers and
+// writes them back; one barrier per half-sweep.  All sweeps of a call run in
+// one launch, so HBM is touched only at its start and end.
+#include "internal.hpp"
+
+namespace smc {
+namespace {
+
+constexpr int kMscBlock = 256;
+
+// LDS geometry: word (group gw, row y, segment s, column xx) at
+// gw*GS + y*RS + s*SS + xx.  The lanes of a wave share xx and differ in
+// (group, row pair, segment); these strides send them to 64 different banks
+// (rows y-1, y, y+1 alike).
+template <int SEG>
+struct MscGeom;
+template <>
+struct MscGeom<1> {
+    static constexpr int RS = 20, SS = 16, GS = 321;
+};
+template <>
+struct MscGeom<2> {
+    static constexpr int RS = 34, SS = 17, GS = 1090;
+};
+template <>
+struct MscGeom<4> {
+    static constexpr int RS = 98, SS = 17, GS = 6272;
+};
+
+struct Msc2dArgs {
+    uint32_t *spins;       // packed [G][L*L] (bit k: replica 32g + k is -1)
+    const uint32_t *coup;  // packed [G][2][L*L] (bit k: J = -1 for replica 32g + k)
+    const ThrRow *thr;     // per group
+    Key key;
+    uint32_t t0;
+    int n_sweeps;
+    int G;
+};
+
+// Colour c of the thread's 16 sites, those at columns OFF, OFF+2, .., 14+OFF
+// of its segment (OFF = (c + y) & 1 is uniform across a wave).
+template <int SEG, int OFF>
+__device__ __forceinline__ void msc_half(uint32_t (&S)[16], const uint32_t (&JR)[16], const uint32_t (&JD)[16],
+                                         const uint32_t (&JU)[16], uint32_t JL, uint32_t *lat, int y, int seg,
+                                         uint32_t g, uint32_t t, uint32_t c, const ThrRow &thr, Key key) {
+    using GE = MscGeom<SEG>;
+    constexpr int L = 16 * SEG;
+    const uint32_t *up = lat + ((y + L - 1) % L) * GE::RS + seg * GE::SS;
+    const uint32_t *dn = lat + ((y + 1) % L) * GE::RS + seg * GE::SS;
+    // the neighbour word outside the segment: column 15 of the segment to
+    // the left (OFF = 0) or column 0 of the one to the right (OFF = 1)
+    const uint32_t bnd = OFF == 0 ? lat[y * GE::RS + ((seg + SEG - 1) % SEG) * GE::SS + 15]
+                                  : lat[y * GE::RS + ((seg + 1) % SEG) * GE::SS];
+    const uint32_t b = (uint32_t)(y * SEG + seg);  // Philox block: in-colour sites 8b .. 8b+7
+    const uint4 w = philox4x32_10(make_uint4(b, t, g, 2 * kTagHead + c), key);
+    const uint32_t T1 = thr.m[1].x, T2 = thr.m[2].x;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int xx = OFF + 2 * j;
+        const uint32_t s = S[xx];
+        const uint32_t left = xx == 0 ? bnd : S[xx == 0 ? 0 : xx - 1];
+        const uint32_t right = xx == 15 ? bnd : S[xx == 15 ? 15 : xx + 1];
+        const uint32_t jl = xx == 0 ? JL : JR[xx == 0 ? 0 : xx - 1];
+        const uint32_t a1 = s ^ left ^ jl;
+        const uint32_t a2 = s ^ right ^ JR[xx];
+        const uint32_t a3 = s ^ up[xx] ^ JU[xx];
+        const uint32_t a4 = s ^ dn[xx] ^ JD[xx];
+        const uint32_t p = a1 ^ a2, q = a1 & a2, r = a3 ^ a4, u = a3 & a4;
+        const uint32_t ge2 = q | u | (p & r);
+        const uint32_t ge1 = a1 | a2 | a3 | a4;
+        const uint32_t word = j < 2 ? w.x : j < 4 ? w.y : j < 6 ? w.z : w.w;
+        const uint32_t head = (j & 1) ? (word >> 16) : (word & 0xFFFFu);
+        bool d1 = head < T1, d2 = head < T2;
+        if (__builtin_expect(head == T1 || head == T2, 0)) {
+            // the head equals the high half of a threshold: the tail decides
+            const uint32_t tail = tail16(8u * b + (uint32_t)j, t, g, c, key);
+            d1 = head < T1 || (head == T1 && tail < thr.m[1].y);
+            d2 = head < T2 || (head == T2 && tail < thr.m[2].y);
+        }
+        const uint32_t flip = d2 ? 0xFFFFFFFFu : (d1 ? ge1 : ge2);
+        S[xx] = s ^ flip;
+    }
+    uint32_t *own = lat + y * GE::RS + seg * GE::SS;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) own[OFF + 2 * j] = S[OFF + 2 * j];
+}
+
+template <int SEG>
+__global__ __launch_bounds__(kMscBlock) void k_msc2d(Msc2dArgs a) {
+    using GE = MscGeom<SEG>;
+    constexpr int L = 16 * SEG, N = L * L;
+    constexpr int TPG = N / 16;         // threads per group
+    constexpr int GPW = kMscBlock / TPG;  // groups per workgroup
+    constexpr int PER = TPG / 2;        // threads per group and row parity
+    __shared__ uint32_t lds[GPW * GE::GS];
+    // threads [0, 128) own even rows, [128, 256) odd rows, so that the
+    // colour offset of a half-sweep is uniform across each wave
+    const int par = (int)threadIdx.x / (kMscBlock / 2);
+    const int q = (int)threadIdx.x % (kMscBlock / 2);
+    const int gw = q / PER, rem = q % PER;
+    const int y = 2 * (rem / SEG) + par, seg = rem % SEG;
+    const int g = (int)blockIdx.x * GPW + gw;
+    const bool live = g < a.G;
+    uint32_t *lat = lds + gw * GE::GS;
+
+    uint32_t S[16], JR[16], JD[16], JU[16], JL = 0;
+    {
+        const size_t base = (size_t)(live ? g : 0) * N;
+        const int x0 = 16 * seg;
+        const int ym = (y + L - 1) % L;
+#pragma unroll
+        for (int xx = 0; xx < 16; ++xx) {
+            S[xx] = live ? a.spins[base + (size_t)(y * L + x0 + xx)] : 0u;
+            JR[xx] = live ? a.coup[2 * base + (size_t)(y * L + x0 + xx)] : 0u;
+            JD[xx] = live ? a.coup[2 * base + N + (size_t)(y * L + x0 + xx)] : 0u;
+            JU[xx] = live ? a.coup[2 * base + N + (size_t)(ym * L + x0 + xx)] : 0u;
+        }
+        JL = live ? a.coup[2 * base + (size_t)(y * L + (x0 + L - 1) % L)] : 0u;
+    }
+    uint32_t *own = lat + y * GE::RS + seg * GE::SS;
+#pragma unroll
+    for (int xx = 0; xx < 16; ++xx) own[xx] = S[xx];
+    const ThrRow thr = a.thr[live ? g : 0];
+    __syncthreads();
+    for (int k = 0; k < a.n_sweeps; ++k) {
+        const uint32_t t = a.t0 + (uint32_t)k;
+#pragma unroll
+        for (uint32_t c = 0; c < 2; ++c) {
+            if (((c + (uint32_t)par) & 1u) == 0u)
+                msc_half<SEG, 0>(S, JR, JD, JU, JL, lat, y, seg, (uint32_t)g, t, c, thr, a.key);
+            else
+                msc_half<SEG, 1>(S, JR, JD, JU, JL, lat, y, seg, (uint32_t)g, t, c, thr, a.key);
+            __syncthreads();
+        }
+    }
+    if (live) {
+        const size_t base = (size_t)g * N + (size_t)(y * L + 16 * seg);
+#pragma unroll
+        for (int xx = 0; xx < 16; ++xx) a.spins[base + xx] = S[xx];
+    }
+}
+
+// int8 +-1 spins of replicas 32g .. 32g+31 -> word (g, i); bit k set for -1.
+__global__ __launch_bounds__(256) void k_msc_pack(const int8_t *src, uint32_t *dst, int64_t N, int64_t words,
+                                                  int64_t stride) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= words) return;
+    const int64_t g = gid / N, i = gid % N;
+    const int8_t *p = src + 32 * g * stride + i;
+    uint32_t w = 0;
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k) w |= (p[(int64_t)k * stride] < 0 ? 1u : 0u) << k;
+    dst[gid] = w;
+}
+
+// The couplings of replicas 32g .. 32g+31 (one sample each, d*N bonds) ->
+// words (g, mu, i); bit k set for J = -1.  Without couplings (Ising) every
+// word is 0.
+__global__ __launch_bounds__(256) void k_msc_pack_coup(const int8_t *coup, uint32_t *dst, int64_t dN, int64_t words) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= words) return;
+    uint32_t w = 0;
+    if (coup) {
+        const int64_t g = gid / dN, b = gid % dN;
+        const int8_t *p = coup + 32 * g * dN + b;
+#pragma unroll 8
+        for (int k = 0; k < 32; ++k) w |= (p[(int64_t)k * dN] < 0 ? 1u : 0u) << k;
+    }
+    dst[gid] = w;
+}
+
+__global__ __launch_bounds__(256) void k_msc_unpack(const uint32_t *src, int8_t *dst, int64_t N, int64_t words) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= words) return;
+    const int64_t g = gid / N, i = gid % N;
+    const uint32_t w = src[gid];
+    int8_t *p = dst + 32 * g * N + i;
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k) p[(int64_t)k * N] = (w >> k) & 1u ? (int8_t)-1 : (int8_t)1;
+}
+
+// dE[r] += E1[r] - E0[r] (energies are exact integers in float64).
+__global__ __launch_bounds__(256) void k_msc_energy_diff(const double *E0, const double *E1, int64_t *dE, int n) {
+    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r < n) dE[r] += (int64_t)E1[r] - (int64_t)E0[r];
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+bool msc2d_supported(int dim, int L) { return dim == 2 && (L == 16 || L == 32 || L == 64); }
+
+hipError_t launch_msc_pack(const int8_t *spins, uint32_t *packed, int64_t N, int n_groups, hipStream_t s) {
+    const int64_t words = (int64_t)n_groups * N;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_msc_pack, dim3(blocks_for(words)), dim3(256), 0, s, spins, packed, N, words, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_msc_pack_coup(const int8_t *coup, uint32_t *packed, int64_t dN, int n_groups, hipStream_t s) {
+    const int64_t words = (int64_t)n_groups * dN;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_msc_pack_coup, dim3(blocks_for(words)), dim3(256), 0, s, coup, packed, dN, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_msc_unpack(const uint32_t *packed, int8_t *spins, int64_t N, int n_groups, hipStream_t s) {
+    const int64_t words = (int64_t)n_groups * N;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_msc_unpack, dim3(blocks_for(words)), dim3(256), 0, s, packed, spins, N, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_msc_energy_diff(const double *E0, const double *E1, int64_t *dE, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_msc_energy_diff, dim3(blocks_for(n)), dim3(256), 0, s, E0, E1, dE, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_msc2d(uint32_t *spins, const uint32_t *coup, const ThrRow *thr, int n_groups, int L, Key key,
+                        uint32_t t0, int n_sweeps, hipStream_t s) {
+    Msc2dArgs a;
+    a.spins = spins;
+    a.coup = coup;
+    a.thr = thr;
+    a.key = key;
+    a.t0 = t0;
+    a.n_sweeps = n_sweeps;
+    a.G = n_groups;
+    const int tpg = L * L / 16;
+    const int gpw = kMscBlock / tpg;
+    const unsigned blocks = (unsigned)((n_groups + gpw - 1) / gpw);
+    if (n_groups <= 0 || n_sweeps <= 0) return hipSuccess;
+    if (L == 16) {
+        hipLaunchKernelGGL(k_msc2d<1>, dim3(blocks), dim3(kMscBlock), 0, s, a);
+    } else if (L == 32) {
+        hipLaunchKernelGGL(k_msc2d<2>, dim3(blocks), dim3(kMscBlock), 0, s, a);
+    } else if (L == 64) {
+        hipLaunchKernelGGL(k_msc2d<4>, dim3(blocks), dim3(kMscBlock), 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace smc

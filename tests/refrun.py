@@ -43,3 +43,13 @@ def init_uneven(model, dim, inst, seed):
         if coup is not None:
             coup[co:co + dim * N] = O.init_couplings(dim, L, seed, q)
     return spins, coup
+
+
+def sweep_msc(model, dim, L, spins, coup, betas, seed, t0, n):
+    """Multi-spin-coded sweeps (groups of 32 replicas share their draws): each
+    replica is the ordinary chain with the group index r // 32 in the counters."""
+    dE = np.zeros(len(spins), np.int64)
+    for r in range(len(spins)):
+        J = None if coup is None else coup[r]
+        dE[r] = O.run(dim, L, J, spins[r], float(betas[r]), seed, r // 32, t0, n)
+    return dE

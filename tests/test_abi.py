@@ -128,3 +128,21 @@ def test_philox_bench_arguments_are_validated():
     assert L.smc_philox_bench(1, 0, 0, 0, 16, 0, FAKE, None) == S.EINVAL
     rc = L.smc_philox_bench(1, 0, 0, 0, 1 << 20, 1 << 13, FAKE, None)
     assert rc == S.EINVAL and b"2^32" in L.smc_last_error()
+
+
+def test_msc_arguments_are_validated():
+    L = S.lib()
+    beta = (C.c_double * 64)(*([0.5] * 64))
+    d = _desc(n_rep=48, spins_len=48 * 256)
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, None, beta, 0, 1, None, None)
+    assert rc == S.EINVAL and b"multiple of 32" in L.smc_last_error()
+    d = _desc(n_rep=64, spins_len=64 * 256, model=S.EA, coup_len=64 * 512)
+    d.rep_per_sample = 2
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, FAKE, beta, 0, 1, None, None)
+    assert rc == S.EINVAL and b"rep_per_sample" in L.smc_last_error()
+    d.rep_per_sample = 1
+    beta2 = (C.c_double * 64)(*([0.5] * 40 + [0.6] * 24))
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, FAKE, beta2, 0, 1, None, None)
+    assert rc == S.EINVAL and b"group of 32" in L.smc_last_error()
+    d = _desc(n_rep=64, spins_len=64 * 256 * 3, model=S.HEISENBERG)
+    assert L.smc_msc_sweep(C.byref(d), FAKE, None, beta, 0, 1, None, None) == S.EUNSUPPORTED
