@@ -145,7 +145,7 @@ def valu_summary(db: str, command: str):
              "# instruction per CU per cycle (four SIMD16 units, four cycles each)",
              f"{'kernel':28s} {'dispatches':>10s} {'VALU_insts':>14s} {'busy_cycles':>12s} {'util':>6s}"]
     for k in ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_tiled", "k_heis3d_half",
-              "k_half_sweep_generic", "k_philox_bench", "k_to_split", "k_from_split"):
+              "k_half_sweep_generic", "k_msc2d", "k_philox_bench", "k_to_split", "k_from_split"):
         if k not in acc or "SQ_INSTS_VALU" not in acc[k] or "GRBM_GUI_ACTIVE" not in acc[k]:
             continue
         v = acc[k]["SQ_INSTS_VALU"]
@@ -343,6 +343,45 @@ def tempering_ea3d(S, W, steps, per_inst_chains=16, per_inst_steps=50, per_step_
             "speedup_vs_per_step_launches": round(rate / rate_ps, 2)}
 
 
+def msc_ea2d(S, W, sweeps, L=16, sizes=(14, 16, 18, 20), single_spin_sweeps=20):
+    """Asynchronous multi-spin coding of the 2D +-J spin glass (Sec. 5,
+    Fig. 14 shape): 16 x 16 lattices, replicas in groups of 32 sharing their
+    draws, at T = 1; ps per attempted flip against the number of replicas,
+    and the same batch swept one replica per lane (generic kernels,
+    per-replica draws) for comparison."""
+    import torch
+
+    seed = W.seed_for(90)
+    rows = []
+    for lg in sizes:
+        n_rep = 1 << lg
+        b = S.Batch(S.EA, 2, L, n_rep, seed)
+        spins = torch.zeros(n_rep * L * L, dtype=torch.int8, device="cuda")
+        coup = torch.zeros(b.coup_len(), dtype=torch.int8, device="cuda")
+        S.spin_init(b, spins, coup)
+        n = sweeps << max(0, sizes[-1] - lg)  # about the same number of flips at every size
+        S.msc_sweep(b, spins, [1.0], 0, 5, couplings=coup)
+        S.kernel_timing_read()
+        S.kernel_timing_enable(True)
+        ms = _timed(lambda: S.msc_sweep(b, spins, [1.0], 5, n, couplings=coup))
+        kernel_ms, _ = S.kernel_timing_read()
+        S.kernel_timing_enable(False)
+        flips = n_rep * L * L * n
+        row = {"replicas": n_rep, "sweeps": n, "ms": round(ms, 3), "ps_per_flip": round(ms * 1e9 / flips, 5),
+               "kernel_ps_per_flip": round(kernel_ms * 1e9 / flips, 5)}
+        if lg == sizes[-1]:
+            t = _timed(lambda: S.metropolis_sweep(b, spins, [1.0], 5 + n, single_spin_sweeps, couplings=coup))
+            row["single_spin_generic_ps_per_flip"] = round(t * 1e9 / (n_rep * L * L * single_spin_sweeps), 4)
+            row["speedup_vs_single_spin"] = round(row["single_spin_generic_ps_per_flip"] / row["ps_per_flip"], 1)
+        rows.append(row)
+        del spins, coup
+        torch.cuda.empty_cache()
+    _, kernel = S.msc_plan(S.Batch(S.EA, 2, L, 32, seed), 1)
+    return {"workload": f"2D +-J EA {L}x{L}, T = 1, replicas packed 32 per word with shared draws, "
+                        f"{sweeps} sweeps at 2^{sizes[-1]} replicas, proportionally more for fewer",
+            "kernel": kernel, "by_replicas": rows}
+
+
 def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):
     """Uneven 2D EA batch, 4096 instances x 16 temperatures, edges from
     {32, ..., 256}: the batch in one call (a graph of steps), against one call
@@ -481,6 +520,8 @@ def main():
     ap.add_argument("--uneven-steps", type=int, default=5000)
     ap.add_argument("--heis-sweeps", type=int, default=1000)
     ap.add_argument("--heis-only", action="store_true", help="only the Heisenberg measurement (for profiling)")
+    ap.add_argument("--msc-sweeps", type=int, default=2000)
+    ap.add_argument("--msc-only", action="store_true", help="only the multi-spin-coded measurement (for profiling)")
     ap.add_argument("--pmc-kernel", default="k_ising2d_split", choices=sorted(KERNEL_SOURCES),
                     help="kernel of the --pmc-summary")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -519,6 +560,9 @@ def main():
 
     if args.heis_only:
         print(json.dumps({"heisenberg": heisenberg3d(S, W, args.heis_sweeps)}))
+        return
+    if args.msc_only:
+        print(json.dumps({"msc_ea2d": msc_ea2d(S, W, args.msc_sweeps)}))
         return
     cfg = W.ising_large(args.L)
     L = cfg.L
@@ -598,6 +642,7 @@ def main():
         out["heisenberg"] = heisenberg3d(S, W, args.heis_sweeps)
         out["tempering"] = {"ea3d_L16": tempering_ea3d(S, W, args.pt3d_steps),
                             "ea2d_uneven": tempering_ea2d_uneven(S, W, args.uneven_steps)}
+        out["msc_ea2d"] = msc_ea2d(S, W, args.msc_sweeps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg)
         out["cpu_baseline"] = cb

@@ -224,8 +224,9 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
  *            smc_metropolis_sweep (dE_accum: DEVICE int64 [n_rep], += the
  *            energy change of each replica).
  *  beta:     HOST [n_rep]; equal within each group of 32, else SMC_EINVAL.
- * 2D batches of edge 16, 32 or 64 run with 32 replicas packed per 32-bit
- * word, every sweep of the call in one launch, the lattices held on chip
+ * 2D batches of edge 16, 32 or 64 (spins and couplings 4-byte aligned) run
+ * with 32 replicas packed per 32-bit word, every sweep of the call in one
+ * launch, the lattices held on chip
  * (SPINMC_MSC2D=0 sends them to the generic kernels); other shapes take the
  * generic kernels.  Results are identical either way.  SMC_EUNSUPPORTED for
  * the Heisenberg model.
@@ -235,8 +236,9 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
 
 /*
  * How smc_msc_sweep will execute: the number of sweep-kernel launches for a
- * call of n_sweeps sweeps and the sweep kernel's name (a static string).
- * The same argument checks as smc_msc_sweep on desc; no device work.
+ * call of n_sweeps sweeps and the sweep kernel's name (a static string),
+ * for aligned buffers.  The same argument checks as smc_msc_sweep on desc;
+ * no device work.
  */
 int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, const char **kernel_name);
 

@@ -228,6 +228,19 @@ struct Plan {
 
 int64_t sites(int dim, int L) { return dim == 3 ? (int64_t)L * L * L : (int64_t)L * L; }
 
+// The coupling samples of a uniform EA batch: sample q at q * d * N.
+void fill_uniform_samples(const smc_desc *d, Plan &plan) {
+    if (d->L <= 0 || d->model != SMC_EA || !plan.samples.empty()) return;
+    plan.samples.resize((size_t)plan.n_samples);
+    for (int64_t q = 0; q < plan.n_samples; ++q) {
+        smc_inst &g = plan.samples[(size_t)q];
+        g.L = d->L;
+        g.sample = (int32_t)q;
+        g.spin_off = 0;
+        g.coup_off = q * d->dim * plan.b.N;
+    }
+}
+
 int validate(const smc_desc *d, bool need_coup, Plan &plan) {
     if (!d) return fail(SMC_EINVAL, "desc is NULL");
     if (d->model < SMC_ISING || d->model > SMC_HEISENBERG) return fail(SMC_EINVAL, "unknown model %d", d->model);
@@ -260,13 +273,12 @@ int validate(const smc_desc *d, bool need_coup, Plan &plan) {
             if (d->rep_per_sample < 1) return fail(SMC_EINVAL, "rep_per_sample must be >= 1 for EA");
             b.rep_per_sample = d->rep_per_sample;
             plan.n_samples = (d->n_rep + d->rep_per_sample - 1) / d->rep_per_sample;
-            for (int64_t q = 0; q < plan.n_samples; ++q) {
-                smc_inst g;
-                g.L = d->L;
-                g.sample = (int32_t)q;
-                g.spin_off = 0;
-                g.coup_off = q * d->dim * b.N;
-                plan.samples.push_back(g);
+            // the sample table is built only where a path needs it (fill_uniform_samples)
+            if (need_coup) {
+                if (d->coup_len <= 0) return fail(SMC_EINVAL, "coup_len must be > 0 for EA");
+                if (plan.n_samples * d->dim * b.N > d->coup_len)
+                    return fail(SMC_EINVAL, "couplings of sample %lld lie outside the coupling buffer",
+                                (long long)(d->coup_len / (d->dim * b.N)));
             }
         }
     } else {
@@ -293,7 +305,7 @@ int validate(const smc_desc *d, bool need_coup, Plan &plan) {
         for (auto &kv : seen) plan.samples.push_back(kv.second);
         plan.n_samples = (int64_t)plan.samples.size();
     }
-    if (ea && need_coup) {
+    if (ea && need_coup && d->L == 0) {
         if (d->coup_len <= 0) return fail(SMC_EINVAL, "coup_len must be > 0 for EA");
         for (const smc_inst &g : plan.samples) {
             const int64_t need = (int64_t)d->dim * sites(d->dim, g.L);
@@ -490,8 +502,9 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
     if (desc->model == SMC_EA) {
         std::vector<smc_inst> samples;
         if (desc->L > 0) {
-            samples = plan.samples;
-            for (smc_inst &g : samples) g.coup_off = (int64_t)g.sample * 2 * (int64_t)desc->L * desc->L;
+            samples.resize((size_t)plan.n_samples);
+            for (int64_t q = 0; q < plan.n_samples; ++q)
+                samples[(size_t)q] = smc_inst{desc->L, (int32_t)q, 0, q * 2 * (int64_t)desc->L * desc->L};
         } else {
             std::map<int32_t, smc_inst> seen;
             for (const smc_inst &g : rows) seen.emplace(g.sample, g);
@@ -795,6 +808,7 @@ int smc_spin_init(const smc_desc *desc, void *spins, int8_t *couplings, void *st
         SMC_HIP(launch_init_spins(plan.b, plan.max_L, (int8_t *)spins, key, s));
     }
     if (want_coup && plan.n_samples > 0) {
+        fill_uniform_samples(desc, plan);
         void *p = nullptr;
         if ((rc = upload(c, s, kSamples, plan.samples.data(), sizeof(smc_inst) * plan.samples.size(), &p))) return rc;
         int maxL = 0;
@@ -816,11 +830,13 @@ int msc_check(const smc_desc *d) {
     return SMC_OK;
 }
 
-// The packed kernel serves 2D batches of edge 16, 32 or 64 (SPINMC_MSC2D=0
-// sends them to the generic kernels, which give the same results).
-bool use_msc2d(const smc_desc *d) {
+// The packed kernel serves 2D batches of edge 16, 32 or 64 with 4-byte
+// aligned spins and couplings (SPINMC_MSC2D=0 sends them to the generic
+// kernels, which give the same results).
+bool use_msc2d(const smc_desc *d, const void *spins, const void *coup) {
     const char *env = getenv("SPINMC_MSC2D");
     if (env && env[0] == '0') return false;
+    if (((uintptr_t)spins & 3u) || ((uintptr_t)coup & 3u)) return false;
     return msc2d_supported(d->dim, d->L);
 }
 
@@ -956,10 +972,11 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     if ((rc = upload_inst(c, s, desc, plan))) return rc;
     const int G = desc->n_rep / 32;
     const bool ea = desc->model == SMC_EA;
-    if (use_msc2d(desc)) {
+    if (use_msc2d(desc, spins, ea ? couplings : nullptr)) {
         const int64_t N = (int64_t)desc->L * desc->L;
         std::vector<ThrRow> rows(G);
-        for (int g = 0; g < G; ++g) rows[g] = threshold_row(beta[32 * g], desc->dim);
+        for (int g = 0; g < G; ++g)
+            rows[g] = (g > 0 && beta[32 * g] == beta[32 * (g - 1)]) ? rows[g - 1] : threshold_row(beta[32 * g], desc->dim);
         void *tp = nullptr, *sp = nullptr, *cp = nullptr, *ep = nullptr, *mp = nullptr;
         if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &tp))) return rc;
         if ((rc = ensure(c, kMscSpins, sizeof(uint32_t) * (size_t)(G * N), &sp))) return rc;
@@ -1018,7 +1035,7 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, cons
     if (rc) return rc;
     if ((rc = msc_check(desc))) return rc;
     if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
-    if (use_msc2d(desc)) {
+    if (use_msc2d(desc, nullptr, nullptr)) {
         *kernel_name = "k_msc2d";
         *launches = n_sweeps > 0 ? 1 : 0;
     } else {

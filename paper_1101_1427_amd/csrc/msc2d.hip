@@ -33,21 +33,22 @@ constexpr int kMscBlock = 256;
 
 // LDS geometry: word (group gw, row y, segment s, column xx) at
 // gw*GS + y*RS + s*SS + xx.  The lanes of a wave share xx and differ in
-// (group, row pair, segment); these strides send them to 64 different banks
-// (rows y-1, y, y+1 alike).
+// (group, row pair, segment); with these strides the 32 lanes of each half
+// wave, which the LDS serves together, hit 32 different banks for every
+// access of a half-sweep (rows y-1, y, y+1 and the neighbouring segments).
 template <int SEG>
 struct MscGeom;
 template <>
 struct MscGeom<1> {
-    static constexpr int RS = 20, SS = 16, GS = 321;
+    static constexpr int RS = 18, SS = 16, GS = 289;
 };
 template <>
 struct MscGeom<2> {
-    static constexpr int RS = 34, SS = 17, GS = 1090;
+    static constexpr int RS = 35, SS = 17, GS = 1120;
 };
 template <>
 struct MscGeom<4> {
-    static constexpr int RS = 98, SS = 17, GS = 6272;
+    static constexpr int RS = 70, SS = 17, GS = 4480;
 };
 
 struct Msc2dArgs {
@@ -163,43 +164,42 @@ __global__ __launch_bounds__(kMscBlock) void k_msc2d(Msc2dArgs a) {
     }
 }
 
-// int8 +-1 spins of replicas 32g .. 32g+31 -> word (g, i); bit k set for -1.
-__global__ __launch_bounds__(256) void k_msc_pack(const int8_t *src, uint32_t *dst, int64_t N, int64_t words,
-                                                  int64_t stride) {
+// int8 +-1 values of replicas 32g .. 32g+31 (M values per replica, e.g. the
+// spins or the d*N couplings) -> words (g, i); bit k set where replica
+// 32g + k holds -1.  Four consecutive values per thread (M % 4 == 0);
+// without a source (Ising couplings) every word is 0.
+__global__ __launch_bounds__(256) void k_msc_pack(const int8_t *src, uint32_t *dst, int64_t M, int64_t quads) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= words) return;
-    const int64_t g = gid / N, i = gid % N;
-    const int8_t *p = src + 32 * g * stride + i;
-    uint32_t w = 0;
+    if (gid >= quads) return;
+    const int64_t g = gid / (M / 4), i = 4 * (gid % (M / 4));
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    if (src) {
+        const int8_t *p = src + 32 * g * M + i;
 #pragma unroll 8
-    for (int k = 0; k < 32; ++k) w |= (p[(int64_t)k * stride] < 0 ? 1u : 0u) << k;
-    dst[gid] = w;
-}
-
-// The couplings of replicas 32g .. 32g+31 (one sample each, d*N bonds) ->
-// words (g, mu, i); bit k set for J = -1.  Without couplings (Ising) every
-// word is 0.
-__global__ __launch_bounds__(256) void k_msc_pack_coup(const int8_t *coup, uint32_t *dst, int64_t dN, int64_t words) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= words) return;
-    uint32_t w = 0;
-    if (coup) {
-        const int64_t g = gid / dN, b = gid % dN;
-        const int8_t *p = coup + 32 * g * dN + b;
-#pragma unroll 8
-        for (int k = 0; k < 32; ++k) w |= (p[(int64_t)k * dN] < 0 ? 1u : 0u) << k;
+        for (int k = 0; k < 32; ++k) {
+            const uint32_t v = *(const uint32_t *)(p + (int64_t)k * M);  // four values; the sign bit of each byte
+            w0 |= ((v >> 7) & 1u) << k;
+            w1 |= ((v >> 15) & 1u) << k;
+            w2 |= ((v >> 23) & 1u) << k;
+            w3 |= (v >> 31) << k;
+        }
     }
-    dst[gid] = w;
+    *(uint4 *)(dst + g * M + i) = make_uint4(w0, w1, w2, w3);
 }
 
-__global__ __launch_bounds__(256) void k_msc_unpack(const uint32_t *src, int8_t *dst, int64_t N, int64_t words) {
+__global__ __launch_bounds__(256) void k_msc_unpack(const uint32_t *src, int8_t *dst, int64_t N, int64_t quads) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= words) return;
-    const int64_t g = gid / N, i = gid % N;
-    const uint32_t w = src[gid];
+    if (gid >= quads) return;
+    const int64_t g = gid / (N / 4), i = 4 * (gid % (N / 4));
+    const uint4 w = *(const uint4 *)(src + g * N + i);
     int8_t *p = dst + 32 * g * N + i;
 #pragma unroll 8
-    for (int k = 0; k < 32; ++k) p[(int64_t)k * N] = (w >> k) & 1u ? (int8_t)-1 : (int8_t)1;
+    for (int k = 0; k < 32; ++k) {
+        // byte b = 0xFF (-1) where bit k of word b is set, else 0x01 (+1)
+        const uint32_t bits = ((w.x >> k) & 1u) | (((w.y >> k) & 1u) << 8) | (((w.z >> k) & 1u) << 16) |
+                              (((w.w >> k) & 1u) << 24);
+        *(uint32_t *)(p + (int64_t)k * N) = (bits * 0xFEu) + 0x01010101u;
+    }
 }
 
 // dE[r] += E1[r] - E0[r] (energies are exact integers in float64).
@@ -215,23 +215,23 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 bool msc2d_supported(int dim, int L) { return dim == 2 && (L == 16 || L == 32 || L == 64); }
 
 hipError_t launch_msc_pack(const int8_t *spins, uint32_t *packed, int64_t N, int n_groups, hipStream_t s) {
-    const int64_t words = (int64_t)n_groups * N;
-    if (words == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_msc_pack, dim3(blocks_for(words)), dim3(256), 0, s, spins, packed, N, words, N);
+    const int64_t quads = (int64_t)n_groups * N / 4;
+    if (quads == 0 || N % 4) return quads == 0 ? hipSuccess : hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_msc_pack, dim3(blocks_for(quads)), dim3(256), 0, s, spins, packed, N, quads);
     return hipGetLastError();
 }
 
 hipError_t launch_msc_pack_coup(const int8_t *coup, uint32_t *packed, int64_t dN, int n_groups, hipStream_t s) {
-    const int64_t words = (int64_t)n_groups * dN;
-    if (words == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_msc_pack_coup, dim3(blocks_for(words)), dim3(256), 0, s, coup, packed, dN, words);
+    const int64_t quads = (int64_t)n_groups * dN / 4;
+    if (quads == 0 || dN % 4) return quads == 0 ? hipSuccess : hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_msc_pack, dim3(blocks_for(quads)), dim3(256), 0, s, coup, packed, dN, quads);
     return hipGetLastError();
 }
 
 hipError_t launch_msc_unpack(const uint32_t *packed, int8_t *spins, int64_t N, int n_groups, hipStream_t s) {
-    const int64_t words = (int64_t)n_groups * N;
-    if (words == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_msc_unpack, dim3(blocks_for(words)), dim3(256), 0, s, packed, spins, N, words);
+    const int64_t quads = (int64_t)n_groups * N / 4;
+    if (quads == 0 || N % 4) return quads == 0 ? hipSuccess : hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_msc_unpack, dim3(blocks_for(quads)), dim3(256), 0, s, packed, spins, N, quads);
     return hipGetLastError();
 }
 

@@ -108,3 +108,19 @@ def test_msc2d_benchmark_shape_sampled():
             d = O.run(2, L, J, s, 1.0, seed, g, 0, n)
             assert np.array_equal(got_s[r], s), r
             assert int(got_dE[r]) == int(d), r
+
+
+def test_msc_unaligned_buffers_take_the_generic_kernels():
+    """Spins one byte past an aligned address: same results as aligned."""
+    L, n_rep, seed, n = 16, 32, W.seed_for(68), 5
+    betas = np.full(n_rep, 0.8)
+    _, ref_s, ref_dE = _run(S.EA, 2, L, n_rep, betas, seed, 0, n)
+    b = S.Batch(S.EA, 2, L, n_rep, seed)
+    buf = torch.zeros(b.spins_shape()[0] + 1, dtype=torch.int8, device=DEV)
+    spins = buf[1:]
+    coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV)
+    S.spin_init(b, spins, coup)
+    dE = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
+    S.msc_sweep(b, spins, betas, 0, n, couplings=coup, dE_accum=dE)
+    assert np.array_equal(_host(spins).reshape(n_rep, -1), ref_s)
+    assert np.array_equal(_host(dE), ref_dE)
