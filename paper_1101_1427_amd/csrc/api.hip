@@ -76,6 +76,7 @@ enum Slot {
     kMscSpins,
     kMscCoup,
     kMscEnergy,
+    kMscGauge,
     kNumSlots
 };
 
@@ -981,6 +982,8 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
         if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &tp))) return rc;
         if ((rc = ensure(c, kMscSpins, sizeof(uint32_t) * (size_t)(G * N), &sp))) return rc;
         if ((rc = ensure(c, kMscCoup, sizeof(uint32_t) * (size_t)(G * 2 * N), &cp))) return rc;
+        void *gp = nullptr;
+        if ((rc = ensure(c, kMscGauge, sizeof(uint32_t) * (size_t)(G * N), &gp))) return rc;
         const size_t mbytes = measure_scratch_bytes(plan.b, plan.max_L);
         if (dE_accum) {
             if ((rc = ensure(c, kMscEnergy, 2 * sizeof(double) * (size_t)desc->n_rep, &ep))) return rc;
@@ -990,11 +993,12 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
         }
         SMC_HIP(launch_msc_pack((const int8_t *)spins, (uint32_t *)sp, N, G, s));
         SMC_HIP(launch_msc_pack_coup(ea ? couplings : nullptr, (uint32_t *)cp, 2 * N, G, s));
+        SMC_HIP(launch_msc_gauge2d((uint32_t *)sp, (uint32_t *)cp, (uint32_t *)gp, desc->L, G, s));
         SweepTimer timer(s, 1);  // all sweeps in one launch
         SMC_HIP(launch_msc2d((uint32_t *)sp, (const uint32_t *)cp, (const ThrRow *)tp, G, desc->L,
                              make_key(desc->seed), (uint32_t)sweep0, n_sweeps, s));
         timer.finish();
-        SMC_HIP(launch_msc_unpack((const uint32_t *)sp, (int8_t *)spins, N, G, s));
+        SMC_HIP(launch_msc_unpack((const uint32_t *)sp, (const uint32_t *)gp, (int8_t *)spins, N, G, s));
         if (dE_accum) {
             double *E0 = (double *)ep, *E1 = E0 + desc->n_rep;
             SMC_HIP(launch_measure(plan.b, spins, ea ? couplings : nullptr, plan.max_L, E1, nullptr, mp, mbytes, s));

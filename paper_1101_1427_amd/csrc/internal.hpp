@@ -125,7 +125,11 @@ hipError_t add_pt_swap_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNo
 bool msc2d_supported(int dim, int L);
 hipError_t launch_msc_pack(const int8_t *spins, uint32_t *packed, int64_t N, int n_groups, hipStream_t s);
 hipError_t launch_msc_pack_coup(const int8_t *coup, uint32_t *packed, int64_t dN, int n_groups, hipStream_t s);
-hipError_t launch_msc_unpack(const uint32_t *packed, int8_t *spins, int64_t N, int n_groups, hipStream_t s);
+hipError_t launch_msc_unpack(const uint32_t *packed, const uint32_t *gauge, int8_t *spins, int64_t N, int n_groups,
+                             hipStream_t s);
+// Gauge fixing of packed 2D words (horizontal bonds +1 except the row's
+// closing bond); gauge [G][L*L] receives the transformation for unpacking.
+hipError_t launch_msc_gauge2d(uint32_t *spins, uint32_t *coup, uint32_t *gauge, int L, int n_groups, hipStream_t s);
 hipError_t launch_msc_energy_diff(const double *E0, const double *E1, int64_t *dE, int n, hipStream_t s);
 hipError_t launch_msc2d(uint32_t *spins, const uint32_t *coup, const ThrRow *thr, int n_groups, int L, Key key,
                         uint32_t t0, int n_sweeps, hipStream_t s);

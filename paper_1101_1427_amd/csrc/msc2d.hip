@@ -16,6 +16,14 @@
 // two 16-bit halves as in the other kernels: the head (one Philox block
 // serves 8 sites) decides unless it equals the high half of a threshold.
 //
+// Gauge: a transformation s_i -> e_i s_i, J_ij -> e_i J_ij e_j (e_i = +-1
+// per site and replica) leaves every unsatisfied-bond count, and so every
+// decision, unchanged.  Before the sweeps each row is transformed so that
+// its horizontal bonds are all +1 except the one that closes the periodic
+// row (e runs as the prefix product of the row's bonds); afterwards the
+// spins are transformed back.  The kernel then needs one horizontal bond
+// word per row instead of one per site.
+//
 // Layout: a workgroup holds whole groups; each group's lattice of words
 // lives in LDS (padded so that the lanes of a wave read 64 different banks)
 // and in registers: a thread owns 16 consecutive sites of one row (8 of
@@ -52,8 +60,9 @@ struct MscGeom<4> {
 };
 
 struct Msc2dArgs {
-    uint32_t *spins;       // packed [G][L*L] (bit k: replica 32g + k is -1)
-    const uint32_t *coup;  // packed [G][2][L*L] (bit k: J = -1 for replica 32g + k)
+    uint32_t *spins;       // packed, gauge-fixed [G][L*L] (bit k: replica 32g + k is -1)
+    const uint32_t *coup;  // packed, gauge-fixed [G][2][L*L] (bit k: J = -1 for replica 32g + k);
+                           // horizontal bonds are +1 except at x = L-1
     const ThrRow *thr;     // per group
     Key key;
     uint32_t t0;
@@ -63,14 +72,40 @@ struct Msc2dArgs {
 
 // Colour c of the thread's 16 sites, those at columns OFF, OFF+2, .., 14+OFF
 // of its segment (OFF = (c + y) & 1 is uniform across a wave).
+// Flip mask of the site in column xx (the 32 replicas of the word) for the
+// decisions d1 = [u < thr(dE = 4)] and d2 = [u < thr(dE = 8)]: with a_j the
+// unsatisfied-bond words of its four bonds, n >= 2 flips always, n = 1 iff
+// d1, n = 0 iff d2 (d2 implies d1).
+template <int OFF>
+__device__ __forceinline__ uint32_t msc_flip_mask(const uint32_t (&S)[16], const uint32_t (&JD)[16], uint32_t JL,
+                                                  uint32_t JR15, uint32_t bnd, const uint32_t *up, const uint32_t *dn,
+                                                  const uint32_t *ju, int xx, bool d1, bool d2) {
+    const uint32_t s = S[xx];
+    const uint32_t left = xx == 0 ? bnd : S[xx == 0 ? 0 : xx - 1];
+    const uint32_t right = xx == 15 ? bnd : S[xx == 15 ? 15 : xx + 1];
+    const uint32_t a1 = xx == 0 ? s ^ left ^ JL : s ^ left;
+    const uint32_t a2 = xx == 15 ? s ^ right ^ JR15 : s ^ right;
+    const uint32_t a3 = s ^ up[xx] ^ ju[xx];
+    const uint32_t a4 = s ^ dn[xx] ^ JD[xx];
+    const uint32_t p = a1 ^ a2, q = a1 & a2, r = a3 ^ a4, u = a3 & a4;
+    const uint32_t ge2 = q | u | (p & r);
+    const uint32_t ge1 = a1 | a2 | a3 | a4;
+    return d2 ? 0xFFFFFFFFu : (d1 ? ge1 : ge2);
+}
+
+// JL / JR15: the horizontal bonds into column 0 and out of column 15 of the
+// segment (the row's closing bond at the lattice edge, +1 elsewhere after the
+// gauge); JD: the bonds down from the owned sites; the bonds up from them are
+// the row above's down bonds, read from the bond plane jd in LDS.
 template <int SEG, int OFF>
-__device__ __forceinline__ void msc_half(uint32_t (&S)[16], const uint32_t (&JR)[16], const uint32_t (&JD)[16],
-                                         const uint32_t (&JU)[16], uint32_t JL, uint32_t *lat, int y, int seg,
-                                         uint32_t g, uint32_t t, uint32_t c, const ThrRow &thr, Key key) {
+__device__ __forceinline__ void msc_half(uint32_t (&S)[16], const uint32_t (&JD)[16], uint32_t JL, uint32_t JR15,
+                                         uint32_t *lat, const uint32_t *jd, int y, int seg, uint32_t g, uint32_t t,
+                                         uint32_t c, const ThrRow &thr, Key key) {
     using GE = MscGeom<SEG>;
     constexpr int L = 16 * SEG;
     const uint32_t *up = lat + ((y + L - 1) % L) * GE::RS + seg * GE::SS;
     const uint32_t *dn = lat + ((y + 1) % L) * GE::RS + seg * GE::SS;
+    const uint32_t *ju = jd + ((y + L - 1) % L) * GE::RS + seg * GE::SS;
     // the neighbour word outside the segment: column 15 of the segment to
     // the left (OFF = 0) or column 0 of the one to the right (OFF = 1)
     const uint32_t bnd = OFF == 0 ? lat[y * GE::RS + ((seg + SEG - 1) % SEG) * GE::SS + 15]
@@ -78,32 +113,42 @@ __device__ __forceinline__ void msc_half(uint32_t (&S)[16], const uint32_t (&JR)
     const uint32_t b = (uint32_t)(y * SEG + seg);  // Philox block: in-colour sites 8b .. 8b+7
     const uint4 w = philox4x32_10(make_uint4(b, t, g, 2 * kTagHead + c), key);
     const uint32_t T1 = thr.m[1].x, T2 = thr.m[2].x;
+    // Flip masks from the heads alone; a head equal to the high half of a
+    // threshold (rare) marks its site for the exact path below, which then
+    // replaces that site's mask.  Nothing is applied before both are done.
+    uint32_t flip[8];
+    bool tie[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int xx = OFF + 2 * j;
-        const uint32_t s = S[xx];
-        const uint32_t left = xx == 0 ? bnd : S[xx == 0 ? 0 : xx - 1];
-        const uint32_t right = xx == 15 ? bnd : S[xx == 15 ? 15 : xx + 1];
-        const uint32_t jl = xx == 0 ? JL : JR[xx == 0 ? 0 : xx - 1];
-        const uint32_t a1 = s ^ left ^ jl;
-        const uint32_t a2 = s ^ right ^ JR[xx];
-        const uint32_t a3 = s ^ up[xx] ^ JU[xx];
-        const uint32_t a4 = s ^ dn[xx] ^ JD[xx];
-        const uint32_t p = a1 ^ a2, q = a1 & a2, r = a3 ^ a4, u = a3 & a4;
-        const uint32_t ge2 = q | u | (p & r);
-        const uint32_t ge1 = a1 | a2 | a3 | a4;
         const uint32_t word = j < 2 ? w.x : j < 4 ? w.y : j < 6 ? w.z : w.w;
         const uint32_t head = (j & 1) ? (word >> 16) : (word & 0xFFFFu);
-        bool d1 = head < T1, d2 = head < T2;
-        if (__builtin_expect(head == T1 || head == T2, 0)) {
-            // the head equals the high half of a threshold: the tail decides
-            const uint32_t tail = tail16(8u * b + (uint32_t)j, t, g, c, key);
-            d1 = head < T1 || (head == T1 && tail < thr.m[1].y);
-            d2 = head < T2 || (head == T2 && tail < thr.m[2].y);
-        }
-        const uint32_t flip = d2 ? 0xFFFFFFFFu : (d1 ? ge1 : ge2);
-        S[xx] = s ^ flip;
+        flip[j] = msc_flip_mask<OFF>(S, JD, JL, JR15, bnd, up, dn, ju, xx, head < T1, head < T2);
+        tie[j] = head == T1 || head == T2;
     }
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) any = any || tie[j];
+    if (__builtin_expect(any, 0)) {
+        // one tied site of this lane per pass (one tail draw at a time)
+        uint32_t pending = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) pending |= tie[j] ? (1u << j) : 0u;
+        while (pending) {
+            const uint32_t jl = (uint32_t)__builtin_ctz(pending);
+            pending &= pending - 1u;
+            const uint32_t word = jl < 2u ? w.x : jl < 4u ? w.y : jl < 6u ? w.z : w.w;
+            const uint32_t head = (jl & 1u) ? (word >> 16) : (word & 0xFFFFu);
+            const uint32_t tail = tail16(8u * b + jl, t, g, c, key);
+            const bool d1 = head < T1 || (head == T1 && tail < thr.m[1].y);
+            const bool d2 = head < T2 || (head == T2 && tail < thr.m[2].y);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (jl == (uint32_t)j) flip[j] = msc_flip_mask<OFF>(S, JD, JL, JR15, bnd, up, dn, ju, OFF + 2 * j, d1, d2);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) S[OFF + 2 * j] ^= flip[j];
     uint32_t *own = lat + y * GE::RS + seg * GE::SS;
 #pragma unroll
     for (int j = 0; j < 8; ++j) own[OFF + 2 * j] = S[OFF + 2 * j];
@@ -117,6 +162,7 @@ __global__ __launch_bounds__(kMscBlock) void k_msc2d(Msc2dArgs a) {
     constexpr int GPW = kMscBlock / TPG;  // groups per workgroup
     constexpr int PER = TPG / 2;        // threads per group and row parity
     __shared__ uint32_t lds[GPW * GE::GS];
+    __shared__ uint32_t lds_jd[GPW * GE::GS];  // down bonds, same geometry
     // threads [0, 128) own even rows, [128, 256) odd rows, so that the
     // colour offset of a half-sweep is uniform across each wave
     const int par = (int)threadIdx.x / (kMscBlock / 2);
@@ -126,24 +172,31 @@ __global__ __launch_bounds__(kMscBlock) void k_msc2d(Msc2dArgs a) {
     const int g = (int)blockIdx.x * GPW + gw;
     const bool live = g < a.G;
     uint32_t *lat = lds + gw * GE::GS;
+    uint32_t *jd = lds_jd + gw * GE::GS;
 
-    uint32_t S[16], JR[16], JD[16], JU[16], JL = 0;
-    {
-        const size_t base = (size_t)(live ? g : 0) * N;
-        const int x0 = 16 * seg;
-        const int ym = (y + L - 1) % L;
+    uint32_t S[16], JD[16], JL = 0, JR15 = 0;
+    if (live) {
+        const uint32_t *sp = a.spins + (size_t)g * N + (size_t)(y * L + 16 * seg);
+        const uint32_t *cp = a.coup + 2 * (size_t)g * N;
 #pragma unroll
         for (int xx = 0; xx < 16; ++xx) {
-            S[xx] = live ? a.spins[base + (size_t)(y * L + x0 + xx)] : 0u;
-            JR[xx] = live ? a.coup[2 * base + (size_t)(y * L + x0 + xx)] : 0u;
-            JD[xx] = live ? a.coup[2 * base + N + (size_t)(y * L + x0 + xx)] : 0u;
-            JU[xx] = live ? a.coup[2 * base + N + (size_t)(ym * L + x0 + xx)] : 0u;
+            S[xx] = sp[xx];
+            JD[xx] = cp[N + y * L + 16 * seg + xx];
         }
-        JL = live ? a.coup[2 * base + (size_t)(y * L + (x0 + L - 1) % L)] : 0u;
+        const uint32_t wrap = cp[y * L + L - 1];  // the row's closing bond (L-1 -> 0)
+        JL = seg == 0 ? wrap : 0u;
+        JR15 = seg == SEG - 1 ? wrap : 0u;
+    } else {
+#pragma unroll
+        for (int xx = 0; xx < 16; ++xx) S[xx] = JD[xx] = 0u;
     }
     uint32_t *own = lat + y * GE::RS + seg * GE::SS;
+    uint32_t *ownj = jd + y * GE::RS + seg * GE::SS;
 #pragma unroll
-    for (int xx = 0; xx < 16; ++xx) own[xx] = S[xx];
+    for (int xx = 0; xx < 16; ++xx) {
+        own[xx] = S[xx];
+        ownj[xx] = JD[xx];
+    }
     const ThrRow thr = a.thr[live ? g : 0];
     __syncthreads();
     for (int k = 0; k < a.n_sweeps; ++k) {
@@ -151,9 +204,9 @@ __global__ __launch_bounds__(kMscBlock) void k_msc2d(Msc2dArgs a) {
 #pragma unroll
         for (uint32_t c = 0; c < 2; ++c) {
             if (((c + (uint32_t)par) & 1u) == 0u)
-                msc_half<SEG, 0>(S, JR, JD, JU, JL, lat, y, seg, (uint32_t)g, t, c, thr, a.key);
+                msc_half<SEG, 0>(S, JD, JL, JR15, lat, jd, y, seg, (uint32_t)g, t, c, thr, a.key);
             else
-                msc_half<SEG, 1>(S, JR, JD, JU, JL, lat, y, seg, (uint32_t)g, t, c, thr, a.key);
+                msc_half<SEG, 1>(S, JD, JL, JR15, lat, jd, y, seg, (uint32_t)g, t, c, thr, a.key);
             __syncthreads();
         }
     }
@@ -187,11 +240,53 @@ __global__ __launch_bounds__(256) void k_msc_pack(const int8_t *src, uint32_t *d
     *(uint4 *)(dst + g * M + i) = make_uint4(w0, w1, w2, w3);
 }
 
-__global__ __launch_bounds__(256) void k_msc_unpack(const uint32_t *src, int8_t *dst, int64_t N, int64_t quads) {
+// Gauge fixing of 2D packed words, one thread per row (g, y): e(0) = 0,
+// e(x+1) = e(x) ^ JR(x); spins ^= e; the row's horizontal bonds become 0
+// (+1) except JR(L-1), which becomes the XOR of all of them (the row loop's
+// sign).  e is kept for the way back.
+__global__ __launch_bounds__(256) void k_msc_gauge_rows(uint32_t *spins, uint32_t *coup, uint32_t *gauge, int L,
+                                                        int64_t rows) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= rows) return;
+    const int64_t N = (int64_t)L * L, g = gid / L, y = gid % L;
+    uint32_t *jr = coup + 2 * g * N + y * L;
+    uint32_t *sp = spins + g * N + y * L;
+    uint32_t *ep = gauge + g * N + y * L;
+    uint32_t e = 0;
+    for (int x = 0; x < L; ++x) {
+        ep[x] = e;
+        sp[x] ^= e;
+        e ^= jr[x];
+        jr[x] = x == L - 1 ? e : 0u;
+    }
+}
+
+// Vertical bonds under the gauge: JD(x, y) ^= e(x, y) ^ e(x, y+1).
+__global__ __launch_bounds__(256) void k_msc_gauge_vertical(uint32_t *coup, const uint32_t *gauge, int L,
+                                                            int64_t words) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= words) return;
+    const int64_t N = (int64_t)L * L, g = gid / N, i = gid % N;
+    const int64_t y = i / L, x = i % L;
+    const int64_t below = ((y + 1) % L) * L + x;
+    coup[2 * g * N + N + i] ^= gauge[g * N + i] ^ gauge[g * N + below];
+}
+
+// Packed words (with gauge e, or none) -> int8 +-1 values of replicas 32g ..
+// 32g+31, four sites per thread.
+__global__ __launch_bounds__(256) void k_msc_unpack(const uint32_t *src, const uint32_t *gauge, int8_t *dst,
+                                                    int64_t N, int64_t quads) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= quads) return;
     const int64_t g = gid / (N / 4), i = 4 * (gid % (N / 4));
-    const uint4 w = *(const uint4 *)(src + g * N + i);
+    uint4 w = *(const uint4 *)(src + g * N + i);
+    if (gauge) {
+        const uint4 e = *(const uint4 *)(gauge + g * N + i);
+        w.x ^= e.x;
+        w.y ^= e.y;
+        w.z ^= e.z;
+        w.w ^= e.w;
+    }
     int8_t *p = dst + 32 * g * N + i;
 #pragma unroll 8
     for (int k = 0; k < 32; ++k) {
@@ -228,10 +323,21 @@ hipError_t launch_msc_pack_coup(const int8_t *coup, uint32_t *packed, int64_t dN
     return hipGetLastError();
 }
 
-hipError_t launch_msc_unpack(const uint32_t *packed, int8_t *spins, int64_t N, int n_groups, hipStream_t s) {
+hipError_t launch_msc_unpack(const uint32_t *packed, const uint32_t *gauge, int8_t *spins, int64_t N, int n_groups,
+                             hipStream_t s) {
     const int64_t quads = (int64_t)n_groups * N / 4;
     if (quads == 0 || N % 4) return quads == 0 ? hipSuccess : hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_msc_unpack, dim3(blocks_for(quads)), dim3(256), 0, s, packed, spins, N, quads);
+    hipLaunchKernelGGL(k_msc_unpack, dim3(blocks_for(quads)), dim3(256), 0, s, packed, gauge, spins, N, quads);
+    return hipGetLastError();
+}
+
+hipError_t launch_msc_gauge2d(uint32_t *spins, uint32_t *coup, uint32_t *gauge, int L, int n_groups, hipStream_t s) {
+    const int64_t rows = (int64_t)n_groups * L, words = rows * L;
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_msc_gauge_rows, dim3(blocks_for(rows)), dim3(256), 0, s, spins, coup, gauge, L, rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_msc_gauge_vertical, dim3(blocks_for(words)), dim3(256), 0, s, coup, gauge, L, words);
     return hipGetLastError();
 }
 
