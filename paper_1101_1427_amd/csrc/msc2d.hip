@@ -27,10 +27,10 @@
 // Layout: a workgroup holds whole groups; each group's lattice of words
 // lives in LDS (padded so that the lanes of a wave read 64 different banks)
 // and in registers: a thread owns 16 consecutive sites of one row (8 of
-// each colour, one Philox block per colour) with their spins and the
-// couplings of all their bonds.  A half-sweep reads the four neighbours'
-// words from LDS, updates the owned words of one colour in registers and
-// writes them back; one barrier per half-sweep.  All sweeps of a call run in
+// each colour, one Philox block per colour) with their spins and down
+// bonds.  A half-sweep reads the neighbours' words and the up bonds from
+// LDS, updates the owned words of one colour in registers and writes them
+// back; one barrier per half-sweep.  All sweeps of a call run in
 // one launch, so HBM is touched only at its start and end.
 #include "internal.hpp"
 
