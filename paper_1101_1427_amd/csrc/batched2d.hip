@@ -77,20 +77,22 @@ __device__ __forceinline__ uint32_t decide4(uint32_t n, uint32_t wa, uint32_t wb
 // (either in LDS or in global memory), all with the row layout above.
 // Offsets (in a row-layout plane) of the words a colour-c group reads.
 struct GroupAt {
-    int own, oth, ext, below, above;
+    uint32_t own, oth, ext, below, above;
 };
 
-__device__ __forceinline__ GroupAt group_at(int L, int y, int k, int c) {
-    const int half = L >> 1;
+// yL = y * L (kept by the caller as the rows advance, without multiplications).
+__device__ __forceinline__ GroupAt group_at(int L, int yL, int y, int k, int c) {
+    const int half = L >> 1, N = L * L;
     const int a = (y & 1) == c ? 0 : 1;
-    const int ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+    const int ymL = yL == 0 ? N - L : yL - L, ypL = yL == N - L ? 0 : yL + L;
     GroupAt o;
-    o.own = y * L + a * half + 8 * k;
-    o.oth = y * L + (1 - a) * half + 8 * k;
+    o.own = (uint32_t)(yL + a * half + 8 * k);
+    o.oth = (uint32_t)(yL + (1 - a) * half + 8 * k);
     // the extra word of the other array: the word before (a = 0) or after (a = 1), wrapping in the row
-    o.ext = y * L + (1 - a) * half + (a == 0 ? (k == 0 ? half - 4 : 8 * k - 4) : (8 * k + 8 == half ? 0 : 8 * k + 8));
-    o.below = ym * L + a * half + 8 * k;
-    o.above = yp * L + a * half + 8 * k;
+    o.ext = (uint32_t)(yL + (1 - a) * half +
+                       (a == 0 ? (k == 0 ? half - 4 : 8 * k - 4) : (8 * k + 8 == half ? 0 : 8 * k + 8)));
+    o.below = (uint32_t)(ymL + a * half + 8 * k);
+    o.above = (uint32_t)(ypL + a * half + 8 * k);
     return o;
 }
 
@@ -248,27 +250,47 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
 
     uint32_t cnt = 0u, nsum = 0u;
     const int groups = N >> 4;  // per colour
+    // The couplings of the next group are requested before this one is
+    // computed; the loop body handles two groups with alternating register
+    // sets, so nothing is copied from one iteration to the next.
+    struct Pos {
+        int y, yL, k;
+    };
+    auto advance = [&](Pos p) {
+        p.y += dy;
+        p.yL += dy * L;
+        p.k += dk;
+        if (p.k >= G) {
+            p.k -= G;
+            ++p.y;
+            p.yL += L;
+        }
+        return p;
+    };
 #pragma unroll 1
     for (int c = 0; c < 2; ++c) {
-        // the couplings of the next group are requested before this one is computed
-        GroupAt at = group_at(L, y0, k0, c);
-        GroupCoup J{};
-        if (EA && tid < groups) J = group_coup(X, Yp, at);
+        // (past the last group the position is clamped to row 0, so every
+        // coupling load stays inside the sample and none is conditional)
+        Pos pa{y0 < L ? y0 : 0, y0 < L ? y0 * L : 0, k0};
+        GroupAt ata = group_at(L, pa.yL, pa.y, pa.k, c);
+        GroupCoup Ja{};
+        if (EA) Ja = group_coup(X, Yp, ata);
 #pragma unroll 1
-        for (int q = tid, y = y0, k = k0; q < groups; q += nt) {
-            int yn = y + dy, kn = k + dk;
-            if (kn >= G) {
-                kn -= G;
-                ++yn;
-            }
-            const GroupAt atn = group_at(L, yn < L ? yn : 0, kn, c);
-            GroupCoup Jn = J;
-            if (EA && q + nt < groups) Jn = group_coup(X, Yp, atn);
-            group<EA>(S, at, J, L, y, k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
-            y = yn;
-            k = kn;
-            at = atn;
-            J = Jn;
+        for (int q = tid; q < groups;) {
+            const Pos pb = advance(pa);
+            const bool hb = q + nt < groups;
+            const GroupAt atb = group_at(L, hb ? pb.yL : 0, hb ? pb.y : 0, pb.k, c);
+            GroupCoup Jb{};
+            if (EA) Jb = group_coup(X, Yp, atb);
+            group<EA>(S, ata, Ja, L, pa.y, pa.k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+            q += nt;
+            if (!hb) break;
+            pa = advance(pb);
+            const bool ha = q + nt < groups;
+            ata = group_at(L, ha ? pa.yL : 0, ha ? pa.y : 0, pa.k, c);
+            if (EA) Ja = group_coup(X, Yp, ata);
+            group<EA>(S, atb, Jb, L, pb.y, pb.k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+            q += nt;
         }
         __syncthreads();
     }
