@@ -145,7 +145,7 @@ def valu_summary(db: str, command: str):
              "# instruction per CU per cycle (four SIMD16 units, four cycles each)",
              f"{'kernel':28s} {'dispatches':>10s} {'VALU_insts':>14s} {'busy_cycles':>12s} {'util':>6s}"]
     for k in ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_tiled", "k_heis3d_half",
-              "k_half_sweep_generic", "k_msc2d", "k_philox_bench", "k_to_split", "k_from_split"):
+              "k_half_sweep_generic", "k_msc2d", "k_dcb2d", "k_philox_bench", "k_to_split", "k_from_split"):
         if k not in acc or "SQ_INSTS_VALU" not in acc[k] or "GRBM_GUI_ACTIVE" not in acc[k]:
             continue
         v = acc[k]["SQ_INSTS_VALU"]
@@ -382,6 +382,40 @@ def msc_ea2d(S, W, sweeps, L=16, sizes=(14, 16, 18, 20), single_spin_sweeps=20):
             "kernel": kernel, "by_replicas": rows}
 
 
+def dcb2d(S, W, sweeps, L=16384, tile=64, hits=(1, 2, 4, 8, 16, 64)):
+    """Double checkerboard with multi-hit updates (Sec. 3.2, Sec. 3.4) on the
+    2D Ising 16384^2 lattice at beta_c: ps per attempted flip against the
+    number of hits k per tile (k attempts per site and sweep), in place on
+    the caller's int8 spins."""
+    import torch
+
+    cfg = W.ising_large(L)
+    b = S.Batch(S.ISING, 2, L, 1, cfg.seed)
+    spins = torch.empty(L * L, dtype=torch.int8, device="cuda")
+    S.spin_init(b, spins)
+    rows = []
+    t0 = 0
+    for k in hits:
+        n = max(2, sweeps // k)
+        S.dcb_sweep(b, spins, [cfg.betas[1]], t0, 1, tile, k)
+        t0 += 1
+        S.kernel_timing_read()
+        S.kernel_timing_enable(True)
+        ms = _timed(lambda: S.dcb_sweep(b, spins, [cfg.betas[1]], t0, n, tile, k))
+        kernel_ms, launches = S.kernel_timing_read()
+        S.kernel_timing_enable(False)
+        t0 += n
+        flips = L * L * k * n
+        rows.append({"hits": k, "sweeps": n, "ms": round(ms, 3), "ps_per_flip": round(ms * 1e9 / flips, 4),
+                     "hbm_frac_at_2B_per_site_sweep": round(2.0 * L * L * n / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                                            4)})
+    del spins
+    torch.cuda.empty_cache()
+    return {"workload": f"2D Ising {L}x{L}, beta_c, double checkerboard with {tile}x{tile} tiles, k hits per tile "
+                        f"and sweep, in place on int8 spins",
+            "kernel": "k_dcb2d", "by_hits": rows}
+
+
 def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):
     """Uneven 2D EA batch, 4096 instances x 16 temperatures, edges from
     {32, ..., 256}: the batch in one call (a graph of steps), against one call
@@ -521,6 +555,8 @@ def main():
     ap.add_argument("--heis-sweeps", type=int, default=1000)
     ap.add_argument("--heis-only", action="store_true", help="only the Heisenberg measurement (for profiling)")
     ap.add_argument("--msc-sweeps", type=int, default=2000)
+    ap.add_argument("--dcb-sweeps", type=int, default=64)
+    ap.add_argument("--dcb-only", action="store_true", help="only the double-checkerboard measurement")
     ap.add_argument("--msc-only", action="store_true", help="only the multi-spin-coded measurement (for profiling)")
     ap.add_argument("--pmc-kernel", default="k_ising2d_split", choices=sorted(KERNEL_SOURCES),
                     help="kernel of the --pmc-summary")
@@ -563,6 +599,9 @@ def main():
         return
     if args.msc_only:
         print(json.dumps({"msc_ea2d": msc_ea2d(S, W, args.msc_sweeps)}))
+        return
+    if args.dcb_only:
+        print(json.dumps({"dcb2d": dcb2d(S, W, args.dcb_sweeps)}))
         return
     cfg = W.ising_large(args.L)
     L = cfg.L
@@ -643,6 +682,7 @@ def main():
         out["tempering"] = {"ea3d_L16": tempering_ea3d(S, W, args.pt3d_steps),
                             "ea2d_uneven": tempering_ea2d_uneven(S, W, args.uneven_steps)}
         out["msc_ea2d"] = msc_ea2d(S, W, args.msc_sweeps)
+        out["dcb2d"] = dcb2d(S, W, args.dcb_sweeps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg)
         out["cpu_baseline"] = cb

@@ -243,6 +243,31 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
 int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, const char **kernel_name);
 
 /*
+ * Double checkerboard sweeps with multi-hit updates (Sec. 3.2, steps 1-7;
+ * Sec. 3.4): a different Markov chain from smc_metropolis_sweep, whose
+ * order depends on the tiling.  The 2D lattice is cut into tile x tile
+ * tiles, B = L / tile per direction; tile (bx, by) has tile colour
+ * (bx + by) & 1.  Sweep t treats every tile of tile colour 0, then every
+ * tile of colour 1; each tile gets `hits` hits, a hit being a Metropolis
+ * attempt (Eq. 2) at each colour-0 site of the tile, then at each colour-1
+ * site, with the sites outside the tile held fixed.  With palindromic != 0
+ * odd sweeps run both orders backwards (tile colour 1 first, colour-1 sites
+ * first; two sweeps then form a palindrome of single-colour updates, Sec.
+ * 3.4).  Hit j of sweep t draws the uniforms smc_metropolis_sweep draws in
+ * sweep t*hits + j; with tile = L and hits = 1 the two calls agree.
+ *  desc:      uniform 2D batch (L > 0), model SMC_ISING or SMC_EA.
+ *  tile:      a multiple of 16 in [16, 128] with L / tile even or 1.
+ *  hits:      >= 1; (sweep0 + n_sweeps) * hits must not exceed 2^32.
+ *  spins, couplings, beta (HOST [n_rep]), sweep0, n_sweeps, dE_accum,
+ *  stream: as for smc_metropolis_sweep; every replica is updated in place.
+ * SMC_EUNSUPPORTED for Heisenberg or 3D batches, SMC_EINVAL for a tile or
+ * hit count outside these limits.
+ */
+int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
+                  int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
+                  void *stream);
+
+/*
  * Throughput probe of the random-number generator (Sec. 3.3, Fig. 4
  * measure generators on their own): thread i of n_threads draws the
  * Philox4x32-10 blocks with counters (i + k * n_threads, t, r, tag) for

@@ -71,6 +71,7 @@ def lib():
             "orc_pt_run": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, I, vp]),
             "orc_swap_u53": (D, [U64, U32, U32, U32]),
             "orc_window_run": (None, [I, I, I, I, i8p, D, U64, U32, U32, I]),
+            "orc_dcb_run": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -197,6 +198,13 @@ def pt_run(dim, L, J, spins, beta, slot_of_temp, E, seed, q, r0, t0, n_steps, sw
     n_temps = len(beta)
     lib().orc_pt_run(dim, L, _ptr(J), spins.reshape(-1), n_temps, np.ascontiguousarray(beta, np.float64),
                      slot_of_temp, E, seed, q, r0, t0, n_steps, _ptr(swap_acc))
+
+
+def dcb_run(L, T, k, J, s, beta, seed, r, t0, n, palindromic=False) -> int:
+    """n double-checkerboard sweeps (T x T tiles, k hits per tile) of a 2D
+    lattice in place; returns the summed Delta E (orc_dcb_run)."""
+    return int(lib().orc_dcb_run(L, T, k, _ptr(J), s, beta, seed & 0xFFFFFFFFFFFFFFFF, r, t0, n,
+                                 1 if palindromic else 0))
 
 
 def window_run(L, x0, y0, win, beta, seed, r, t0, n):

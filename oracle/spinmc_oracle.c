@@ -291,6 +291,67 @@ EXPORT int64_t orc_run(int dim, int L, const int8_t *J, int8_t *s, double beta,
     return dE;
 }
 
+/* Double checkerboard sweeps with multi-hit updates of a 2D lattice
+ * (Sec. 3.2 steps 1-7; Sec. 3.4 for k hits and the palindromic order).
+ * The lattice of edge L is cut into T x T tiles, B = L / T per direction
+ * (B even, or B = 1); tile (bx, by) has tile colour (bx + by) & 1.  Sweep t
+ * treats the tiles of tile colour 0, then those of tile colour 1; each tile
+ * gets k hits, a hit being a Metropolis attempt (Eq. 2) at every colour-0
+ * site of the tile followed by one at every colour-1 site, with the
+ * neighbours outside the tile (tiles of the other tile colour) held fixed.
+ * Tiles of one tile colour share no bond, so their order is irrelevant.
+ * With palindromic != 0, odd sweeps run both orders backwards (tile colour
+ * 1 first, colour-1 sites first), so that two consecutive sweeps form a
+ * palindrome of single-colour updates.  Hit j of sweep t draws the uniform
+ * of "sweep" t*k + j of the plain checkerboard (orc_metropolis_u32); with
+ * T = L and k = 1 the sweep is exactly orc_sweep.  Returns the summed
+ * Delta E of accepted flips. */
+EXPORT int64_t orc_dcb_run(int L, int T, int k, const int8_t *J, int8_t *s, double beta, uint64_t seed,
+                           uint32_t r, uint32_t t0, int n, int palindromic)
+{
+    uint64_t thr[4];
+    orc_thresholds(beta, 2, thr);
+    const int B = L / T;
+    int64_t dE_sum = 0;
+    for (int m = 0; m < n; ++m) {
+        const uint32_t t = t0 + (uint32_t)m;
+        const int rev = palindromic && (t & 1u);
+        for (int ci = 0; ci < 2; ++ci) {
+            const int tile_colour = rev ? 1 - ci : ci;
+            for (int by = 0; by < B; ++by) {
+                for (int bx = 0; bx < B; ++bx) {
+                    if (((bx + by) & 1) != tile_colour) continue;
+                    for (int j = 0; j < k; ++j) {
+                        const uint32_t th = t * (uint32_t)k + (uint32_t)j;
+                        for (int si = 0; si < 2; ++si) {
+                            const int c = rev ? 1 - si : si;
+                            for (int v = 0; v < T; ++v) {
+                                for (int u = 0; u < T; ++u) {
+                                    const int x = bx * T + u, y = by * T + v;
+                                    if (((x + y) & 1) != c) continue;
+                                    const int64_t i = (int64_t)y * L + x;
+                                    const int h = local_field(2, L, J, s, i);
+                                    const int dE = 2 * s[i] * h;
+                                    int accept = 1;
+                                    if (dE > 0) {
+                                        uint32_t uu = orc_metropolis_u32(seed, th, r, c, (uint64_t)(i >> 1));
+                                        accept = (uint64_t)uu < thr[dE / 4];
+                                    }
+                                    if (accept) {
+                                        s[i] = (int8_t)(-s[i]);
+                                        dE_sum += dE;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return dE_sum;
+}
+
 /* n sweeps t0 .. t0+n-1 of a W x W window of a 2D Ising lattice of edge L
  * (no couplings), for checking sampled sites of lattices too large to sweep
  * here.  win[v*W + u] is the site (x0 + u, y0 + v) mod L; every interior

@@ -72,6 +72,9 @@ def lib():
         L.smc_msc_sweep.restype = C.c_int
         L.smc_msc_plan.argtypes = [P(Desc), C.c_int32, P(C.c_int32), P(C.c_char_p)]
         L.smc_msc_plan.restype = C.c_int
+        L.smc_dcb_sweep.argtypes = [P(Desc), C.c_void_p, C.c_void_p, P(C.c_double), C.c_uint64, C.c_int32,
+                                    C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+        L.smc_dcb_sweep.restype = C.c_int
         L.smc_philox_bench.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
                                        C.c_void_p, C.c_void_p]
         L.smc_philox_bench.restype = C.c_int
@@ -171,6 +174,17 @@ def msc_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, couplings=N
     b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (batch.n_rep,)))
     _check(lib().smc_msc_sweep(C.byref(d), _ptr(spins), _ptr(couplings), b.ctypes.data_as(C.POINTER(C.c_double)),
                                sweep0, n_sweeps, _ptr(dE_accum), _stream(stream)), "smc_msc_sweep")
+
+
+def dcb_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, tile: int, hits: int, palindromic=False,
+              couplings=None, dE_accum=None, stream=None):
+    """n_sweeps double-checkerboard sweeps (tile x tile tiles, `hits` hits per
+    tile and sweep; see smc_dcb_sweep); beta is a host sequence [n_rep]."""
+    d = _desc(batch, spins, couplings)
+    b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (batch.n_rep,)))
+    _check(lib().smc_dcb_sweep(C.byref(d), _ptr(spins), _ptr(couplings), b.ctypes.data_as(C.POINTER(C.c_double)),
+                               sweep0, n_sweeps, tile, hits, 1 if palindromic else 0, _ptr(dE_accum),
+                               _stream(stream)), "smc_dcb_sweep")
 
 
 def msc_plan(batch: Batch, n_sweeps: int):

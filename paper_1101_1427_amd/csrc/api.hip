@@ -77,6 +77,7 @@ enum Slot {
     kMscCoup,
     kMscEnergy,
     kMscGauge,
+    kDcbSlots,
     kNumSlots
 };
 
@@ -1028,6 +1029,57 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
         SMC_HIP(launch_half_sweep_generic(a, 0, s));
         SMC_HIP(launch_half_sweep_generic(a, 1, s));
     }
+    return SMC_OK;
+}
+
+int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
+                  int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
+                  void *stream) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, true, plan);
+    if (rc) return rc;
+    if (desc->model != SMC_ISING && desc->model != SMC_EA)
+        return fail(SMC_EUNSUPPORTED, "the double checkerboard is provided for the Ising and EA models");
+    if (desc->dim != 2) return fail(SMC_EUNSUPPORTED, "the double checkerboard is provided for 2D lattices");
+    if (desc->L <= 0) return fail(SMC_EINVAL, "the double checkerboard needs a uniform batch (L > 0)");
+    if (!dcb2d_supported(desc->L, tile))
+        return fail(SMC_EINVAL, "tile %d: need a multiple of 16 in [16, 128] dividing L = %d into an even number "
+                                "of tiles per row (or one)", tile, desc->L);
+    if (hits < 1) return fail(SMC_EINVAL, "hits must be >= 1");
+    if (!spins) return fail(SMC_EINVAL, "spins is NULL");
+    if (!beta) return fail(SMC_EINVAL, "beta is NULL");
+    if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
+    if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+    if ((sweep0 + (uint64_t)n_sweeps) * (uint64_t)hits > (1ull << 32))
+        return fail(SMC_EINVAL, "(sweep0 + n_sweeps) * hits exceeds 2^32 (the hit index is one 32-bit word)");
+    for (int r = 0; r < desc->n_rep; ++r)
+        if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
+    if (n_sweeps == 0) return SMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    StreamCtx &c = ctx_for(s);
+    std::vector<ThrRow> rows(desc->n_rep);
+    for (int r = 0; r < desc->n_rep; ++r)
+        rows[r] = (r > 0 && beta[r] == beta[r - 1]) ? rows[r - 1] : threshold_row(beta[r], desc->dim);
+    void *tp = nullptr, *sp = nullptr;
+    if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &tp))) return rc;
+    const int per_rep = 2 * dcb2d_tiles_per_colour(desc->L, tile);
+    if (dE_accum) {
+        if ((rc = ensure(c, kDcbSlots, sizeof(int64_t) * (size_t)desc->n_rep * per_rep, &sp))) return rc;
+        SMC_HIP(launch_dcb_zero((int64_t *)sp, (int64_t)desc->n_rep * per_rep, s));
+    }
+    const bool ea = desc->model == SMC_EA;
+    SweepTimer timer(s, 2 * (int64_t)n_sweeps);
+    for (int32_t m = 0; m < n_sweeps; ++m) {
+        const uint64_t t = sweep0 + (uint64_t)m;
+        const bool rev = palindromic && (t & 1u);
+        for (int ci = 0; ci < 2; ++ci)
+            SMC_HIP(launch_dcb2d((int8_t *)spins, ea ? couplings : nullptr, ea ? desc->rep_per_sample : 1,
+                                 (const ThrRow *)tp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits,
+                                 make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, s));
+    }
+    timer.finish();
+    if (dE_accum) SMC_HIP(launch_dcb_collect((const int64_t *)sp, dE_accum, desc->n_rep, per_rep, s));
     return SMC_OK;
 }
 

@@ -134,6 +134,15 @@ hipError_t launch_msc_energy_diff(const double *E0, const double *E1, int64_t *d
 hipError_t launch_msc2d(uint32_t *spins, const uint32_t *coup, const ThrRow *thr, int n_groups, int L, Key key,
                         uint32_t t0, int n_sweeps, hipStream_t s);
 
+// Double checkerboard with multi-hit (2D Ising / EA, T x T tiles, T a
+// multiple of 16 in [16, 128], L / T even or 1): one launch per tile colour.
+bool dcb2d_supported(int L, int T);
+int dcb2d_tiles_per_colour(int L, int T);
+hipError_t launch_dcb2d(int8_t *spins, const int8_t *coup, int rep_per_sample, const ThrRow *thr, int64_t *dE_slots,
+                        int n_rep, int L, int T, int k, Key key, uint32_t t, int tile_colour, bool rev, hipStream_t s);
+hipError_t launch_dcb_zero(int64_t *p, int64_t n, hipStream_t s);
+hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, hipStream_t s);
+
 // Generator throughput: out[i] = XOR of the four words of the blocks with
 // counters (i + k * n_threads, t, r, tag), k < per_thread.
 hipError_t launch_philox_bench(Key key, uint32_t t, uint32_t r, uint32_t tag, uint32_t n_threads, int per_thread,
