@@ -382,11 +382,11 @@ def msc_ea2d(S, W, sweeps, L=16, sizes=(14, 16, 18, 20), single_spin_sweeps=20):
             "kernel": kernel, "by_replicas": rows}
 
 
-def dcb2d(S, W, sweeps, L=16384, tile=64, hits=(1, 2, 4, 8, 16, 64)):
+def dcb2d(S, W, sweeps, L=16384, tiles=(64, 128), hits=(1, 2, 4, 8, 16, 64, 100)):
     """Double checkerboard with multi-hit updates (Sec. 3.2, Sec. 3.4) on the
     2D Ising 16384^2 lattice at beta_c: ps per attempted flip against the
-    number of hits k per tile (k attempts per site and sweep), in place on
-    the caller's int8 spins."""
+    tile edge and the number of hits k per tile (k attempts per site and
+    sweep), in place on the caller's int8 spins."""
     import torch
 
     cfg = W.ising_large(L)
@@ -395,25 +395,27 @@ def dcb2d(S, W, sweeps, L=16384, tile=64, hits=(1, 2, 4, 8, 16, 64)):
     S.spin_init(b, spins)
     rows = []
     t0 = 0
-    for k in hits:
-        n = max(2, sweeps // k)
-        S.dcb_sweep(b, spins, [cfg.betas[1]], t0, 1, tile, k)
-        t0 += 1
-        S.kernel_timing_read()
-        S.kernel_timing_enable(True)
-        ms = _timed(lambda: S.dcb_sweep(b, spins, [cfg.betas[1]], t0, n, tile, k))
-        kernel_ms, launches = S.kernel_timing_read()
-        S.kernel_timing_enable(False)
-        t0 += n
-        flips = L * L * k * n
-        rows.append({"hits": k, "sweeps": n, "ms": round(ms, 3), "ps_per_flip": round(ms * 1e9 / flips, 4),
-                     "hbm_frac_at_2B_per_site_sweep": round(2.0 * L * L * n / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                                            4)})
+    for tile in tiles:
+        for k in hits:
+            n = max(2, sweeps // k)
+            S.dcb_sweep(b, spins, [cfg.betas[1]], t0, 1, tile, k)
+            t0 += 1
+            S.kernel_timing_read()
+            S.kernel_timing_enable(True)
+            ms = _timed(lambda: S.dcb_sweep(b, spins, [cfg.betas[1]], t0, n, tile, k))
+            kernel_ms, launches = S.kernel_timing_read()
+            S.kernel_timing_enable(False)
+            t0 += n
+            flips = L * L * k * n
+            rows.append({"tile": tile, "hits": k, "sweeps": n, "ms": round(ms, 3),
+                         "ps_per_flip": round(ms * 1e9 / flips, 4),
+                         "hbm_frac_at_2B_per_site_sweep": round(
+                             2.0 * L * L * n / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
     del spins
     torch.cuda.empty_cache()
-    return {"workload": f"2D Ising {L}x{L}, beta_c, double checkerboard with {tile}x{tile} tiles, k hits per tile "
+    return {"workload": f"2D Ising {L}x{L}, beta_c, double checkerboard with T x T tiles, k hits per tile "
                         f"and sweep, in place on int8 spins",
-            "kernel": "k_dcb2d", "by_hits": rows}
+            "kernel": S.dcb_plan(b, [cfg.betas[1]], tiles[0]), "by_tile_and_hits": rows}
 
 
 def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):

@@ -243,8 +243,7 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
 int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, const char **kernel_name);
 
 /*
- * Double checkerboard sweeps with multi-hit updates (Sec. 3.2, steps 1-7;
- * Sec. 3.4): a different Markov chain from smc_metropolis_sweep, whose
+ * Double checkerboard sweeps with multi-hit updates (Sec. 3.2, Sec. 3.4): a different Markov chain from smc_metropolis_sweep, whose
  * order depends on the tiling.  The 2D lattice is cut into tile x tile
  * tiles, B = L / tile per direction; tile (bx, by) has tile colour
  * (bx + by) & 1.  Sweep t treats every tile of tile colour 0, then every
@@ -266,6 +265,16 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, cons
 int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
                   int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
                   void *stream);
+
+/*
+ * Which kernel smc_dcb_sweep uses for this batch, tile and beta (HOST
+ * [n_rep]), for 16-byte aligned spins and couplings: "k_dcb2d_packed" (four
+ * sites per word; tile 16, 32, 64 or 128 and every beta > 0) or "k_dcb2d"
+ * (one site per thread).  Results are identical either way.  The same
+ * argument checks as smc_dcb_sweep on desc, tile and beta; no device work.
+ * kernel_name receives a static string.
+ */
+int smc_dcb_plan(const smc_desc *desc, const double *beta, int32_t tile, const char **kernel_name);
 
 /*
  * Throughput probe of the random-number generator (Sec. 3.3, Fig. 4

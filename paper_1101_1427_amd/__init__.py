@@ -75,6 +75,8 @@ def lib():
         L.smc_dcb_sweep.argtypes = [P(Desc), C.c_void_p, C.c_void_p, P(C.c_double), C.c_uint64, C.c_int32,
                                     C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
         L.smc_dcb_sweep.restype = C.c_int
+        L.smc_dcb_plan.argtypes = [P(Desc), P(C.c_double), C.c_int32, P(C.c_char_p)]
+        L.smc_dcb_plan.restype = C.c_int
         L.smc_philox_bench.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
                                        C.c_void_p, C.c_void_p]
         L.smc_philox_bench.restype = C.c_int
@@ -185,6 +187,16 @@ def dcb_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, tile: int, 
     _check(lib().smc_dcb_sweep(C.byref(d), _ptr(spins), _ptr(couplings), b.ctypes.data_as(C.POINTER(C.c_double)),
                                sweep0, n_sweeps, tile, hits, 1 if palindromic else 0, _ptr(dE_accum),
                                _stream(stream)), "smc_dcb_sweep")
+
+
+def dcb_plan(batch: Batch, beta, tile: int) -> str:
+    """Name of the kernel smc_dcb_sweep uses for this batch, beta and tile (aligned buffers)."""
+    d = batch.desc(batch.spins_shape()[0], batch.coup_len())
+    b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (batch.n_rep,)))
+    name = C.c_char_p()
+    _check(lib().smc_dcb_plan(C.byref(d), b.ctypes.data_as(C.POINTER(C.c_double)), tile, C.byref(name)),
+           "smc_dcb_plan")
+    return name.value.decode()
 
 
 def msc_plan(batch: Batch, n_sweeps: int):

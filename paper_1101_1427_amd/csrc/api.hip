@@ -1032,10 +1032,22 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     return SMC_OK;
 }
 
-int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
-                  int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
-                  void *stream) {
-    g_last_error.clear();
+// The packed double-checkerboard kernel: thresholds with 16-bit high halves,
+// 16-byte aligned buffers, a power-of-two tile; SPINMC_DCB_PACKED=0 forces
+// the per-site kernel (same results).
+static bool use_dcb_packed(const smc_desc *d, const std::vector<ThrRow> &rows, const void *spins,
+                           const int8_t *coup, int tile) {
+    const char *env = getenv("SPINMC_DCB_PACKED");
+    if (env && env[0] == '0') return false;
+    if (!dcb2d_packed_supported(d->L, tile)) return false;
+    if (((uintptr_t)spins & 15u) || ((uintptr_t)coup & 15u)) return false;
+    for (const ThrRow &r : rows)
+        if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu) return false;
+    return true;
+}
+
+// Checks shared by smc_dcb_sweep and smc_dcb_plan.
+static int dcb_check(const smc_desc *desc, const double *beta, int tile) {
     Plan plan;
     int rc = validate(desc, true, plan);
     if (rc) return rc;
@@ -1046,21 +1058,44 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     if (!dcb2d_supported(desc->L, tile))
         return fail(SMC_EINVAL, "tile %d: need a multiple of 16 in [16, 128] dividing L = %d into an even number "
                                 "of tiles per row (or one)", tile, desc->L);
+    if (!beta) return fail(SMC_EINVAL, "beta is NULL");
+    for (int r = 0; r < desc->n_rep; ++r)
+        if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
+    return SMC_OK;
+}
+
+static std::vector<ThrRow> dcb_rows(const smc_desc *desc, const double *beta) {
+    std::vector<ThrRow> rows(desc->n_rep);
+    for (int r = 0; r < desc->n_rep; ++r)
+        rows[r] = (r > 0 && beta[r] == beta[r - 1]) ? rows[r - 1] : threshold_row(beta[r], desc->dim);
+    return rows;
+}
+
+int smc_dcb_plan(const smc_desc *desc, const double *beta, int32_t tile, const char **kernel_name) {
+    g_last_error.clear();
+    if (!kernel_name) return fail(SMC_EINVAL, "kernel_name is NULL");
+    int rc = dcb_check(desc, beta, tile);
+    if (rc) return rc;
+    *kernel_name = use_dcb_packed(desc, dcb_rows(desc, beta), nullptr, nullptr, tile) ? "k_dcb2d_packed" : "k_dcb2d";
+    return SMC_OK;
+}
+
+int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
+                  int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
+                  void *stream) {
+    g_last_error.clear();
+    int rc = dcb_check(desc, beta, tile);
+    if (rc) return rc;
     if (hits < 1) return fail(SMC_EINVAL, "hits must be >= 1");
     if (!spins) return fail(SMC_EINVAL, "spins is NULL");
-    if (!beta) return fail(SMC_EINVAL, "beta is NULL");
     if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
     if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
     if ((sweep0 + (uint64_t)n_sweeps) * (uint64_t)hits > (1ull << 32))
         return fail(SMC_EINVAL, "(sweep0 + n_sweeps) * hits exceeds 2^32 (the hit index is one 32-bit word)");
-    for (int r = 0; r < desc->n_rep; ++r)
-        if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
     if (n_sweeps == 0) return SMC_OK;
     hipStream_t s = (hipStream_t)stream;
     StreamCtx &c = ctx_for(s);
-    std::vector<ThrRow> rows(desc->n_rep);
-    for (int r = 0; r < desc->n_rep; ++r)
-        rows[r] = (r > 0 && beta[r] == beta[r - 1]) ? rows[r - 1] : threshold_row(beta[r], desc->dim);
+    const std::vector<ThrRow> rows = dcb_rows(desc, beta);
     void *tp = nullptr, *sp = nullptr;
     if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &tp))) return rc;
     const int per_rep = 2 * dcb2d_tiles_per_colour(desc->L, tile);
@@ -1069,6 +1104,7 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
         SMC_HIP(launch_dcb_zero((int64_t *)sp, (int64_t)desc->n_rep * per_rep, s));
     }
     const bool ea = desc->model == SMC_EA;
+    const bool packed = use_dcb_packed(desc, rows, spins, ea ? couplings : nullptr, tile);
     SweepTimer timer(s, 2 * (int64_t)n_sweeps);
     for (int32_t m = 0; m < n_sweeps; ++m) {
         const uint64_t t = sweep0 + (uint64_t)m;
@@ -1076,7 +1112,7 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
         for (int ci = 0; ci < 2; ++ci)
             SMC_HIP(launch_dcb2d((int8_t *)spins, ea ? couplings : nullptr, ea ? desc->rep_per_sample : 1,
                                  (const ThrRow *)tp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits,
-                                 make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, s));
+                                 make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, packed, s));
     }
     timer.finish();
     if (dE_accum) SMC_HIP(launch_dcb_collect((const int64_t *)sp, dE_accum, desc->n_rep, per_rep, s));

@@ -136,10 +136,15 @@ hipError_t launch_msc2d(uint32_t *spins, const uint32_t *coup, const ThrRow *thr
 
 // Double checkerboard with multi-hit (2D Ising / EA, T x T tiles, T a
 // multiple of 16 in [16, 128], L / T even or 1): one launch per tile colour.
+// The packed kernel (four sites per word; T in {16, 32, 64, 128}) needs
+// thresholds whose high halves fit 16 bits (beta > 0) and 16-byte aligned
+// spins and couplings; the per-site kernel takes everything else.
 bool dcb2d_supported(int L, int T);
+bool dcb2d_packed_supported(int L, int T);
 int dcb2d_tiles_per_colour(int L, int T);
 hipError_t launch_dcb2d(int8_t *spins, const int8_t *coup, int rep_per_sample, const ThrRow *thr, int64_t *dE_slots,
-                        int n_rep, int L, int T, int k, Key key, uint32_t t, int tile_colour, bool rev, hipStream_t s);
+                        int n_rep, int L, int T, int k, Key key, uint32_t t, int tile_colour, bool rev, bool packed,
+                        hipStream_t s);
 hipError_t launch_dcb_zero(int64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, hipStream_t s);
 

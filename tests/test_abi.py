@@ -160,3 +160,20 @@ def test_dcb_arguments_are_validated():
     assert rc == S.EINVAL and b"2^32" in L.smc_last_error()
     d3 = _desc(dim=3, L=32, n_rep=1, spins_len=32 ** 3)
     assert L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 16, 1, 0, None, None) == S.EUNSUPPORTED
+
+
+def test_dcb_plan_names_the_kernel():
+    """smc_dcb_plan: the packed kernel for power-of-two tiles and beta > 0,
+    the per-site kernel for other tiles or a replica at beta = 0."""
+    L = S.lib()
+    name = C.c_char_p()
+    d = _desc(L=96, n_rep=2, spins_len=2 * 96 * 96)
+    beta = (C.c_double * 2)(0.4, 0.5)
+    assert L.smc_dcb_plan(C.byref(d), beta, 48, C.byref(name)) == S.OK and name.value == b"k_dcb2d"
+    d = _desc(L=128, n_rep=2, spins_len=2 * 128 * 128)
+    for tile in (16, 32, 64, 128):
+        assert L.smc_dcb_plan(C.byref(d), beta, tile, C.byref(name)) == S.OK and name.value == b"k_dcb2d_packed"
+    beta0 = (C.c_double * 2)(0.4, 0.0)
+    assert L.smc_dcb_plan(C.byref(d), beta0, 64, C.byref(name)) == S.OK and name.value == b"k_dcb2d"
+    assert L.smc_dcb_plan(C.byref(d), beta, 24, C.byref(name)) == S.EINVAL
+    assert L.smc_dcb_plan(C.byref(d), None, 64, C.byref(name)) == S.EINVAL

@@ -41,11 +41,20 @@ def _oracle(model, L, n_rep, betas, seed, t0, n, T, k, pal, rps=1):
     return np.stack(out), np.array(dEs, np.int64)
 
 
+@pytest.fixture(params=["packed", "per_site"])
+def kernel(request, monkeypatch):
+    """Both kernels: the packed one (four sites per word) and the per-site one."""
+    monkeypatch.setenv("SPINMC_DCB_PACKED", "1" if request.param == "packed" else "0")
+    return request.param
+
+
 @pytest.mark.parametrize("model,L,T,k,pal", [
     (S.EA, 32, 16, 1, False), (S.EA, 64, 16, 3, True), (S.ISING, 64, 32, 5, False),
     (S.EA, 128, 64, 2, True), (S.ISING, 256, 128, 4, False), (S.EA, 16, 16, 2, False),
+    (S.ISING, 128, 64, 3, True), (S.EA, 256, 128, 2, False), (S.ISING, 32, 32, 4, True),
+    (S.EA, 96, 48, 2, False),
 ])
-def test_dcb_matches_oracle(model, L, T, k, pal):
+def test_dcb_matches_oracle(kernel, model, L, T, k, pal):
     seed, n_rep = W.seed_for(71), 3
     betas = [0.3, 0.44, 0.9]
     got_s, got_dE = _gpu(model, L, n_rep, betas, seed, [(5, 3), (8, 2)], T, k, pal)
@@ -54,7 +63,7 @@ def test_dcb_matches_oracle(model, L, T, k, pal):
     assert np.array_equal(got_dE, ref_dE)
 
 
-def test_dcb_shared_samples():
+def test_dcb_shared_samples(kernel):
     """Two replicas per coupling sample."""
     seed, L, T, k = W.seed_for(72), 64, 32, 3
     betas = [0.5, 1.1, 0.5, 1.1]
@@ -63,7 +72,27 @@ def test_dcb_shared_samples():
     assert np.array_equal(got_s, ref_s) and np.array_equal(got_dE, ref_dE)
 
 
-def test_single_tile_single_hit_equals_plain_sweep():
+def test_dcb_beta_zero_in_the_batch(kernel):
+    """A replica at beta = 0 (threshold 2^32) sends the batch to the per-site
+    kernel; results stay those of the oracle."""
+    seed, L, T, k = W.seed_for(75), 64, 16, 2
+    betas = [0.0, 0.44, 0.8]
+    got_s, got_dE = _gpu(S.EA, L, 3, betas, seed, [(2, 3)], T, k, True)
+    ref_s, ref_dE = _oracle(S.EA, L, 3, betas, seed, 2, 3, T, k, True)
+    assert np.array_equal(got_s, ref_s) and np.array_equal(got_dE, ref_dE)
+
+
+def test_dcb_many_small_tiles_per_workgroup(kernel):
+    """16 x 16 tiles (four per workgroup in the packed kernel) over a batch
+    whose tile count is not a multiple of four."""
+    seed, L, T, k = W.seed_for(76), 32, 16, 3
+    betas = [0.2, 0.35, 0.44, 0.5, 0.7]
+    got_s, got_dE = _gpu(S.ISING, L, 5, betas, seed, [(0, 2), (2, 3)], T, k, False)
+    ref_s, ref_dE = _oracle(S.ISING, L, 5, betas, seed, 0, 5, T, k, False)
+    assert np.array_equal(got_s, ref_s) and np.array_equal(got_dE, ref_dE)
+
+
+def test_single_tile_single_hit_equals_plain_sweep(kernel):
     """tile = L and hits = 1: the same chain as smc_metropolis_sweep."""
     seed, L, n_rep = W.seed_for(73), 64, 2
     b = S.Batch(S.EA, 2, L, n_rep, seed)
@@ -81,7 +110,7 @@ def test_single_tile_single_hit_equals_plain_sweep():
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
-def test_dcb_large_lattice():
+def test_dcb_large_lattice(kernel):
     """1024 x 1024, 64 x 64 tiles, 8 hits, 2 sweeps, every site."""
     seed, L = W.seed_for(74), 1024
     got_s, got_dE = _gpu(S.ISING, L, 1, [0.44], seed, [(0, 2)], 64, 8, False)
