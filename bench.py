@@ -145,7 +145,7 @@ def valu_summary(db: str, command: str):
              "# instruction per CU per cycle (four SIMD16 units, four cycles each)",
              f"{'kernel':28s} {'dispatches':>10s} {'VALU_insts':>14s} {'busy_cycles':>12s} {'util':>6s}"]
     for k in ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_tiled", "k_heis3d_half",
-              "k_half_sweep_generic", "k_msc2d", "k_dcb2d", "k_philox_bench", "k_to_split", "k_from_split"):
+              "k_half_sweep_generic", "k_msc2d", "k_dcb2d_packed", "k_dcb2d", "k_philox_bench", "k_to_split", "k_from_split"):
         if k not in acc or "SQ_INSTS_VALU" not in acc[k] or "GRBM_GUI_ACTIVE" not in acc[k]:
             continue
         v = acc[k]["SQ_INSTS_VALU"]
@@ -418,6 +418,90 @@ def dcb2d(S, W, sweeps, L=16384, tiles=(64, 128), hits=(1, 2, 4, 8, 16, 64, 100)
             "kernel": S.dcb_plan(b, [cfg.betas[1]], tiles[0]), "by_tile_and_hits": rows}
 
 
+def tau_int(series, c=6.0):
+    """Integrated autocorrelation time of equilibrium series (rows =
+    independent replicas, columns = measurement times), in units of the
+    measurement interval: tau = 1/2 + sum_{t=1}^{W} rho(t), with rho the
+    normalised autocorrelation function averaged over replicas (the global
+    mean subtracted) and Sokal's self-consistent window, the smallest W with
+    W >= c tau(W).  Returns (tau, W, the Madras-Sokal error
+    tau sqrt(2 (2W + 1) / (n R)))."""
+    import numpy as np
+
+    x = np.asarray(series, np.float64)
+    R, n = x.shape
+    x = x - x.mean()
+    f = np.fft.rfft(x, 2 * n, axis=1)
+    acov = np.fft.irfft(f * np.conj(f), axis=1)[:, :n].sum(axis=0) / (R * (n - np.arange(n)))
+    rho = acov / acov[0]
+    tau, W = 0.5, 0
+    for W in range(1, n):
+        tau += rho[W]
+        if W >= c * tau:
+            break
+    return float(tau), int(W), float(tau * np.sqrt(2.0 * (2 * W + 1) / (n * R)))
+
+
+def tau_dcb(S, W, L=128, tile=16, hits=(1, 2, 5, 10, 20, 50, 100), n_rep=256, updates=1 << 15,
+            therm=1 << 15, betas=(0.35, 0.40, 0.42, 0.43, 0.4406868, 0.45, 0.46, 0.48, 0.55),
+            palindromic_betas=(0.4406868,)):
+    """Autocorrelation study of the double checkerboard (Sec. 3.4, the
+    paper's 128^2 Ising system with 16 x 16 tiles): for each beta, n_rep
+    replicas are brought to equilibrium from an ordered start (a random
+    start leaves long-lived stripes below T_c), then each hit count k runs
+    updates / k sweeps from that state with the energy measured after every
+    sweep (dE_trace); tau_int of the energy is reported in attempts per site
+    (tau in sweeps times k) next to the plain checkerboard (one tile, k = 1),
+    and with the palindromic order at palindromic_betas.  t_flip is the
+    measured time per attempted flip of the same batch, and
+    tau~ = tau_int t_flip the time per site for an independent sample."""
+    import numpy as np
+    import torch
+
+    seed = W.seed_for(90)
+    b = S.Batch(S.ISING, 2, L, n_rep, seed)
+    N = L * L
+    # time per flip of every k on this batch (no trace)
+    spins = torch.empty(n_rep * N, dtype=torch.int8, device="cuda")
+    S.spin_init(b, spins)
+    t_flip = {}
+    for k in sorted(set(hits) | {1}):
+        for T in sorted({tile, L}):
+            if T == L and k != 1:
+                continue
+            n = max(4, 4096 // k)
+            S.dcb_sweep(b, spins, [0.44] * n_rep, 0, 2, T, k)
+            ms = _timed(lambda: S.dcb_sweep(b, spins, [0.44] * n_rep, 2, n, T, k))
+            t_flip[(T, k)] = ms * 1e9 / (n * k * n_rep * N)  # ps
+    rows = []
+    todo = [(beta, False) for beta in betas] + [(beta, True) for beta in palindromic_betas]
+    for beta, pal in todo:
+        bl = [beta] * n_rep
+        spins.fill_(1)
+        S.dcb_sweep(b, spins, bl, 0, therm // 10, tile, 10)  # equilibrate (any valid update will do)
+        E0 = torch.empty(n_rep, dtype=torch.float64, device="cuda")
+        S.measure_energy_magnetisation(b, spins, E0)
+        runs = ([] if pal else [(L, 1)]) + [(tile, k) for k in hits]
+        for i, (T, k) in enumerate(runs):
+            n = updates // k
+            sp = spins.clone()
+            trace = torch.empty(n * n_rep, dtype=torch.int64, device="cuda")
+            S.dcb_sweep(b, sp, bl, (i + 1) * (1 << 22) // k, n, T, k, palindromic=pal, dE_trace=trace)
+            E = (E0.cpu().numpy()[None, :] + trace.view(n, n_rep).cpu().numpy()).T / N
+            tau, Wn, err = tau_int(E)
+            rows.append({"beta": beta, "palindromic": pal, "tile": T, "hits": k, "sweeps": n,
+                         "tau_int_sweeps": round(tau, 3),
+                         "tau_int": round(tau * k, 2), "tau_err": round(err * k, 2), "window": Wn,
+                         "e_mean": round(float(E.mean()), 5), "t_flip_ps": round(t_flip[(T, k)], 4),
+                         "tau_tilde_ps": round(tau * k * t_flip[(T, k)], 3)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del sp, trace
+    return {"workload": f"2D Ising {L}x{L}, {n_rep} replicas per beta, double checkerboard with {tile}x{tile} "
+                        f"tiles and k hits (plus the plain sweep: one {L}x{L} tile, k = 1), {updates} attempts per "
+                        f"site after {therm} of equilibration; energy after every sweep",
+            "tau_unit": "attempts per site", "rows": rows}
+
+
 def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):
     """Uneven 2D EA batch, 4096 instances x 16 temperatures, edges from
     {32, ..., 256}: the batch in one call (a graph of steps), against one call
@@ -559,6 +643,10 @@ def main():
     ap.add_argument("--msc-sweeps", type=int, default=2000)
     ap.add_argument("--dcb-sweeps", type=int, default=64)
     ap.add_argument("--dcb-only", action="store_true", help="only the double-checkerboard measurement")
+    ap.add_argument("--tau-only", action="store_true",
+                    help="only the double-checkerboard autocorrelation study (128^2, 16x16 tiles)")
+    ap.add_argument("--tau-updates", type=int, default=1 << 15, help="attempts per site per (beta, k) series")
+    ap.add_argument("--tau-replicas", type=int, default=256)
     ap.add_argument("--msc-only", action="store_true", help="only the multi-spin-coded measurement (for profiling)")
     ap.add_argument("--pmc-kernel", default="k_ising2d_split", choices=sorted(KERNEL_SOURCES),
                     help="kernel of the --pmc-summary")
@@ -604,6 +692,9 @@ def main():
         return
     if args.dcb_only:
         print(json.dumps({"dcb2d": dcb2d(S, W, args.dcb_sweeps)}))
+        return
+    if args.tau_only:
+        print(json.dumps({"tau_dcb": tau_dcb(S, W, n_rep=args.tau_replicas, updates=args.tau_updates)}))
         return
     cfg = W.ising_large(args.L)
     L = cfg.L

@@ -259,12 +259,16 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, cons
  *  hits:      >= 1; (sweep0 + n_sweeps) * hits must not exceed 2^32.
  *  spins, couplings, beta (HOST [n_rep]), sweep0, n_sweeps, dE_accum,
  *  stream: as for smc_metropolis_sweep; every replica is updated in place.
+ *  dE_trace:  device int64 [n_sweeps][n_rep] or NULL: row m receives each
+ *             replica's energy change from the start of the call through
+ *             sweep m (a measurement after every sweep, as in the
+ *             autocorrelation study of Sec. 3.4); written, not added to.
  * SMC_EUNSUPPORTED for Heisenberg or 3D batches, SMC_EINVAL for a tile or
  * hit count outside these limits.
  */
 int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
                   int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
-                  void *stream);
+                  int64_t *dE_trace, void *stream);
 
 /*
  * Which kernel smc_dcb_sweep uses for this batch, tile and beta (HOST

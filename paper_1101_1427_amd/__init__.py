@@ -73,7 +73,7 @@ def lib():
         L.smc_msc_plan.argtypes = [P(Desc), C.c_int32, P(C.c_int32), P(C.c_char_p)]
         L.smc_msc_plan.restype = C.c_int
         L.smc_dcb_sweep.argtypes = [P(Desc), C.c_void_p, C.c_void_p, P(C.c_double), C.c_uint64, C.c_int32,
-                                    C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+                                    C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.smc_dcb_sweep.restype = C.c_int
         L.smc_dcb_plan.argtypes = [P(Desc), P(C.c_double), C.c_int32, P(C.c_char_p)]
         L.smc_dcb_plan.restype = C.c_int
@@ -179,14 +179,23 @@ def msc_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, couplings=N
 
 
 def dcb_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, tile: int, hits: int, palindromic=False,
-              couplings=None, dE_accum=None, stream=None):
+              couplings=None, dE_accum=None, dE_trace=None, stream=None):
     """n_sweeps double-checkerboard sweeps (tile x tile tiles, `hits` hits per
-    tile and sweep; see smc_dcb_sweep); beta is a host sequence [n_rep]."""
+    tile and sweep; see smc_dcb_sweep); beta is a host sequence [n_rep];
+    dE_trace, if given, is an int64 device tensor of n_sweeps * n_rep entries."""
     d = _desc(batch, spins, couplings)
     b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (batch.n_rep,)))
+    if dE_trace is not None:
+        import torch
+
+        if dE_trace.dtype != torch.int64 or not dE_trace.is_cuda or not dE_trace.is_contiguous():
+            raise TypeError("dE_trace must be a contiguous int64 device tensor")
+        if dE_trace.numel() < n_sweeps * batch.n_rep:
+            raise ValueError(f"dE_trace holds {dE_trace.numel()} entries, needs n_sweeps * n_rep = "
+                             f"{n_sweeps * batch.n_rep}")
     _check(lib().smc_dcb_sweep(C.byref(d), _ptr(spins), _ptr(couplings), b.ctypes.data_as(C.POINTER(C.c_double)),
                                sweep0, n_sweeps, tile, hits, 1 if palindromic else 0, _ptr(dE_accum),
-                               _stream(stream)), "smc_dcb_sweep")
+                               _ptr(dE_trace), _stream(stream)), "smc_dcb_sweep")
 
 
 def dcb_plan(batch: Batch, beta, tile: int) -> str:

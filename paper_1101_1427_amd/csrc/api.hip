@@ -1082,7 +1082,7 @@ int smc_dcb_plan(const smc_desc *desc, const double *beta, int32_t tile, const c
 
 int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
                   int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
-                  void *stream) {
+                  int64_t *dE_trace, void *stream) {
     g_last_error.clear();
     int rc = dcb_check(desc, beta, tile);
     if (rc) return rc;
@@ -1099,7 +1099,7 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     void *tp = nullptr, *sp = nullptr;
     if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &tp))) return rc;
     const int per_rep = 2 * dcb2d_tiles_per_colour(desc->L, tile);
-    if (dE_accum) {
+    if (dE_accum || dE_trace) {
         if ((rc = ensure(c, kDcbSlots, sizeof(int64_t) * (size_t)desc->n_rep * per_rep, &sp))) return rc;
         SMC_HIP(launch_dcb_zero((int64_t *)sp, (int64_t)desc->n_rep * per_rep, s));
     }
@@ -1113,9 +1113,12 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
             SMC_HIP(launch_dcb2d((int8_t *)spins, ea ? couplings : nullptr, ea ? desc->rep_per_sample : 1,
                                  (const ThrRow *)tp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits,
                                  make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, packed, s));
+        if (dE_trace)
+            SMC_HIP(launch_dcb_collect((const int64_t *)sp, dE_trace + (int64_t)m * desc->n_rep, desc->n_rep, per_rep,
+                                       true, s));
     }
     timer.finish();
-    if (dE_accum) SMC_HIP(launch_dcb_collect((const int64_t *)sp, dE_accum, desc->n_rep, per_rep, s));
+    if (dE_accum) SMC_HIP(launch_dcb_collect((const int64_t *)sp, dE_accum, desc->n_rep, per_rep, false, s));
     return SMC_OK;
 }
 

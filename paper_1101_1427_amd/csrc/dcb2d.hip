@@ -500,8 +500,8 @@ __global__ __launch_bounds__(256) void k_dcb_zero(int64_t *p, int64_t n) {
     if (i < n) p[i] = 0;
 }
 
-// dE[r] += the sum of replica r's slots.
-__global__ __launch_bounds__(256) void k_dcb_collect(const int64_t *slots, int64_t *dE, int per_rep) {
+// dE[r] = (assign) or += the sum of replica r's slots.
+__global__ __launch_bounds__(256) void k_dcb_collect(const int64_t *slots, int64_t *dE, int per_rep, int assign) {
     __shared__ long long red[4];
     const int r = (int)blockIdx.x;
     long long v = 0;
@@ -510,7 +510,10 @@ __global__ __launch_bounds__(256) void k_dcb_collect(const int64_t *slots, int64
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) dE[r] += red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        const long long sum = red[0] + red[1] + red[2] + red[3];
+        dE[r] = assign ? sum : dE[r] + sum;
+    }
 }
 
 }  // namespace
@@ -532,8 +535,8 @@ hipError_t launch_dcb_zero(int64_t *p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, hipStream_t s) {
-    hipLaunchKernelGGL(k_dcb_collect, dim3((unsigned)n_rep), dim3(256), 0, s, slots, dE, per_rep);
+hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, bool assign, hipStream_t s) {
+    hipLaunchKernelGGL(k_dcb_collect, dim3((unsigned)n_rep), dim3(256), 0, s, slots, dE, per_rep, assign ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -146,7 +146,8 @@ hipError_t launch_dcb2d(int8_t *spins, const int8_t *coup, int rep_per_sample, c
                         int n_rep, int L, int T, int k, Key key, uint32_t t, int tile_colour, bool rev, bool packed,
                         hipStream_t s);
 hipError_t launch_dcb_zero(int64_t *p, int64_t n, hipStream_t s);
-hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, hipStream_t s);
+// dE[r] = (assign) or += (otherwise) the sum of replica r's slots.
+hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, bool assign, hipStream_t s);
 
 // Generator throughput: out[i] = XOR of the four words of the blocks with
 // counters (i + k * n_threads, t, r, tag), k < per_thread.

@@ -153,13 +153,13 @@ def test_dcb_arguments_are_validated():
     beta = (C.c_double * 2)(0.5, 0.5)
     d = _desc(L=64, n_rep=2, spins_len=2 * 64 * 64)
     for tile, frag in ((24, b"multiple of 16"), (48, b"multiple of 16"), (256, b"multiple of 16")):
-        rc = L.smc_dcb_sweep(C.byref(d), FAKE, None, beta, 0, 1, tile, 1, 0, None, None)
+        rc = L.smc_dcb_sweep(C.byref(d), FAKE, None, beta, 0, 1, tile, 1, 0, None, None, None)
         assert rc == S.EINVAL and frag in L.smc_last_error()
-    assert L.smc_dcb_sweep(C.byref(d), FAKE, None, beta, 0, 1, 32, 0, 0, None, None) == S.EINVAL
-    rc = L.smc_dcb_sweep(C.byref(d), FAKE, None, beta, (1 << 31), 1, 32, 2, 0, None, None)
+    assert L.smc_dcb_sweep(C.byref(d), FAKE, None, beta, 0, 1, 32, 0, 0, None, None, None) == S.EINVAL
+    rc = L.smc_dcb_sweep(C.byref(d), FAKE, None, beta, (1 << 31), 1, 32, 2, 0, None, None, None)
     assert rc == S.EINVAL and b"2^32" in L.smc_last_error()
     d3 = _desc(dim=3, L=32, n_rep=1, spins_len=32 ** 3)
-    assert L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 16, 1, 0, None, None) == S.EUNSUPPORTED
+    assert L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 16, 1, 0, None, None, None) == S.EUNSUPPORTED
 
 
 def test_dcb_plan_names_the_kernel():

@@ -116,3 +116,25 @@ def test_dcb_large_lattice(kernel):
     got_s, got_dE = _gpu(S.ISING, L, 1, [0.44], seed, [(0, 2)], 64, 8, False)
     ref_s, ref_dE = _oracle(S.ISING, L, 1, [0.44], seed, 0, 2, 64, 8, False)
     assert np.array_equal(got_s, ref_s) and np.array_equal(got_dE, ref_dE)
+
+
+def test_dcb_energy_trace(kernel):
+    """dE_trace row m = the oracle's energy change over sweeps 0 .. m of the call."""
+    seed, L, T, k, n, n_rep = W.seed_for(77), 64, 16, 3, 6, 3
+    betas = [0.3, 0.44, 0.7]
+    b = S.Batch(S.EA, 2, L, n_rep, seed)
+    spins = torch.zeros(n_rep * L * L, dtype=torch.int8, device=DEV)
+    coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV)
+    S.spin_init(b, spins, coup)
+    trace = torch.full((n, n_rep), -7, dtype=torch.int64, device=DEV)
+    S.dcb_sweep(b, spins, betas, 4, n, T, k, palindromic=True, couplings=coup, dE_trace=trace)
+    got = _host(trace)
+    ref = np.zeros((n, n_rep), np.int64)
+    for r in range(n_rep):
+        s = O.init_spins(2, L, seed, r)
+        J = O.init_couplings(2, L, seed, r)
+        acc = 0
+        for m in range(n):
+            acc += O.dcb_run(L, T, k, J, s, betas[r], seed, r, 4 + m, 1, palindromic=True)
+            ref[m, r] = acc
+    assert np.array_equal(got, ref)
