@@ -72,6 +72,7 @@ def lib():
             "orc_swap_u53": (D, [U64, U32, U32, U32]),
             "orc_window_run": (None, [I, I, I, I, i8p, D, U64, U32, U32, I]),
             "orc_dcb_run": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
+            "orc_heis_dcb_run": (I64, [I, I, I, f64p, D, U64, U32, U32, I, I, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -205,6 +206,14 @@ def dcb_run(L, T, k, J, s, beta, seed, r, t0, n, palindromic=False) -> int:
     lattice in place; returns the summed Delta E (orc_dcb_run)."""
     return int(lib().orc_dcb_run(L, T, k, _ptr(J), s, beta, seed & 0xFFFFFFFFFFFFFFFF, r, t0, n,
                                  1 if palindromic else 0))
+
+
+def heis_dcb_run(L, T, k, s, beta, seed, r, t0, n, palindromic=False, renorm_every=16) -> int:
+    """n double-checkerboard sweeps (T x T tiles, k hits per tile) of a 2D
+    Heisenberg lattice (float64 [N*3]) in place; returns the number of
+    accepted moves (orc_heis_dcb_run)."""
+    return int(lib().orc_heis_dcb_run(L, T, k, s, beta, seed & 0xFFFFFFFFFFFFFFFF, r, t0, n,
+                                      1 if palindromic else 0, renorm_every))
 
 
 def window_run(L, x0, y0, win, beta, seed, r, t0, n):

@@ -431,10 +431,35 @@ EXPORT void orc_run_series(int dim, int L, const int8_t *J, int8_t *s, double be
 /* Heisenberg (O(3)) model, Eq. (10), FP64.                                  */
 /* ------------------------------------------------------------------------ */
 
-/* One half-sweep of colour c: at each site propose a fresh uniform direction
- * s' (independent of s, Sec. 4) from words 0, 1 of (h, t, r, HEIS+c) and
- * accept iff Delta E = -(s' - s).h <= 0 or u < exp(-beta Delta E), u from
- * word 2.  Returns the number of accepted moves. */
+/* The Metropolis move at site i of colour c in sweep t: propose a fresh
+ * uniform direction s' (independent of s, Sec. 4) from words 0, 1 of
+ * (i >> 1, t, r, HEIS+c) and accept iff Delta E = -(s' - s).h <= 0 or
+ * u < exp(-beta Delta E), u from word 2.  Returns 1 if accepted. */
+static int heis_site_move(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r, uint32_t t, int c,
+                          int64_t i)
+{
+    int x[3];
+    coords(dim, L, i, x);
+    double h[3] = {0.0, 0.0, 0.0};
+    for (int mu = 0; mu < dim; ++mu) {
+        int64_t up = neighbour(dim, L, x, mu, +1);
+        int64_t dn = neighbour(dim, L, x, mu, -1);
+        for (int a = 0; a < 3; ++a) h[a] += s[3 * up + a] + s[3 * dn + a];
+    }
+    uint32_t w[4];
+    draw(seed, (uint32_t)(i >> 1), t, r, (uint32_t)(TAG_HEIS * 2 + c), w);
+    double sp[3];
+    sphere_point(unit23(w[0]), unit23(w[1]), sp);
+    double dE = 0.0;
+    for (int a = 0; a < 3; ++a) dE -= (sp[a] - s[3 * i + a]) * h[a];
+    int accept = (dE <= 0.0) || (unit23(w[2]) < exp(-beta * dE));
+    if (accept)
+        for (int a = 0; a < 3; ++a) s[3 * i + a] = sp[a];
+    return accept;
+}
+
+/* One half-sweep of colour c: the move above at every site of colour c.
+ * Returns the number of accepted moves. */
 EXPORT int64_t orc_heis_half_sweep(int dim, int L, double *s, double beta,
                                    uint64_t seed, uint32_t r, uint32_t t, int c)
 {
@@ -444,23 +469,7 @@ EXPORT int64_t orc_heis_half_sweep(int dim, int L, double *s, double beta,
         int x[3];
         coords(dim, L, i, x);
         if (colour_of(dim, x) != c) continue;
-        double h[3] = {0.0, 0.0, 0.0};
-        for (int mu = 0; mu < dim; ++mu) {
-            int64_t up = neighbour(dim, L, x, mu, +1);
-            int64_t dn = neighbour(dim, L, x, mu, -1);
-            for (int a = 0; a < 3; ++a) h[a] += s[3 * up + a] + s[3 * dn + a];
-        }
-        uint32_t w[4];
-        draw(seed, (uint32_t)(i >> 1), t, r, (uint32_t)(TAG_HEIS * 2 + c), w);
-        double sp[3];
-        sphere_point(unit23(w[0]), unit23(w[1]), sp);
-        double dE = 0.0;
-        for (int a = 0; a < 3; ++a) dE -= (sp[a] - s[3 * i + a]) * h[a];
-        int accept = (dE <= 0.0) || (unit23(w[2]) < exp(-beta * dE));
-        if (accept) {
-            for (int a = 0; a < 3; ++a) s[3 * i + a] = sp[a];
-            ++n_acc;
-        }
+        n_acc += heis_site_move(dim, L, s, beta, seed, r, t, c, i);
     }
     return n_acc;
 }
@@ -492,6 +501,49 @@ EXPORT int64_t orc_heis_run(int dim, int L, double *s, double beta, uint64_t see
     int64_t acc = 0;
     for (int k = 0; k < n; ++k) acc += orc_heis_sweep(dim, L, s, beta, seed, r, t0 + (uint32_t)k, renorm_every);
     return acc;
+}
+
+/* Double checkerboard with multi-hit updates (Sec. 3.2, Sec. 3.4) for the
+ * 2D Heisenberg model, in the order of orc_dcb_run: sweep t treats the
+ * tiles of tile colour 0, then those of colour 1 (both reversed on odd
+ * sweeps when palindromic != 0); a tile gets k hits, each a move at every
+ * colour-0 site of the tile, then at every colour-1 site, the spins outside
+ * the tile held fixed.  Hit j of sweep t draws as plain sweep t*k + j, so
+ * T = L and k = 1 is orc_heis_sweep.  Spins are renormalised after sweep t
+ * when renorm_every > 0 and (t + 1) is a multiple of it.  Returns the
+ * number of accepted moves. */
+EXPORT int64_t orc_heis_dcb_run(int L, int T, int k, double *s, double beta, uint64_t seed, uint32_t r,
+                                uint32_t t0, int n, int palindromic, int renorm_every)
+{
+    const int B = L / T;
+    int64_t n_acc = 0;
+    for (int m = 0; m < n; ++m) {
+        const uint32_t t = t0 + (uint32_t)m;
+        const int rev = palindromic && (t & 1u);
+        for (int ci = 0; ci < 2; ++ci) {
+            const int tile_colour = rev ? 1 - ci : ci;
+            for (int by = 0; by < B; ++by) {
+                for (int bx = 0; bx < B; ++bx) {
+                    if (((bx + by) & 1) != tile_colour) continue;
+                    for (int j = 0; j < k; ++j) {
+                        const uint32_t th = t * (uint32_t)k + (uint32_t)j;
+                        for (int si = 0; si < 2; ++si) {
+                            const int c = rev ? 1 - si : si;
+                            for (int v = 0; v < T; ++v) {
+                                for (int u = 0; u < T; ++u) {
+                                    const int x = bx * T + u, y = by * T + v;
+                                    if (((x + y) & 1) != c) continue;
+                                    n_acc += heis_site_move(2, L, s, beta, seed, r, th, c, (int64_t)y * L + x);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (renorm_every > 0 && ((uint64_t)t + 1) % (uint64_t)renorm_every == 0) orc_heis_renormalise(2, L, s);
+    }
+    return n_acc;
 }
 
 /* Kahan-compensated FP64 sums of E = -sum_bonds s_i . s_j and of M. */
