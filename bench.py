@@ -418,6 +418,36 @@ def dcb2d(S, W, sweeps, L=16384, tiles=(64, 128), hits=(1, 2, 4, 8, 16, 64, 100)
             "kernel": S.dcb_plan(b, [cfg.betas[1]], tiles[0]), "by_tile_and_hits": rows}
 
 
+def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
+    """The paper's Heisenberg benchmark (Sec. 4): 2D, L = 4096, double
+    checkerboard with k = 100 hits, in the three arithmetic modes (float32
+    with accurate functions, float32 with hardware functions, float64):
+    ps per attempted move, from a random start at beta = 1."""
+    import torch
+
+    seed = W.seed_for(91)
+    b = S.Batch(S.HEISENBERG, 2, L, 1, seed, renorm_every=16)
+    base = torch.empty(L * L * 3, dtype=torch.float32, device="cuda")
+    S.spin_init(b, base)
+    rows = []
+    for name, mode in (("float", S.HEIS_FLOAT), ("fast", S.HEIS_FAST), ("double", S.HEIS_DOUBLE)):
+        for tile in tiles:
+            if mode == S.HEIS_DOUBLE and tile > 32:
+                continue
+            spins = base.double() if mode == S.HEIS_DOUBLE else base.clone()
+            acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+            S.heis_dcb_sweep(b, spins, [1.0], 0, 1, tile, hits, precision=mode)
+            ms = _timed(lambda: S.heis_dcb_sweep(b, spins, [1.0], 1, sweeps, tile, hits, precision=mode, accepts=acc))
+            flips = L * L * hits * sweeps
+            rows.append({"mode": name, "tile": tile, "ms": round(ms, 3), "ps_per_flip": round(ms * 1e9 / flips, 4),
+                         "acceptance": round(float(acc.item()) / flips, 4)})
+            del spins
+    torch.cuda.empty_cache()
+    return {"workload": f"2D Heisenberg {L}x{L}, beta = 1, double checkerboard with T x T tiles and k = {hits} "
+                        f"hits, {sweeps} sweeps after one warm-up sweep",
+            "kernel": "k_heis_dcb2d", "by_mode": rows}
+
+
 def tau_int(series, c=6.0):
     """Integrated autocorrelation time of equilibrium series (rows =
     independent replicas, columns = measurement times), in units of the
@@ -643,6 +673,9 @@ def main():
     ap.add_argument("--msc-sweeps", type=int, default=2000)
     ap.add_argument("--dcb-sweeps", type=int, default=64)
     ap.add_argument("--dcb-only", action="store_true", help="only the double-checkerboard measurement")
+    ap.add_argument("--heis-dcb-sweeps", type=int, default=4)
+    ap.add_argument("--heis-dcb-only", action="store_true",
+                    help="only the 2D Heisenberg double checkerboard (L = 4096, k = 100, three modes)")
     ap.add_argument("--tau-only", action="store_true",
                     help="only the double-checkerboard autocorrelation study (128^2, 16x16 tiles)")
     ap.add_argument("--tau-updates", type=int, default=1 << 15, help="attempts per site per (beta, k) series")
@@ -692,6 +725,9 @@ def main():
         return
     if args.dcb_only:
         print(json.dumps({"dcb2d": dcb2d(S, W, args.dcb_sweeps)}))
+        return
+    if args.heis_dcb_only:
+        print(json.dumps({"heis_dcb2d": heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)}))
         return
     if args.tau_only:
         print(json.dumps({"tau_dcb": tau_dcb(S, W, n_rep=args.tau_replicas, updates=args.tau_updates)}))
@@ -776,6 +812,7 @@ def main():
                             "ea2d_uneven": tempering_ea2d_uneven(S, W, args.uneven_steps)}
         out["msc_ea2d"] = msc_ea2d(S, W, args.msc_sweeps)
         out["dcb2d"] = dcb2d(S, W, args.dcb_sweeps)
+        out["heis_dcb2d"] = heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg)
         out["cpu_baseline"] = cb

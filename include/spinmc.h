@@ -76,6 +76,14 @@ typedef enum {
     SMC_HEISENBERG = 2   /* O(3) unit vectors, ferromagnetic (Eq. 10)          */
 } smc_model;
 
+/* Arithmetic of the Heisenberg double checkerboard (Sec. 4 compares them). */
+typedef enum {
+    SMC_HEIS_FLOAT = 0,  /* float32 spins, accurate library sin/cos/exp, IEEE sqrt */
+    SMC_HEIS_FAST = 1,   /* float32 spins, hardware sin/cos/exp/sqrt (the move of
+                            smc_metropolis_sweep's Heisenberg kernels)           */
+    SMC_HEIS_DOUBLE = 2  /* float64 spins and arithmetic                          */
+} smc_heis_precision;
+
 /* One replica of an uneven batch. */
 typedef struct smc_inst {
     int32_t L;        /* even edge length >= 4                                  */
@@ -269,6 +277,35 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, cons
 int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
                   int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
                   int64_t *dE_trace, void *stream);
+
+/*
+ * Double checkerboard sweeps with multi-hit updates of the 2D Heisenberg
+ * model (Sec. 3.2, Sec. 3.4, Sec. 4): the order of smc_dcb_sweep (tile
+ * colour 0, then 1; k = hits hits per tile, each a move at every colour-0
+ * site of the tile, then at every colour-1 site, with the sites outside the
+ * tile held fixed; palindromic != 0 reverses both orders on odd sweeps).
+ * The move at a site is that of smc_metropolis_sweep (uniform proposal from
+ * words 0, 1 and acceptance from word 2 of the Heisenberg draw) with the
+ * draws of sweep t*hits + j for hit j of sweep t, so tile = L, hits = 1 and
+ * precision = SMC_HEIS_FAST reproduce smc_metropolis_sweep.  After sweep t
+ * every spin is renormalised when desc.renorm_every > 0 divides t + 1.
+ *  desc:      uniform 2D batch (L > 0), model SMC_HEISENBERG; spins_len in
+ *             elements (3 per site).
+ *  spins:     DEVICE, 16-byte aligned; float32 [n_rep][N][3], or float64
+ *             for SMC_HEIS_DOUBLE; updated in place.
+ *  beta:      HOST [n_rep], finite and >= 0 (used as float32 in the float
+ *             modes).
+ *  tile:      16 or 32 (any precision) or 64 (float modes), with L / tile
+ *             even or 1.
+ *  hits:      >= 1; (sweep0 + n_sweeps) * hits must not exceed 2^32.
+ *  precision: smc_heis_precision.
+ *  accepts:   DEVICE int64 [n_rep] or NULL: += the number of accepted moves.
+ * SMC_EINVAL for a bad tile, hit count, precision or unaligned spins;
+ * SMC_EUNSUPPORTED for other models or 3D.
+ */
+int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, uint64_t sweep0, int32_t n_sweeps,
+                       int32_t tile, int32_t hits, int32_t precision, int32_t palindromic, int64_t *accepts,
+                       void *stream);
 
 /*
  * Which kernel smc_dcb_sweep uses for this batch, tile and beta (HOST

@@ -1122,6 +1122,63 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     return SMC_OK;
 }
 
+int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, uint64_t sweep0, int32_t n_sweeps,
+                       int32_t tile, int32_t hits, int32_t precision, int32_t palindromic, int64_t *accepts,
+                       void *stream) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, false, plan);
+    if (rc) return rc;
+    if (desc->model != SMC_HEISENBERG)
+        return fail(SMC_EUNSUPPORTED, "smc_heis_dcb_sweep is for the Heisenberg model (smc_dcb_sweep: Ising, EA)");
+    if (desc->dim != 2) return fail(SMC_EUNSUPPORTED, "the Heisenberg double checkerboard is provided for 2D");
+    if (desc->L <= 0) return fail(SMC_EINVAL, "the double checkerboard needs a uniform batch (L > 0)");
+    if (precision < SMC_HEIS_FLOAT || precision > SMC_HEIS_DOUBLE)
+        return fail(SMC_EINVAL, "unknown precision %d", precision);
+    if (!heis_dcb2d_supported(desc->L, tile, precision))
+        return fail(SMC_EINVAL, "tile %d: need 16, 32 or (float modes) 64, dividing L = %d into an even number "
+                                "of tiles per row (or one)", tile, desc->L);
+    if (hits < 1) return fail(SMC_EINVAL, "hits must be >= 1");
+    if (!spins) return fail(SMC_EINVAL, "spins is NULL");
+    if ((uintptr_t)spins & 15u) return fail(SMC_EINVAL, "spins must be 16-byte aligned");
+    if (!beta) return fail(SMC_EINVAL, "beta is NULL");
+    if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+    if ((sweep0 + (uint64_t)n_sweeps) * (uint64_t)hits > (1ull << 32))
+        return fail(SMC_EINVAL, "(sweep0 + n_sweeps) * hits exceeds 2^32 (the hit index is one 32-bit word)");
+    for (int r = 0; r < desc->n_rep; ++r)
+        if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
+    if (n_sweeps == 0) return SMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    StreamCtx &c = ctx_for(s);
+    void *bp = nullptr, *sp = nullptr;
+    if (precision == SMC_HEIS_DOUBLE) {
+        if ((rc = upload(c, s, kTables, beta, sizeof(double) * desc->n_rep, &bp))) return rc;
+    } else {
+        std::vector<float> bf(desc->n_rep);
+        for (int r = 0; r < desc->n_rep; ++r) bf[r] = (float)beta[r];
+        if ((rc = upload(c, s, kTables, bf.data(), sizeof(float) * bf.size(), &bp))) return rc;
+    }
+    const int per_rep = 2 * dcb2d_tiles_per_colour(desc->L, tile);
+    if (accepts) {
+        if ((rc = ensure(c, kDcbSlots, sizeof(int64_t) * (size_t)desc->n_rep * per_rep, &sp))) return rc;
+        SMC_HIP(launch_dcb_zero((int64_t *)sp, (int64_t)desc->n_rep * per_rep, s));
+    }
+    const int64_t n_spins = (int64_t)desc->n_rep * desc->L * desc->L;
+    SweepTimer timer(s, 2 * (int64_t)n_sweeps);
+    for (int32_t m = 0; m < n_sweeps; ++m) {
+        const uint64_t t = sweep0 + (uint64_t)m;
+        const bool rev = palindromic && (t & 1u);
+        for (int ci = 0; ci < 2; ++ci)
+            SMC_HIP(launch_heis_dcb2d(spins, bp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits, precision,
+                                      make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, s));
+        if (desc->renorm_every > 0 && (t + 1) % (uint64_t)desc->renorm_every == 0)
+            SMC_HIP(launch_heis_dcb_renorm(spins, n_spins, precision, s));
+    }
+    timer.finish();
+    if (accepts) SMC_HIP(launch_dcb_collect((const int64_t *)sp, accepts, desc->n_rep, per_rep, false, s));
+    return SMC_OK;
+}
+
 int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, const char **kernel_name) {
     g_last_error.clear();
     if (!launches || !kernel_name) return fail(SMC_EINVAL, "output pointers are required");

@@ -149,6 +149,15 @@ hipError_t launch_dcb_zero(int64_t *p, int64_t n, hipStream_t s);
 // dE[r] = (assign) or += (otherwise) the sum of replica r's slots.
 hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, bool assign, hipStream_t s);
 
+// Heisenberg double checkerboard (2D; T = 16, 32, or 64 in the float modes;
+// L / T even or 1): one launch per tile colour, and the renormalisation of
+// every spin of the batch in the mode's arithmetic.  beta is float or double
+// per precision.
+bool heis_dcb2d_supported(int L, int T, int precision);
+hipError_t launch_heis_dcb2d(void *spins, const void *beta, int64_t *acc_slots, int n_rep, int L, int T, int k,
+                             int precision, Key key, uint32_t t, int tile_colour, bool rev, hipStream_t s);
+hipError_t launch_heis_dcb_renorm(void *spins, int64_t n_spins, int precision, hipStream_t s);
+
 // Generator throughput: out[i] = XOR of the four words of the blocks with
 // counters (i + k * n_threads, t, r, tag), k < per_thread.
 hipError_t launch_philox_bench(Key key, uint32_t t, uint32_t r, uint32_t tag, uint32_t n_threads, int per_thread,
