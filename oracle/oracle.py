@@ -67,8 +67,8 @@ def lib():
             "orc_heis_run": (I64, [I, I, f64p, D, U64, U32, U32, I, I]),
             "orc_heis_energy": (D, [I, I, f64p]),
             "orc_heis_magnetisation": (None, [I, I, f64p, f64p]),
-            "orc_pt_step": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, vp]),
-            "orc_pt_run": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, I, vp]),
+            "orc_pt_step": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, I, vp]),
+            "orc_pt_run": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, I, I, vp]),
             "orc_swap_u53": (D, [U64, U32, U32, U32]),
             "orc_window_run": (None, [I, I, I, I, i8p, D, U64, U32, U32, I]),
             "orc_dcb_run": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
@@ -189,8 +189,9 @@ def heis_magnetisation(dim, L, s) -> np.ndarray:
 
 
 # ---------------------------------------------------- parallel tempering --
-def pt_run(dim, L, J, spins, beta, slot_of_temp, E, seed, q, r0, t0, n_steps, swap_acc=None):
-    """n_steps PT steps of one chain in place.
+def pt_run(dim, L, J, spins, beta, slot_of_temp, E, seed, q, r0, t0, n_steps, swap_acc=None, sweeps_per_step=1):
+    """n_steps PT steps of one chain in place (each: sweeps_per_step sweeps,
+    then an exchange round).
 
     spins: int8 [n_temps, N]; beta: float64 [n_temps]; slot_of_temp: int32
     [n_temps]; E: int64 [n_temps] (energy per slot); swap_acc: uint64
@@ -198,7 +199,7 @@ def pt_run(dim, L, J, spins, beta, slot_of_temp, E, seed, q, r0, t0, n_steps, sw
     """
     n_temps = len(beta)
     lib().orc_pt_run(dim, L, _ptr(J), spins.reshape(-1), n_temps, np.ascontiguousarray(beta, np.float64),
-                     slot_of_temp, E, seed, q, r0, t0, n_steps, _ptr(swap_acc))
+                     slot_of_temp, E, seed, q, r0, t0, n_steps, sweeps_per_step, _ptr(swap_acc))
 
 
 def dcb_run(L, T, k, J, s, beta, seed, r, t0, n, palindromic=False) -> int:

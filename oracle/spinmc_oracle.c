@@ -589,8 +589,9 @@ EXPORT void orc_heis_magnetisation(int dim, int L, const double *s, double m[3])
 /* coldest end of the ladder by convention.  E[slot] is the energy of the    */
 /* configuration in that slot.                                               */
 /*                                                                           */
-/* Step t: one sweep (index t) of every slot at its current temperature,     */
-/* tracking E; then for every k with k = t (mod 2), k <= n_temps - 2, the    */
+/* Step t: m sweeps (indices t*m .. t*m + m - 1; Sec. 6 attempts exchanges  */
+/* once per m sweeps) of every slot at its current temperature, tracking E;  */
+/* then for every k with k = t (mod 2), k <= n_temps - 2, the                */
 /* exchange of temperatures k and k+1 is attempted with Eq. (12):            */
 /*   x = (beta[k+1] - beta[k]) (E[B] - E[A]),  A = slot at k, B = at k+1,    */
 /*   accept iff x >= 0 or u < exp(x), u the 53-bit uniform of (k, t, q, SWAP)*/
@@ -598,12 +599,14 @@ EXPORT void orc_heis_magnetisation(int dim, int L, const double *s, double m[3])
 /* ------------------------------------------------------------------------ */
 EXPORT void orc_pt_step(int dim, int L, const int8_t *J, int8_t *spins /* [n_temps][N] */,
                         int n_temps, const double *beta, int32_t *slot_of_temp, int64_t *E,
-                        uint64_t seed, uint32_t q, uint32_t r0, uint32_t t, uint64_t *swap_acc)
+                        uint64_t seed, uint32_t q, uint32_t r0, uint32_t t, int m, uint64_t *swap_acc)
 {
     int64_t N = n_sites(dim, L);
     for (int k = 0; k < n_temps; ++k) {
         int slot = slot_of_temp[k];
-        E[slot] += orc_sweep(dim, L, J, spins + (int64_t)slot * N, beta[k], seed, r0 + (uint32_t)slot, t);
+        for (int j = 0; j < m; ++j)
+            E[slot] += orc_sweep(dim, L, J, spins + (int64_t)slot * N, beta[k], seed, r0 + (uint32_t)slot,
+                                 t * (uint32_t)m + (uint32_t)j);
     }
     for (int k = (int)(t & 1u); k + 1 < n_temps; k += 2) {
         int A = slot_of_temp[k], B = slot_of_temp[k + 1];
@@ -621,10 +624,10 @@ EXPORT void orc_pt_step(int dim, int L, const int8_t *J, int8_t *spins /* [n_tem
 
 EXPORT void orc_pt_run(int dim, int L, const int8_t *J, int8_t *spins, int n_temps,
                        const double *beta, int32_t *slot_of_temp, int64_t *E, uint64_t seed,
-                       uint32_t q, uint32_t r0, uint32_t t0, int n_steps, uint64_t *swap_acc)
+                       uint32_t q, uint32_t r0, uint32_t t0, int n_steps, int m, uint64_t *swap_acc)
 {
     for (int k = 0; k < n_steps; ++k)
-        orc_pt_step(dim, L, J, spins, n_temps, beta, slot_of_temp, E, seed, q, r0, t0 + (uint32_t)k, swap_acc);
+        orc_pt_step(dim, L, J, spins, n_temps, beta, slot_of_temp, E, seed, q, r0, t0 + (uint32_t)k, m, swap_acc);
 }
 
 /* The swap uniform itself, exposed for the near-tie audit of exp(x). */

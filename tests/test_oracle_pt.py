@@ -33,6 +33,23 @@ def test_equal_temperatures_accept_every_swap():
     assert int(acc.sum()) == sum(len(range(t & 1, n - 1, 2)) for t in range(9))
 
 
+def test_sweeps_per_step_numbering():
+    """Step t with m sweeps per exchange: every slot gets the plain sweeps
+    t*m .. t*m + m - 1 at its temperature (equal temperatures: every swap is
+    accepted, so the permutation is the transposition walk)."""
+    n, L, m, t = 4, 8, 3, 5
+    spins, E, sot = _chain(2, L, n, 40)
+    ref = spins.copy()
+    beta = np.full(n, 0.45)
+    O.pt_run(2, L, None, spins, beta, sot, E, SEED, 0, 40, t, 1, sweeps_per_step=m)
+    for slot in range(n):
+        O.run(2, L, None, ref[slot], 0.45, SEED, 40 + slot, t * m, m)
+    assert np.array_equal(spins, ref)
+    assert list(sot) == [0, 2, 1, 3]  # t odd: the pair (1, 2) exchanges
+    for k in range(n):
+        assert E[k] == O.energy(2, L, None, spins[k])
+
+
 def test_energy_tracking_and_permutation_validity():
     J = O.init_couplings(2, 8, SEED, 3)
     n = 8
@@ -44,9 +61,11 @@ def test_energy_tracking_and_permutation_validity():
         assert E[k] == O.energy(2, 8, J, spins[k])
 
 
-def test_swap_rate_matches_exact_double_sum():
+@pytest.mark.parametrize("m", [1, 3])
+def test_swap_rate_matches_exact_double_sum(m):
     """For two temperatures on the 4x4 Ising model the mean acceptance of a
-    swap attempt is sum_{E1,E2} P_b1(E1) P_b2(E2) min(1, exp((b2-b1)(E2-E1)))."""
+    swap attempt is sum_{E1,E2} P_b1(E1) P_b2(E2) min(1, exp((b2-b1)(E2-E1))),
+    whatever the number m of sweeps between exchange rounds."""
     b1, b2 = 0.30, 0.45
     E_all, M_all = X.enumerate_states(2, 4)
     lev, cnt = X.density_of_states(E_all)
@@ -62,9 +81,9 @@ def test_swap_rate_matches_exact_double_sum():
     rates = []
     for q in range(64):
         spins, E, sot = _chain(2, 4, 2, 2 * q)
-        O.pt_run(2, 4, None, spins, beta, sot, E, SEED, q, 2 * q, 0, 100)   # equilibrate
+        O.pt_run(2, 4, None, spins, beta, sot, E, SEED, q, 2 * q, 0, 100, sweeps_per_step=m)   # equilibrate
         acc = np.zeros(2, np.uint64)
-        O.pt_run(2, 4, None, spins, beta, sot, E, SEED, q, 2 * q, 100, 2000, acc)
+        O.pt_run(2, 4, None, spins, beta, sot, E, SEED, q, 2 * q, 100, 2000, acc, sweeps_per_step=m)
         rates.append(float(acc[0]) / 1000.0)   # pair 0 is attempted on even steps
     m, err = np.mean(rates), np.std(rates, ddof=1) / math.sqrt(len(rates))
     assert abs(m - exact) < 4.5 * err, (m, exact, err)
