@@ -292,6 +292,32 @@ def _pt_batch(S, model, dim, L, n_chains, n_temps, seed, rps=1, inst=None):
     return b, spins, coup, E, sot
 
 
+def tempering_ising2d(S, W, sizes=(64, 128, 256, 1024, 2048), n_temps=20, every=(100, 10), flips=2e9):
+    """The paper's tempering benchmark (Sec. 6): one chain of 20 replicas of
+    the 2D Ising model at inverse temperatures equally spaced in
+    [0.1, 0.15], one exchange round per 100 (or 10) sweeps: ps per attempted
+    flip (exchange rounds included) against L.  Steps per size are chosen
+    for about `flips` attempted flips."""
+    import numpy as np
+
+    beta = np.linspace(0.10, 0.15, n_temps)
+    rows = []
+    for L in sizes:
+        for m in every:
+            b, spins, coup, E, sot = _pt_batch(S, S.ISING, 2, L, 1, n_temps, W.seed_for(96))
+            per_step = n_temps * L * L * m
+            steps = max(2, int(flips // per_step))
+            _, kernel = S.pt_plan(b, 1, n_temps, beta, steps, sweeps_per_step=m)
+            S.pt_sweep_swap(b, 1, n_temps, beta, spins, sot, E, 0, 1, sweeps_per_step=m)  # warm-up
+            ms = _timed(lambda: S.pt_sweep_swap(b, 1, n_temps, beta, spins, sot, E, 1, steps, sweeps_per_step=m))
+            rows.append({"L": L, "sweeps_per_exchange": m, "steps": steps, "kernel": kernel, "ms": round(ms, 3),
+                         "ps_per_flip": round(ms * 1e9 / (per_step * steps), 4)})
+            del spins, E, sot
+    return {"workload": f"2D Ising parallel tempering, one chain of {n_temps} replicas, beta equally spaced in "
+                        f"[0.10, 0.15], one exchange round per m sweeps; ps per attempted flip",
+            "by_size": rows}
+
+
 def tempering_ea3d(S, W, steps, per_inst_chains=16, per_inst_steps=50, per_step_steps=3):
     """3D EA, L = 16, 512 samples x 2 replicas x 32 temperatures: the whole
     batch in one call (one launch), against one call per chain and against
@@ -422,7 +448,9 @@ def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
     """The paper's Heisenberg benchmark (Sec. 4): 2D, L = 4096, double
     checkerboard with k = 100 hits, in the three arithmetic modes (float32
     with accurate functions, float32 with hardware functions, float64):
-    ps per attempted move, from a random start at beta = 1."""
+    ps per attempted move, from a random start at beta = 1, and the mean and
+    largest deviation of |s| from 1 after the run (no renormalisation falls
+    in the 5 sweeps; Fig. 12)."""
     import torch
 
     seed = W.seed_for(91)
@@ -439,8 +467,12 @@ def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
             S.heis_dcb_sweep(b, spins, [1.0], 0, 1, tile, hits, precision=mode)
             ms = _timed(lambda: S.heis_dcb_sweep(b, spins, [1.0], 1, sweeps, tile, hits, precision=mode, accepts=acc))
             flips = L * L * hits * sweeps
+            # deviation of |s| from 1 after 5 sweeps without renormalisation (Fig. 12)
+            dev = (spins.view(-1, 3).double().norm(dim=1) - 1.0).abs()
             rows.append({"mode": name, "tile": tile, "ms": round(ms, 3), "ps_per_flip": round(ms * 1e9 / flips, 4),
-                         "acceptance": round(float(acc.item()) / flips, 4)})
+                         "acceptance": round(float(acc.item()) / flips, 4),
+                         "norm_dev_mean": float(f"{dev.mean().item():.3g}"),
+                         "norm_dev_max": float(f"{dev.max().item():.3g}")})
             del spins
     torch.cuda.empty_cache()
     return {"workload": f"2D Heisenberg {L}x{L}, beta = 1, double checkerboard with T x T tiles and k = {hits} "
@@ -676,6 +708,8 @@ def main():
     ap.add_argument("--heis-dcb-sweeps", type=int, default=4)
     ap.add_argument("--heis-dcb-only", action="store_true",
                     help="only the 2D Heisenberg double checkerboard (L = 4096, k = 100, three modes)")
+    ap.add_argument("--pt-ising-only", action="store_true",
+                    help="only the 2D Ising tempering benchmark of 20 replicas (L = 64 .. 2048)")
     ap.add_argument("--tau-only", action="store_true",
                     help="only the double-checkerboard autocorrelation study (128^2, 16x16 tiles)")
     ap.add_argument("--tau-updates", type=int, default=1 << 15, help="attempts per site per (beta, k) series")
@@ -728,6 +762,9 @@ def main():
         return
     if args.heis_dcb_only:
         print(json.dumps({"heis_dcb2d": heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)}))
+        return
+    if args.pt_ising_only:
+        print(json.dumps({"ising2d_paper": tempering_ising2d(S, W)}))
         return
     if args.tau_only:
         print(json.dumps({"tau_dcb": tau_dcb(S, W, n_rep=args.tau_replicas, updates=args.tau_updates)}))
@@ -809,7 +846,8 @@ def main():
     if not args.no_tempering:
         out["heisenberg"] = heisenberg3d(S, W, args.heis_sweeps)
         out["tempering"] = {"ea3d_L16": tempering_ea3d(S, W, args.pt3d_steps),
-                            "ea2d_uneven": tempering_ea2d_uneven(S, W, args.uneven_steps)}
+                            "ea2d_uneven": tempering_ea2d_uneven(S, W, args.uneven_steps),
+                            "ising2d_paper": tempering_ising2d(S, W)}
         out["msc_ea2d"] = msc_ea2d(S, W, args.msc_sweeps)
         out["dcb2d"] = dcb2d(S, W, args.dcb_sweeps)
         out["heis_dcb2d"] = heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)

@@ -113,7 +113,7 @@ typedef struct smc_pt_desc {
     int32_t n_chains;       /* independent chains                                 */
     int32_t n_temps;        /* temperatures (= replicas) per chain, >= 2          */
     int32_t beta_per_chain; /* 0: beta is [n_temps]; 1: beta is [n_chains][n_temps] */
-    int32_t reserved;
+    int32_t sweeps_per_step; /* m: sweeps between exchange rounds (0 or 1: one)  */
     const double *beta;     /* HOST inverse temperatures of the ladder, index k   */
 } smc_pt_desc;
 
@@ -151,8 +151,9 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
 
 /*
  * n_steps parallel-tempering steps with indices step0 .. step0+n_steps-1
- * (Sec. 6, Eq. 12).  Step t: one sweep (sweep index t) of every replica at
- * its current temperature, energies tracked from the accepted flips; then
+ * (Sec. 6, Eq. 12).  Step t: m = pt.sweeps_per_step sweeps (sweep indices
+ * t*m .. t*m + m - 1; m = 1 when the field is 0) of every replica at its
+ * current temperature, energies tracked from the accepted flips; then
  * for every pair (k, k+1) with k = t (mod 2), k <= n_temps-2, in every
  * chain q: A = slot_of_temp[q][k], B = slot_of_temp[q][k+1],
  * x = (beta_{k+1} - beta_k) * (E_B - E_A) in float64, accepted iff x >= 0 or
@@ -168,7 +169,7 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
  *                smc_measure_energy_magnetisation).
  *  swap_accepts: DEVICE uint64 [n_chains][n_temps-1] or NULL; += accepted
  *                exchanges of pair k.
- *  Constraint: step0 + n_steps <= 2^32.
+ *  Constraint: (step0 + n_steps) * m <= 2^32.
  */
 int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins,
                       const int8_t *couplings, int32_t *slot_of_temp, double *energy,

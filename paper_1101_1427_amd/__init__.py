@@ -39,7 +39,7 @@ class Desc(C.Structure):
 
 class PTDesc(C.Structure):
     _fields_ = [("n_chains", C.c_int32), ("n_temps", C.c_int32), ("beta_per_chain", C.c_int32),
-                ("reserved", C.c_int32), ("beta", C.POINTER(C.c_double))]
+                ("sweeps_per_step", C.c_int32), ("beta", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -240,12 +240,14 @@ def msc_plan(batch: Batch, n_sweeps: int):
 
 
 def pt_sweep_swap(batch: Batch, n_chains: int, n_temps: int, beta, spins, slot_of_temp, energy, step0: int,
-                  n_steps: int, couplings=None, swap_accepts=None, beta_per_chain: bool = False, stream=None):
-    """n_steps parallel-tempering steps (sweep + exchange round); beta is host [n_temps]
-    (or [n_chains, n_temps] with beta_per_chain)."""
+                  n_steps: int, couplings=None, swap_accepts=None, beta_per_chain: bool = False,
+                  sweeps_per_step: int = 1, stream=None):
+    """n_steps parallel-tempering steps (sweeps_per_step sweeps, then an exchange
+    round); beta is host [n_temps] (or [n_chains, n_temps] with beta_per_chain)."""
     d = _desc(batch, spins, couplings)
     b = np.ascontiguousarray(np.asarray(beta, np.float64).reshape(-1))
-    pt = PTDesc(n_chains, n_temps, 1 if beta_per_chain else 0, 0, b.ctypes.data_as(C.POINTER(C.c_double)))
+    pt = PTDesc(n_chains, n_temps, 1 if beta_per_chain else 0, sweeps_per_step,
+                b.ctypes.data_as(C.POINTER(C.c_double)))
     _check(lib().smc_pt_sweep_swap(C.byref(d), C.byref(pt), _ptr(spins), _ptr(couplings), _ptr(slot_of_temp),
                                    _ptr(energy), step0, n_steps, _ptr(swap_accepts), _stream(stream)),
            "smc_pt_sweep_swap")
@@ -269,12 +271,14 @@ def sweep_plan(batch: Batch):
     return int(n.value), name.value.decode()
 
 
-def pt_plan(batch: Batch, n_chains: int, n_temps: int, beta, n_steps: int, beta_per_chain: bool = False):
+def pt_plan(batch: Batch, n_chains: int, n_temps: int, beta, n_steps: int, beta_per_chain: bool = False,
+            sweeps_per_step: int = 1):
     """(kernel launches, sweep kernel name) that smc_pt_sweep_swap uses for a call of n_steps steps."""
     spins_len = batch.spins_shape()[0]
     d = batch.desc(spins_len, batch.coup_len())
     b = np.ascontiguousarray(np.asarray(beta, np.float64).reshape(-1))
-    pt = PTDesc(n_chains, n_temps, 1 if beta_per_chain else 0, 0, b.ctypes.data_as(C.POINTER(C.c_double)))
+    pt = PTDesc(n_chains, n_temps, 1 if beta_per_chain else 0, sweeps_per_step,
+                b.ctypes.data_as(C.POINTER(C.c_double)))
     n = C.c_int32(0)
     name = C.c_char_p()
     _check(lib().smc_pt_plan(C.byref(d), C.byref(pt), n_steps, C.byref(n), C.byref(name)), "smc_pt_plan")

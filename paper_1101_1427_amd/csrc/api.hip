@@ -78,6 +78,9 @@ enum Slot {
     kMscEnergy,
     kMscGauge,
     kDcbSlots,
+    kPtThr,
+    kPtDelta,
+    kPtOut,
     kNumSlots
 };
 
@@ -218,6 +221,16 @@ bool use_lattice2d(const smc_desc *d, const void *spins, const std::vector<ThrRo
     for (const ThrRow &r : rows)
         if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu) return false;
     return true;
+}
+
+// Tempering of a uniform 2D Ising batch on the one-pass colour-split sweep:
+// L a power of two in [1024, 16384], aligned spins, thresholds of every
+// temperature with 16-bit high halves; SPINMC_PT_SPLIT2D=0 sends such
+// batches to the generic kernels (same results).
+bool use_pt_split2d(const smc_desc *d, const void *spins, const std::vector<ThrRow> &rows) {
+    const char *env = getenv("SPINMC_PT_SPLIT2D");
+    if (env && env[0] == '0') return false;
+    return use_lattice2d(d, spins, rows);
 }
 
 // --------------------------------------------------------------- validation --
@@ -476,7 +489,7 @@ std::vector<smc_inst> inst_rows(const smc_desc *d) {
 
 int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &plan, const smc_pt_desc *pt,
                  void *spins, const int8_t *couplings, SwapArgs &sw, const ThrRow *thr, double *energy,
-                 uint64_t step0, int32_t n_steps) {
+                 uint64_t step0, int32_t n_steps, int m) {
     int rc;
     // instance table, classes by edge (largest first), work list in replica order within a class
     const std::vector<smc_inst> rows = inst_rows(desc);
@@ -526,20 +539,26 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
         SMC_HIP(launch_coup_split2d(couplings, csplit, (const smc_inst *)samp_dev, (int)samples.size(), total,
                                     (const int64_t *)start_dev, s));
     }
+    // device counters: the step index (exchange rounds) and, with m > 1
+    // sweeps per step, the sweep index t*m + j (with m = 1 they coincide)
     void *tp = nullptr;
-    if ((rc = ensure(c, kStep, sizeof(uint32_t), &tp))) return rc;
+    if ((rc = ensure(c, kStep, 2 * sizeof(uint32_t), &tp))) return rc;
     uint32_t *t_dev = (uint32_t *)tp;
+    uint32_t *sweep_dev = m > 1 ? t_dev + 1 : t_dev;
     SMC_HIP(launch_set_step(t_dev, (uint32_t)step0, s));
+    if (m > 1) SMC_HIP(launch_set_step(sweep_dev, (uint32_t)(step0 * (uint64_t)m), s));
     sw.t_dev = t_dev;
     SMC_HIP(launch_pt_prepare(sw, energy, s));
-    const Uneven2dArgs a = make_uneven2d_args((int8_t *)spins, (const smc_inst *)inst_dev, csplit, sw.row_of_rep,
-                                              thr, sw.E, t_dev, make_key(desc->seed));
+    // every sweep launch runs the m sweeps of a step with the replica in LDS
+    Uneven2dArgs a = make_uneven2d_args((int8_t *)spins, (const smc_inst *)inst_dev, csplit, sw.row_of_rep, thr,
+                                        sw.E, sweep_dev, make_key(desc->seed));
     const int32_t *wl = (const int32_t *)work_dev;
     const bool ea = desc->model == SMC_EA;
     for (auto &e : classes) {
         const std::vector<int32_t> reps(work.begin() + e.first, work.begin() + e.first + e.count);
         if ((rc = uneven2d_threads(c, s, a, e.L, ea, reps, rows, &e.threads))) return rc;
     }
+    a.sweeps = m;
 
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     SMC_HIP(hipStreamIsCapturing(s, &cap));
@@ -549,11 +568,13 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
             for (const EdgeClass &e : classes)
                 SMC_HIP(launch_uneven2d_sweep(a, wl + e.first, e.count, e.L, ea, e.threads, s));
             SMC_HIP(launch_pt_swap(sw, s));
+            if (m > 1) SMC_HIP(launch_advance_step(sweep_dev, s, (uint32_t)m));
             SMC_HIP(launch_advance_step(t_dev, s));
         }
     } else {
         // a graph of K steps: per step the edge classes run as parallel
-        // branches, then the exchange round, then the step counter
+        // branches (m sweeps each), then the exchange round, then (m > 1) the
+        // sweep counter, then the step counter
         const int32_t K = n_steps < 32 ? n_steps : 32;
         const int32_t reps = n_steps / K, rest = n_steps % K;
         for (int which = 0; which < 2; ++which) {
@@ -565,7 +586,7 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
                                          (uint64_t)(uintptr_t)t_dev, a.key.k0, a.key.k1, (uint64_t)(uintptr_t)wl,
                                          (uint64_t)(uintptr_t)sw.beta, (uint64_t)(uintptr_t)sw.slot_of_temp,
                                          (uint64_t)(uintptr_t)sw.acc, (uint64_t)sw.n_chains, (uint64_t)sw.n_temps,
-                                         (uint64_t)sw.beta_per_chain};
+                                         (uint64_t)sw.beta_per_chain, (uint64_t)m};
             for (const EdgeClass &e : classes) {
                 sig.push_back((uint64_t)e.L);
                 sig.push_back((uint64_t)e.threads);
@@ -590,9 +611,11 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
                         e = add_uneven2d_sweep_node(g, &sweeps[q], prev ? &prev : nullptr, prev ? 1 : 0, a,
                                                     wl + ec.first, ec.count, ec.L, ea, ec.threads);
                     }
-                    hipGraphNode_t swap = nullptr;
+                    hipGraphNode_t swap = nullptr, after = nullptr;
                     if (e == hipSuccess) e = add_pt_swap_node(g, &swap, sweeps.data(), sweeps.size(), sw);
-                    if (e == hipSuccess) e = add_advance_node(g, &prev, &swap, 1, t_dev);
+                    after = swap;
+                    if (m > 1 && e == hipSuccess) e = add_advance_node(g, &after, &swap, 1, sweep_dev, (uint32_t)m);
+                    if (e == hipSuccess) e = add_advance_node(g, &prev, &after, 1, t_dev);
                 }
                 if (e == hipSuccess) e = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
@@ -757,7 +780,11 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
     if (!pt || !launches || !kernel_name) return fail(SMC_EINVAL, "pt desc and output pointers are required");
     if (n_steps < 0) return fail(SMC_EINVAL, "n_steps must be >= 0");
     if (pt->n_temps < 2 || !pt->beta) return fail(SMC_EINVAL, "need n_temps >= 2 and beta");
+    if (pt->sweeps_per_step < 0) return fail(SMC_EINVAL, "sweeps_per_step must be >= 0");
+    const int m = pt->sweeps_per_step > 0 ? pt->sweeps_per_step : 1;
     const int rows_n = pt->beta_per_chain ? pt->n_chains : 1;
+    std::vector<ThrRow> all_rows((size_t)rows_n * pt->n_temps);
+    for (size_t k = 0; k < all_rows.size(); ++k) all_rows[k] = threshold_row(pt->beta[k], desc->dim);
     bool fits = pt3d_enabled() && pt3d_supported(desc, pt->n_temps);
     for (int64_t k = 0; fits && k < (int64_t)rows_n * pt->n_temps; ++k) {
         const ThrRow r = threshold_row(pt->beta[k], desc->dim);
@@ -779,15 +806,19 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
     if (fits) {
         *launches = n_steps > 0 ? 1 : 0;
         *kernel_name = "k_pt3d_chain";
+    } else if (use_pt_split2d(desc, (const void *)nullptr, all_rows)) {
+        // prepare, zero, to split; per step: thresholds, m sweeps, collect, add, exchange; from split, copy, finish
+        *launches = n_steps > 0 ? 6 + n_steps * (m + 4) : 0;
+        *kernel_name = "k_ising2d_split";
     } else if (fits2d) {
-        // set step, prepare, (coupling split), graph launches of up to 32 steps, finish
+        // set step(s), prepare, (coupling split), graph launches of up to 32 steps, finish
         const int32_t K = n_steps < 32 ? n_steps : 32;
         const int32_t graphs = n_steps < 4 ? 0 : n_steps / K + (n_steps % K ? 1 : 0);
         const int32_t direct = n_steps < 4 ? n_steps * (int32_t)(2 + 7) : 0;
         *launches = n_steps > 0 ? 3 + (desc->model == SMC_EA ? 1 : 0) + graphs + direct : 0;
         *kernel_name = "k_uneven2d_sweep";
     } else {
-        *launches = n_steps > 0 ? 3 * n_steps + 2 : 0;
+        *launches = n_steps > 0 ? (2 * m + 1) * n_steps + 2 : 0;
         *kernel_name = "k_half_sweep_generic";
     }
     return SMC_OK;
@@ -1197,6 +1228,48 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, cons
     return SMC_OK;
 }
 
+int run_pt_split2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, void *spins, SwapArgs &sw,
+                   const ThrRow *thr_rows, double *energy, uint64_t step0, int32_t n_steps, int m) {
+    int rc;
+    const int L = desc->L, n_rep = desc->n_rep;
+    const int64_t N = (int64_t)L * L;
+    const size_t bytes = (size_t)n_rep * lattice2d_split_bytes(L);
+    const size_t slots = lattice2d_de_slots(L, n_rep);
+    if (slots == 0) return fail(SMC_EINVAL, "no band shape for L=%d", L);
+    void *pp = nullptr, *q = nullptr, *tr = nullptr, *dd = nullptr, *op = nullptr;
+    if ((rc = ensure(c, kPingPong, 2 * bytes, &pp))) return rc;
+    if ((rc = ensure(c, kL2dPart, slots * sizeof(int64_t), &q))) return rc;
+    if ((rc = ensure(c, kPtThr, sizeof(ThrRow) * (size_t)n_rep, &tr))) return rc;
+    if ((rc = ensure(c, kPtDelta, sizeof(int64_t) * (size_t)n_rep, &dd))) return rc;
+    if ((rc = ensure(c, kPtOut, (size_t)N * (size_t)n_rep, &op))) return rc;
+    uint8_t *A = (uint8_t *)pp, *B = A + bytes;
+    int64_t *part = (int64_t *)q, *d = (int64_t *)dd;
+    ThrRow *thr_rep = (ThrRow *)tr;
+    const Key key = make_key(desc->seed);
+    SMC_HIP(launch_pt_prepare(sw, energy, s));
+    SMC_HIP(launch_zero64(d, n_rep, s));
+    SMC_HIP(launch_to_split((const int8_t *)spins, A, L, n_rep, s));
+    int64_t done = 0;  // sweeps so far (ping-pong parity)
+    SweepTimer timer(s, (int64_t)n_steps * m);
+    for (int32_t st = 0; st < n_steps; ++st) {
+        const uint32_t t = (uint32_t)(step0 + (uint64_t)st);
+        sw.t = t;
+        SMC_HIP(launch_pt_gather_thr(thr_rows, sw.row_of_rep, thr_rep, n_rep, s));
+        for (int j = 0; j < m; ++j, ++done)
+            SMC_HIP(launch_ising2d_split(done & 1 ? B : A, done & 1 ? A : B, L, n_rep, thr_rep, part, j == 0, key,
+                                         t * (uint32_t)m + (uint32_t)j, s));
+        SMC_HIP(launch_lattice2d_de_collect(part, d, L, n_rep, s));
+        SMC_HIP(launch_pt_add_masked(d, sw.E, sw.row_of_rep, n_rep, s));
+        SMC_HIP(launch_pt_swap(sw, s));
+    }
+    timer.finish();
+    // back to lattice order; replicas of chains that are not permutations keep their spins
+    SMC_HIP(launch_from_split(done & 1 ? B : A, (int8_t *)op, L, n_rep, s));
+    SMC_HIP(launch_copy_valid((const int8_t *)op, (int8_t *)spins, sw.row_of_rep, N, n_rep, s));
+    SMC_HIP(launch_pt_finish(sw, energy, s));
+    return SMC_OK;
+}
+
 int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, const int8_t *couplings,
                       int32_t *slot_of_temp, double *energy, uint64_t step0, int32_t n_steps,
                       uint64_t *swap_accepts, void *stream) {
@@ -1214,7 +1287,10 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, 
     if (!spins || !slot_of_temp || !energy) return fail(SMC_EINVAL, "spins, slot_of_temp and energy are required");
     if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
     if (n_steps < 0) return fail(SMC_EINVAL, "n_steps must be >= 0");
-    if (step0 + (uint64_t)n_steps > (1ull << 32)) return fail(SMC_EINVAL, "step index exceeds 32 bits");
+    if (pt->sweeps_per_step < 0) return fail(SMC_EINVAL, "sweeps_per_step must be >= 0");
+    const int m = pt->sweeps_per_step > 0 ? pt->sweeps_per_step : 1;
+    if ((step0 + (uint64_t)n_steps) * (uint64_t)m > (1ull << 32))
+        return fail(SMC_EINVAL, "(step0 + n_steps) * sweeps_per_step exceeds 2^32 (the sweep index is 32 bits)");
     const int n = pt->n_temps;
     const int rows_n = pt->beta_per_chain ? pt->n_chains : 1;
     for (int64_t k = 0; k < (int64_t)rows_n * n; ++k)
@@ -1250,7 +1326,7 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, 
         SMC_HIP(launch_pt3d(desc->model, (int8_t *)spins, desc->model == SMC_EA ? couplings : nullptr,
                             desc->rep_per_sample, pt->n_chains, n, pt->beta_per_chain ? 1 : 0, (const double *)bdev,
                             (const ThrRow *)thr, slot_of_temp, energy, (unsigned long long *)swap_accepts,
-                            make_key(desc->seed), (uint32_t)step0, n_steps, s));
+                            make_key(desc->seed), (uint32_t)step0, n_steps, m, s));
         return SMC_OK;
     }
     if ((rc = ensure(c, kEnergy64, sizeof(int64_t) * desc->n_rep, &E64))) return rc;
@@ -1280,15 +1356,20 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, 
     a.thr = (const ThrRow *)thr;
     a.row_of_rep = (const int32_t *)rowrep;
 
+    if (use_pt_split2d(desc, spins, rows))
+        return run_pt_split2d(c, s, desc, spins, sw, (const ThrRow *)thr, energy, step0, n_steps, m);
     if (use_uneven2d(desc, spins, couplings, rows))
-        return run_uneven2d(c, s, desc, plan, pt, spins, couplings, sw, (const ThrRow *)thr, energy, step0, n_steps);
+        return run_uneven2d(c, s, desc, plan, pt, spins, couplings, sw, (const ThrRow *)thr, energy, step0, n_steps,
+                            m);
     SMC_HIP(launch_pt_prepare(sw, energy, s));
     for (int32_t k = 0; k < n_steps; ++k) {
         const uint32_t t = (uint32_t)(step0 + (uint64_t)k);
-        a.t = t;
         sw.t = t;
-        SMC_HIP(launch_half_sweep_generic(a, 0, s));
-        SMC_HIP(launch_half_sweep_generic(a, 1, s));
+        for (int j = 0; j < m; ++j) {
+            a.t = t * (uint32_t)m + (uint32_t)j;
+            SMC_HIP(launch_half_sweep_generic(a, 0, s));
+            SMC_HIP(launch_half_sweep_generic(a, 1, s));
+        }
         SMC_HIP(launch_pt_swap(sw, s));
     }
     SMC_HIP(launch_pt_finish(sw, energy, s));

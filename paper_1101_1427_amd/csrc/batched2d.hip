@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
     }
     const ThrRow &th = a.thr[row];
     const Lut2 K = lut2(th);
-    const uint32_t t = *a.t_dev;
+    const uint32_t t0 = *a.t_dev;
     __syncthreads();
 
     uint32_t cnt = 0u, nsum = 0u;
@@ -268,31 +268,35 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
         return p;
     };
 #pragma unroll 1
-    for (int c = 0; c < 2; ++c) {
-        // (past the last group the position is clamped to row 0, so every
-        // coupling load stays inside the sample and none is conditional)
-        Pos pa{y0 < L ? y0 : 0, y0 < L ? y0 * L : 0, k0};
-        GroupAt ata = group_at(L, pa.yL, pa.y, pa.k, c);
-        GroupCoup Ja{};
-        if (EA) Ja = group_coup(X, Yp, ata);
+    for (int sw = 0; sw < a.sweeps; ++sw) {
+        const uint32_t t = t0 + (uint32_t)sw;
 #pragma unroll 1
-        for (int q = tid; q < groups;) {
-            const Pos pb = advance(pa);
-            const bool hb = q + nt < groups;
-            const GroupAt atb = group_at(L, hb ? pb.yL : 0, hb ? pb.y : 0, pb.k, c);
-            GroupCoup Jb{};
-            if (EA) Jb = group_coup(X, Yp, atb);
-            group<EA>(S, ata, Ja, L, pa.y, pa.k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
-            q += nt;
-            if (!hb) break;
-            pa = advance(pb);
-            const bool ha = q + nt < groups;
-            ata = group_at(L, ha ? pa.yL : 0, ha ? pa.y : 0, pa.k, c);
+        for (int c = 0; c < 2; ++c) {
+            // (past the last group the position is clamped to row 0, so every
+            // coupling load stays inside the sample and none is conditional)
+            Pos pa{y0 < L ? y0 : 0, y0 < L ? y0 * L : 0, k0};
+            GroupAt ata = group_at(L, pa.yL, pa.y, pa.k, c);
+            GroupCoup Ja{};
             if (EA) Ja = group_coup(X, Yp, ata);
-            group<EA>(S, atb, Jb, L, pb.y, pb.k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
-            q += nt;
+#pragma unroll 1
+            for (int q = tid; q < groups;) {
+                const Pos pb = advance(pa);
+                const bool hb = q + nt < groups;
+                const GroupAt atb = group_at(L, hb ? pb.yL : 0, hb ? pb.y : 0, pb.k, c);
+                GroupCoup Jb{};
+                if (EA) Jb = group_coup(X, Yp, atb);
+                group<EA>(S, ata, Ja, L, pa.y, pa.k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+                q += nt;
+                if (!hb) break;
+                pa = advance(pb);
+                const bool ha = q + nt < groups;
+                ata = group_at(L, ha ? pa.yL : 0, ha ? pa.y : 0, pa.k, c);
+                if (EA) Ja = group_coup(X, Yp, ata);
+                group<EA>(S, atb, Jb, L, pb.y, pb.k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+                q += nt;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // split 0/1 bytes -> row-major +-1
@@ -351,7 +355,7 @@ __global__ __launch_bounds__(256) void k_coup_split2d(const int8_t *coup, uint8_
 }
 
 __global__ void k_set_step(uint32_t *t_dev, uint32_t t) { *t_dev = t; }
-__global__ void k_advance_step(uint32_t *t_dev) { *t_dev += 1u; }
+__global__ void k_advance_step(uint32_t *t_dev, uint32_t inc) { *t_dev += inc; }
 
 }  // namespace
 
@@ -378,6 +382,7 @@ Uneven2dArgs make_uneven2d_args(int8_t *spins, const smc_inst *inst, const uint8
     a.thr = thr;
     a.E = E;
     a.t_dev = t_dev;
+    a.sweeps = 1;
     a.key = key;
     a.one2 = 0x00010001u;
     a.four = 4u;
@@ -417,9 +422,10 @@ hipError_t add_uneven2d_sweep_node(hipGraph_t g, hipGraphNode_t *node, const hip
 }
 
 hipError_t add_advance_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
-                            uint32_t *t_dev) {
+                            uint32_t *t_dev, uint32_t inc) {
     uint32_t *tp = t_dev;
-    void *params[] = {&tp};
+    uint32_t by = inc;
+    void *params[] = {&tp, &by};
     hipKernelNodeParams p;
     memset(&p, 0, sizeof p);
     p.func = (void *)k_advance_step;
@@ -439,8 +445,8 @@ hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int
     return hipGetLastError();
 }
 
-hipError_t launch_advance_step(uint32_t *t_dev, hipStream_t s) {
-    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, s, t_dev);
+hipError_t launch_advance_step(uint32_t *t_dev, hipStream_t s, uint32_t inc) {
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, s, t_dev, inc);
     return hipGetLastError();
 }
 

@@ -86,7 +86,8 @@ bool pt3d_supported(const smc_desc *d, int n_temps);
 size_t pt3d_lds_bytes(int model, int n_temps);
 hipError_t launch_pt3d(int model, int8_t *spins, const int8_t *coup, int rep_per_sample, int n_chains, int n_temps,
                        int beta_per_chain, const double *beta, const ThrRow *thr, int32_t *slot_of_temp,
-                       double *energy, unsigned long long *acc, Key key, uint32_t t0, int n_steps, hipStream_t s);
+                       double *energy, unsigned long long *acc, Key key, uint32_t t0, int n_steps, int m,
+                       hipStream_t s);
 
 // Uneven 2D batches: one workgroup per replica with the replica in LDS.
 struct Uneven2dArgs {
@@ -96,7 +97,8 @@ struct Uneven2dArgs {
     const int32_t *row_of_rep; // threshold row per replica; -1 leaves the replica unchanged
     const ThrRow *thr;
     int64_t *E;                // tracked energy per replica
-    const uint32_t *t_dev;     // step index (device), read by every sweep of the step
+    const uint32_t *t_dev;     // first sweep index of the launch (device)
+    int sweeps;                // sweeps per launch (indices *t_dev .. *t_dev + sweeps - 1), the replica kept in LDS
     Key key;
     uint32_t one2;  // 0x00010001 (opaque to the compiler)
     uint32_t four;  // 4 (opaque trip count of the exact-decision loop)
@@ -111,12 +113,12 @@ hipError_t launch_coup_split2d(const int8_t *coup, uint8_t *out, const smc_inst 
 hipError_t launch_set_step(uint32_t *t_dev, uint32_t t, hipStream_t s);
 hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int n_work, int L, bool ea, int threads,
                                  hipStream_t s);
-hipError_t launch_advance_step(uint32_t *t_dev, hipStream_t s);
+hipError_t launch_advance_step(uint32_t *t_dev, hipStream_t s, uint32_t inc = 1);
 hipError_t add_uneven2d_sweep_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
                                    const Uneven2dArgs &a, const int32_t *work, int n_work, int L, bool ea,
                                    int threads);
 hipError_t add_advance_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
-                            uint32_t *t_dev);
+                            uint32_t *t_dev, uint32_t inc = 1);
 hipError_t add_pt_swap_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, size_t n_deps,
                             const SwapArgs &a);
 
@@ -157,6 +159,16 @@ bool heis_dcb2d_supported(int L, int T, int precision);
 hipError_t launch_heis_dcb2d(void *spins, const void *beta, int64_t *acc_slots, int n_rep, int L, int T, int k,
                              int precision, Key key, uint32_t t, int tile_colour, bool rev, hipStream_t s);
 hipError_t launch_heis_dcb_renorm(void *spins, int64_t n_spins, int precision, hipStream_t s);
+
+// Tempering on the 2D colour-split sweep (pt_split2d.hip): per-replica
+// threshold rows from row_of_rep, masked energy updates (d is zeroed), and
+// the copy back of replicas of valid chains (N a multiple of 16).
+hipError_t launch_pt_gather_thr(const ThrRow *rows, const int32_t *row_of_rep, ThrRow *out, int n_rep,
+                                hipStream_t s);
+hipError_t launch_pt_add_masked(int64_t *d, int64_t *E, const int32_t *row_of_rep, int n_rep, hipStream_t s);
+hipError_t launch_copy_valid(const int8_t *src, int8_t *dst, const int32_t *row_of_rep, int64_t N, int n_rep,
+                             hipStream_t s);
+hipError_t launch_zero64(int64_t *p, int n, hipStream_t s);
 
 // Generator throughput: out[i] = XOR of the four words of the blocks with
 // counters (i + k * n_threads, t, r, tag), k < per_thread.

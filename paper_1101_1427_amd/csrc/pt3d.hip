@@ -1,9 +1,10 @@
 // Parallel tempering of 3D Ising / +-J Edwards-Anderson lattices of edge 16
-// with every step of a call inside one launch (Sec. 5.2, Eq. 12).
+// with every step of a call inside one launch (Sec. 6, Eq. 12).
 //
 // One workgroup runs one chain: the n_temps replicas of the chain and the
-// coupling sample they share stay in LDS for all n_steps steps (sweep of
-// every replica, then the exchange round of the step), and go back to HBM
+// coupling sample they share stay in LDS for all n_steps steps (m sweeps of
+// every replica, sweep indices t*m .. t*m + m - 1, then the exchange round
+// of step t), and go back to HBM
 // once at the end.  Results are those of the sweep and exchange kernels of
 // the generic path step for step: colour 0 then colour 1 per sweep, the same
 // Philox streams keyed by (seed, step, replica storage index, site), the
@@ -43,6 +44,7 @@ struct Pt3dArgs {
     Key key;
     uint32_t t0;
     int n_steps;
+    int m;          // sweeps per step
     uint32_t one2;  // 0x00010001 (opaque to the compiler, keeps the packed 16-bit ops)
     uint32_t four;  // 4 (opaque trip count of the rarely taken exact-decision loop)
 };
@@ -308,25 +310,28 @@ __global__ __launch_bounds__(kThreads) void k_pt3d_chain(Pt3dArgs a) {
     const bool active = s0 < n;
     for (int step = 0; step < a.n_steps; ++step) {
         const uint32_t t = a.t0 + (uint32_t)step;
-        uint32_t cnt[2] = {0u, 0u}, nsum[2] = {0u, 0u};
+        for (int j = 0; j < a.m; ++j) {
+            const uint32_t ts = t * (uint32_t)a.m + (uint32_t)j;  // sweep index
+            uint32_t cnt[2] = {0u, 0u}, nsum[2] = {0u, 0u};
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+            for (int c = 0; c < 2; ++c) {
+                if (active) {
+                    // rows with (y+z)&1 == c update array E, the others array O
+                    half_pass<EA>(S, Cb, cs, 0, c, c, s0, n, rbase, ts, a.key, a.one2, a.four, cnt, nsum);
+                    half_pass<EA>(S, Cb, cs, 1, 1 - c, c, s0, n, rbase, ts, a.key, a.one2, a.four, cnt, nsum);
+                }
+                __syncthreads();
+            }
             if (active) {
-                // rows with (y+z)&1 == c update array E, the others array O
-                half_pass<EA>(S, Cb, cs, 0, c, c, s0, n, rbase, t, a.key, a.one2, a.four, cnt, nsum);
-                half_pass<EA>(S, Cb, cs, 1, 1 - c, c, s0, n, rbase, t, a.key, a.one2, a.four, cnt, nsum);
+                const int d0 = wave_sum(3 * (int)cnt[0] - (int)nsum[0]);
+                const int d1 = wave_sum(3 * (int)cnt[1] - (int)nsum[1]);
+                if (lane == 0) {
+                    cs.E[s0] += 4 * d0;
+                    if (s0 + kWaves < n) cs.E[s0 + kWaves] += 4 * d1;
+                }
             }
             __syncthreads();
         }
-        if (active) {
-            const int d0 = wave_sum(3 * (int)cnt[0] - (int)nsum[0]);
-            const int d1 = wave_sum(3 * (int)cnt[1] - (int)nsum[1]);
-            if (lane == 0) {
-                cs.E[s0] += 4 * d0;
-                if (s0 + kWaves < n) cs.E[s0 + kWaves] += 4 * d1;
-            }
-        }
-        __syncthreads();
         // exchange round: pairs (k, k+1) with k = t mod 2, one thread each
         if (tid < n - 1 && (((uint32_t)tid ^ t) & 1u) == 0u) {
 #pragma clang fp contract(off)
@@ -381,7 +386,8 @@ size_t pt3d_lds_bytes(int model, int n_temps) {
 
 hipError_t launch_pt3d(int model, int8_t *spins, const int8_t *coup, int rep_per_sample, int n_chains, int n_temps,
                        int beta_per_chain, const double *beta, const ThrRow *thr, int32_t *slot_of_temp,
-                       double *energy, unsigned long long *acc, Key key, uint32_t t0, int n_steps, hipStream_t s) {
+                       double *energy, unsigned long long *acc, Key key, uint32_t t0, int n_steps, int m,
+                       hipStream_t s) {
     Pt3dArgs a;
     a.spins = spins;
     a.coup = coup;
@@ -397,6 +403,7 @@ hipError_t launch_pt3d(int model, int8_t *spins, const int8_t *coup, int rep_per
     a.key = key;
     a.t0 = t0;
     a.n_steps = n_steps;
+    a.m = m;
     a.one2 = 0x00010001u;
     a.four = 4u;
     const size_t lds = pt3d_lds_bytes(model, n_temps);

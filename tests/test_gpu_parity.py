@@ -196,7 +196,7 @@ def test_heisenberg_first_sweep_within_tolerance():
 
 
 # --------------------------------------------------------- parallel tempering --
-def _pt_case(model, dim, sizes, n_temps, steps, seed, beta):
+def _pt_case(model, dim, sizes, n_temps, steps, seed, beta, m=1):
     inst = refrun.uneven_table(dim, sizes, n_temps, model)
     n_chains = len(sizes)
     b = S.Batch(model, dim, 0, len(inst), seed, inst=inst)
@@ -205,9 +205,10 @@ def _pt_case(model, dim, sizes, n_temps, steps, seed, beta):
     S.measure_energy_magnetisation(b, spins, E, couplings=coup)
     sot = torch.arange(n_temps, dtype=torch.int32, device=DEV).repeat(n_chains)
     acc = torch.zeros(n_chains * (n_temps - 1), dtype=torch.int64, device=DEV)
-    S.pt_sweep_swap(b, n_chains, n_temps, beta, spins, sot, E, 0, steps // 2, couplings=coup, swap_accepts=acc)
+    S.pt_sweep_swap(b, n_chains, n_temps, beta, spins, sot, E, 0, steps // 2, couplings=coup, swap_accepts=acc,
+                    sweeps_per_step=m)
     S.pt_sweep_swap(b, n_chains, n_temps, beta, spins, sot, E, steps // 2, steps - steps // 2, couplings=coup,
-                    swap_accepts=acc)
+                    swap_accepts=acc, sweeps_per_step=m)
     # oracle
     ref_s, ref_c = refrun.init_uneven(model, dim, inst, seed)
     for q, L in enumerate(sizes):
@@ -219,7 +220,7 @@ def _pt_case(model, dim, sizes, n_temps, steps, seed, beta):
         Eq = np.array([O.energy(dim, int(L), J, chain[k]) for k in range(n_temps)], np.int64)
         sq = np.arange(n_temps, dtype=np.int32)
         aq = np.zeros(n_temps, np.uint64)
-        O.pt_run(dim, int(L), J, chain, beta, sq, Eq, seed, q, q * n_temps, 0, steps, aq)
+        O.pt_run(dim, int(L), J, chain, beta, sq, Eq, seed, q, q * n_temps, 0, steps, aq, sweeps_per_step=m)
         assert np.array_equal(_host(spins)[so0:so0 + n_temps * N].reshape(n_temps, N), chain), q
         assert np.array_equal(_host(sot)[q * n_temps:(q + 1) * n_temps], sq), q
         assert np.array_equal(_host(E)[q * n_temps:(q + 1) * n_temps], Eq.astype(np.float64)), q
@@ -228,6 +229,11 @@ def _pt_case(model, dim, sizes, n_temps, steps, seed, beta):
 
 def test_pt_uneven_2d_bit_exact():
     _pt_case(S.EA, 2, [8, 12, 32, 6], 5, 40, W.seed_for(19), W.geometric_ladder(0.5, 2.0, 5))
+
+
+def test_pt_generic_sweeps_per_step():
+    """Four sweeps between exchange rounds on the generic kernels."""
+    _pt_case(S.EA, 2, [8, 12, 6], 4, 11, W.seed_for(23), W.geometric_ladder(0.5, 2.0, 4), m=4)
 
 
 def test_pt_3d_bit_exact():

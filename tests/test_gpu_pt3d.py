@@ -30,7 +30,7 @@ def _perms(n_chains, n_temps, seed):
     return np.concatenate([rng.permutation(n_temps) for _ in range(n_chains)]).astype(np.int32)
 
 
-def _run_gpu(model, n_chains, n_temps, rps, seed, beta, calls, perms, beta_per_chain=False):
+def _run_gpu(model, n_chains, n_temps, rps, seed, beta, calls, perms, beta_per_chain=False, m=1):
     b = S.Batch(model, 3, L, n_chains * n_temps, seed, rep_per_sample=rps)
     assert S.pt_plan(b, n_chains, n_temps, beta, 10, beta_per_chain)[1] == "k_pt3d_chain"
     spins = torch.zeros(b.spins_shape()[0], dtype=torch.int8, device=DEV)
@@ -42,37 +42,42 @@ def _run_gpu(model, n_chains, n_temps, rps, seed, beta, calls, perms, beta_per_c
     acc = torch.zeros(n_chains * (n_temps - 1), dtype=torch.int64, device=DEV)
     for step0, n in calls:
         S.pt_sweep_swap(b, n_chains, n_temps, beta, spins, sot, E, step0, n, couplings=coup, swap_accepts=acc,
-                        beta_per_chain=beta_per_chain)
+                        beta_per_chain=beta_per_chain, sweeps_per_step=m)
     return _host(spins).reshape(-1, N), _host(sot), _host(E), _host(acc)
 
 
-def _oracle_chain(model, q, n_temps, rps, seed, beta_q, perm_q, t0, steps):
+def _oracle_chain(model, q, n_temps, rps, seed, beta_q, perm_q, t0, steps, m=1):
     r0 = q * n_temps
     chain = np.stack([O.init_spins(3, L, seed, r0 + k) for k in range(n_temps)])
     J = O.init_couplings(3, L, seed, r0 // rps) if model == S.EA else None
     E = np.array([O.energy(3, L, J, chain[k]) for k in range(n_temps)], np.int64)
     sq = perm_q.astype(np.int32).copy()
     aq = np.zeros(n_temps, np.uint64)
-    O.pt_run(3, L, J, chain, np.asarray(beta_q, np.float64), sq, E, seed, q, r0, t0, steps, aq)
+    O.pt_run(3, L, J, chain, np.asarray(beta_q, np.float64), sq, E, seed, q, r0, t0, steps, aq, sweeps_per_step=m)
     return chain, sq, E, aq[:n_temps - 1]
 
 
-def _check(model, n_chains, n_temps, rps, seed, beta, calls, chains=None, beta_per_chain=False):
+def _check(model, n_chains, n_temps, rps, seed, beta, calls, chains=None, beta_per_chain=False, m=1):
     perms = _perms(n_chains, n_temps, seed & 0xFFFF)
-    got_s, got_p, got_E, got_a = _run_gpu(model, n_chains, n_temps, rps, seed, beta, calls, perms, beta_per_chain)
+    got_s, got_p, got_E, got_a = _run_gpu(model, n_chains, n_temps, rps, seed, beta, calls, perms, beta_per_chain, m)
     t0 = calls[0][0]
     steps = sum(n for _, n in calls)
     beta = np.asarray(beta, np.float64).reshape(-1, n_temps)
     for q in (range(n_chains) if chains is None else chains):
         bq = beta[q] if beta_per_chain else beta[0]
         chain, sq, E, aq = _oracle_chain(model, q, n_temps, rps, seed, bq, perms[q * n_temps:(q + 1) * n_temps], t0,
-                                         steps)
+                                         steps, m)
         sl = slice(q * n_temps, (q + 1) * n_temps)
         assert np.array_equal(got_s[sl], chain), f"spins of chain {q}"
         assert np.array_equal(got_p[sl], sq), f"permutation of chain {q}"
         assert np.array_equal(got_E[sl], E.astype(np.float64)), f"energies of chain {q}"
         assert np.array_equal(got_a[q * (n_temps - 1):(q + 1) * (n_temps - 1)], aq.astype(np.int64)), f"counts {q}"
     return got_s, got_E
+
+
+def test_pt3d_sweeps_per_step():
+    """Three sweeps between exchange rounds (sweep indices t*3 .. t*3 + 2)."""
+    _check(S.EA, 3, 6, 6, W.seed_for(45), W.geometric_ladder(0.8, 2.0, 6), [(2, 5), (7, 4)], m=3)
 
 
 def test_pt3d_ea_bit_exact_two_calls():

@@ -22,12 +22,12 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def _run(model, sizes, n_temps, beta, seed, calls, perms=None):
+def _run(model, sizes, n_temps, beta, seed, calls, perms=None, m=1):
     inst = refrun.uneven_table(2, sizes, n_temps, model)
     n_chains = len(sizes)
     b = S.Batch(model, 2, 0, len(inst), seed, inst=inst)
     n_steps = sum(n for _, n in calls)
-    assert S.pt_plan(b, n_chains, n_temps, beta, n_steps)[1] == "k_uneven2d_sweep"
+    assert S.pt_plan(b, n_chains, n_temps, beta, n_steps, sweeps_per_step=m)[1] == "k_uneven2d_sweep"
     spins = torch.zeros(b.spins_shape()[0], dtype=torch.int8, device=DEV)
     coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV) if model == S.EA else None
     S.spin_init(b, spins, coup)
@@ -38,11 +38,12 @@ def _run(model, sizes, n_temps, beta, seed, calls, perms=None):
     sot = torch.from_numpy(perms.copy()).to(DEV)
     acc = torch.zeros(n_chains * (n_temps - 1), dtype=torch.int64, device=DEV)
     for step0, n in calls:
-        S.pt_sweep_swap(b, n_chains, n_temps, beta, spins, sot, E, step0, n, couplings=coup, swap_accepts=acc)
+        S.pt_sweep_swap(b, n_chains, n_temps, beta, spins, sot, E, step0, n, couplings=coup, swap_accepts=acc,
+                        sweeps_per_step=m)
     return inst, _host(spins), _host(sot), _host(E), _host(acc), perms
 
 
-def _check_chain(model, inst, q, n_temps, beta, seed, t0, steps, got, perms):
+def _check_chain(model, inst, q, n_temps, beta, seed, t0, steps, got, perms, m=1):
     got_s, got_p, got_E, got_a = got
     rows = inst[q * n_temps:(q + 1) * n_temps]
     L = int(rows[0][0])
@@ -52,7 +53,8 @@ def _check_chain(model, inst, q, n_temps, beta, seed, t0, steps, got, perms):
     Eq = np.array([O.energy(2, L, J, chain[k]) for k in range(n_temps)], np.int64)
     sq = perms[q * n_temps:(q + 1) * n_temps].astype(np.int32).copy()
     aq = np.zeros(n_temps, np.uint64)
-    O.pt_run(2, L, J, chain, np.asarray(beta, np.float64), sq, Eq, seed, q, q * n_temps, t0, steps, aq)
+    O.pt_run(2, L, J, chain, np.asarray(beta, np.float64), sq, Eq, seed, q, q * n_temps, t0, steps, aq,
+             sweeps_per_step=m)
     so = int(rows[0][2])
     assert np.array_equal(got_s[so:so + n_temps * N].reshape(n_temps, N), chain), f"spins of chain {q} (L={L})"
     assert np.array_equal(got_p[q * n_temps:(q + 1) * n_temps], sq), f"permutation of chain {q}"
@@ -72,6 +74,20 @@ def test_uneven2d_every_edge_graph_and_remainder(model):
     got, perms = got[:4], got[4]
     for q in range(len(sizes)):
         _check_chain(model, inst, q, n_temps, beta, seed, 5, 39, got, perms)
+
+
+@pytest.mark.parametrize("m", [3, 40])
+def test_uneven2d_sweeps_per_step(m):
+    """m sweeps between exchange rounds, all m in one launch per edge class
+    with the replicas in LDS: a 13-step graph and a plain call of 2 steps."""
+    sizes = [16, 32, 64, 256] if m < 10 else [16, 32, 64]
+    n_temps, seed = 4, W.seed_for(58)
+    beta = W.geometric_ladder(0.5, 2.0, n_temps)
+    perms = np.concatenate([np.random.default_rng(9).permutation(n_temps) for _ in sizes]).astype(np.int32)
+    inst, *got = _run(S.EA, sizes, n_temps, beta, seed, [(1, 13), (14, 2)], perms, m=m)
+    got, perms = got[:4], got[4]
+    for q in range(len(sizes)):
+        _check_chain(S.EA, inst, q, n_temps, beta, seed, 1, 15, got, perms, m=m)
 
 
 def test_uneven2d_repeated_calls_reuse_the_graph():
