@@ -72,7 +72,7 @@ def lib():
             "orc_swap_u53": (D, [U64, U32, U32, U32]),
             "orc_window_run": (None, [I, I, I, I, i8p, D, U64, U32, U32, I]),
             "orc_dcb_run": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
-            "orc_heis_dcb_run": (I64, [I, I, I, f64p, D, U64, U32, U32, I, I, I]),
+            "orc_heis_dcb_run": (I64, [I, I, I, f64p, D, U64, U32, U32, I, I, I, D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -209,12 +209,13 @@ def dcb_run(L, T, k, J, s, beta, seed, r, t0, n, palindromic=False) -> int:
                                  1 if palindromic else 0))
 
 
-def heis_dcb_run(L, T, k, s, beta, seed, r, t0, n, palindromic=False, renorm_every=16) -> int:
+def heis_dcb_run(L, T, k, s, beta, seed, r, t0, n, palindromic=False, renorm_every=16, cap=0.0) -> int:
     """n double-checkerboard sweeps (T x T tiles, k hits per tile) of a 2D
-    Heisenberg lattice (float64 [N*3]) in place; returns the number of
+    Heisenberg lattice (float64 [N*3]) in place, with uniform proposals
+    (cap = 0) or small steps on a cap of size cap; returns the number of
     accepted moves (orc_heis_dcb_run)."""
     return int(lib().orc_heis_dcb_run(L, T, k, s, beta, seed & 0xFFFFFFFFFFFFFFFF, r, t0, n,
-                                      1 if palindromic else 0, renorm_every))
+                                      1 if palindromic else 0, renorm_every, cap))
 
 
 def window_run(L, x0, y0, win, beta, seed, r, t0, n):

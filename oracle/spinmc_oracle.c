@@ -431,12 +431,45 @@ EXPORT void orc_run_series(int dim, int L, const int8_t *J, int8_t *s, double be
 /* Heisenberg (O(3)) model, Eq. (10), FP64.                                  */
 /* ------------------------------------------------------------------------ */
 
+/* Small-step proposal (Sec. 4 suggests small changes instead of uniform
+ * re-orientations for low temperatures): s' uniform on the spherical cap
+ * {s' : 1 - a.s' <= cap} around a = s/|s|, cap in (0, 2], so that the
+ * proposal density is symmetric in s and s'.  From two uniforms: w = cap u0,
+ * the cosine of the angle 1 - w, the radius sqrt(w (2 - w)), the azimuth
+ * 2 pi u1 in the frame (e1, e2): e1 a unit vector perpendicular to a (in the
+ * x-y plane when |a_x| > |a_z|, else in the y-z plane), e2 = a x e1. */
+static void cap_point(const double *s, double cap, double u0, double u1, double out[3])
+{
+    double n = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    double a[3] = {s[0] / n, s[1] / n, s[2] / n};
+    double e1[3];
+    if (fabs(a[0]) > fabs(a[2])) {
+        double m = sqrt(a[0] * a[0] + a[1] * a[1]);
+        e1[0] = -a[1] / m;
+        e1[1] = a[0] / m;
+        e1[2] = 0.0;
+    } else {
+        double m = sqrt(a[1] * a[1] + a[2] * a[2]);
+        e1[0] = 0.0;
+        e1[1] = -a[2] / m;
+        e1[2] = a[1] / m;
+    }
+    double e2[3] = {a[1] * e1[2] - a[2] * e1[1], a[2] * e1[0] - a[0] * e1[2], a[0] * e1[1] - a[1] * e1[0]};
+    double w = cap * u0;
+    double zc = 1.0 - w;
+    double rc = sqrt(w * (2.0 - w));
+    double phi = TWO_PI * u1;
+    double cs = cos(phi), sn = sin(phi);
+    for (int k = 0; k < 3; ++k) out[k] = zc * a[k] + rc * (cs * e1[k] + sn * e2[k]);
+}
+
 /* The Metropolis move at site i of colour c in sweep t: propose a fresh
- * uniform direction s' (independent of s, Sec. 4) from words 0, 1 of
+ * uniform direction s' (independent of s, Sec. 4; cap == 0) or a point of
+ * the cap of size cap around s (0 < cap <= 2) from words 0, 1 of
  * (i >> 1, t, r, HEIS+c) and accept iff Delta E = -(s' - s).h <= 0 or
  * u < exp(-beta Delta E), u from word 2.  Returns 1 if accepted. */
-static int heis_site_move(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r, uint32_t t, int c,
-                          int64_t i)
+static int heis_site_move_cap(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r, uint32_t t, int c,
+                              int64_t i, double cap)
 {
     int x[3];
     coords(dim, L, i, x);
@@ -449,13 +482,22 @@ static int heis_site_move(int dim, int L, double *s, double beta, uint64_t seed,
     uint32_t w[4];
     draw(seed, (uint32_t)(i >> 1), t, r, (uint32_t)(TAG_HEIS * 2 + c), w);
     double sp[3];
-    sphere_point(unit23(w[0]), unit23(w[1]), sp);
+    if (cap > 0.0)
+        cap_point(&s[3 * i], cap, unit23(w[0]), unit23(w[1]), sp);
+    else
+        sphere_point(unit23(w[0]), unit23(w[1]), sp);
     double dE = 0.0;
     for (int a = 0; a < 3; ++a) dE -= (sp[a] - s[3 * i + a]) * h[a];
     int accept = (dE <= 0.0) || (unit23(w[2]) < exp(-beta * dE));
     if (accept)
         for (int a = 0; a < 3; ++a) s[3 * i + a] = sp[a];
     return accept;
+}
+
+static int heis_site_move(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r, uint32_t t, int c,
+                          int64_t i)
+{
+    return heis_site_move_cap(dim, L, s, beta, seed, r, t, c, i, 0.0);
 }
 
 /* One half-sweep of colour c: the move above at every site of colour c.
@@ -509,11 +551,12 @@ EXPORT int64_t orc_heis_run(int dim, int L, double *s, double beta, uint64_t see
  * sweeps when palindromic != 0); a tile gets k hits, each a move at every
  * colour-0 site of the tile, then at every colour-1 site, the spins outside
  * the tile held fixed.  Hit j of sweep t draws as plain sweep t*k + j, so
- * T = L and k = 1 is orc_heis_sweep.  Spins are renormalised after sweep t
+ * T = L, k = 1 and cap = 0 is orc_heis_sweep.  cap > 0 takes the small-step
+ * proposal of heis_site_move_cap.  Spins are renormalised after sweep t
  * when renorm_every > 0 and (t + 1) is a multiple of it.  Returns the
  * number of accepted moves. */
 EXPORT int64_t orc_heis_dcb_run(int L, int T, int k, double *s, double beta, uint64_t seed, uint32_t r,
-                                uint32_t t0, int n, int palindromic, int renorm_every)
+                                uint32_t t0, int n, int palindromic, int renorm_every, double cap)
 {
     const int B = L / T;
     int64_t n_acc = 0;
@@ -533,7 +576,8 @@ EXPORT int64_t orc_heis_dcb_run(int L, int T, int k, double *s, double beta, uin
                                 for (int u = 0; u < T; ++u) {
                                     const int x = bx * T + u, y = by * T + v;
                                     if (((x + y) & 1) != c) continue;
-                                    n_acc += heis_site_move(2, L, s, beta, seed, r, th, c, (int64_t)y * L + x);
+                                    n_acc += heis_site_move_cap(2, L, s, beta, seed, r, th, c,
+                                                                (int64_t)y * L + x, cap);
                                 }
                             }
                         }

@@ -81,3 +81,66 @@ def test_high_temperature_tree_energy(T, k, pal):
         means.append(np.mean(series))
     m, err = np.mean(means), np.std(means, ddof=1) / math.sqrt(len(means))
     assert abs(m - X.heis_tree_energy(beta, 2)) < 4.5 * err + 1e-5
+
+
+@pytest.mark.parametrize("cap", [0.05, 0.6, 2.0])
+def test_small_step_proposals_fill_the_cap_uniformly(cap):
+    """beta = 0, one hit: every spin moves to a uniform point of the cap
+    1 - s.s' <= cap around its old direction (uniform in the cosine and the
+    azimuth), and stays a unit vector."""
+    L = 32
+    s0 = O.init_heis(2, L, SEED, 30)
+    s = s0.copy()
+    n = O.heis_dcb_run(L, 16, 1, s, 0.0, SEED, 30, 0, 1, renorm_every=0, cap=cap)
+    assert n == L * L
+    assert np.allclose(np.linalg.norm(s, axis=1), 1.0, atol=1e-14)
+    w = 1.0 - (s * s0).sum(axis=1)  # 1 - cos(angle)
+    assert w.min() >= -1e-14 and w.max() <= cap + 1e-12
+    counts = np.histogram(w / cap, bins=16, range=(0, 1))[0]
+    chi2 = ((counts - L * L / 16) ** 2 / (L * L / 16)).sum()
+    assert chi2 < 15 + 6 * math.sqrt(30)
+    # azimuth about the old direction: the component along any fixed
+    # perpendicular direction averages to zero
+    perp = np.cross(s0, np.array([0.3, -0.5, 0.8]))
+    perp /= np.linalg.norm(perp, axis=1, keepdims=True)
+    proj = (s * perp).sum(axis=1)
+    sd = math.sqrt((cap - cap * cap / 3) / 2 / (L * L))  # E[w (2 - w)] / 2 over w uniform in [0, cap]
+    assert abs(proj.mean()) < 5 * sd
+
+
+@pytest.mark.parametrize("cap", [0.3, 1.0])
+def test_small_step_high_temperature_tree_energy(cap):
+    """The small-step chain samples the same distribution: e = -2 L(beta) at
+    beta = 0.05."""
+    L, beta = 32, 0.05
+    means = []
+    for r in range(6):
+        s = O.init_heis(2, L, SEED, 40 + r)
+        series = []
+        for t in range(160):
+            O.heis_dcb_run(L, 16, 2, s, beta, SEED, 40 + r, t, 1, cap=cap)
+            if t >= 20:
+                series.append(O.heis_energy(2, L, s) / L ** 2)
+        means.append(np.mean(series))
+    m, err = np.mean(means), np.std(means, ddof=1) / math.sqrt(len(means))
+    assert abs(m - X.heis_tree_energy(beta, 2)) < 4.5 * err + 1e-5
+
+
+def test_small_step_low_temperature_matches_uniform_proposals():
+    """beta = 2 on 16^2: the long-run energy with small steps (cap 0.2) and
+    with uniform proposals agree within their errors."""
+    L, beta = 16, 2.0
+    res = {}
+    for cap in (0.0, 0.2):
+        means = []
+        for r in range(8):
+            s = O.init_heis(2, L, SEED, 60 + r)
+            series = []
+            for t in range(400):
+                O.heis_dcb_run(L, 8, 2, s, beta, SEED, 60 + r, t, 1, cap=cap)
+                if t >= 100 and t % 4 == 0:
+                    series.append(O.heis_energy(2, L, s) / L ** 2)
+            means.append(np.mean(series))
+        res[cap] = (np.mean(means), np.std(means, ddof=1) / math.sqrt(len(means)))
+    (m0, e0), (m1, e1) = res[0.0], res[0.2]
+    assert abs(m0 - m1) < 4.5 * math.hypot(e0, e1), res
