@@ -450,7 +450,7 @@ def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
     with accurate functions, float32 with hardware functions, float64):
     ps per attempted move, from a random start at beta = 1, and the mean and
     largest deviation of |s| from 1 after the run (no renormalisation falls
-    in the 5 sweeps; Fig. 12)."""
+    in the 5 sweeps; Fig. 12); also small-step proposals (cap 0.3)."""
     import torch
 
     seed = W.seed_for(91)
@@ -458,22 +458,25 @@ def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
     base = torch.empty(L * L * 3, dtype=torch.float32, device="cuda")
     S.spin_init(b, base)
     rows = []
-    for name, mode in (("float", S.HEIS_FLOAT), ("fast", S.HEIS_FAST), ("double", S.HEIS_DOUBLE)):
-        for tile in tiles:
-            if mode == S.HEIS_DOUBLE and tile > 32:
-                continue
-            spins = base.double() if mode == S.HEIS_DOUBLE else base.clone()
-            acc = torch.zeros(1, dtype=torch.int64, device="cuda")
-            S.heis_dcb_sweep(b, spins, [1.0], 0, 1, tile, hits, precision=mode)
-            ms = _timed(lambda: S.heis_dcb_sweep(b, spins, [1.0], 1, sweeps, tile, hits, precision=mode, accepts=acc))
-            flips = L * L * hits * sweeps
-            # deviation of |s| from 1 after 5 sweeps without renormalisation (Fig. 12)
-            dev = (spins.view(-1, 3).double().norm(dim=1) - 1.0).abs()
-            rows.append({"mode": name, "tile": tile, "ms": round(ms, 3), "ps_per_flip": round(ms * 1e9 / flips, 4),
-                         "acceptance": round(float(acc.item()) / flips, 4),
-                         "norm_dev_mean": float(f"{dev.mean().item():.3g}"),
-                         "norm_dev_max": float(f"{dev.max().item():.3g}")})
-            del spins
+    cases = [(name, mode, tile, 0.0) for name, mode in (("float", S.HEIS_FLOAT), ("fast", S.HEIS_FAST),
+                                                         ("double", S.HEIS_DOUBLE)) for tile in tiles
+             if not (mode == S.HEIS_DOUBLE and tile > 32)]
+    cases += [("fast", S.HEIS_FAST, tiles[0], 0.3), ("double", S.HEIS_DOUBLE, tiles[0], 0.3)]  # small steps
+    for name, mode, tile, cap in cases:
+        spins = base.double() if mode == S.HEIS_DOUBLE else base.clone()
+        acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+        S.heis_dcb_sweep(b, spins, [1.0], 0, 1, tile, hits, precision=mode, cap=cap)
+        ms = _timed(lambda: S.heis_dcb_sweep(b, spins, [1.0], 1, sweeps, tile, hits, precision=mode, cap=cap,
+                                             accepts=acc))
+        flips = L * L * hits * sweeps
+        # deviation of |s| from 1 after 5 sweeps without renormalisation (Fig. 12)
+        dev = (spins.view(-1, 3).double().norm(dim=1) - 1.0).abs()
+        rows.append({"mode": name, "tile": tile, "cap": cap, "ms": round(ms, 3),
+                     "ps_per_flip": round(ms * 1e9 / flips, 4),
+                     "acceptance": round(float(acc.item()) / flips, 4),
+                     "norm_dev_mean": float(f"{dev.mean().item():.3g}"),
+                     "norm_dev_max": float(f"{dev.max().item():.3g}")})
+        del spins
     torch.cuda.empty_cache()
     return {"workload": f"2D Heisenberg {L}x{L}, beta = 1, double checkerboard with T x T tiles and k = {hits} "
                         f"hits, {sweeps} sweeps after one warm-up sweep",

@@ -300,13 +300,20 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
  *             even or 1.
  *  hits:      >= 1; (sweep0 + n_sweeps) * hits must not exceed 2^32.
  *  precision: smc_heis_precision.
+ *  cap:       0: the proposal is a uniform re-orientation (independent of
+ *             the spin); 0 < cap <= 2: small steps, the proposal uniform on
+ *             the spherical cap 1 - a.s' <= cap around a = s/|s| (Sec. 4
+ *             suggests them for low temperatures): w = cap u0 is one minus
+ *             the cosine of the angle, 2 pi u1 the azimuth in the frame
+ *             e1 = (-a_y, a_x, 0)/|..| when |a_x| > |a_z|, else
+ *             (0, -a_z, a_y)/|..|, and e2 = a x e1.
  *  accepts:   DEVICE int64 [n_rep] or NULL: += the number of accepted moves.
- * SMC_EINVAL for a bad tile, hit count, precision or unaligned spins;
+ * SMC_EINVAL for a bad tile, hit count, precision, cap or unaligned spins;
  * SMC_EUNSUPPORTED for other models or 3D.
  */
 int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, uint64_t sweep0, int32_t n_sweeps,
-                       int32_t tile, int32_t hits, int32_t precision, int32_t palindromic, int64_t *accepts,
-                       void *stream);
+                       int32_t tile, int32_t hits, int32_t precision, int32_t palindromic, double cap,
+                       int64_t *accepts, void *stream);
 
 /*
  * Which kernel smc_dcb_sweep uses for this batch, tile and beta (HOST

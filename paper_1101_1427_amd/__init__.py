@@ -76,7 +76,7 @@ def lib():
                                     C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.smc_dcb_sweep.restype = C.c_int
         L.smc_heis_dcb_sweep.argtypes = [P(Desc), C.c_void_p, P(C.c_double), C.c_uint64, C.c_int32, C.c_int32,
-                                         C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+                                         C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p]
         L.smc_heis_dcb_sweep.restype = C.c_int
         L.smc_dcb_plan.argtypes = [P(Desc), P(C.c_double), C.c_int32, P(C.c_char_p)]
         L.smc_dcb_plan.restype = C.c_int
@@ -205,9 +205,10 @@ HEIS_FLOAT, HEIS_FAST, HEIS_DOUBLE = 0, 1, 2
 
 
 def heis_dcb_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, tile: int, hits: int,
-                   precision: int = HEIS_FAST, palindromic=False, accepts=None, stream=None):
+                   precision: int = HEIS_FAST, palindromic=False, cap: float = 0.0, accepts=None, stream=None):
     """n_sweeps double-checkerboard sweeps of a 2D Heisenberg batch (see
-    smc_heis_dcb_sweep); spins float32 [n_rep*N*3] (float64 for HEIS_DOUBLE)."""
+    smc_heis_dcb_sweep); spins float32 [n_rep*N*3] (float64 for HEIS_DOUBLE);
+    cap > 0 selects small-step proposals."""
     import torch
 
     want = torch.float64 if precision == HEIS_DOUBLE else torch.float32
@@ -216,8 +217,8 @@ def heis_dcb_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, tile: 
     d = _desc(batch, spins, None)
     b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (batch.n_rep,)))
     _check(lib().smc_heis_dcb_sweep(C.byref(d), _ptr(spins), b.ctypes.data_as(C.POINTER(C.c_double)), sweep0,
-                                    n_sweeps, tile, hits, precision, 1 if palindromic else 0, _ptr(accepts),
-                                    _stream(stream)), "smc_heis_dcb_sweep")
+                                    n_sweeps, tile, hits, precision, 1 if palindromic else 0, float(cap),
+                                    _ptr(accepts), _stream(stream)), "smc_heis_dcb_sweep")
 
 
 def dcb_plan(batch: Batch, beta, tile: int) -> str:

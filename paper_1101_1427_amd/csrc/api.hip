@@ -1154,8 +1154,8 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
 }
 
 int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, uint64_t sweep0, int32_t n_sweeps,
-                       int32_t tile, int32_t hits, int32_t precision, int32_t palindromic, int64_t *accepts,
-                       void *stream) {
+                       int32_t tile, int32_t hits, int32_t precision, int32_t palindromic, double cap,
+                       int64_t *accepts, void *stream) {
     g_last_error.clear();
     Plan plan;
     int rc = validate(desc, false, plan);
@@ -1170,6 +1170,7 @@ int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, ui
         return fail(SMC_EINVAL, "tile %d: need 16, 32 or (float modes) 64, dividing L = %d into an even number "
                                 "of tiles per row (or one)", tile, desc->L);
     if (hits < 1) return fail(SMC_EINVAL, "hits must be >= 1");
+    if (!(cap >= 0.0 && cap <= 2.0)) return fail(SMC_EINVAL, "cap must be in [0, 2]");
     if (!spins) return fail(SMC_EINVAL, "spins is NULL");
     if ((uintptr_t)spins & 15u) return fail(SMC_EINVAL, "spins must be 16-byte aligned");
     if (!beta) return fail(SMC_EINVAL, "beta is NULL");
@@ -1200,7 +1201,7 @@ int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, ui
         const uint64_t t = sweep0 + (uint64_t)m;
         const bool rev = palindromic && (t & 1u);
         for (int ci = 0; ci < 2; ++ci)
-            SMC_HIP(launch_heis_dcb2d(spins, bp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits, precision,
+            SMC_HIP(launch_heis_dcb2d(spins, bp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits, precision, cap,
                                       make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, s));
         if (desc->renorm_every > 0 && (t + 1) % (uint64_t)desc->renorm_every == 0)
             SMC_HIP(launch_heis_dcb_renorm(spins, n_spins, precision, s));

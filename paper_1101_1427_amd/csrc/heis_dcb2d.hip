@@ -11,7 +11,9 @@
 // gives the tile k hits (colour-0 sites, then colour-1 sites, the halo held
 // fixed) and writes it back in place.  Hit j of sweep t takes the plain
 // sweep's draws of sweep t*k + j: the move at in-colour site h uses words 0,
-// 1 (proposal) and 2 (acceptance) of (h, t*k + j, r, 2*HEIS + c).
+// 1 (proposal) and 2 (acceptance) of (h, t*k + j, r, 2*HEIS + c).  The
+// proposal is a uniform re-orientation, or with cap > 0 a uniform point of
+// the cap of that size around the current direction.
 //
 // A thread owns four consecutive sites of a tile row in registers for all k
 // hits; per half-hit it updates the two of the current colour, reading their
@@ -39,6 +41,12 @@ struct HeisArith<SMC_HEIS_FAST> {
         z = p.z;
     }
     __device__ static R boltzmann(R beta, R dE) { return heis_boltzmann(beta, dE); }
+    __device__ static R sq(R x) { return __builtin_amdgcn_sqrtf(x); }
+    __device__ static R dv(R a, R b) { return __fdividef(a, b); }
+    __device__ static void sincos_rev(R u, R &sn, R &cs) {
+        sn = __builtin_amdgcn_sinf(u);
+        cs = __builtin_amdgcn_cosf(u);
+    }
     __device__ static void unit(R &x, R &y, R &z) {
         const float3 u = heis_unit(x, y, z);
         x = u.x;
@@ -61,6 +69,9 @@ struct HeisArith<SMC_HEIS_FLOAT> {
         z = zz;
     }
     __device__ static R boltzmann(R beta, R dE) { return expf(-beta * dE); }
+    __device__ static R sq(R x) { return __fsqrt_rn(x); }
+    __device__ static R dv(R a, R b) { return __fdiv_rn(a, b); }
+    __device__ static void sincos_rev(R u, R &sn, R &cs) { sincospif(2.0f * u, &sn, &cs); }
     __device__ static void unit(R &x, R &y, R &z) {
         const float n = __fsqrt_rn(x * x + y * y + z * z);
         x = __fdiv_rn(x, n);
@@ -83,6 +94,9 @@ struct HeisArith<SMC_HEIS_DOUBLE> {
         z = zz;
     }
     __device__ static R boltzmann(R beta, R dE) { return exp(-beta * dE); }
+    __device__ static R sq(R x) { return sqrt(x); }
+    __device__ static R dv(R a, R b) { return a / b; }
+    __device__ static void sincos_rev(R u, R &sn, R &cs) { sincospi(2.0 * u, &sn, &cs); }
     __device__ static void unit(R &x, R &y, R &z) {
         const double n = sqrt(x * x + y * y + z * z);
         x /= n;
@@ -90,6 +104,37 @@ struct HeisArith<SMC_HEIS_DOUBLE> {
         z /= n;
     }
 };
+
+// Small-step proposal: s' uniform on the spherical cap {s' : 1 - a.s' <= cap}
+// around a = s / |s| (a symmetric proposal density).  w = cap u0 gives the
+// cosine 1 - w of the angle and the radius sqrt(w (2 - w)); the azimuth
+// 2 pi u1 is taken in the frame (e1, e2): e1 perpendicular to a in the x-y
+// plane when |a_x| > |a_z|, else in the y-z plane, and e2 = a x e1.
+template <class A, typename R>
+__device__ __forceinline__ void cap_proposal(R x, R y, R z, R cap, R u0, R u1, R &px, R &py, R &pz) {
+    const R n = A::sq(x * x + y * y + z * z);
+    const R ax = A::dv(x, n), ay = A::dv(y, n), az = A::dv(z, n);
+    R e1x, e1y, e1z;
+    if (fabs(ax) > fabs(az)) {
+        const R m = A::sq(ax * ax + ay * ay);
+        e1x = A::dv(-ay, m);
+        e1y = A::dv(ax, m);
+        e1z = R(0);
+    } else {
+        const R m = A::sq(ay * ay + az * az);
+        e1x = R(0);
+        e1y = A::dv(-az, m);
+        e1z = A::dv(ay, m);
+    }
+    const R e2x = ay * e1z - az * e1y, e2y = az * e1x - ax * e1z, e2z = ax * e1y - ay * e1x;
+    const R w = cap * u0;
+    const R zc = R(1) - w, rc = A::sq(w * (R(2) - w));
+    R sn, cs;
+    A::sincos_rev(u1, sn, cs);
+    px = zc * ax + rc * (cs * e1x + sn * e2x);
+    py = zc * ay + rc * (cs * e1y + sn * e2y);
+    pz = zc * az + rc * (cs * e1z + sn * e2z);
+}
 
 // One LDS cell: a spin and padding to 16 (float) or 32 (double) bytes.
 template <typename R>
@@ -108,6 +153,7 @@ struct HeisGeom {
 struct HeisDcbArgs {
     void *spins;         // float or double [n_rep][N][3], updated in place
     const void *beta;    // float or double [n_rep]
+    double cap;          // small-step cap (> 0 in the CAP kernels)
     int64_t *acc_slots;  // [n_rep][2 * tiles_per_colour] or nullptr
     Key key;
     uint32_t t;          // sweep index
@@ -115,7 +161,7 @@ struct HeisDcbArgs {
     int tile_colour, rev, tiles_per_colour;
 };
 
-template <int T, int MODE>
+template <int T, int MODE, bool CAP>
 __global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs a) {
     using A = HeisArith<MODE>;
     using R = typename A::R;
@@ -149,6 +195,7 @@ __global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs
     const int64_t N = (int64_t)L * L;
     R *S = (R *)a.spins + (int64_t)r * N * 3;
     const R beta = ((const R *)a.beta)[r];
+    const R cap = (R)a.cap;
 
     // own sites: columns xq .. xq + 3 of row y
     R sx[4], sy[4], sz[4];
@@ -208,7 +255,10 @@ __global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs
         const uint32_t h = hrow + (uint32_t)(m >> 1);
         const uint4 w = philox4x32_10(make_uint4(h, tj, (uint32_t)r, 2 * kTagHeis + (uint32_t)C), a.key);
         R px, py, pz;
-        A::propose(A::uni(w.x), A::uni(w.y), px, py, pz);
+        if constexpr (CAP)
+            cap_proposal<A, R>(sx[m], sy[m], sz[m], cap, A::uni(w.x), A::uni(w.y), px, py, pz);
+        else
+            A::propose(A::uni(w.x), A::uni(w.y), px, py, pz);
         const R dE = -((px - sx[m]) * hx + (py - sy[m]) * hy + (pz - sz[m]) * hz);
         if (dE <= R(0) || A::uni(w.z) < A::boltzmann(beta, dE)) {
             sx[m] = px;
@@ -298,7 +348,10 @@ __global__ __launch_bounds__(256) void k_heis_dcb_renorm(void *spins, int64_t n_
 template <int T, int MODE>
 hipError_t launch_t(const HeisDcbArgs &a, int n_rep, hipStream_t s) {
     const unsigned blocks = (unsigned)(n_rep * a.tiles_per_colour);
-    hipLaunchKernelGGL((k_heis_dcb2d<T, MODE>), dim3(blocks), dim3(HeisGeom<T>::THREADS), 0, s, a);
+    if (a.cap > 0.0)
+        hipLaunchKernelGGL((k_heis_dcb2d<T, MODE, true>), dim3(blocks), dim3(HeisGeom<T>::THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_heis_dcb2d<T, MODE, false>), dim3(blocks), dim3(HeisGeom<T>::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -324,13 +377,15 @@ bool heis_dcb2d_supported(int L, int T, int precision) {
 }
 
 hipError_t launch_heis_dcb2d(void *spins, const void *beta, int64_t *acc_slots, int n_rep, int L, int T, int k,
-                             int precision, Key key, uint32_t t, int tile_colour, bool rev, hipStream_t s) {
+                             int precision, double cap, Key key, uint32_t t, int tile_colour, bool rev,
+                             hipStream_t s) {
     if (!heis_dcb2d_supported(L, T, precision) || k < 1) return hipErrorInvalidValue;
     const int B = L / T;
     if (B == 1 && tile_colour == 1) return hipSuccess;  // one tile, of tile colour 0
     HeisDcbArgs a;
     a.spins = spins;
     a.beta = beta;
+    a.cap = cap;
     a.acc_slots = acc_slots;
     a.key = key;
     a.t = t;

@@ -157,7 +157,8 @@ hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int 
 // per precision.
 bool heis_dcb2d_supported(int L, int T, int precision);
 hipError_t launch_heis_dcb2d(void *spins, const void *beta, int64_t *acc_slots, int n_rep, int L, int T, int k,
-                             int precision, Key key, uint32_t t, int tile_colour, bool rev, hipStream_t s);
+                             int precision, double cap, Key key, uint32_t t, int tile_colour, bool rev,
+                             hipStream_t s);
 hipError_t launch_heis_dcb_renorm(void *spins, int64_t n_spins, int precision, hipStream_t s);
 
 // Tempering on the 2D colour-split sweep (pt_split2d.hip): per-replica

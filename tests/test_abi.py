@@ -183,12 +183,14 @@ def test_heis_dcb_arguments_are_validated():
     L = S.lib()
     beta = (C.c_double * 2)(0.5, 0.5)
     d = _desc(model=S.HEISENBERG, L=64, n_rep=2, spins_len=2 * 64 * 64 * 3)
-    call = lambda tile, hits, prec, dd=d, sp=FAKE: L.smc_heis_dcb_sweep(C.byref(dd), sp, beta, 0, 1, tile, hits,
-                                                                         prec, 0, None, None)
+    call = lambda tile, hits, prec, dd=d, sp=FAKE, cap=0.0: L.smc_heis_dcb_sweep(C.byref(dd), sp, beta, 0, 1, tile,
+                                                                                  hits, prec, 0, cap, None, None)
     assert call(48, 1, S.HEIS_FAST) == S.EINVAL
     assert call(64, 1, S.HEIS_DOUBLE) == S.EINVAL and b"float modes" in L.smc_last_error()
     assert call(32, 0, S.HEIS_FLOAT) == S.EINVAL
     assert call(32, 1, 3) == S.EINVAL and b"precision" in L.smc_last_error()
+    assert call(32, 1, S.HEIS_FAST, cap=2.5) == S.EINVAL and b"cap" in L.smc_last_error()
+    assert call(32, 1, S.HEIS_FAST, cap=-0.1) == S.EINVAL
     assert call(32, 1, S.HEIS_FAST, sp=C.c_void_p(FAKE.value + 4)) == S.EINVAL
     assert b"aligned" in L.smc_last_error()
     di = _desc(L=64, n_rep=2, spins_len=2 * 64 * 64)

@@ -40,14 +40,14 @@ def _starts(L, n_rep, seed, mode):
     return spins, [np.ascontiguousarray(x) for x in ref]
 
 
-def _run_both(mode, L, T, k, pal, betas, seed, t0, n, renorm=16):
+def _run_both(mode, L, T, k, pal, betas, seed, t0, n, renorm=16, cap=0.0):
     n_rep = len(betas)
     b = S.Batch(S.HEISENBERG, 2, L, n_rep, seed, renorm_every=renorm)
     spins, ref = _starts(L, n_rep, seed, mode)
     acc = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
-    S.heis_dcb_sweep(b, spins, betas, t0, n, T, k, precision=mode, palindromic=pal, accepts=acc)
-    ref_acc = [O.heis_dcb_run(L, T, k, ref[r], betas[r], seed, r, t0, n, palindromic=pal, renorm_every=renorm)
-               for r in range(n_rep)]
+    S.heis_dcb_sweep(b, spins, betas, t0, n, T, k, precision=mode, palindromic=pal, cap=cap, accepts=acc)
+    ref_acc = [O.heis_dcb_run(L, T, k, ref[r], betas[r], seed, r, t0, n, palindromic=pal, renorm_every=renorm,
+                              cap=cap) for r in range(n_rep)]
     got = _host(spins).astype(np.float64).reshape(n_rep, L * L, 3)
     return got, np.stack(ref), _host(acc), np.array(ref_acc)
 
@@ -59,11 +59,21 @@ def test_double_matches_oracle(L, T, k, pal):
     assert np.array_equal(acc, ref_acc)
 
 
+@pytest.mark.parametrize("cap", [0.25, 2.0])
+def test_double_small_steps_match_oracle(cap):
+    """Small-step proposals (cap around the current direction) in float64."""
+    got, ref, acc, ref_acc = _run_both(S.HEIS_DOUBLE, 64, 16, 3, False, [0.4, 1.5, 3.0], W.seed_for(87), 14, 3,
+                                       cap=cap)
+    assert np.abs(got - ref).max() < 1e-12
+    assert np.array_equal(acc, ref_acc)
+
+
 @pytest.mark.parametrize("mode", ["float", "fast"])
-@pytest.mark.parametrize("L,T,k,pal", [(64, 16, 2, False), (128, 64, 2, True), (64, 32, 3, False)])
-def test_float_modes_match_oracle_sitewise(mode, L, T, k, pal):
+@pytest.mark.parametrize("L,T,k,pal,cap", [(64, 16, 2, False, 0.0), (128, 64, 2, True, 0.0), (64, 32, 3, False, 0.0),
+                                           (64, 16, 2, False, 0.3), (64, 32, 2, True, 1.5)])
+def test_float_modes_match_oracle_sitewise(mode, L, T, k, pal, cap):
     betas = [0.5, 1.5, 3.0]
-    got, ref, acc, ref_acc = _run_both(MODES[mode], L, T, k, pal, betas, W.seed_for(83), 7, 1)
+    got, ref, acc, ref_acc = _run_both(MODES[mode], L, T, k, pal, betas, W.seed_for(83), 7, 1, cap=cap)
     dev = np.abs(got - ref).max(axis=2)
     mismatches = int((dev > 1e-5).sum())
     # a decision differs only where u is within a few float32 ulps of exp(-beta dE)
@@ -91,14 +101,14 @@ def test_fast_single_tile_single_hit_is_the_plain_sweep():
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
-def _energy_series(mode, L, T, k, beta, n_rep, seed, sweeps, every=2):
+def _energy_series(mode, L, T, k, beta, n_rep, seed, sweeps, every=2, cap=0.0):
     b = S.Batch(S.HEISENBERG, 2, L, n_rep, seed, renorm_every=16)
     work, _ = _starts(L, n_rep, seed, mode)
     E = torch.zeros(n_rep, dtype=torch.float64, device=DEV)
     out = []
     t = 0
     while t < sweeps:
-        S.heis_dcb_sweep(b, work, [beta] * n_rep, t, every, T, k, precision=mode)
+        S.heis_dcb_sweep(b, work, [beta] * n_rep, t, every, T, k, precision=mode, cap=cap)
         t += every
         # the energy of float64 spins is measured on their float32 rounding
         S.measure_energy_magnetisation(b, work if mode != S.HEIS_DOUBLE else work.float(), E)
@@ -115,9 +125,11 @@ def test_high_temperature_tree_energy(mode):
     assert abs(m - X.heis_tree_energy(0.05, 2)) < 4.5 * err + 1e-5
 
 
-def test_modes_agree_with_the_oracle_at_low_temperature():
-    """beta = 1.5 on 32^2 with 16 x 16 tiles and 4 hits: the long-run energy
-    of every GPU mode within the combined errors of the oracle's."""
+@pytest.mark.parametrize("cap", [0.0, 0.3])
+def test_modes_agree_with_the_oracle_at_low_temperature(cap):
+    """beta = 1.5 on 32^2 with 16 x 16 tiles and 4 hits, uniform and
+    small-step proposals: the long-run energy of every GPU mode within the
+    combined errors of the oracle's."""
     L, T, k, beta, seed = 32, 16, 4, 1.5, W.seed_for(86)
     burn, sweeps = 50, 450
     ref = []
@@ -125,13 +137,13 @@ def test_modes_agree_with_the_oracle_at_low_temperature():
         s = O.init_heis(2, L, seed, 100 + r)
         series = []
         for t in range(sweeps):
-            O.heis_dcb_run(L, T, k, s, beta, seed, 100 + r, t, 1)
+            O.heis_dcb_run(L, T, k, s, beta, seed, 100 + r, t, 1, cap=cap)
             if t >= burn and t % 2 == 0:
                 series.append(O.heis_energy(2, L, s) / (L * L))
         ref.append(np.mean(series))
     ref_m, ref_err = np.mean(ref), np.std(ref, ddof=1) / np.sqrt(len(ref))
     for mode in MODES.values():
-        e = _energy_series(mode, L, T, k, beta, 64, seed, sweeps)[burn // 2:]
+        e = _energy_series(mode, L, T, k, beta, 64, seed, sweeps, cap=cap)[burn // 2:]
         per_rep = e.mean(axis=0)
         m, err = per_rep.mean(), per_rep.std(ddof=1) / np.sqrt(len(per_rep))
         assert abs(m - ref_m) < 4.5 * np.hypot(err, ref_err), (mode, m, ref_m, err, ref_err)
