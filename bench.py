@@ -483,6 +483,78 @@ def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
             "kernel": "k_heis_dcb2d", "by_mode": rows}
 
 
+TABLE1_EXACT = {"e": 1.106079207, "C": 0.8616983594}  # Table 1, row "exact" (L = 1024, beta = 0.4)
+
+
+def _e_and_c(E, N, beta):
+    """e = -E/N and C_V = beta^2 N var(e) per replica (rows of E), their
+    means over replicas and the standard errors from the replica spread."""
+    import numpy as np
+
+    e = -np.asarray(E, np.float64) / N
+    e_r = e.mean(axis=1)
+    c_r = beta * beta * N * e.var(axis=1)
+    R = e.shape[0]
+    return (float(e_r.mean()), float(e_r.std(ddof=1) / np.sqrt(R)), float(c_r.mean()),
+            float(c_r.std(ddof=1) / np.sqrt(R)))
+
+
+def table1(S, W, updates=10_000_000, n_rep=64, L=1024, beta=0.4, therm=2000, every=10):
+    """Table 1 with the Philox streams: internal energy e and specific heat
+    C_V of the 1024^2 Ising model at beta = 0.4 from `updates` attempts per
+    spin in total (n_rep independent replicas), for the plain checkerboard
+    sweep (energy every `every` sweeps) and the double checkerboard with
+    64 x 64 tiles and one hit (energy after every sweep); Delta_rel =
+    (estimate - exact) / standard error against the printed exact values."""
+    import numpy as np
+    import torch
+
+    N = L * L
+    per_rep = updates // n_rep
+    rows = []
+    for method in ("checkerboard", "double checkerboard 64x64, k = 1"):
+        b = S.Batch(S.ISING, 2, L, n_rep, W.seed_for(97))
+        spins = torch.empty(n_rep * N, dtype=torch.int8, device="cuda")
+        S.spin_init(b, spins)
+        S.metropolis_sweep(b, spins, [beta] * n_rep, 0, therm)
+        E0 = torch.empty(n_rep, dtype=torch.float64, device="cuda")
+        S.measure_energy_magnetisation(b, spins, E0)
+        t0 = time.perf_counter()
+        if method == "checkerboard":
+            calls = per_rep // every
+            dE = torch.zeros(n_rep, dtype=torch.int64, device="cuda")
+            trace = torch.empty(calls, n_rep, dtype=torch.int64, device="cuda")
+            for i in range(calls):
+                S.metropolis_sweep(b, spins, [beta] * n_rep, therm + i * every, every, dE_accum=dE)
+                trace[i].copy_(dE)
+        else:
+            chunk = 4096
+            n = per_rep
+            trace = torch.empty(n, n_rep, dtype=torch.int64, device="cuda")
+            done = 0
+            base = torch.zeros(n_rep, dtype=torch.int64, device="cuda")
+            while done < n:
+                m = min(chunk, n - done)
+                S.dcb_sweep(b, spins, [beta] * n_rep, therm + done, m, 64, 1, dE_trace=trace[done:done + m])
+                trace[done:done + m] += base
+                base = trace[done + m - 1].clone()
+                done += m
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        E = (E0.cpu().numpy()[None, :] + trace.cpu().numpy()).T  # [replica, time]
+        e, de, c, dc = _e_and_c(E, N, beta)
+        rows.append({"method": method, "measurements_per_replica": int(E.shape[1]),
+                     "e": round(e, 9), "e_err": float(f"{de:.2g}"),
+                     "e_delta_rel": round((e - TABLE1_EXACT["e"]) / de, 2),
+                     "C": round(c, 7), "C_err": float(f"{dc:.2g}"),
+                     "C_delta_rel": round((c - TABLE1_EXACT["C"]) / dc, 2), "seconds": round(secs, 2)})
+        del spins, trace
+        torch.cuda.empty_cache()
+    return {"workload": f"2D Ising {L}x{L}, beta = {beta}, {n_rep} replicas, {updates:.0e} attempts per spin in "
+                        f"total after {therm} sweeps of equilibration (Table 1 with Philox4x32-10)",
+            "exact": TABLE1_EXACT, "rows": rows}
+
+
 def tau_int(series, c=6.0):
     """Integrated autocorrelation time of equilibrium series (rows =
     independent replicas, columns = measurement times), in units of the
@@ -713,6 +785,8 @@ def main():
                     help="only the 2D Heisenberg double checkerboard (L = 4096, k = 100, three modes)")
     ap.add_argument("--pt-ising-only", action="store_true",
                     help="only the 2D Ising tempering benchmark of 20 replicas (L = 64 .. 2048)")
+    ap.add_argument("--table1-only", action="store_true",
+                    help="only Table 1 with the Philox streams (1024^2, beta = 0.4, 1e7 attempts per spin)")
     ap.add_argument("--tau-only", action="store_true",
                     help="only the double-checkerboard autocorrelation study (128^2, 16x16 tiles)")
     ap.add_argument("--tau-updates", type=int, default=1 << 15, help="attempts per site per (beta, k) series")
@@ -768,6 +842,9 @@ def main():
         return
     if args.pt_ising_only:
         print(json.dumps({"ising2d_paper": tempering_ising2d(S, W)}))
+        return
+    if args.table1_only:
+        print(json.dumps({"table1": table1(S, W)}))
         return
     if args.tau_only:
         print(json.dumps({"tau_dcb": tau_dcb(S, W, n_rep=args.tau_replicas, updates=args.tau_updates)}))
