@@ -292,6 +292,14 @@ def _pt_batch(S, model, dim, L, n_chains, n_temps, seed, rps=1, inst=None):
     return b, spins, coup, E, sot
 
 
+def _section(name, fn):
+    """Run one measurement section and report its wall time on stderr."""
+    t0 = time.perf_counter()
+    res = fn()
+    print(f"[bench] {name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return res
+
+
 def tempering_ising2d(S, W, sizes=(64, 128, 256, 1024, 2048), n_temps=20, every=(100, 10), flips=2e9):
     """The paper's tempering benchmark (Sec. 6): one chain of 20 replicas of
     the 2D Ising model at inverse temperatures equally spaced in
@@ -783,6 +791,10 @@ def main():
     ap.add_argument("--heis-dcb-sweeps", type=int, default=4)
     ap.add_argument("--heis-dcb-only", action="store_true",
                     help="only the 2D Heisenberg double checkerboard (L = 4096, k = 100, three modes)")
+    ap.add_argument("--paper-pt-sizes", default="64,128,256,1024,2048",
+                    help="lattice edges of the 20-replica 2D Ising tempering section")
+    ap.add_argument("--paper-pt-flips", type=float, default=2e9,
+                    help="attempted flips per size and exchange interval in that section")
     ap.add_argument("--pt-ising-only", action="store_true",
                     help="only the 2D Ising tempering benchmark of 20 replicas (L = 64 .. 2048)")
     ap.add_argument("--table1-only", action="store_true",
@@ -841,7 +853,8 @@ def main():
         print(json.dumps({"heis_dcb2d": heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)}))
         return
     if args.pt_ising_only:
-        print(json.dumps({"ising2d_paper": tempering_ising2d(S, W)}))
+        sizes = tuple(int(x) for x in args.paper_pt_sizes.split(","))
+        print(json.dumps({"ising2d_paper": tempering_ising2d(S, W, sizes=sizes, flips=args.paper_pt_flips)}))
         return
     if args.table1_only:
         print(json.dumps({"table1": table1(S, W)}))
@@ -924,13 +937,16 @@ def main():
         "wall_s": round(wall, 4),
     }
     if not args.no_tempering:
-        out["heisenberg"] = heisenberg3d(S, W, args.heis_sweeps)
-        out["tempering"] = {"ea3d_L16": tempering_ea3d(S, W, args.pt3d_steps),
-                            "ea2d_uneven": tempering_ea2d_uneven(S, W, args.uneven_steps),
-                            "ising2d_paper": tempering_ising2d(S, W)}
-        out["msc_ea2d"] = msc_ea2d(S, W, args.msc_sweeps)
-        out["dcb2d"] = dcb2d(S, W, args.dcb_sweeps)
-        out["heis_dcb2d"] = heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)
+        sizes = tuple(int(x) for x in args.paper_pt_sizes.split(","))
+        out["heisenberg"] = _section("heisenberg", lambda: heisenberg3d(S, W, args.heis_sweeps))
+        out["tempering"] = {
+            "ea3d_L16": _section("tempering.ea3d_L16", lambda: tempering_ea3d(S, W, args.pt3d_steps)),
+            "ea2d_uneven": _section("tempering.ea2d_uneven", lambda: tempering_ea2d_uneven(S, W, args.uneven_steps)),
+            "ising2d_paper": _section("tempering.ising2d_paper",
+                                      lambda: tempering_ising2d(S, W, sizes=sizes, flips=args.paper_pt_flips))}
+        out["msc_ea2d"] = _section("msc_ea2d", lambda: msc_ea2d(S, W, args.msc_sweeps))
+        out["dcb2d"] = _section("dcb2d", lambda: dcb2d(S, W, args.dcb_sweeps))
+        out["heis_dcb2d"] = _section("heis_dcb2d", lambda: heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg)
         out["cpu_baseline"] = cb
