@@ -145,7 +145,7 @@ def valu_summary(db: str, command: str):
              "# instruction per CU per cycle (four SIMD16 units, four cycles each)",
              f"{'kernel':28s} {'dispatches':>10s} {'VALU_insts':>14s} {'busy_cycles':>12s} {'util':>6s}"]
     for k in ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_tiled", "k_heis3d_half",
-              "k_half_sweep_generic", "k_msc2d", "k_dcb2d_packed", "k_dcb2d", "k_philox_bench", "k_to_split", "k_from_split"):
+              "k_half_sweep_generic", "k_msc2d", "k_dcb2d_packed", "k_dcb2d", "k_heis_dcb2d", "k_philox_bench", "k_to_split", "k_from_split"):
         if k not in acc or "SQ_INSTS_VALU" not in acc[k] or "GRBM_GUI_ACTIVE" not in acc[k]:
             continue
         v = acc[k]["SQ_INSTS_VALU"]
