@@ -379,10 +379,10 @@ def tempering_ea3d(S, W, steps, per_inst_chains=16, per_inst_steps=50, per_step_
 
 def msc_ea2d(S, W, sweeps, L=16, sizes=(14, 16, 18, 20), single_spin_sweeps=20):
     """Asynchronous multi-spin coding of the 2D +-J spin glass (Sec. 5,
-    Fig. 14 shape): 16 x 16 lattices, replicas in groups of 32 sharing their
-    draws, at T = 1; ps per attempted flip against the number of replicas,
-    and the same batch swept one replica per lane (generic kernels,
-    per-replica draws) for comparison."""
+    Fig. 14 shape): 16 x 16 lattices, replicas in groups of 32 (and 64)
+    sharing their draws, at T = 1; ps per attempted flip against the number
+    of replicas, and the same batch swept one replica per lane (generic
+    kernels, per-replica draws) for comparison."""
     import torch
 
     seed = W.seed_for(90)
@@ -403,8 +403,16 @@ def msc_ea2d(S, W, sweeps, L=16, sizes=(14, 16, 18, 20), single_spin_sweeps=20):
         flips = n_rep * L * L * n
         row = {"replicas": n_rep, "sweeps": n, "ms": round(ms, 3), "ps_per_flip": round(ms * 1e9 / flips, 5),
                "kernel_ps_per_flip": round(kernel_ms * 1e9 / flips, 5)}
+        # 64 replicas per draw (the paper's w = 64): two words per thread, one draw
+        S.kernel_timing_read()
+        S.kernel_timing_enable(True)
+        ms64 = _timed(lambda: S.msc_sweep(b, spins, [1.0], 5 + n, n, couplings=coup, word_bits=64))
+        kernel_ms64, _ = S.kernel_timing_read()
+        S.kernel_timing_enable(False)
+        row["w64_ps_per_flip"] = round(ms64 * 1e9 / flips, 5)
+        row["w64_kernel_ps_per_flip"] = round(kernel_ms64 * 1e9 / flips, 5)
         if lg == sizes[-1]:
-            t = _timed(lambda: S.metropolis_sweep(b, spins, [1.0], 5 + n, single_spin_sweeps, couplings=coup))
+            t = _timed(lambda: S.metropolis_sweep(b, spins, [1.0], 5 + 2 * n, single_spin_sweeps, couplings=coup))
             row["single_spin_generic_ps_per_flip"] = round(t * 1e9 / (n_rep * L * L * single_spin_sweeps), 4)
             row["speedup_vs_single_spin"] = round(row["single_spin_generic_ps_per_flip"] / row["ps_per_flip"], 1)
         rows.append(row)

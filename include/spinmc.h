@@ -221,39 +221,44 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
 /*
  * Asynchronous multi-spin coding (Sec. 5): the same sweeps as
  * smc_metropolis_sweep for a uniform Ising or EA batch whose replicas come
- * in groups of 32 (replicas 32g .. 32g+31 form group g) that share their
- * Metropolis random numbers: the draws of every site of replica r are made
- * with the group index r / 32 in the place of the replica index (counters
- * (h/8, t, r/32, 6 + c) and (h, t, r/32, 8 + c)), as the paper uses one
- * random number per site for all replicas coded in one word.  Each replica
- * keeps its own spins and couplings (EA: rep_per_sample must be 1).
+ * in groups of w = word_bits (32 or 64; replicas wg .. wg+w-1 form group g)
+ * that share their Metropolis random numbers: the draws of every site of
+ * replica r are made with the group index r / w in the place of the
+ * replica index (counters (h/8, t, r/w, 6 + c) and (h, t, r/w, 8 + c)), as
+ * the paper uses one random number per site for all replicas coded in one
+ * w-bit word.  Each replica keeps its own spins and couplings (EA:
+ * rep_per_sample must be 1).
  *  desc:     uniform batch (L > 0), model SMC_ISING or SMC_EA, n_rep a
- *            multiple of 32.
+ *            multiple of w.
  *  spins, couplings, sweep0, n_sweeps, dE_accum, stream: as for
  *            smc_metropolis_sweep (dE_accum: DEVICE int64 [n_rep], += the
  *            energy change of each replica).
- *  beta:     HOST [n_rep]; equal within each group of 32, else SMC_EINVAL.
+ *  beta:     HOST [n_rep]; equal within each group of w, else SMC_EINVAL.
+ *  word_bits: 32 or 64, else SMC_EINVAL.
  * 2D batches of edge 16, 32 or 64 (spins and couplings 4-byte aligned) run
- * with 32 replicas packed per 32-bit word, every sweep of the call in one
+ * with 32 replicas packed per 32-bit word (w = 64: a thread updates the two
+ * words of a group with one draw), every sweep of the call in one
  * launch, the lattices held on chip
  * (SPINMC_MSC2D=0 sends them to the generic kernels); other shapes take the
  * generic kernels.  Results are identical either way.  SMC_EUNSUPPORTED for
  * the Heisenberg model.
  */
 int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
-                  int32_t n_sweeps, int64_t *dE_accum, void *stream);
+                  int32_t n_sweeps, int32_t word_bits, int64_t *dE_accum, void *stream);
 
 /*
  * How smc_msc_sweep will execute: the number of sweep-kernel launches for a
  * call of n_sweeps sweeps and the sweep kernel's name (a static string),
- * for aligned buffers.  The same argument checks as smc_msc_sweep on desc;
- * no device work.
+ * for aligned buffers.  The same argument checks as smc_msc_sweep on desc
+ * and word_bits; no device work.
  */
-int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, const char **kernel_name);
+int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t word_bits, int32_t *launches,
+                 const char **kernel_name);
 
 /*
- * Double checkerboard sweeps with multi-hit updates (Sec. 3.2, Sec. 3.4): a different Markov chain from smc_metropolis_sweep, whose
- * order depends on the tiling.  The 2D lattice is cut into tile x tile
+ * Double checkerboard sweeps with multi-hit updates (Sec. 3.2, Sec. 3.4): a
+ * different Markov chain from smc_metropolis_sweep, whose order depends on
+ * the tiling.  The 2D lattice is cut into tile x tile
  * tiles, B = L / tile per direction; tile (bx, by) has tile colour
  * (bx + by) & 1.  Sweep t treats every tile of tile colour 0, then every
  * tile of colour 1; each tile gets `hits` hits, a hit being a Metropolis

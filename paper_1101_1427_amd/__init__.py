@@ -68,9 +68,9 @@ def lib():
         L.smc_kernel_timing_read.argtypes = [P(C.c_double), P(C.c_int64)]
         L.smc_kernel_timing_read.restype = C.c_int
         L.smc_msc_sweep.argtypes = [P(Desc), C.c_void_p, C.c_void_p, P(C.c_double), C.c_uint64, C.c_int32,
-                                    C.c_void_p, C.c_void_p]
+                                    C.c_int32, C.c_void_p, C.c_void_p]
         L.smc_msc_sweep.restype = C.c_int
-        L.smc_msc_plan.argtypes = [P(Desc), C.c_int32, P(C.c_int32), P(C.c_char_p)]
+        L.smc_msc_plan.argtypes = [P(Desc), C.c_int32, C.c_int32, P(C.c_int32), P(C.c_char_p)]
         L.smc_msc_plan.restype = C.c_int
         L.smc_dcb_sweep.argtypes = [P(Desc), C.c_void_p, C.c_void_p, P(C.c_double), C.c_uint64, C.c_int32,
                                     C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -171,14 +171,15 @@ def metropolis_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, coup
                                       _ptr(dE_accum), _stream(stream)), "smc_metropolis_sweep")
 
 
-def msc_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, couplings=None, dE_accum=None, stream=None):
+def msc_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, couplings=None, dE_accum=None,
+              word_bits: int = 32, stream=None):
     """n_sweeps sweeps with asynchronous multi-spin coding: replicas in groups of
-    32 share their random numbers (see smc_msc_sweep); beta is a host sequence
-    [n_rep], equal within each group."""
+    word_bits (32 or 64) share their random numbers (see smc_msc_sweep); beta is
+    a host sequence [n_rep], equal within each group."""
     d = _desc(batch, spins, couplings)
     b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (batch.n_rep,)))
     _check(lib().smc_msc_sweep(C.byref(d), _ptr(spins), _ptr(couplings), b.ctypes.data_as(C.POINTER(C.c_double)),
-                               sweep0, n_sweeps, _ptr(dE_accum), _stream(stream)), "smc_msc_sweep")
+                               sweep0, n_sweeps, word_bits, _ptr(dE_accum), _stream(stream)), "smc_msc_sweep")
 
 
 def dcb_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, tile: int, hits: int, palindromic=False,
@@ -231,12 +232,12 @@ def dcb_plan(batch: Batch, beta, tile: int) -> str:
     return name.value.decode()
 
 
-def msc_plan(batch: Batch, n_sweeps: int):
+def msc_plan(batch: Batch, n_sweeps: int, word_bits: int = 32):
     """(sweep-kernel launches, kernel name) that smc_msc_sweep uses for n_sweeps sweeps."""
     d = batch.desc(batch.spins_shape()[0], batch.coup_len())
     n = C.c_int32(0)
     name = C.c_char_p()
-    _check(lib().smc_msc_plan(C.byref(d), n_sweeps, C.byref(n), C.byref(name)), "smc_msc_plan")
+    _check(lib().smc_msc_plan(C.byref(d), n_sweeps, word_bits, C.byref(n), C.byref(name)), "smc_msc_plan")
     return int(n.value), name.value.decode()
 
 

@@ -853,11 +853,13 @@ int smc_spin_init(const smc_desc *desc, void *spins, int8_t *couplings, void *st
 
 // ------------------------------------- asynchronous multi-spin coding ----
 // Replicas 32g .. 32g+31 form group g and share its Metropolis draws.
-int msc_check(const smc_desc *d) {
+int msc_check(const smc_desc *d, int word_bits) {
     if (d->model != SMC_ISING && d->model != SMC_EA)
         return fail(SMC_EUNSUPPORTED, "multi-spin coding is provided for the Ising and EA models");
+    if (word_bits != 32 && word_bits != 64) return fail(SMC_EINVAL, "word_bits must be 32 or 64 (got %d)", word_bits);
     if (d->L <= 0) return fail(SMC_EINVAL, "multi-spin coding needs a uniform batch (L > 0)");
-    if (d->n_rep % 32 != 0) return fail(SMC_EINVAL, "n_rep (%d) must be a multiple of 32", d->n_rep);
+    if (d->n_rep % word_bits != 0)
+        return fail(SMC_EINVAL, "n_rep (%d) must be a multiple of %d", d->n_rep, word_bits);
     if (d->model == SMC_EA && d->rep_per_sample != 1)
         return fail(SMC_EINVAL, "multi-spin coding needs one coupling sample per replica (rep_per_sample = 1)");
     return SMC_OK;
@@ -983,12 +985,12 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
 }
 
 int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
-                  int32_t n_sweeps, int64_t *dE_accum, void *stream) {
+                  int32_t n_sweeps, int32_t word_bits, int64_t *dE_accum, void *stream) {
     g_last_error.clear();
     Plan plan;
     int rc = validate(desc, true, plan);
     if (rc) return rc;
-    if ((rc = msc_check(desc))) return rc;
+    if ((rc = msc_check(desc, word_bits))) return rc;
     if (!spins) return fail(SMC_EINVAL, "spins is NULL");
     if (!beta) return fail(SMC_EINVAL, "beta is NULL");
     if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
@@ -996,8 +998,8 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     if (sweep0 + (uint64_t)n_sweeps > (1ull << 32)) return fail(SMC_EINVAL, "sweep index exceeds 32 bits");
     for (int r = 0; r < desc->n_rep; ++r) {
         if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
-        if (beta[r] != beta[r - r % 32])
-            return fail(SMC_EINVAL, "beta[%d] differs from the rest of its group of 32", r);
+        if (beta[r] != beta[r - r % word_bits])
+            return fail(SMC_EINVAL, "beta[%d] differs from the rest of its group of %d", r, word_bits);
     }
     if (n_sweeps == 0) return SMC_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -1028,7 +1030,7 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
         SMC_HIP(launch_msc_gauge2d((uint32_t *)sp, (uint32_t *)cp, (uint32_t *)gp, desc->L, G, s));
         SweepTimer timer(s, 1);  // all sweeps in one launch
         SMC_HIP(launch_msc2d((uint32_t *)sp, (const uint32_t *)cp, (const ThrRow *)tp, G, desc->L,
-                             make_key(desc->seed), (uint32_t)sweep0, n_sweeps, s));
+                             make_key(desc->seed), (uint32_t)sweep0, n_sweeps, word_bits / 32, s));
         timer.finish();
         SMC_HIP(launch_msc_unpack((const uint32_t *)sp, (const uint32_t *)gp, (int8_t *)spins, N, G, s));
         if (dE_accum) {
@@ -1053,7 +1055,7 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     a.dE = dE_accum;
     a.max_L = plan.max_L;
     a.row_of_rep = nullptr;
-    a.rng_shift = 5;
+    a.rng_shift = word_bits == 64 ? 6 : 5;  // the draw group r / word_bits
     SweepTimer timer(s, 2 * (int64_t)n_sweeps);
     for (int32_t k = 0; k < n_sweeps; ++k) {
         a.t = (uint32_t)(sweep0 + (uint64_t)k);
@@ -1211,13 +1213,14 @@ int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, ui
     return SMC_OK;
 }
 
-int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t *launches, const char **kernel_name) {
+int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t word_bits, int32_t *launches,
+                 const char **kernel_name) {
     g_last_error.clear();
     if (!launches || !kernel_name) return fail(SMC_EINVAL, "output pointers are required");
     Plan plan;
     int rc = validate(desc, false, plan);
     if (rc) return rc;
-    if ((rc = msc_check(desc))) return rc;
+    if ((rc = msc_check(desc, word_bits))) return rc;
     if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
     if (use_msc2d(desc, nullptr, nullptr)) {
         *kernel_name = "k_msc2d";

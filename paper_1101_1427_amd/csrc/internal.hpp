@@ -133,8 +133,9 @@ hipError_t launch_msc_unpack(const uint32_t *packed, const uint32_t *gauge, int8
 // closing bond); gauge [G][L*L] receives the transformation for unpacking.
 hipError_t launch_msc_gauge2d(uint32_t *spins, uint32_t *coup, uint32_t *gauge, int L, int n_groups, hipStream_t s);
 hipError_t launch_msc_energy_diff(const double *E0, const double *E1, int64_t *dE, int n, hipStream_t s);
+// words_per_draw: 1 (32 replicas share a draw) or 2 (64: words 2h, 2h + 1).
 hipError_t launch_msc2d(uint32_t *spins, const uint32_t *coup, const ThrRow *thr, int n_groups, int L, Key key,
-                        uint32_t t0, int n_sweeps, hipStream_t s);
+                        uint32_t t0, int n_sweeps, int words_per_draw, hipStream_t s);
 
 // Double checkerboard with multi-hit (2D Ising / EA, T x T tiles, T a
 // multiple of 16 in [16, 128], L / T even or 1): one launch per tile colour.

@@ -1,10 +1,11 @@
 // Asynchronous multi-spin coding of the 2D +-J spin glass (Sec. 5): bit k of
-// a 32-bit word holds replica 32g + k of group g, so one word operation
+// a 32-bit word holds replica 32g + k of word g, so one word operation
 // updates the same site of 32 independent lattices, each with its own
-// couplings.  The 32 replicas of a group share the Metropolis uniform of
-// each site and sweep (the paper draws one random number per word); their
-// counters carry the group index g where the single-replica sweep carries
-// the replica index.
+// couplings.  The w = 32 or 64 replicas of a draw group share the
+// Metropolis uniform of each site and sweep (the paper draws one random
+// number per w-bit word); their counters carry the group index r / w where
+// the single-replica sweep carries the replica index.  With w = 64 a thread
+// updates the two words of a group with one draw.
 //
 // Decision for one site of the 32 replicas: with a_j = s ^ s_j ^ J_j the
 // unsatisfied-bond bits of the four bonds, n = a_1 + .. + a_4 per replica
@@ -96,34 +97,41 @@ __device__ __forceinline__ uint32_t msc_flip_mask(const uint32_t (&S)[16], const
 // JL / JR15: the horizontal bonds into column 0 and out of column 15 of the
 // segment (the row's closing bond at the lattice edge, +1 elsewhere after the
 // gauge); JD: the bonds down from the owned sites; the bonds up from them are
-// the row above's down bonds, read from the bond plane jd in LDS.
-template <int SEG, int OFF>
-__device__ __forceinline__ void msc_half(uint32_t (&S)[16], const uint32_t (&JD)[16], uint32_t JL, uint32_t JR15,
-                                         uint32_t *lat, const uint32_t *jd, int y, int seg, uint32_t g, uint32_t t,
+// the row above's down bonds, read from the bond plane jd in LDS.  A thread
+// updates NW words (1, or 2 for 64 replicas per draw) of the same sites with
+// one Philox block per colour; g is the draw's group index.
+template <int SEG, int OFF, int NW>
+__device__ __forceinline__ void msc_half(uint32_t (&S)[NW][16], const uint32_t (&JD)[NW][16], const uint32_t (&JL)[NW],
+                                         const uint32_t (&JR15)[NW], uint32_t *const (&lat)[NW],
+                                         const uint32_t *const (&jd)[NW], int y, int seg, uint32_t g, uint32_t t,
                                          uint32_t c, const ThrRow &thr, Key key) {
     using GE = MscGeom<SEG>;
     constexpr int L = 16 * SEG;
-    const uint32_t *up = lat + ((y + L - 1) % L) * GE::RS + seg * GE::SS;
-    const uint32_t *dn = lat + ((y + 1) % L) * GE::RS + seg * GE::SS;
-    const uint32_t *ju = jd + ((y + L - 1) % L) * GE::RS + seg * GE::SS;
+    const int ru = ((y + L - 1) % L) * GE::RS + seg * GE::SS;
+    const int rd = ((y + 1) % L) * GE::RS + seg * GE::SS;
     // the neighbour word outside the segment: column 15 of the segment to
     // the left (OFF = 0) or column 0 of the one to the right (OFF = 1)
-    const uint32_t bnd = OFF == 0 ? lat[y * GE::RS + ((seg + SEG - 1) % SEG) * GE::SS + 15]
-                                  : lat[y * GE::RS + ((seg + 1) % SEG) * GE::SS];
+    const int rb = OFF == 0 ? y * GE::RS + ((seg + SEG - 1) % SEG) * GE::SS + 15 : y * GE::RS + ((seg + 1) % SEG) * GE::SS;
+    uint32_t bnd[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) bnd[w] = lat[w][rb];
     const uint32_t b = (uint32_t)(y * SEG + seg);  // Philox block: in-colour sites 8b .. 8b+7
-    const uint4 w = philox4x32_10(make_uint4(b, t, g, 2 * kTagHead + c), key);
+    const uint4 wd = philox4x32_10(make_uint4(b, t, g, 2 * kTagHead + c), key);
     const uint32_t T1 = thr.m[1].x, T2 = thr.m[2].x;
     // Flip masks from the heads alone; a head equal to the high half of a
     // threshold (rare) marks its site for the exact path below, which then
-    // replaces that site's mask.  Nothing is applied before both are done.
-    uint32_t flip[8];
+    // replaces that site's masks.  Nothing is applied before both are done.
+    uint32_t flip[NW][8];
     bool tie[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int xx = OFF + 2 * j;
-        const uint32_t word = j < 2 ? w.x : j < 4 ? w.y : j < 6 ? w.z : w.w;
+        const uint32_t word = j < 2 ? wd.x : j < 4 ? wd.y : j < 6 ? wd.z : wd.w;
         const uint32_t head = (j & 1) ? (word >> 16) : (word & 0xFFFFu);
-        flip[j] = msc_flip_mask<OFF>(S, JD, JL, JR15, bnd, up, dn, ju, xx, head < T1, head < T2);
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            flip[w][j] = msc_flip_mask<OFF>(S[w], JD[w], JL[w], JR15[w], bnd[w], lat[w] + ru, lat[w] + rd, jd[w] + ru,
+                                            xx, head < T1, head < T2);
         tie[j] = head == T1 || head == T2;
     }
     bool any = false;
@@ -137,83 +145,109 @@ __device__ __forceinline__ void msc_half(uint32_t (&S)[16], const uint32_t (&JD)
         while (pending) {
             const uint32_t jl = (uint32_t)__builtin_ctz(pending);
             pending &= pending - 1u;
-            const uint32_t word = jl < 2u ? w.x : jl < 4u ? w.y : jl < 6u ? w.z : w.w;
+            const uint32_t word = jl < 2u ? wd.x : jl < 4u ? wd.y : jl < 6u ? wd.z : wd.w;
             const uint32_t head = (jl & 1u) ? (word >> 16) : (word & 0xFFFFu);
             const uint32_t tail = tail16(8u * b + jl, t, g, c, key);
             const bool d1 = head < T1 || (head == T1 && tail < thr.m[1].y);
             const bool d2 = head < T2 || (head == T2 && tail < thr.m[2].y);
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                if (jl == (uint32_t)j) flip[j] = msc_flip_mask<OFF>(S, JD, JL, JR15, bnd, up, dn, ju, OFF + 2 * j, d1, d2);
+                if (jl == (uint32_t)j) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w)
+                        flip[w][j] = msc_flip_mask<OFF>(S[w], JD[w], JL[w], JR15[w], bnd[w], lat[w] + ru,
+                                                        lat[w] + rd, jd[w] + ru, OFF + 2 * j, d1, d2);
+                }
         }
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) S[OFF + 2 * j] ^= flip[j];
-    uint32_t *own = lat + y * GE::RS + seg * GE::SS;
+    for (int w = 0; w < NW; ++w) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) own[OFF + 2 * j] = S[OFF + 2 * j];
+        for (int j = 0; j < 8; ++j) S[w][OFF + 2 * j] ^= flip[w][j];
+        uint32_t *own = lat[w] + y * GE::RS + seg * GE::SS;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) own[OFF + 2 * j] = S[w][OFF + 2 * j];
+    }
 }
 
-template <int SEG>
+// NW words per thread: 1 (32 replicas per draw) or 2 (64 replicas per draw,
+// words 2h and 2h + 1 drawing as group h).
+template <int SEG, int NW>
 __global__ __launch_bounds__(kMscBlock) void k_msc2d(Msc2dArgs a) {
     using GE = MscGeom<SEG>;
     constexpr int L = 16 * SEG, N = L * L;
-    constexpr int TPG = N / 16;         // threads per group
-    constexpr int GPW = kMscBlock / TPG;  // groups per workgroup
-    constexpr int PER = TPG / 2;        // threads per group and row parity
-    __shared__ uint32_t lds[GPW * GE::GS];
-    __shared__ uint32_t lds_jd[GPW * GE::GS];  // down bonds, same geometry
+    constexpr int TPG = N / 16;           // threads per set of NW words
+    constexpr int SPW = kMscBlock / TPG;  // thread sets per workgroup
+    constexpr int WPW = SPW * NW;         // words per workgroup
+    constexpr int PER = TPG / 2;          // threads per set and row parity
+    __shared__ uint32_t lds[WPW * GE::GS];
+    __shared__ uint32_t lds_jd[WPW * GE::GS];  // down bonds, same geometry
     // threads [0, 128) own even rows, [128, 256) odd rows, so that the
     // colour offset of a half-sweep is uniform across each wave
     const int par = (int)threadIdx.x / (kMscBlock / 2);
     const int q = (int)threadIdx.x % (kMscBlock / 2);
-    const int gw = q / PER, rem = q % PER;
+    const int set = q / PER, rem = q % PER;
     const int y = 2 * (rem / SEG) + par, seg = rem % SEG;
-    const int g = (int)blockIdx.x * GPW + gw;
-    const bool live = g < a.G;
-    uint32_t *lat = lds + gw * GE::GS;
-    uint32_t *jd = lds_jd + gw * GE::GS;
+    const int g0 = (int)blockIdx.x * WPW + set * NW;  // first word (group of 32 replicas)
+    const bool live = g0 < a.G;                        // (the G words come in whole sets)
+    uint32_t *lat[NW];
+    const uint32_t *jd[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        lat[w] = lds + (set * NW + w) * GE::GS;
+        jd[w] = lds_jd + (set * NW + w) * GE::GS;
+    }
 
-    uint32_t S[16], JD[16], JL = 0, JR15 = 0;
-    if (live) {
-        const uint32_t *sp = a.spins + (size_t)g * N + (size_t)(y * L + 16 * seg);
-        const uint32_t *cp = a.coup + 2 * (size_t)g * N;
+    uint32_t S[NW][16], JD[NW][16], JL[NW], JR15[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (live) {
+            const int g = g0 + w;
+            const uint32_t *sp = a.spins + (size_t)g * N + (size_t)(y * L + 16 * seg);
+            const uint32_t *cp = a.coup + 2 * (size_t)g * N;
+#pragma unroll
+            for (int xx = 0; xx < 16; ++xx) {
+                S[w][xx] = sp[xx];
+                JD[w][xx] = cp[N + y * L + 16 * seg + xx];
+            }
+            const uint32_t wrap = cp[y * L + L - 1];  // the row's closing bond (L-1 -> 0)
+            JL[w] = seg == 0 ? wrap : 0u;
+            JR15[w] = seg == SEG - 1 ? wrap : 0u;
+        } else {
+#pragma unroll
+            for (int xx = 0; xx < 16; ++xx) S[w][xx] = JD[w][xx] = 0u;
+            JL[w] = JR15[w] = 0u;
+        }
+        uint32_t *own = lat[w] + y * GE::RS + seg * GE::SS;
+        uint32_t *ownj = (uint32_t *)jd[w] + y * GE::RS + seg * GE::SS;
 #pragma unroll
         for (int xx = 0; xx < 16; ++xx) {
-            S[xx] = sp[xx];
-            JD[xx] = cp[N + y * L + 16 * seg + xx];
+            own[xx] = S[w][xx];
+            ownj[xx] = JD[w][xx];
         }
-        const uint32_t wrap = cp[y * L + L - 1];  // the row's closing bond (L-1 -> 0)
-        JL = seg == 0 ? wrap : 0u;
-        JR15 = seg == SEG - 1 ? wrap : 0u;
-    } else {
-#pragma unroll
-        for (int xx = 0; xx < 16; ++xx) S[xx] = JD[xx] = 0u;
     }
-    uint32_t *own = lat + y * GE::RS + seg * GE::SS;
-    uint32_t *ownj = jd + y * GE::RS + seg * GE::SS;
-#pragma unroll
-    for (int xx = 0; xx < 16; ++xx) {
-        own[xx] = S[xx];
-        ownj[xx] = JD[xx];
-    }
-    const ThrRow thr = a.thr[live ? g : 0];
+    // the draws' group index: the word for 32 replicas per draw, the word pair for 64
+    const uint32_t gdraw = (uint32_t)(NW == 2 ? g0 >> 1 : g0);
+    const ThrRow thr = a.thr[live ? g0 : 0];
     __syncthreads();
     for (int k = 0; k < a.n_sweeps; ++k) {
         const uint32_t t = a.t0 + (uint32_t)k;
 #pragma unroll
         for (uint32_t c = 0; c < 2; ++c) {
             if (((c + (uint32_t)par) & 1u) == 0u)
-                msc_half<SEG, 0>(S, JD, JL, JR15, lat, jd, y, seg, (uint32_t)g, t, c, thr, a.key);
+                msc_half<SEG, 0, NW>(S, JD, JL, JR15, lat, jd, y, seg, gdraw, t, c, thr, a.key);
             else
-                msc_half<SEG, 1>(S, JD, JL, JR15, lat, jd, y, seg, (uint32_t)g, t, c, thr, a.key);
+                msc_half<SEG, 1, NW>(S, JD, JL, JR15, lat, jd, y, seg, gdraw, t, c, thr, a.key);
             __syncthreads();
         }
     }
     if (live) {
-        const size_t base = (size_t)g * N + (size_t)(y * L + 16 * seg);
 #pragma unroll
-        for (int xx = 0; xx < 16; ++xx) a.spins[base + xx] = S[xx];
+        for (int w = 0; w < NW; ++w) {
+            const size_t base = (size_t)(g0 + w) * N + (size_t)(y * L + 16 * seg);
+#pragma unroll
+            for (int xx = 0; xx < 16; ++xx) a.spins[base + xx] = S[w][xx];
+        }
     }
 }
 
@@ -346,8 +380,20 @@ hipError_t launch_msc_energy_diff(const double *E0, const double *E1, int64_t *d
     return hipGetLastError();
 }
 
+template <int SEG>
+hipError_t launch_msc2d_seg(const Msc2dArgs &a, int words_per_draw, hipStream_t s) {
+    constexpr int tpg = 16 * SEG * 16 * SEG / 16;
+    const int wpw = kMscBlock / tpg * words_per_draw;
+    const unsigned blocks = (unsigned)((a.G + wpw - 1) / wpw);
+    if (words_per_draw == 2)
+        hipLaunchKernelGGL((k_msc2d<SEG, 2>), dim3(blocks), dim3(kMscBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_msc2d<SEG, 1>), dim3(blocks), dim3(kMscBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_msc2d(uint32_t *spins, const uint32_t *coup, const ThrRow *thr, int n_groups, int L, Key key,
-                        uint32_t t0, int n_sweeps, hipStream_t s) {
+                        uint32_t t0, int n_sweeps, int words_per_draw, hipStream_t s) {
     Msc2dArgs a;
     a.spins = spins;
     a.coup = coup;
@@ -356,20 +402,15 @@ hipError_t launch_msc2d(uint32_t *spins, const uint32_t *coup, const ThrRow *thr
     a.t0 = t0;
     a.n_sweeps = n_sweeps;
     a.G = n_groups;
-    const int tpg = L * L / 16;
-    const int gpw = kMscBlock / tpg;
-    const unsigned blocks = (unsigned)((n_groups + gpw - 1) / gpw);
     if (n_groups <= 0 || n_sweeps <= 0) return hipSuccess;
-    if (L == 16) {
-        hipLaunchKernelGGL(k_msc2d<1>, dim3(blocks), dim3(kMscBlock), 0, s, a);
-    } else if (L == 32) {
-        hipLaunchKernelGGL(k_msc2d<2>, dim3(blocks), dim3(kMscBlock), 0, s, a);
-    } else if (L == 64) {
-        hipLaunchKernelGGL(k_msc2d<4>, dim3(blocks), dim3(kMscBlock), 0, s, a);
-    } else {
-        return hipErrorInvalidValue;
+    if (words_per_draw != 1 && words_per_draw != 2) return hipErrorInvalidValue;
+    if (n_groups % words_per_draw) return hipErrorInvalidValue;  // whole word pairs
+    switch (L) {
+        case 16: return launch_msc2d_seg<1>(a, words_per_draw, s);
+        case 32: return launch_msc2d_seg<2>(a, words_per_draw, s);
+        case 64: return launch_msc2d_seg<4>(a, words_per_draw, s);
+        default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace smc

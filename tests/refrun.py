@@ -45,11 +45,11 @@ def init_uneven(model, dim, inst, seed):
     return spins, coup
 
 
-def sweep_msc(model, dim, L, spins, coup, betas, seed, t0, n):
-    """Multi-spin-coded sweeps (groups of 32 replicas share their draws): each
-    replica is the ordinary chain with the group index r // 32 in the counters."""
+def sweep_msc(model, dim, L, spins, coup, betas, seed, t0, n, w=32):
+    """Multi-spin-coded sweeps (groups of w replicas share their draws): each
+    replica is the ordinary chain with the group index r // w in the counters."""
     dE = np.zeros(len(spins), np.int64)
     for r in range(len(spins)):
         J = None if coup is None else coup[r]
-        dE[r] = O.run(dim, L, J, spins[r], float(betas[r]), seed, r // 32, t0, n)
+        dE[r] = O.run(dim, L, J, spins[r], float(betas[r]), seed, r // w, t0, n)
     return dE

@@ -132,20 +132,28 @@ def test_philox_bench_arguments_are_validated():
 
 def test_msc_arguments_are_validated():
     L = S.lib()
-    beta = (C.c_double * 64)(*([0.5] * 64))
+    beta = (C.c_double * 128)(*([0.5] * 128))
     d = _desc(n_rep=48, spins_len=48 * 256)
-    rc = L.smc_msc_sweep(C.byref(d), FAKE, None, beta, 0, 1, None, None)
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, None, beta, 0, 1, 32, None, None)
     assert rc == S.EINVAL and b"multiple of 32" in L.smc_last_error()
+    d = _desc(n_rep=96, spins_len=96 * 256)
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, None, beta, 0, 1, 64, None, None)
+    assert rc == S.EINVAL and b"multiple of 64" in L.smc_last_error()
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, None, beta, 0, 1, 16, None, None)
+    assert rc == S.EINVAL and b"word_bits" in L.smc_last_error()
     d = _desc(n_rep=64, spins_len=64 * 256, model=S.EA, coup_len=64 * 512)
     d.rep_per_sample = 2
-    rc = L.smc_msc_sweep(C.byref(d), FAKE, FAKE, beta, 0, 1, None, None)
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, FAKE, beta, 0, 1, 32, None, None)
     assert rc == S.EINVAL and b"rep_per_sample" in L.smc_last_error()
     d.rep_per_sample = 1
     beta2 = (C.c_double * 64)(*([0.5] * 40 + [0.6] * 24))
-    rc = L.smc_msc_sweep(C.byref(d), FAKE, FAKE, beta2, 0, 1, None, None)
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, FAKE, beta2, 0, 1, 32, None, None)
     assert rc == S.EINVAL and b"group of 32" in L.smc_last_error()
+    beta3 = (C.c_double * 64)(*([0.5] * 32 + [0.6] * 32))
+    rc = L.smc_msc_sweep(C.byref(d), FAKE, FAKE, beta3, 0, 1, 64, None, None)
+    assert rc == S.EINVAL and b"group of 64" in L.smc_last_error()
     d = _desc(n_rep=64, spins_len=64 * 256 * 3, model=S.HEISENBERG)
-    assert L.smc_msc_sweep(C.byref(d), FAKE, None, beta, 0, 1, None, None) == S.EUNSUPPORTED
+    assert L.smc_msc_sweep(C.byref(d), FAKE, None, beta, 0, 1, 32, None, None) == S.EUNSUPPORTED
 
 
 def test_dcb_arguments_are_validated():

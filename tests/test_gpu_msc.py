@@ -21,21 +21,52 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def _run(model, dim, L, n_rep, betas, seed, t0, n, calls=None):
+def _run(model, dim, L, n_rep, betas, seed, t0, n, calls=None, w=32):
     b = S.Batch(model, dim, L, n_rep, seed)
     spins = torch.zeros(b.spins_shape()[0], dtype=torch.int8, device=DEV)
     coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV) if model == S.EA else None
     S.spin_init(b, spins, coup)
     dE = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
     for s0, k in calls or [(t0, n)]:
-        S.msc_sweep(b, spins, betas, s0, k, couplings=coup, dE_accum=dE)
+        S.msc_sweep(b, spins, betas, s0, k, couplings=coup, dE_accum=dE, word_bits=w)
     return b, _host(spins).reshape(n_rep, -1), _host(dE)
 
 
-def _reference(model, dim, L, n_rep, betas, seed, t0, n):
+def _reference(model, dim, L, n_rep, betas, seed, t0, n, w=32):
     ref_s, ref_c = refrun.init_uniform(model, dim, L, n_rep, seed)
-    ref_dE = refrun.sweep_msc(model, dim, L, ref_s, ref_c, betas, seed, t0, n)
+    ref_dE = refrun.sweep_msc(model, dim, L, ref_s, ref_c, betas, seed, t0, n, w=w)
     return ref_s, ref_dE
+
+
+@pytest.mark.parametrize("L,pairs,n", [(16, 3, 7), (32, 1, 5), (64, 1, 4)])
+def test_msc2d_64_replicas_per_draw(L, pairs, n):
+    """64 replicas per draw group (two words updated with one draw per site)."""
+    seed, n_rep = W.seed_for(69 + L), 64 * pairs
+    betas = np.repeat(np.linspace(0.6, 1.4, pairs), 64)
+    b, got_s, got_dE = _run(S.EA, 2, L, n_rep, betas, seed, 3, n, w=64)
+    assert S.msc_plan(b, n, word_bits=64) == (1, "k_msc2d")
+    ref_s, ref_dE = _reference(S.EA, 2, L, n_rep, betas, seed, 3, n, w=64)
+    assert np.array_equal(got_s, ref_s)
+    assert np.array_equal(got_dE, ref_dE)
+
+
+def test_msc_64_generic_path_and_ties(monkeypatch):
+    """64 per draw: the generic kernels give the packed kernel's result, and
+    32 groups x 50 sweeps at beta = 1 (head ties) match the oracle."""
+    L, n_rep, seed, n = 16, 128, W.seed_for(70), 6
+    betas = np.full(n_rep, 0.9)
+    _, fast_s, fast_dE = _run(S.ISING, 2, L, n_rep, betas, seed, 2, n, w=64)
+    monkeypatch.setenv("SPINMC_MSC2D", "0")
+    b, gen_s, gen_dE = _run(S.ISING, 2, L, n_rep, betas, seed, 2, n, w=64)
+    assert S.msc_plan(b, n, word_bits=64)[1] == "k_half_sweep_generic"
+    assert np.array_equal(fast_s, gen_s) and np.array_equal(fast_dE, gen_dE)
+    monkeypatch.delenv("SPINMC_MSC2D")
+    n_rep, n = 64 * 32, 50
+    betas = np.full(n_rep, 1.0)
+    _, got_s, got_dE = _run(S.EA, 2, L, n_rep, betas, seed, 0, n, w=64)
+    ref_s, ref_dE = _reference(S.EA, 2, L, n_rep, betas, seed, 0, n, w=64)
+    assert np.array_equal(got_s, ref_s)
+    assert np.array_equal(got_dE, ref_dE)
 
 
 @pytest.mark.parametrize("L,groups,n", [(16, 3, 7), (32, 2, 5), (64, 1, 4)])
