@@ -460,6 +460,35 @@ def dcb2d(S, W, sweeps, L=16384, tiles=(64, 128), hits=(1, 2, 4, 8, 16, 64, 100)
             "kernel": S.dcb_plan(b, [cfg.betas[1]], tiles[0]), "by_tile_and_hits": rows}
 
 
+def dcb_scan(S, W, sizes=(64, 256, 1024, 4096, 16384), hits=(1, 100), beta=0.4, flips=4e9):
+    """Spin-flip time against L for one 2D Ising lattice at beta = 0.4 (the
+    shape of the paper's Figs. 8 and 9): the plain checkerboard sweep and the
+    double checkerboard with k = 1 and 100 hits (tiles of 16 up to L = 256,
+    64 above)."""
+    import torch
+
+    rows = []
+    for L in sizes:
+        b = S.Batch(S.ISING, 2, L, 1, W.seed_for(100))
+        spins = torch.empty(L * L, dtype=torch.int8, device="cuda")
+        S.spin_init(b, spins)
+        tile = 16 if L <= 256 else 64
+        n = max(2, min(20000, int(flips // (L * L))))  # small lattices: capped by launches
+        S.metropolis_sweep(b, spins, [beta], 0, 2)
+        ms = _timed(lambda: S.metropolis_sweep(b, spins, [beta], 2, n))
+        row = {"L": L, "plain_ps_per_flip": round(ms * 1e9 / (n * L * L), 4), "tile": tile}
+        for k in hits:
+            nk = max(2, n // k)
+            S.dcb_sweep(b, spins, [beta], 0, 1, tile, k)
+            ms = _timed(lambda: S.dcb_sweep(b, spins, [beta], 1, nk, tile, k))
+            row[f"dcb_k{k}_ps_per_flip"] = round(ms * 1e9 / (nk * k * L * L), 4)
+        rows.append(row)
+        del spins
+    torch.cuda.empty_cache()
+    return {"workload": f"2D Ising L x L, one lattice, beta = {beta}: plain checkerboard sweeps and double "
+                        f"checkerboard with k hits, ps per attempted flip", "by_size": rows}
+
+
 def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
     """The paper's Heisenberg benchmark (Sec. 4): 2D, L = 4096, double
     checkerboard with k = 100 hits, in the three arithmetic modes (float32
@@ -795,7 +824,9 @@ def main():
     ap.add_argument("--heis-only", action="store_true", help="only the Heisenberg measurement (for profiling)")
     ap.add_argument("--msc-sweeps", type=int, default=2000)
     ap.add_argument("--dcb-sweeps", type=int, default=64)
-    ap.add_argument("--dcb-only", action="store_true", help="only the double-checkerboard measurement")
+    ap.add_argument("--dcb-only", action="store_true", help="only the double-checkerboard measurements")
+    ap.add_argument("--dcb-scan-flips", type=float, default=4e9,
+                    help="attempted flips per lattice size and update in the L scan")
     ap.add_argument("--heis-dcb-sweeps", type=int, default=4)
     ap.add_argument("--heis-dcb-only", action="store_true",
                     help="only the 2D Heisenberg double checkerboard (L = 4096, k = 100, three modes)")
@@ -855,7 +886,8 @@ def main():
         print(json.dumps({"msc_ea2d": msc_ea2d(S, W, args.msc_sweeps)}))
         return
     if args.dcb_only:
-        print(json.dumps({"dcb2d": dcb2d(S, W, args.dcb_sweeps)}))
+        print(json.dumps({"dcb2d": dcb2d(S, W, args.dcb_sweeps),
+                          "dcb_scan": dcb_scan(S, W, flips=args.dcb_scan_flips)}))
         return
     if args.heis_dcb_only:
         print(json.dumps({"heis_dcb2d": heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)}))
@@ -954,6 +986,7 @@ def main():
                                       lambda: tempering_ising2d(S, W, sizes=sizes, flips=args.paper_pt_flips))}
         out["msc_ea2d"] = _section("msc_ea2d", lambda: msc_ea2d(S, W, args.msc_sweeps))
         out["dcb2d"] = _section("dcb2d", lambda: dcb2d(S, W, args.dcb_sweeps))
+        out["dcb_scan"] = _section("dcb_scan", lambda: dcb_scan(S, W, flips=args.dcb_scan_flips))
         out["heis_dcb2d"] = _section("heis_dcb2d", lambda: heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg)

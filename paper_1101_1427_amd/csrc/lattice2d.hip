@@ -589,10 +589,19 @@ int lattice2d_chunks(int L) {
 
 bool lattice2d_supported(int L) { return lattice2d_chunks(L) > 0; }
 
+// 32 rows per band; a batch with fewer than two such bands per compute unit
+// (a single lattice of L <= 4096) takes lower bands, down to 4 rows, so
+// that every compute unit has work (the halo rows then cost relatively
+// more).  SPINMC_L2D_H forces a height.
 int lattice2d_band_height(int L, int n_rep) {
-    (void)n_rep;
-    int H = env_int("SPINMC_L2D_H", 32);
-    if (H < 4 || H % 4 || L % H) H = 32;
+    int H = env_int("SPINMC_L2D_H", 0);
+    if (H < 4 || H % 4 || L % H) {
+        int cus = 0, dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        H = 32;
+        while (H > 4 && cus > 0 && (int64_t)n_rep * (L / H) < 2 * (int64_t)cus) H >>= 1;
+    }
     while (H > 4 && L % H) H >>= 1;
     return (L % H || H % 4) ? 0 : H;
 }
