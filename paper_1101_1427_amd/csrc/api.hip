@@ -487,33 +487,36 @@ std::vector<smc_inst> inst_rows(const smc_desc *d) {
     return rows;
 }
 
-int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &plan, const smc_pt_desc *pt,
-                 void *spins, const int8_t *couplings, SwapArgs &sw, const ThrRow *thr, double *energy,
-                 uint64_t step0, int32_t n_steps, int m) {
-    int rc;
-    // instance table, classes by edge (largest first), work list in replica order within a class
-    const std::vector<smc_inst> rows = inst_rows(desc);
-    void *inst_dev = nullptr;
-    if ((rc = upload(c, s, kInst, rows.data(), sizeof(smc_inst) * rows.size(), &inst_dev))) return rc;
-    std::map<int, std::vector<int32_t>, std::greater<int>> by_edge;
-    for (int r = 0; r < desc->n_rep; ++r) by_edge[rows[r].L].push_back(r);
+// What the LDS-resident 2D kernel needs for a batch: the instance table, the
+// replicas grouped by edge (classes, largest first; replica order within a
+// class) and the colour-split couplings of every sample.
+struct Lds2dSetup {
+    std::vector<smc_inst> rows;
     std::vector<EdgeClass> classes;
     std::vector<int32_t> work;
+    void *inst_dev = nullptr;
+    void *work_dev = nullptr;
+    uint8_t *csplit = nullptr;
+};
+
+int lds2d_setup(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &plan, const int8_t *couplings,
+                Lds2dSetup &st) {
+    int rc;
+    st.rows = inst_rows(desc);
+    if ((rc = upload(c, s, kInst, st.rows.data(), sizeof(smc_inst) * st.rows.size(), &st.inst_dev))) return rc;
+    std::map<int, std::vector<int32_t>, std::greater<int>> by_edge;
+    for (int r = 0; r < desc->n_rep; ++r) by_edge[st.rows[r].L].push_back(r);
     for (auto &kv : by_edge) {
         EdgeClass e;
         e.L = kv.first;
-        e.threads = 0;  // chosen below
-        e.first = (int32_t)work.size();
+        e.threads = 0;  // chosen by the caller
+        e.first = (int32_t)st.work.size();
         e.count = (int32_t)kv.second.size();
-        work.insert(work.end(), kv.second.begin(), kv.second.end());
-        classes.push_back(e);
+        st.work.insert(st.work.end(), kv.second.begin(), kv.second.end());
+        st.classes.push_back(e);
         SMC_HIP(uneven2d_prepare_kernel(desc->model == SMC_EA, e.L));
     }
-    void *work_dev = nullptr;
-    if ((rc = upload(c, s, kWork, work.data(), sizeof(int32_t) * work.size(), &work_dev))) return rc;
-
-    // colour-split couplings of every sample
-    uint8_t *csplit = nullptr;
+    if ((rc = upload(c, s, kWork, st.work.data(), sizeof(int32_t) * st.work.size(), &st.work_dev))) return rc;
     if (desc->model == SMC_EA) {
         std::vector<smc_inst> samples;
         if (desc->L > 0) {
@@ -522,7 +525,7 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
                 samples[(size_t)q] = smc_inst{desc->L, (int32_t)q, 0, q * 2 * (int64_t)desc->L * desc->L};
         } else {
             std::map<int32_t, smc_inst> seen;
-            for (const smc_inst &g : rows) seen.emplace(g.sample, g);
+            for (const smc_inst &g : st.rows) seen.emplace(g.sample, g);
             for (auto &kv : seen) samples.push_back(kv.second);
         }
         std::vector<int64_t> start(samples.size());
@@ -535,10 +538,24 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
         if ((rc = upload(c, s, kSamples, samples.data(), sizeof(smc_inst) * samples.size(), &samp_dev))) return rc;
         if ((rc = upload(c, s, kChunks, start.data(), sizeof(int64_t) * start.size(), &start_dev))) return rc;
         if ((rc = ensure(c, kCoupSplit, (size_t)desc->coup_len, &cs))) return rc;
-        csplit = (uint8_t *)cs;
-        SMC_HIP(launch_coup_split2d(couplings, csplit, (const smc_inst *)samp_dev, (int)samples.size(), total,
+        st.csplit = (uint8_t *)cs;
+        SMC_HIP(launch_coup_split2d(couplings, st.csplit, (const smc_inst *)samp_dev, (int)samples.size(), total,
                                     (const int64_t *)start_dev, s));
     }
+    return SMC_OK;
+}
+
+int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &plan, const smc_pt_desc *pt,
+                 void *spins, const int8_t *couplings, SwapArgs &sw, const ThrRow *thr, double *energy,
+                 uint64_t step0, int32_t n_steps, int m) {
+    int rc;
+    Lds2dSetup st;
+    if ((rc = lds2d_setup(c, s, desc, plan, couplings, st))) return rc;
+    std::vector<EdgeClass> &classes = st.classes;
+    const std::vector<int32_t> &work = st.work;
+    const std::vector<smc_inst> &rows = st.rows;
+    void *inst_dev = st.inst_dev, *work_dev = st.work_dev;
+    uint8_t *csplit = st.csplit;
     // device counters: the step index (exchange rounds) and, with m > 1
     // sweeps per step, the sweep index t*m + j (with m = 1 they coincide)
     void *tp = nullptr;
@@ -684,6 +701,68 @@ struct SweepTimer {
     ~SweepTimer() { finish(); }
 };
 
+// Sweeps of a uniform 2D Ising / EA batch of edge 16 .. 256 (a multiple of
+// 16) on the LDS-resident kernel: each replica stays in one workgroup's LDS
+// for up to kLdsSweeps sweeps per launch, so small lattices are not bound
+// by two launches per sweep.  Same results as the generic kernels;
+// SPINMC_SWEEP_LDS2D=0 sends such batches to them.
+constexpr int kLdsSweeps = 256;
+
+// A workgroup sweeps about 6e9 sites per second, so one replica of edge 256
+// (65536 sites) takes longer in one workgroup than the generic kernels take
+// over the whole chip; above edge 128 the batch must hold at least 2^19 sites.
+bool lds2d_sweep_shape(const smc_desc *d) {
+    const char *env = getenv("SPINMC_SWEEP_LDS2D");
+    if (env && env[0] == '0') return false;
+    if (d->dim != 2 || d->L <= 0 || !uneven2d_edge_supported(d->L)) return false;
+    return d->L <= 128 || (int64_t)d->n_rep * d->L * d->L >= (int64_t)1 << 19;
+}
+
+bool use_sweep_lds2d(const smc_desc *d, const void *spins, const int8_t *coup, const std::vector<ThrRow> &rows) {
+    return lds2d_sweep_shape(d) && use_uneven2d(d, spins, coup, rows);
+}
+
+int run_sweep_lds2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &plan, void *spins,
+                    const int8_t *couplings, const ThrRow *thr, int64_t *dE_accum, uint64_t sweep0,
+                    int32_t n_sweeps) {
+    int rc;
+    Lds2dSetup st;
+    if ((rc = lds2d_setup(c, s, desc, plan, couplings, st))) return rc;
+    // threshold row of replica r: row r; energy changes into dE_accum (or scratch)
+    std::vector<int32_t> ident(desc->n_rep);
+    for (int r = 0; r < desc->n_rep; ++r) ident[r] = r;
+    void *rp = nullptr, *ep = nullptr, *tp = nullptr;
+    if ((rc = upload(c, s, kRows, ident.data(), sizeof(int32_t) * ident.size(), &rp))) return rc;
+    int64_t *E = dE_accum;
+    if (!E) {
+        if ((rc = ensure(c, kEnergy64, sizeof(int64_t) * desc->n_rep, &ep))) return rc;
+        E = (int64_t *)ep;
+    }
+    if ((rc = ensure(c, kStep, 2 * sizeof(uint32_t), &tp))) return rc;
+    uint32_t *t_dev = (uint32_t *)tp;
+    SMC_HIP(launch_set_step(t_dev, (uint32_t)sweep0, s));
+    Uneven2dArgs a = make_uneven2d_args((int8_t *)spins, (const smc_inst *)st.inst_dev, st.csplit,
+                                        (const int32_t *)rp, thr, E, t_dev, make_key(desc->seed));
+    const bool ea = desc->model == SMC_EA;
+    for (auto &e : st.classes) {
+        const std::vector<int32_t> reps(st.work.begin() + e.first, st.work.begin() + e.first + e.count);
+        if ((rc = uneven2d_threads(c, s, a, e.L, ea, reps, st.rows, &e.threads))) return rc;
+    }
+    const int32_t *wl = (const int32_t *)st.work_dev;
+    const int64_t launches = ((int64_t)n_sweeps + kLdsSweeps - 1) / kLdsSweeps * (int64_t)st.classes.size();
+    SweepTimer timer(s, launches);
+    for (int32_t done = 0; done < n_sweeps;) {
+        const int32_t chunk = n_sweeps - done < kLdsSweeps ? n_sweeps - done : kLdsSweeps;
+        a.sweeps = chunk;
+        for (const EdgeClass &e : st.classes)
+            SMC_HIP(launch_uneven2d_sweep(a, wl + e.first, e.count, e.L, ea, e.threads, s));
+        done += chunk;
+        if (done < n_sweeps) SMC_HIP(launch_advance_step(t_dev, s, (uint32_t)chunk));
+    }
+    timer.finish();
+    return SMC_OK;
+}
+
 }  // namespace
 }  // namespace smc
 
@@ -764,6 +843,9 @@ int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char
     } else if (desc->model == SMC_ISING && desc->dim == 2 && desc->L > 0 && lattice2d_supported(desc->L)) {
         *launches_per_sweep = 1;
         *kernel_name = "k_ising2d_split";
+    } else if (lds2d_sweep_shape(desc) && !(getenv("SPINMC_UNEVEN2D") && getenv("SPINMC_UNEVEN2D")[0] == '0')) {
+        *launches_per_sweep = 1;  // at most: up to 256 sweeps per launch
+        *kernel_name = "k_uneven2d_sweep";
     } else {
         *launches_per_sweep = 2;
         *kernel_name = "k_half_sweep_generic";
@@ -948,6 +1030,8 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
     for (int r = 0; r < desc->n_rep; ++r) rows[r] = threshold_row(beta[r], desc->dim);
     if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &p))) return rc;
     a.thr = (const ThrRow *)p;
+    if (use_sweep_lds2d(desc, spins, couplings, rows))
+        return run_sweep_lds2d(c, s, desc, plan, spins, couplings, a.thr, dE_accum, sweep0, n_sweeps);
     if (use_lattice2d(desc, spins, rows)) {
         // one-pass sweeps on the colour-split layout, ping-pong between two buffers
         const size_t bytes = (size_t)desc->n_rep * lattice2d_split_bytes(desc->L);

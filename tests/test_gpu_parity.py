@@ -281,3 +281,42 @@ def test_split_kernel_launch_shape_invariance(monkeypatch):
         outs.append((_host(spins).copy(), int(_host(dE)[0])))
     for s, d in outs[1:]:
         assert np.array_equal(s, outs[0][0]) and d == outs[0][1]
+
+
+# ------------------------------------------------- LDS-resident small lattices --
+@pytest.mark.parametrize("model,L,n_rep,rps", [(S.ISING, 16, 5, 1), (S.EA, 64, 4, 2), (S.EA, 256, 8, 1)])
+def test_small_lattice_sweeps_in_lds(model, L, n_rep, rps):
+    """Uniform 2D batches of edge 16 .. 128 (and edge 256 with at least 2^19
+    sites in the batch) keep each replica in LDS for up to 256 sweeps per
+    launch: 300 sweeps (two launches) bit-exact against the oracle."""
+    seed = W.seed_for(24)
+    betas = np.linspace(0.3, 1.0, n_rep)
+    b = S.Batch(model, 2, L, n_rep, seed, rep_per_sample=rps)
+    assert S.sweep_plan(b)[1] == "k_uneven2d_sweep"
+    spins, coup = gpu_init(b)
+    dE = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
+    n = 300 if L <= 64 else 40
+    S.metropolis_sweep(b, spins, betas, 11, n, couplings=coup, dE_accum=dE)
+    ref_s, ref_c = refrun.init_uniform(model, 2, L, n_rep, seed, rps)
+    ref_dE = refrun.sweep_uniform(model, 2, L, ref_s, ref_c, betas, seed, 11, n, rps)
+    assert np.array_equal(_host(spins).reshape(ref_s.shape), ref_s)
+    assert np.array_equal(_host(dE), ref_dE)
+
+
+def test_small_lattice_lds_path_equals_generic(monkeypatch):
+    """The LDS path and the generic kernels agree on a call that crosses the
+    256-sweep chunk boundary at an odd sweep index; one replica of edge 256
+    takes the generic kernels."""
+    assert S.sweep_plan(S.Batch(S.ISING, 2, 256, 1, 1))[1] == "k_half_sweep_generic"
+    seed, L, n_rep = W.seed_for(25), 32, 3
+    betas = [0.4, 0.44, 0.6]
+    outs = []
+    for lds in ("1", "0"):
+        monkeypatch.setenv("SPINMC_SWEEP_LDS2D", lds)
+        b = S.Batch(S.EA, 2, L, n_rep, seed)
+        spins, coup = gpu_init(b)
+        dE = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
+        S.metropolis_sweep(b, spins, betas, 255, 520, couplings=coup, dE_accum=dE)
+        outs.append((_host(spins).copy(), _host(dE).copy()))
+    assert S.sweep_plan(S.Batch(S.EA, 2, L, n_rep, seed))[1] == "k_half_sweep_generic"
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
