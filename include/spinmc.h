@@ -41,17 +41,21 @@
  * - Return value: SMC_OK (0) or a negative smc_status.
  * - Execution paths.  Uniform 2D Ising batches with L a power of two in
  *   [1024, 16384] sweep on a colour-split copy of the lattice in one launch
- *   per sweep; 3D edge-16 tempering runs all steps of a call in one launch;
- *   2D tempering with edges in {16, 32, ..., 256} runs one workgroup per
- *   replica per step (a graph of steps); everything else takes generic
- *   per-site kernels.  All paths give identical results.  Environment
- *   variables for comparisons and tuning (read at each call):
- *   SPINMC_PT3D=0 and SPINMC_UNEVEN2D=0 send tempering to the generic
- *   kernels; SPINMC_L2D_CHUNKS (1 or 2), SPINMC_L2D_H (band height, a
- *   multiple of 4), SPINMC_L2D_H1 / SPINMC_L2D_H2 (heights of the bands of
- *   the first and second half of the grid) and SPINMC_L2D_PAD (row padding
- *   in bytes) set the launch shape of the 2D Ising sweep.  SPINMC_HEIS3D=0
- *   sends uniform 3D Heisenberg batches to the generic kernel.
+ *   per sweep (tempering too); uniform 2D Ising / EA batches of edge 16 ..
+ *   128 (or 256 with at least 2^19 sites) keep each replica in one
+ *   workgroup's LDS for up to 256 sweeps per launch; 3D edge-16 tempering
+ *   runs all steps of a call in one launch; 2D tempering with edges in
+ *   {16, 32, ..., 256} runs one workgroup per replica per step (a graph of
+ *   steps); everything else takes generic per-site kernels.  All paths give
+ *   identical results.  Environment variables for comparisons and tuning
+ *   (read at each call): SPINMC_PT3D=0, SPINMC_UNEVEN2D=0 and
+ *   SPINMC_PT_SPLIT2D=0 send tempering to the generic kernels,
+ *   SPINMC_SWEEP_LDS2D=0 small 2D sweeps; SPINMC_L2D_CHUNKS (1 or 2),
+ *   SPINMC_L2D_H (band height, a multiple of 4), SPINMC_L2D_H1 /
+ *   SPINMC_L2D_H2 (heights of the bands of the first and second half of
+ *   the grid) and SPINMC_L2D_PAD (row padding in bytes) set the launch
+ *   shape of the 2D Ising sweep.  SPINMC_HEIS3D=0 sends uniform 3D
+ *   Heisenberg batches to the generic kernel.
  */
 #ifndef SPINMC_H
 #define SPINMC_H
