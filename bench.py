@@ -7,9 +7,13 @@ starts, swept as one batch of three replicas: a step is one sweep (colour 0
 then colour 1, with Delta E tracking) of all three, one kernel launch.
 Spins are resident in HBM before the timed region.  Prints one JSON line:
 ns per spin flip (lower is better), the HBM roofline of the sweep kernel
-(and the same kernel on one lattice alone), the batched tempering
-workloads against per-instance launches, the 3D Heisenberg workload, and
-the CPU oracle timed on a bounded sample (1024^2 lattice) of the workload.
+(and the same kernel on one lattice alone), the 3D Heisenberg workload,
+the batched tempering workloads against per-instance launches and the
+paper's 20-replica tempering workload, multi-spin coding, the double
+checkerboard against k and L, the paper's 2D Heisenberg workload in three
+arithmetic modes, and the CPU oracle timed on a bounded sample (1024^2
+lattice) of the workload.  Separate modes (--tau-only, --table1-only, ...)
+run the autocorrelation study and Table 1 with the Philox streams.
 """
 from __future__ import annotations
 

@@ -1,9 +1,11 @@
-// Parallel tempering of uneven batches of 2D lattices (Sec. 6, Eq. 12; many
-// independent instances at once, Sec. 5.2).
+// Sweeps of batches of small 2D lattices with each replica in LDS: parallel
+// tempering of uneven batches (Sec. 6, Eq. 12; many independent instances at
+// once) and plain sweeps of small uniform batches.
 //
-// A sweep of the batch is one launch per lattice size: one workgroup per
-// replica holds the replica in LDS, runs colour 0 then colour 1 and writes it
-// back, tracking the replica's energy.  Couplings are read from a
+// A launch per lattice size runs one workgroup per replica: it holds the
+// replica in LDS, runs `sweeps` sweeps (colour 0 then colour 1 each, sweep
+// indices from the device counter *t_dev on) and writes it back, tracking
+// the replica's energy.  Couplings are read from a
 // colour-split copy made once per call; the replicas of one instance run
 // next to each other on one XCD, so the copy is served from its L2 (keeping
 // the couplings out of LDS leaves room for more workgroups per CU, which
