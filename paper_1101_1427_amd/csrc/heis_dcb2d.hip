@@ -142,12 +142,12 @@ struct alignas(4 * sizeof(R)) Cell {
     R x, y, z, pad;
 };
 
-template <int T>
+template <int T, int SPT>
 struct HeisGeom {
-    static constexpr int QPR = T / 4;              // threads per tile row (four sites each)
-    static constexpr int THREADS = T * T / 4;      // 64, 256, 1024
+    static constexpr int QPR = T / SPT;              // threads per tile row (SPT sites each)
+    static constexpr int THREADS = T * T / SPT;
     static constexpr bool UNIFORM = THREADS >= 128;  // every wave holds rows of one parity
-    static constexpr int W = T + 2;                // staged square: tile and halo
+    static constexpr int W = T + 2;                  // staged square: tile and halo
 };
 
 struct HeisDcbArgs {
@@ -161,11 +161,11 @@ struct HeisDcbArgs {
     int tile_colour, rev, tiles_per_colour;
 };
 
-template <int T, int MODE, bool CAP>
-__global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs a) {
+template <int T, int SPT, int MODE, bool CAP>
+__global__ __launch_bounds__((HeisGeom<T, SPT>::THREADS)) void k_heis_dcb2d(HeisDcbArgs a) {
     using A = HeisArith<MODE>;
     using R = typename A::R;
-    using Gm = HeisGeom<T>;
+    using Gm = HeisGeom<T, SPT>;
     constexpr int QPR = Gm::QPR, W = Gm::W;
     __shared__ Cell<R> cell[W * W];
     __shared__ long long red[(Gm::THREADS + 63) / 64];
@@ -191,22 +191,22 @@ __global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs
         by = ti / half;
         bx = 2 * (ti % half) + ((by + a.tile_colour) & 1);
     }
-    const int L = a.L, x0 = bx * T, y0 = by * T, y = y0 + v, xq = x0 + 4 * q;
+    const int L = a.L, x0 = bx * T, y0 = by * T, y = y0 + v, xq = x0 + SPT * q;
     const int64_t N = (int64_t)L * L;
     R *S = (R *)a.spins + (int64_t)r * N * 3;
     const R beta = ((const R *)a.beta)[r];
     const R cap = (R)a.cap;
 
-    // own sites: columns xq .. xq + 3 of row y
-    R sx[4], sy[4], sz[4];
+    // own sites: columns xq .. xq + SPT - 1 of row y
+    R sx[SPT], sy[SPT], sz[SPT];
     {
         const R *p = S + ((int64_t)y * L + xq) * 3;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < SPT; ++m) {
             sx[m] = p[3 * m];
             sy[m] = p[3 * m + 1];
             sz[m] = p[3 * m + 2];
-            cell[(v + 1) * W + 4 * q + m + 1] = Cell<R>{sx[m], sy[m], sz[m], R(0)};
+            cell[(v + 1) * W + SPT * q + m + 1] = Cell<R>{sx[m], sy[m], sz[m], R(0)};
         }
     }
     if (a.B > 1) {
@@ -217,12 +217,12 @@ __global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs
         if (v == 0) {
             const int yy = y0 == 0 ? L - 1 : y0 - 1;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) stage(yy, xq + m, 4 * q + m + 1);
+            for (int m = 0; m < SPT; ++m) stage(yy, xq + m, SPT * q + m + 1);
         }
         if (v == T - 1) {
             const int yy = y0 + T == L ? 0 : y0 + T;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) stage(yy, xq + m, (T + 1) * W + 4 * q + m + 1);
+            for (int m = 0; m < SPT; ++m) stage(yy, xq + m, (T + 1) * W + SPT * q + m + 1);
         }
         if (q == 0) stage(y, x0 == 0 ? L - 1 : x0 - 1, (v + 1) * W);
         if (q == QPR - 1) stage(y, x0 + T == L ? 0 : x0 + T, (v + 1) * W + T + 1);
@@ -233,8 +233,8 @@ __global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs
     const int rowU = (v == 0 ? (one ? T : 0) : v) * W;
     const int rowD = (v == T - 1 ? (one ? 1 : T + 1) : v + 2) * W;
     const int rowO = (v + 1) * W;
-    const int colL = q == 0 && one ? T : 4 * q;             // LDS column of x - 1 of site 0
-    const int colR = q == QPR - 1 && one ? 1 : 4 * q + 5;   // LDS column of x + 1 of site 3
+    const int colL = q == 0 && one ? T : SPT * q;                // LDS column of x - 1 of site 0
+    const int colR = q == QPR - 1 && one ? 1 : SPT * q + SPT + 1;  // LDS column of x + 1 of site SPT - 1
     const uint32_t hrow = (uint32_t)(((int64_t)y * L + xq) >> 1);  // in-colour index of the first own site pair
     __syncthreads();
 
@@ -268,23 +268,28 @@ __global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs
         }
     };
     auto own = [&](int m) { return Cell<R>{sx[m], sy[m], sz[m], R(0)}; };
-    // Half-hit of colour C; P = 1 when the row's colour-C sites are the odd columns.
+    // Half-hit of colour C; P = 1 when the row's colour-C sites are the odd
+    // columns.  The own sites of colour C are P, P + 2, ..; their horizontal
+    // neighbours are own sites of the other colour except at the two ends.
     auto half = [&](auto cc, auto pp, uint32_t tj) __attribute__((always_inline)) {
         constexpr int C = decltype(cc)::value, P = decltype(pp)::value;
-        constexpr int ma = P, mb = P + 2;  // own sites of colour C
-        const Cell<R> ua = cell[rowU + 4 * q + ma + 1], da = cell[rowD + 4 * q + ma + 1];
-        const Cell<R> ub = cell[rowU + 4 * q + mb + 1], db = cell[rowD + 4 * q + mb + 1];
-        if constexpr (P == 0) {
-            const Cell<R> edge = cell[rowO + colL];
-            move(ma, C, own(1), edge, da, ua, tj);
-            move(mb, C, own(3), own(1), db, ub, tj);
-        } else {
-            const Cell<R> edge = cell[rowO + colR];
-            move(ma, C, own(2), own(0), da, ua, tj);
-            move(mb, C, edge, own(2), db, ub, tj);
+        constexpr int K = SPT / 2;
+        Cell<R> up[K], dn[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            up[i] = cell[rowU + SPT * q + P + 2 * i + 1];
+            dn[i] = cell[rowD + SPT * q + P + 2 * i + 1];
         }
-        cell[rowO + 4 * q + ma + 1] = own(ma);
-        cell[rowO + 4 * q + mb + 1] = own(mb);
+        const Cell<R> edge = cell[rowO + (P == 0 ? colL : colR)];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int m = P + 2 * i;
+            const Cell<R> lf = m == 0 ? edge : own(m == 0 ? 0 : m - 1);
+            const Cell<R> rt = m == SPT - 1 ? edge : own(m == SPT - 1 ? 0 : m + 1);
+            move(m, C, rt, lf, dn[i], up[i], tj);
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) cell[rowO + SPT * q + P + 2 * i + 1] = own(P + 2 * i);
         __syncthreads();
     };
     using I0 = std::integral_constant<int, 0>;
@@ -310,7 +315,7 @@ __global__ __launch_bounds__(HeisGeom<T>::THREADS) void k_heis_dcb2d(HeisDcbArgs
     {
         R *p = S + ((int64_t)y * L + xq) * 3;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < SPT; ++m) {
             p[3 * m] = sx[m];
             p[3 * m + 1] = sy[m];
             p[3 * m + 2] = sz[m];
@@ -345,23 +350,28 @@ __global__ __launch_bounds__(256) void k_heis_dcb_renorm(void *spins, int64_t n_
     s[2] = z;
 }
 
-template <int T, int MODE>
+template <int T, int SPT, int MODE>
 hipError_t launch_t(const HeisDcbArgs &a, int n_rep, hipStream_t s) {
     const unsigned blocks = (unsigned)(n_rep * a.tiles_per_colour);
+    constexpr unsigned threads = HeisGeom<T, SPT>::THREADS;
     if (a.cap > 0.0)
-        hipLaunchKernelGGL((k_heis_dcb2d<T, MODE, true>), dim3(blocks), dim3(HeisGeom<T>::THREADS), 0, s, a);
+        hipLaunchKernelGGL((k_heis_dcb2d<T, SPT, MODE, true>), dim3(blocks), dim3(threads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_heis_dcb2d<T, MODE, false>), dim3(blocks), dim3(HeisGeom<T>::THREADS), 0, s, a);
+        hipLaunchKernelGGL((k_heis_dcb2d<T, SPT, MODE, false>), dim3(blocks), dim3(threads), 0, s, a);
     return hipGetLastError();
 }
+
+// Four sites per thread (eight were measured: 154 VGPRs, 3 % faster for one
+// case and up to 1.8x slower for the others).
+constexpr int kSpt = 4;
 
 template <int MODE>
 hipError_t launch_mode(const HeisDcbArgs &a, int T, int n_rep, hipStream_t s) {
     switch (T) {
-        case 16: return launch_t<16, MODE>(a, n_rep, s);
-        case 32: return launch_t<32, MODE>(a, n_rep, s);
+        case 16: return launch_t<16, kSpt, MODE>(a, n_rep, s);
+        case 32: return launch_t<32, kSpt, MODE>(a, n_rep, s);
         case 64:
-            if constexpr (MODE != SMC_HEIS_DOUBLE) return launch_t<64, MODE>(a, n_rep, s);
+            if constexpr (MODE != SMC_HEIS_DOUBLE) return launch_t<64, kSpt, MODE>(a, n_rep, s);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
