@@ -193,6 +193,22 @@ int smc_measure_energy_magnetisation(const smc_desc *desc, const void *spins,
                                      double *magnetisation, void *stream);
 
 /*
+ * Autotuning of launch shapes; it never changes results.  For a 2D Ising or
+ * EA batch it measures the workgroup size of the LDS-resident 2D kernel
+ * (small lattices, uneven tempering) for every edge of the batch that this
+ * kernel takes and keeps the choice for later calls in the process (calls
+ * that meet an edge first measure it themselves, on copies of their own
+ * replicas).  Other batches have nothing to tune (SMC_OK).
+ *  cache_path: NULL, or a text file read first (choices recorded for this
+ *              device, identified by its architecture name and compute
+ *              units, are not measured again) and written afterwards (lines
+ *              of other devices are kept).  SMC_EINVAL if it cannot be
+ *              written.
+ * Synchronous with respect to the host; not allowed under stream capture.
+ */
+int smc_autotune(const smc_desc *desc, const char *cache_path, void *stream);
+
+/*
  * How smc_metropolis_sweep will execute this batch: the number of kernel
  * launches per sweep and the name of the sweep kernel (a static string).
  * Used by benchmarks to attribute per-launch time; no device work.

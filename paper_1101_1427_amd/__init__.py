@@ -78,6 +78,8 @@ def lib():
         L.smc_heis_dcb_sweep.argtypes = [P(Desc), C.c_void_p, P(C.c_double), C.c_uint64, C.c_int32, C.c_int32,
                                          C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p]
         L.smc_heis_dcb_sweep.restype = C.c_int
+        L.smc_autotune.argtypes = [P(Desc), C.c_char_p, C.c_void_p]
+        L.smc_autotune.restype = C.c_int
         L.smc_dcb_plan.argtypes = [P(Desc), P(C.c_double), C.c_int32, P(C.c_char_p)]
         L.smc_dcb_plan.restype = C.c_int
         L.smc_philox_bench.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
@@ -220,6 +222,14 @@ def heis_dcb_sweep(batch: Batch, spins, beta, sweep0: int, n_sweeps: int, tile: 
     _check(lib().smc_heis_dcb_sweep(C.byref(d), _ptr(spins), b.ctypes.data_as(C.POINTER(C.c_double)), sweep0,
                                     n_sweeps, tile, hits, precision, 1 if palindromic else 0, float(cap),
                                     _ptr(accepts), _stream(stream)), "smc_heis_dcb_sweep")
+
+
+def autotune(batch: Batch, cache_path=None, stream=None):
+    """Measure the launch shapes of the batch's 2D kernels (see smc_autotune);
+    cache_path: a text file read before and written after tuning, or None."""
+    d = batch.desc(batch.spins_shape()[0], batch.coup_len())
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().smc_autotune(C.byref(d), path, _stream(stream)), "smc_autotune")
 
 
 def dcb_plan(batch: Batch, beta, tile: int) -> str:

@@ -906,6 +906,104 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
     return SMC_OK;
 }
 
+// The device's identity in the autotune cache file: architecture and CUs.
+static std::string device_tag(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "";
+    std::string arch(p.gcnArchName);
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    return arch + ":" + std::to_string(p.multiProcessorCount);
+}
+
+int smc_autotune(const smc_desc *desc, const char *cache_path, void *stream) {
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, false, plan);
+    if (rc) return rc;
+    // the tuned shape: the workgroup size of the LDS-resident 2D kernel per edge
+    if (desc->dim != 2 || (desc->model != SMC_ISING && desc->model != SMC_EA)) return SMC_OK;
+    std::map<int, int> count;  // edge -> replicas
+    for (int r = 0; r < desc->n_rep; ++r) {
+        const int L = desc->L > 0 ? desc->L : desc->inst[r].L;
+        if (uneven2d_edge_supported(L)) ++count[L];
+    }
+    if (count.empty()) return SMC_OK;
+    const bool ea = desc->model == SMC_EA;
+    int dev = 0;
+    SMC_HIP(hipGetDevice(&dev));
+    const std::string tag = device_tag(dev);
+    std::vector<std::string> keep;  // lines of other devices
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char line[256];
+            while (fgets(line, sizeof line, f)) {
+                char t[160];
+                int L = 0, e = 0, th = 0;
+                if (line[0] == '#' || sscanf(line, "%159s %d %d %d", t, &L, &e, &th) != 4) continue;
+                if (tag != t) {
+                    keep.emplace_back(line);
+                    continue;
+                }
+                if (uneven2d_edge_supported(L) && (e == 0 || e == 1) &&
+                    (th == 64 || th == 128 || th == 256 || th == 512)) {
+                    std::lock_guard<std::mutex> lk(g_tune_mutex);
+                    g_tuned[std::make_tuple(dev, L, e)] = th;
+                }
+            }
+            fclose(f);
+        }
+    }
+    // measure the edges not known yet, on scratch lattices (all spins up,
+    // ferromagnetic couplings: the sweep's time does not depend on them)
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    SMC_HIP(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone) return fail(SMC_EINVAL, "smc_autotune cannot run under stream capture");
+    StreamCtx &c = ctx_for(s);
+    const ThrRow row = threshold_row(0.44, 2);
+    void *tp = nullptr, *st = nullptr;
+    if ((rc = upload(c, s, kTables, &row, sizeof row, &tp))) return rc;
+    if ((rc = ensure(c, kStep, 2 * sizeof(uint32_t), &st))) return rc;
+    SMC_HIP(launch_set_step((uint32_t *)st, 0u, s));
+    for (auto &kv : count) {
+        const int L = kv.first, M = std::min(kv.second, 4096);
+        const int64_t N = (int64_t)L * L;
+        void *sp = nullptr, *cp = nullptr;
+        if ((rc = ensure(c, kPingPong, (size_t)(M * N), &sp))) return rc;
+        SMC_HIP(hipMemsetAsync(sp, 0x01, (size_t)(M * N), s));
+        if (ea) {
+            if ((rc = ensure(c, kCoupSplit, (size_t)(2 * N), &cp))) return rc;
+            SMC_HIP(hipMemsetAsync(cp, 0, (size_t)(2 * N), s));
+        }
+        std::vector<smc_inst> rows(M);
+        std::vector<int32_t> reps(M);
+        for (int m = 0; m < M; ++m) {
+            rows[m] = smc_inst{L, 0, (int64_t)m * N, 0};
+            reps[m] = m;
+        }
+        SMC_HIP(uneven2d_prepare_kernel(ea, L));
+        const Uneven2dArgs a = make_uneven2d_args((int8_t *)sp, nullptr, (const uint8_t *)cp, nullptr,
+                                                  (const ThrRow *)tp, nullptr, (const uint32_t *)st,
+                                                  make_key(desc->seed));
+        int th = 0;
+        if ((rc = uneven2d_threads(c, s, a, L, ea, reps, rows, &th))) return rc;
+    }
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "w");
+        if (!f) return fail(SMC_EINVAL, "cannot write the autotune cache %s", cache_path);
+        fprintf(f, "# spinmc autotune cache: device edge ea threads (workgroup size of the LDS-resident 2D sweep)\n");
+        for (const std::string &l : keep) fputs(l.c_str(), f);
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        for (const auto &kv : g_tuned)
+            if (std::get<0>(kv.first) == dev)
+                fprintf(f, "%s %d %d %d\n", tag.c_str(), std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
+        fclose(f);
+    }
+    return SMC_OK;
+}
+
 int smc_spin_init(const smc_desc *desc, void *spins, int8_t *couplings, void *stream) {
     g_last_error.clear();
     Plan plan;
