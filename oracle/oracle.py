@@ -72,6 +72,7 @@ def lib():
             "orc_swap_u53": (D, [U64, U32, U32, U32]),
             "orc_window_run": (None, [I, I, I, I, i8p, D, U64, U32, U32, I]),
             "orc_dcb_run": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
+            "orc_dcb_run3": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
             "orc_heis_dcb_run": (I64, [I, I, I, f64p, D, U64, U32, U32, I, I, I, D]),
         }
         for name, (res, args) in sig.items():
@@ -202,11 +203,11 @@ def pt_run(dim, L, J, spins, beta, slot_of_temp, E, seed, q, r0, t0, n_steps, sw
                      slot_of_temp, E, seed, q, r0, t0, n_steps, sweeps_per_step, _ptr(swap_acc))
 
 
-def dcb_run(L, T, k, J, s, beta, seed, r, t0, n, palindromic=False) -> int:
-    """n double-checkerboard sweeps (T x T tiles, k hits per tile) of a 2D
-    lattice in place; returns the summed Delta E (orc_dcb_run)."""
-    return int(lib().orc_dcb_run(L, T, k, _ptr(J), s, beta, seed & 0xFFFFFFFFFFFFFFFF, r, t0, n,
-                                 1 if palindromic else 0))
+def dcb_run(L, T, k, J, s, beta, seed, r, t0, n, palindromic=False, dim=2) -> int:
+    """n double-checkerboard sweeps (T^dim tiles, k hits per tile) of a 2D or
+    3D lattice in place; returns the summed Delta E (orc_dcb_run, orc_dcb_run3)."""
+    f = lib().orc_dcb_run if dim == 2 else lib().orc_dcb_run3
+    return int(f(L, T, k, _ptr(J), s, beta, seed & 0xFFFFFFFFFFFFFFFF, r, t0, n, 1 if palindromic else 0))
 
 
 def heis_dcb_run(L, T, k, s, beta, seed, r, t0, n, palindromic=False, renorm_every=16, cap=0.0) -> int:

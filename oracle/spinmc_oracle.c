@@ -352,6 +352,57 @@ EXPORT int64_t orc_dcb_run(int L, int T, int k, const int8_t *J, int8_t *s, doub
     return dE_sum;
 }
 
+/* The same in three dimensions (the paper carries the tiled update over to
+ * 3D): T x T x T tiles, tile colour (bx + by + bz) & 1, tile colour 0 first,
+ * colour-0 sites (x + y + z even) of a tile before its colour-1 sites, the
+ * sites outside the tile held fixed; hit j of sweep t draws as plain sweep
+ * t*k + j, so T = L and k = 1 is orc_sweep in 3D. */
+EXPORT int64_t orc_dcb_run3(int L, int T, int k, const int8_t *J, int8_t *s, double beta, uint64_t seed,
+                            uint32_t r, uint32_t t0, int n, int palindromic)
+{
+    uint64_t thr[4];
+    orc_thresholds(beta, 3, thr);
+    const int B = L / T;
+    int64_t dE_sum = 0;
+    for (int m = 0; m < n; ++m) {
+        const uint32_t t = t0 + (uint32_t)m;
+        const int rev = palindromic && (t & 1u);
+        for (int ci = 0; ci < 2; ++ci) {
+            const int tile_colour = rev ? 1 - ci : ci;
+            for (int bz = 0; bz < B; ++bz)
+                for (int by = 0; by < B; ++by)
+                    for (int bx = 0; bx < B; ++bx) {
+                        if (((bx + by + bz) & 1) != tile_colour) continue;
+                        for (int j = 0; j < k; ++j) {
+                            const uint32_t th = t * (uint32_t)k + (uint32_t)j;
+                            for (int si = 0; si < 2; ++si) {
+                                const int c = rev ? 1 - si : si;
+                                for (int w = 0; w < T; ++w)
+                                    for (int v = 0; v < T; ++v)
+                                        for (int u = 0; u < T; ++u) {
+                                            const int x = bx * T + u, y = by * T + v, z = bz * T + w;
+                                            if (((x + y + z) & 1) != c) continue;
+                                            const int64_t i = ((int64_t)z * L + y) * L + x;
+                                            const int h = local_field(3, L, J, s, i);
+                                            const int dE = 2 * s[i] * h;
+                                            int accept = 1;
+                                            if (dE > 0) {
+                                                uint32_t uu = orc_metropolis_u32(seed, th, r, c, (uint64_t)(i >> 1));
+                                                accept = (uint64_t)uu < thr[dE / 4];
+                                            }
+                                            if (accept) {
+                                                s[i] = (int8_t)(-s[i]);
+                                                dE_sum += dE;
+                                            }
+                                        }
+                            }
+                        }
+                    }
+        }
+    }
+    return dE_sum;
+}
+
 /* n sweeps t0 .. t0+n-1 of a W x W window of a 2D Ising lattice of edge L
  * (no couplings), for checking sampled sites of lattices too large to sweep
  * here.  win[v*W + u] is the site (x0 + u, y0 + v) mod L; every interior

@@ -100,3 +100,60 @@ def test_4x4_tiled_runs_match_enumeration(ea, k, pal):
         vals = np.array(vals)
         err = vals.std(ddof=1) / math.sqrt(len(vals))
         assert abs(vals.mean() - ex[key]) < 4.5 * err, (key, vals.mean(), ex[key], err)
+
+
+# ---------------------------------------------------------------- 3D --
+@pytest.mark.parametrize("ea", [False, True])
+def test_3d_single_tile_single_hit_is_the_plain_sweep(ea):
+    L = 8
+    J = O.init_couplings(3, L, SEED, 5) if ea else None
+    a = O.init_spins(3, L, SEED, 5)
+    b = a.copy()
+    da = O.run(3, L, J, a, 0.3, SEED, 5, 4, 3)
+    db = O.dcb_run(L, L, 1, J, b, 0.3, SEED, 5, 4, 3, dim=3)
+    assert np.array_equal(a, b) and da == db
+
+
+def test_3d_single_tile_k_hits_are_k_plain_sweeps():
+    L, k = 8, 3
+    a = O.init_spins(3, L, SEED, 6)
+    b = a.copy()
+    O.run(3, L, None, a, 0.25, SEED, 6, 2 * k, 2 * k)
+    O.dcb_run(L, L, k, None, b, 0.25, SEED, 6, 2, 2, dim=3)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("T,k,pal", [(4, 2, False), (2, 3, True)])
+def test_3d_beta_zero_flips_every_attempt(T, k, pal):
+    L, n = 8, 2
+    s = O.init_spins(3, L, SEED, 7)
+    s0 = s.copy()
+    O.dcb_run(L, T, k, None, s, 0.0, SEED, 7, 0, n, palindromic=pal, dim=3)
+    assert np.array_equal(s, s0 * (-1) ** (n * k))
+
+
+def test_3d_tiling_changes_the_chain():
+    L = 8
+    a = O.init_spins(3, L, SEED, 8)
+    b = a.copy()
+    O.dcb_run(L, 4, 1, None, a, 0.3, SEED, 8, 0, 1, dim=3)
+    O.dcb_run(L, L, 1, None, b, 0.3, SEED, 8, 0, 1, dim=3)
+    assert not np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("T,k", [(4, 2), (2, 4)])
+def test_3d_high_temperature_energy(T, k):
+    """beta = 0.1 (t^5 corrections below 1e-5): the tiled multi-hit chain
+    samples the energy of the high-temperature series."""
+    L, beta = 8, 0.1
+    means = []
+    for r in range(8):
+        s = O.init_spins(3, L, SEED, 20 + r)
+        series = []
+        for t in range(150):
+            O.dcb_run(L, T, k, None, s, beta, SEED, 20 + r, t, 1, dim=3)
+            if t >= 10:
+                series.append(O.energy(3, L, None, s) / L ** 3)
+        means.append(np.mean(series))
+    m, err = np.mean(means), np.std(means, ddof=1) / math.sqrt(len(means))
+    assert abs(m - X.ising_highT_energy(beta, 3)) < 4.5 * err + 2e-5
