@@ -494,6 +494,30 @@ def dcb_scan(S, W, sizes=(64, 256, 1024, 4096, 16384), hits=(1, 100), beta=0.4, 
                         f"checkerboard with k hits, ps per attempted flip", "by_size": rows}
 
 
+def dcb3d(S, W, L=256, hits=(1, 10, 100), beta=0.22, flips=4e9):
+    """3D Ising double checkerboard (16^3 tiles; the paper's 3D timings use
+    k = 100) on one 256^3 lattice near the critical coupling: ps per
+    attempted flip against k, and the plain 3D checkerboard sweep."""
+    import torch
+
+    b = S.Batch(S.ISING, 3, L, 1, W.seed_for(102))
+    spins = torch.empty(L ** 3, dtype=torch.int8, device="cuda")
+    S.spin_init(b, spins)
+    n = max(2, int(flips // L ** 3))
+    S.metropolis_sweep(b, spins, [beta], 0, 2)
+    ms = _timed(lambda: S.metropolis_sweep(b, spins, [beta], 2, n))
+    rows = [{"update": "checkerboard", "kernel": S.sweep_plan(b)[1], "ps_per_flip": round(ms * 1e9 / (n * L ** 3), 4)}]
+    for k in hits:
+        nk = max(2, n // k)
+        S.dcb_sweep(b, spins, [beta], 0, 1, 16, k)
+        ms = _timed(lambda: S.dcb_sweep(b, spins, [beta], 1, nk, 16, k))
+        rows.append({"update": f"double checkerboard k = {k}", "kernel": S.dcb_plan(b, [beta], 16),
+                     "ps_per_flip": round(ms * 1e9 / (nk * k * L ** 3), 4)})
+    del spins
+    torch.cuda.empty_cache()
+    return {"workload": f"3D Ising {L}^3, beta = {beta}, one lattice, 16^3 tiles", "rows": rows}
+
+
 def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
     """The paper's Heisenberg benchmark (Sec. 4): 2D, L = 4096, double
     checkerboard with k = 100 hits, in the three arithmetic modes (float32
@@ -892,7 +916,8 @@ def main():
         return
     if args.dcb_only:
         print(json.dumps({"dcb2d": dcb2d(S, W, args.dcb_sweeps),
-                          "dcb_scan": dcb_scan(S, W, flips=args.dcb_scan_flips)}))
+                          "dcb_scan": dcb_scan(S, W, flips=args.dcb_scan_flips),
+                          "dcb3d": dcb3d(S, W, flips=args.dcb_scan_flips)}))
         return
     if args.heis_dcb_only:
         print(json.dumps({"heis_dcb2d": heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)}))
@@ -992,6 +1017,7 @@ def main():
         out["msc_ea2d"] = _section("msc_ea2d", lambda: msc_ea2d(S, W, args.msc_sweeps))
         out["dcb2d"] = _section("dcb2d", lambda: dcb2d(S, W, args.dcb_sweeps))
         out["dcb_scan"] = _section("dcb_scan", lambda: dcb_scan(S, W, flips=args.dcb_scan_flips))
+        out["dcb3d"] = _section("dcb3d", lambda: dcb3d(S, W, flips=args.dcb_scan_flips))
         out["heis_dcb2d"] = _section("heis_dcb2d", lambda: heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg)

@@ -278,9 +278,8 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t word_bits, int3
 /*
  * Double checkerboard sweeps with multi-hit updates (Sec. 3.2, Sec. 3.4): a
  * different Markov chain from smc_metropolis_sweep, whose order depends on
- * the tiling.  The 2D lattice is cut into tile x tile
- * tiles, B = L / tile per direction; tile (bx, by) has tile colour
- * (bx + by) & 1.  Sweep t treats every tile of tile colour 0, then every
+ * the tiling.  The lattice is cut into tiles of edge `tile`, B = L / tile
+ * per direction; tile (bx, by) has tile colour (bx + by) & 1.  Sweep t treats every tile of tile colour 0, then every
  * tile of colour 1; each tile gets `hits` hits, a hit being a Metropolis
  * attempt (Eq. 2) at each colour-0 site of the tile, then at each colour-1
  * site, with the sites outside the tile held fixed.  With palindromic != 0
@@ -288,8 +287,10 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t word_bits, int3
  * first; two sweeps then form a palindrome of single-colour updates, Sec.
  * 3.4).  Hit j of sweep t draws the uniforms smc_metropolis_sweep draws in
  * sweep t*hits + j; with tile = L and hits = 1 the two calls agree.
- *  desc:      uniform 2D batch (L > 0), model SMC_ISING or SMC_EA.
- *  tile:      a multiple of 16 in [16, 128] with L / tile even or 1.
+ *  desc:      uniform 2D or 3D batch (L > 0), model SMC_ISING or SMC_EA.
+ *             In 3D the tiles are cubes and tile colour is (bx + by + bz) & 1.
+ *  tile:      2D: a multiple of 16 in [16, 128] with L / tile even or 1;
+ *             3D: 16, with L / 16 even or 1.
  *  hits:      >= 1; (sweep0 + n_sweeps) * hits must not exceed 2^32.
  *  spins, couplings, beta (HOST [n_rep]), sweep0, n_sweeps, dE_accum,
  *  stream: as for smc_metropolis_sweep; every replica is updated in place.
@@ -297,8 +298,8 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t word_bits, int3
  *             replica's energy change from the start of the call through
  *             sweep m (a measurement after every sweep, as in the
  *             autocorrelation study of Sec. 3.4); written, not added to.
- * SMC_EUNSUPPORTED for Heisenberg or 3D batches, SMC_EINVAL for a tile or
- * hit count outside these limits.
+ * SMC_EUNSUPPORTED for Heisenberg batches (see smc_heis_dcb_sweep),
+ * SMC_EINVAL for a tile or hit count outside these limits.
  */
 int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
                   int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,

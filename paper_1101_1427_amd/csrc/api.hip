@@ -1254,7 +1254,7 @@ static bool use_dcb_packed(const smc_desc *d, const std::vector<ThrRow> &rows, c
                            const int8_t *coup, int tile) {
     const char *env = getenv("SPINMC_DCB_PACKED");
     if (env && env[0] == '0') return false;
-    if (!dcb2d_packed_supported(d->L, tile)) return false;
+    if (d->dim != 2 || !dcb2d_packed_supported(d->L, tile)) return false;
     if (((uintptr_t)spins & 15u) || ((uintptr_t)coup & 15u)) return false;
     for (const ThrRow &r : rows)
         if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu) return false;
@@ -1268,11 +1268,13 @@ static int dcb_check(const smc_desc *desc, const double *beta, int tile) {
     if (rc) return rc;
     if (desc->model != SMC_ISING && desc->model != SMC_EA)
         return fail(SMC_EUNSUPPORTED, "the double checkerboard is provided for the Ising and EA models");
-    if (desc->dim != 2) return fail(SMC_EUNSUPPORTED, "the double checkerboard is provided for 2D lattices");
     if (desc->L <= 0) return fail(SMC_EINVAL, "the double checkerboard needs a uniform batch (L > 0)");
-    if (!dcb2d_supported(desc->L, tile))
+    if (desc->dim == 2 && !dcb2d_supported(desc->L, tile))
         return fail(SMC_EINVAL, "tile %d: need a multiple of 16 in [16, 128] dividing L = %d into an even number "
                                 "of tiles per row (or one)", tile, desc->L);
+    if (desc->dim == 3 && !dcb3d_supported(desc->L, tile))
+        return fail(SMC_EINVAL, "tile %d: 3D tiles are 16 x 16 x 16, dividing L = %d into an even number of tiles "
+                                "per direction (or one)", tile, desc->L);
     if (!beta) return fail(SMC_EINVAL, "beta is NULL");
     for (int r = 0; r < desc->n_rep; ++r)
         if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
@@ -1291,7 +1293,9 @@ int smc_dcb_plan(const smc_desc *desc, const double *beta, int32_t tile, const c
     if (!kernel_name) return fail(SMC_EINVAL, "kernel_name is NULL");
     int rc = dcb_check(desc, beta, tile);
     if (rc) return rc;
-    *kernel_name = use_dcb_packed(desc, dcb_rows(desc, beta), nullptr, nullptr, tile) ? "k_dcb2d_packed" : "k_dcb2d";
+    *kernel_name = desc->dim == 3 ? "k_dcb3d"
+                   : use_dcb_packed(desc, dcb_rows(desc, beta), nullptr, nullptr, tile) ? "k_dcb2d_packed"
+                                                                                        : "k_dcb2d";
     return SMC_OK;
 }
 
@@ -1313,7 +1317,8 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     const std::vector<ThrRow> rows = dcb_rows(desc, beta);
     void *tp = nullptr, *sp = nullptr;
     if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &tp))) return rc;
-    const int per_rep = 2 * dcb2d_tiles_per_colour(desc->L, tile);
+    const int per_rep =
+        2 * (desc->dim == 3 ? dcb3d_tiles_per_colour(desc->L, tile) : dcb2d_tiles_per_colour(desc->L, tile));
     if (dE_accum || dE_trace) {
         if ((rc = ensure(c, kDcbSlots, sizeof(int64_t) * (size_t)desc->n_rep * per_rep, &sp))) return rc;
         SMC_HIP(launch_dcb_zero((int64_t *)sp, (int64_t)desc->n_rep * per_rep, s));
@@ -1324,10 +1329,16 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     for (int32_t m = 0; m < n_sweeps; ++m) {
         const uint64_t t = sweep0 + (uint64_t)m;
         const bool rev = palindromic && (t & 1u);
-        for (int ci = 0; ci < 2; ++ci)
-            SMC_HIP(launch_dcb2d((int8_t *)spins, ea ? couplings : nullptr, ea ? desc->rep_per_sample : 1,
-                                 (const ThrRow *)tp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits,
-                                 make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, packed, s));
+        for (int ci = 0; ci < 2; ++ci) {
+            if (desc->dim == 3)
+                SMC_HIP(launch_dcb3d((int8_t *)spins, ea ? couplings : nullptr, ea ? desc->rep_per_sample : 1,
+                                     (const ThrRow *)tp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits,
+                                     make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, s));
+            else
+                SMC_HIP(launch_dcb2d((int8_t *)spins, ea ? couplings : nullptr, ea ? desc->rep_per_sample : 1,
+                                     (const ThrRow *)tp, (int64_t *)sp, desc->n_rep, desc->L, tile, hits,
+                                     make_key(desc->seed), (uint32_t)t, rev ? 1 - ci : ci, rev, packed, s));
+        }
         if (dE_trace)
             SMC_HIP(launch_dcb_collect((const int64_t *)sp, dE_trace + (int64_t)m * desc->n_rep, desc->n_rep, per_rep,
                                        true, s));

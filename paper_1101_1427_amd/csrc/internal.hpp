@@ -152,6 +152,13 @@ hipError_t launch_dcb_zero(int64_t *p, int64_t n, hipStream_t s);
 // dE[r] = (assign) or += (otherwise) the sum of replica r's slots.
 hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, bool assign, hipStream_t s);
 
+// 3D double checkerboard (dcb3d.hip): 16^3 tiles, L / 16 even or 1.
+bool dcb3d_supported(int L, int T);
+int dcb3d_tiles_per_colour(int L, int T);
+hipError_t launch_dcb3d(int8_t *spins, const int8_t *coup, int rep_per_sample, const ThrRow *thr, int64_t *dE_slots,
+                        int n_rep, int L, int T, int k, Key key, uint32_t t, int tile_colour, bool rev,
+                        hipStream_t s);
+
 // Heisenberg double checkerboard (2D; T = 16, 32, or 64 in the float modes;
 // L / T even or 1): one launch per tile colour, and the renormalisation of
 // every spin of the batch in the mode's arithmetic.  beta is float or double

@@ -167,7 +167,12 @@ def test_dcb_arguments_are_validated():
     rc = L.smc_dcb_sweep(C.byref(d), FAKE, None, beta, (1 << 31), 1, 32, 2, 0, None, None, None)
     assert rc == S.EINVAL and b"2^32" in L.smc_last_error()
     d3 = _desc(dim=3, L=32, n_rep=1, spins_len=32 ** 3)
-    assert L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 16, 1, 0, None, None, None) == S.EUNSUPPORTED
+    rc = L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 32, 1, 0, None, None, None)
+    assert rc == S.EINVAL and b"16 x 16 x 16" in L.smc_last_error()
+    d3 = _desc(dim=3, L=48, n_rep=1, spins_len=48 ** 3)
+    assert L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 16, 1, 0, None, None, None) == S.EINVAL
+    dh = _desc(model=S.HEISENBERG, dim=3, L=32, n_rep=1, spins_len=3 * 32 ** 3)
+    assert L.smc_dcb_sweep(C.byref(dh), FAKE, None, beta, 0, 1, 16, 1, 0, None, None, None) == S.EUNSUPPORTED
 
 
 def test_dcb_plan_names_the_kernel():

@@ -138,3 +138,62 @@ def test_dcb_energy_trace(kernel):
             acc += O.dcb_run(L, T, k, J, s, betas[r], seed, r, 4 + m, 1, palindromic=True)
             ref[m, r] = acc
     assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- 3D --
+def _gpu3(model, L, n_rep, betas, seed, calls, k, pal, rps=1):
+    b = S.Batch(model, 3, L, n_rep, seed, rep_per_sample=rps)
+    assert S.dcb_plan(b, betas, 16) == "k_dcb3d"
+    spins = torch.zeros(n_rep * L ** 3, dtype=torch.int8, device=DEV)
+    coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV) if model == S.EA else None
+    S.spin_init(b, spins, coup)
+    dE = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
+    for s0, n in calls:
+        S.dcb_sweep(b, spins, betas, s0, n, 16, k, palindromic=pal, couplings=coup, dE_accum=dE)
+    return _host(spins).reshape(n_rep, L ** 3), _host(dE)
+
+
+def _oracle3(model, L, n_rep, betas, seed, t0, n, k, pal, rps=1):
+    out, dEs = [], []
+    for r in range(n_rep):
+        s = O.init_spins(3, L, seed, r)
+        J = O.init_couplings(3, L, seed, r // rps) if model == S.EA else None
+        dEs.append(O.dcb_run(L, 16, k, J, s, float(betas[r]), seed, r, t0, n, palindromic=pal, dim=3))
+        out.append(s)
+    return np.stack(out), np.array(dEs, np.int64)
+
+
+@pytest.mark.parametrize("model,L,k,pal,rps", [(S.ISING, 32, 2, True, 1), (S.EA, 32, 3, False, 1),
+                                               (S.EA, 16, 2, True, 1), (S.EA, 32, 1, False, 3)])
+def test_dcb3d_matches_oracle(model, L, k, pal, rps):
+    seed, n_rep = W.seed_for(78), 3
+    betas = [0.15, 0.22, 0.4]
+    got_s, got_dE = _gpu3(model, L, n_rep, betas, seed, [(2, 2), (4, 1)], k, pal, rps)
+    ref_s, ref_dE = _oracle3(model, L, n_rep, betas, seed, 2, 3, k, pal, rps)
+    assert np.array_equal(got_s, ref_s)
+    assert np.array_equal(got_dE, ref_dE)
+
+
+def test_dcb3d_single_tile_single_hit_equals_plain_sweep():
+    seed, L = W.seed_for(79), 16
+    b = S.Batch(S.EA, 3, L, 2, seed)
+    outs = []
+    for use_dcb in (True, False):
+        spins = torch.zeros(2 * L ** 3, dtype=torch.int8, device=DEV)
+        coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV)
+        S.spin_init(b, spins, coup)
+        dE = torch.zeros(2, dtype=torch.int64, device=DEV)
+        if use_dcb:
+            S.dcb_sweep(b, spins, [0.3, 0.8], 3, 5, L, 1, couplings=coup, dE_accum=dE)
+        else:
+            S.metropolis_sweep(b, spins, [0.3, 0.8], 3, 5, couplings=coup, dE_accum=dE)
+        outs.append((_host(spins).copy(), _host(dE).copy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_dcb3d_64_every_site():
+    """64^3, 16^3 tiles (B = 4), 4 hits, 2 sweeps, every site."""
+    seed, L = W.seed_for(80), 64
+    got_s, got_dE = _gpu3(S.ISING, L, 1, [0.22], seed, [(0, 2)], 4, False)
+    ref_s, ref_dE = _oracle3(S.ISING, L, 1, [0.22], seed, 0, 2, 4, False)
+    assert np.array_equal(got_s, ref_s) and np.array_equal(got_dE, ref_dE)
