@@ -34,6 +34,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = {
     "k_ising2d_split": ("lattice2d.hip", "lattice2d.hpp", "philox.hpp", "tables.hpp"),
     "k_heis3d_tiled": ("heis3d.hip", "heis_math.hpp", "philox.hpp"),
+    "k_ising3d_half": ("sweep3d.hip", "philox.hpp", "tables.hpp"),
 }
 
 
@@ -212,6 +213,10 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
     if kernel == "k_heis3d_tiled":
         algorithmic = 24.0 * L ** 3
         what = f"one launch = one sweep of a 3D Heisenberg {L}^3 lattice (24 B per site)"
+    elif kernel == "k_ising3d_half":
+        algorithmic = 1.0 * L ** 3
+        what = (f"one launch = one half-sweep of a 3D Ising {L}^3 lattice; algorithmic bytes = half of the "
+                f"sweep's one read and one write of every spin (1 B per site per launch)")
     else:
         algorithmic = BYTES_PER_FLIP * L * L * 3
         what = f"one launch = one sweep of a batch of three 2D Ising {L}x{L} lattices"
@@ -516,6 +521,39 @@ def dcb3d(S, W, L=256, hits=(1, 10, 100), beta=0.22, flips=4e9):
     del spins
     torch.cuda.empty_cache()
     return {"workload": f"3D Ising {L}^3, beta = {beta}, one lattice, 16^3 tiles", "rows": rows}
+
+
+def sweep3d(S, W, sizes=(256, 512, 1024), beta=0.2216, flips=8e9, models=("ising", "ea")):
+    """Plain 3D checkerboard sweeps (Ising, and EA with one coupling sample)
+    on one L^3 lattice: ps per attempted flip for the segment-per-thread
+    kernel and the per-site kernels, and the rate at 2 B/flip (one read and
+    one write of every spin per sweep) against 8 TB/s."""
+    import os
+    import torch
+
+    rows = []
+    for L in sizes:
+        for model in [m for name, m in (("ising", S.ISING), ("ea", S.EA)) if name in models]:
+            b = S.Batch(model, 3, L, 1, W.seed_for(103))
+            spins = torch.empty(L ** 3, dtype=torch.int8, device="cuda")
+            coup = torch.empty(3 * L ** 3, dtype=torch.int8, device="cuda") if model == S.EA else None
+            S.spin_init(b, spins, coup)
+            n = max(2, int(flips // L ** 3))
+            row = {"model": "EA" if model == S.EA else "Ising", "L": L}
+            for flag in ("1", "0"):
+                os.environ["SPINMC_SWEEP3D"] = flag
+                S.metropolis_sweep(b, spins, [beta], 0, 2, couplings=coup)
+                ms = _timed(lambda: S.metropolis_sweep(b, spins, [beta], 2, n, couplings=coup))
+                ps = ms * 1e9 / (n * L ** 3)
+                key = "segment" if flag == "1" else "per_site"
+                row[key] = {"kernel": S.sweep_plan(b)[1], "ps_per_flip": round(ps, 4),
+                            "hbm_frac_2B": round(2.0 / (ps * 1e-12) / 8e12, 4)}
+            os.environ.pop("SPINMC_SWEEP3D", None)
+            rows.append(row)
+            del spins, coup
+            torch.cuda.empty_cache()
+    return {"workload": f"3D Ising and EA (one +-J sample) checkerboard sweeps, one L^3 lattice, beta = {beta}",
+            "rows": rows}
 
 
 def heis_dcb2d(S, W, sweeps=4, L=4096, hits=100, tiles=(32, 64)):
@@ -854,6 +892,9 @@ def main():
     ap.add_argument("--msc-sweeps", type=int, default=2000)
     ap.add_argument("--dcb-sweeps", type=int, default=64)
     ap.add_argument("--dcb-only", action="store_true", help="only the double-checkerboard measurements")
+    ap.add_argument("--sweep3d-only", action="store_true", help="only the plain 3D Ising / EA sweep measurements")
+    ap.add_argument("--sweep3d-sizes", type=int, nargs="+", default=[256, 512, 1024])
+    ap.add_argument("--sweep3d-models", nargs="+", default=["ising", "ea"], choices=["ising", "ea"])
     ap.add_argument("--dcb-scan-flips", type=float, default=4e9,
                     help="attempted flips per lattice size and update in the L scan")
     ap.add_argument("--heis-dcb-sweeps", type=int, default=4)
@@ -892,7 +933,8 @@ def main():
         kt_summary(*args.kt_summary, kernel="k_ising2d_split", L=args.L, command=args.kt_command)
         return
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, kernel=args.pmc_kernel, L=256 if args.pmc_kernel == "k_heis3d_tiled" else args.L,
+        pmc_L = {"k_heis3d_tiled": 256, "k_ising3d_half": max(args.sweep3d_sizes)}.get(args.pmc_kernel, args.L)
+        pmc_summary(*args.pmc_summary, kernel=args.pmc_kernel, L=pmc_L,
                     commands=args.pmc_command)
         return
     if args.gpus != 1:
@@ -918,6 +960,9 @@ def main():
         print(json.dumps({"dcb2d": dcb2d(S, W, args.dcb_sweeps),
                           "dcb_scan": dcb_scan(S, W, flips=args.dcb_scan_flips),
                           "dcb3d": dcb3d(S, W, flips=args.dcb_scan_flips)}))
+        return
+    if args.sweep3d_only:
+        print(json.dumps({"sweep3d": sweep3d(S, W, sizes=tuple(args.sweep3d_sizes), models=tuple(args.sweep3d_models))}))
         return
     if args.heis_dcb_only:
         print(json.dumps({"heis_dcb2d": heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)}))
@@ -1018,6 +1063,7 @@ def main():
         out["dcb2d"] = _section("dcb2d", lambda: dcb2d(S, W, args.dcb_sweeps))
         out["dcb_scan"] = _section("dcb_scan", lambda: dcb_scan(S, W, flips=args.dcb_scan_flips))
         out["dcb3d"] = _section("dcb3d", lambda: dcb3d(S, W, flips=args.dcb_scan_flips))
+        out["sweep3d"] = _section("sweep3d", lambda: sweep3d(S, W))
         out["heis_dcb2d"] = _section("heis_dcb2d", lambda: heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg)

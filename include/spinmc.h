@@ -46,11 +46,16 @@
  *   workgroup's LDS for up to 256 sweeps per launch; 3D edge-16 tempering
  *   runs all steps of a call in one launch; 2D tempering with edges in
  *   {16, 32, ..., 256} runs one workgroup per replica per step (a graph of
- *   steps); everything else takes generic per-site kernels.  All paths give
+ *   steps); uniform 3D Ising / EA batches with L a multiple of 16 sweep
+ *   16-site row segments per thread (two launches per sweep, in place);
+ *   everything else takes generic per-site kernels.  All paths give
  *   identical results.  Environment variables for comparisons and tuning
  *   (read at each call): SPINMC_PT3D=0, SPINMC_UNEVEN2D=0 and
  *   SPINMC_PT_SPLIT2D=0 send tempering to the generic kernels,
- *   SPINMC_SWEEP_LDS2D=0 small 2D sweeps; SPINMC_L2D_CHUNKS (1 or 2),
+ *   SPINMC_SWEEP_LDS2D=0 small 2D sweeps, SPINMC_SWEEP3D=0 3D Ising / EA
+ *   sweeps (SPINMC_SWEEP3D_Z = 1 .. 16 rows per thread and
+ *   SPINMC_SWEEP3D_NT=0, plain stores, set their launch shape);
+ *   SPINMC_L2D_CHUNKS (1 or 2),
  *   SPINMC_L2D_H (band height, a multiple of 4), SPINMC_L2D_H1 /
  *   SPINMC_L2D_H2 (heights of the bands of the first and second half of
  *   the grid) and SPINMC_L2D_PAD (row padding in bytes) set the launch

@@ -223,6 +223,24 @@ bool use_lattice2d(const smc_desc *d, const void *spins, const std::vector<ThrRo
     return true;
 }
 
+// Uniform 3D Ising / EA batches with an edge that is a multiple of 16 take
+// the segment-per-thread half-sweeps when spins (and couplings) are 16-byte
+// aligned and every threshold has a 16-bit high half; SPINMC_SWEEP3D=0 keeps
+// them on the generic kernels (same results).
+bool sweep3d_shape(const smc_desc *d) {
+    const char *env = getenv("SPINMC_SWEEP3D");
+    if (env && env[0] == '0') return false;
+    return d->dim == 3 && d->L > 0 && (d->model == SMC_ISING || d->model == SMC_EA) && sweep3d_supported(d->L);
+}
+
+bool use_sweep3d(const smc_desc *d, const void *spins, const int8_t *coup, const std::vector<ThrRow> &rows) {
+    if (!sweep3d_shape(d)) return false;
+    if (((uintptr_t)spins & 15u) != 0 || ((uintptr_t)coup & 15u) != 0) return false;
+    for (const ThrRow &r : rows)
+        if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu || r.m[3].x > 0xFFFFu) return false;
+    return true;
+}
+
 // Tempering of a uniform 2D Ising batch on the one-pass colour-split sweep:
 // L a power of two in [1024, 16384], aligned spins, thresholds of every
 // temperature with 16-bit high halves; SPINMC_PT_SPLIT2D=0 sends such
@@ -843,6 +861,9 @@ int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char
     } else if (desc->model == SMC_ISING && desc->dim == 2 && desc->L > 0 && lattice2d_supported(desc->L)) {
         *launches_per_sweep = 1;
         *kernel_name = "k_ising2d_split";
+    } else if (sweep3d_shape(desc)) {
+        *launches_per_sweep = 2;
+        *kernel_name = "k_ising3d_half";
     } else if (lds2d_sweep_shape(desc) && !(getenv("SPINMC_UNEVEN2D") && getenv("SPINMC_UNEVEN2D")[0] == '0')) {
         *launches_per_sweep = 1;  // at most: up to 256 sweeps per launch
         *kernel_name = "k_uneven2d_sweep";
@@ -1155,6 +1176,16 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         timer.finish();
         if (part) SMC_HIP(launch_lattice2d_de_collect(part, dE_accum, desc->L, desc->n_rep, s));
         SMC_HIP(launch_from_split(n_sweeps & 1 ? B : A, (int8_t *)spins, desc->L, desc->n_rep, s));
+        return SMC_OK;
+    }
+    if (use_sweep3d(desc, spins, a.coup, rows)) {
+        SweepTimer timer(s, 2 * (int64_t)n_sweeps);
+        for (int32_t k = 0; k < n_sweeps; ++k) {
+            const uint32_t t = (uint32_t)(sweep0 + (uint64_t)k);
+            for (int col = 0; col < 2; ++col)
+                SMC_HIP(launch_ising3d_half((int8_t *)spins, a.coup, plan.b.rep_per_sample, a.thr, dE_accum,
+                                            desc->n_rep, desc->L, a.key, t, col, s));
+        }
         return SMC_OK;
     }
     SweepTimer timer(s, 2 * (int64_t)n_sweeps);

@@ -152,6 +152,13 @@ hipError_t launch_dcb_zero(int64_t *p, int64_t n, hipStream_t s);
 // dE[r] = (assign) or += (otherwise) the sum of replica r's slots.
 hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, bool assign, hipStream_t s);
 
+// Half-sweeps of uniform 3D Ising / EA batches with L a multiple of 16
+// (sweep3d.hip): in place, 16-byte aligned spins and couplings, threshold
+// high halves <= 0xFFFF; dE (nullable) accumulates per replica.
+bool sweep3d_supported(int L);
+hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, int rep_per_sample, const ThrRow *thr,
+                               int64_t *dE, int n_rep, int L, Key key, uint32_t t, int c, hipStream_t s);
+
 // 3D double checkerboard (dcb3d.hip): 16^3 tiles, L / 16 even or 1.
 bool dcb3d_supported(int L, int T);
 int dcb3d_tiles_per_colour(int L, int T);

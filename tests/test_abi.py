@@ -222,3 +222,15 @@ def test_autotune_has_nothing_to_tune_for_other_batches(tmp_path):
         assert L.smc_autotune(C.byref(d), path, None) == S.OK
     assert not (tmp_path / "tune.txt").exists()
     assert L.smc_autotune(None, path, None) == S.EINVAL
+
+
+def test_sweep_plan_names_the_3d_kernel(monkeypatch):
+    """smc_sweep_plan: uniform 3D Ising / EA batches with an edge that is a
+    multiple of 16 take the segment-per-thread half-sweeps; other edges,
+    Heisenberg batches and SPINMC_SWEEP3D=0 the generic kernels."""
+    for model, L, want in ((S.ISING, 16, "k_ising3d_half"), (S.EA, 48, "k_ising3d_half"),
+                           (S.ISING, 20, "k_half_sweep_generic"), (S.EA, 8, "k_half_sweep_generic")):
+        assert S.sweep_plan(S.Batch(model, 3, L, 2, 1)) == (2, want)
+    assert S.sweep_plan(S.Batch(S.HEISENBERG, 3, 32, 1, 1))[1] != "k_ising3d_half"
+    monkeypatch.setenv("SPINMC_SWEEP3D", "0")
+    assert S.sweep_plan(S.Batch(S.ISING, 3, 64, 1, 1)) == (2, "k_half_sweep_generic")
