@@ -164,7 +164,8 @@ def _oracle3(model, L, n_rep, betas, seed, t0, n, k, pal, rps=1):
 
 
 @pytest.mark.parametrize("model,L,k,pal,rps", [(S.ISING, 32, 2, True, 1), (S.EA, 32, 3, False, 1),
-                                               (S.EA, 16, 2, True, 1), (S.EA, 32, 1, False, 3)])
+                                               (S.EA, 16, 2, True, 1), (S.EA, 32, 1, False, 3),
+                                               (S.EA, 64, 2, True, 2)])
 def test_dcb3d_matches_oracle(model, L, k, pal, rps):
     seed, n_rep = W.seed_for(78), 3
     betas = [0.15, 0.22, 0.4]
@@ -197,3 +198,13 @@ def test_dcb3d_64_every_site():
     got_s, got_dE = _gpu3(S.ISING, L, 1, [0.22], seed, [(0, 2)], 4, False)
     ref_s, ref_dE = _oracle3(S.ISING, L, 1, [0.22], seed, 0, 2, 4, False)
     assert np.array_equal(got_s, ref_s) and np.array_equal(got_dE, ref_dE)
+
+
+def test_dcb3d_beta_zero_in_the_batch():
+    """A replica at beta = 0 (threshold 2^32: every attempt flips) beside one
+    at beta = 0.5, both orders, on one tile and on 2^3 tiles."""
+    seed = W.seed_for(81)
+    for L, pal in ((16, True), (32, False)):
+        got_s, got_dE = _gpu3(S.EA, L, 2, [0.0, 0.5], seed, [(1, 2)], 3, pal)
+        ref_s, ref_dE = _oracle3(S.EA, L, 2, [0.0, 0.5], seed, 1, 2, 3, pal)
+        assert np.array_equal(got_s, ref_s) and np.array_equal(got_dE, ref_dE)
