@@ -34,7 +34,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = {
     "k_ising2d_split": ("lattice2d.hip", "lattice2d.hpp", "philox.hpp", "tables.hpp"),
     "k_heis3d_tiled": ("heis3d.hip", "heis_math.hpp", "philox.hpp"),
-    "k_ising3d_half": ("sweep3d.hip", "philox.hpp", "tables.hpp"),
+    "k_ising3d_half": ("sweep3d.hip", "segment3d.hpp", "philox.hpp", "tables.hpp"),
 }
 
 
