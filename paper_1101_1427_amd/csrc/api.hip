@@ -81,6 +81,7 @@ enum Slot {
     kPtThr,
     kPtDelta,
     kPtOut,
+    kBonds3d,    // bit-packed 3D EA bonds of the segment sweep
     kNumSlots
 };
 
@@ -1179,11 +1180,25 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         return SMC_OK;
     }
     if (use_sweep3d(desc, spins, a.coup, rows)) {
+        // EA calls of several sweeps read the bonds bit-packed (one pass to
+        // pack them: 3 B per site per sample in, 0.5 B out; the int8 bonds
+        // cost 3 B per site and launch); SPINMC_SWEEP3D_PACK=0 keeps the int8 bonds
+        const int8_t *coup8 = a.coup;
+        const uint2 *packed = nullptr;
+        const char *env = getenv("SPINMC_SWEEP3D_PACK");
+        if (a.coup && n_sweeps >= 4 && !(env && env[0] == '0')) {
+            void *q = nullptr;
+            if ((rc = ensure(c, kBonds3d, (size_t)plan.n_samples * (size_t)(plan.b.N / 16) * sizeof(uint2), &q)))
+                return rc;
+            packed = (const uint2 *)q;
+            coup8 = nullptr;
+            SMC_HIP(launch_pack_bonds3d(a.coup, (uint2 *)q, desc->L, (int)plan.n_samples, s));
+        }
         SweepTimer timer(s, 2 * (int64_t)n_sweeps);
         for (int32_t k = 0; k < n_sweeps; ++k) {
             const uint32_t t = (uint32_t)(sweep0 + (uint64_t)k);
             for (int col = 0; col < 2; ++col)
-                SMC_HIP(launch_ising3d_half((int8_t *)spins, a.coup, plan.b.rep_per_sample, a.thr, dE_accum,
+                SMC_HIP(launch_ising3d_half((int8_t *)spins, coup8, packed, plan.b.rep_per_sample, a.thr, dE_accum,
                                             desc->n_rep, desc->L, a.key, t, col, s));
         }
         return SMC_OK;

@@ -155,9 +155,13 @@ hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int 
 // Half-sweeps of uniform 3D Ising / EA batches with L a multiple of 16
 // (sweep3d.hip): in place, 16-byte aligned spins and couplings, threshold
 // high halves <= 0xFFFF; dE (nullable) accumulates per replica.
+// EA bonds come as int8 (coup) or bit-packed (pbonds, from
+// launch_pack_bonds3d: [sample][L^3 / 16] uint2), the other nullptr.
 bool sweep3d_supported(int L);
-hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, int rep_per_sample, const ThrRow *thr,
-                               int64_t *dE, int n_rep, int L, Key key, uint32_t t, int c, hipStream_t s);
+hipError_t launch_pack_bonds3d(const int8_t *coup, uint2 *out, int L, int n_samples, hipStream_t s);
+hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, const uint2 *pbonds, int rep_per_sample,
+                               const ThrRow *thr, int64_t *dE, int n_rep, int L, Key key, uint32_t t, int c,
+                               hipStream_t s);
 
 // 3D double checkerboard (dcb3d.hip): 16^3 tiles, L / 16 even or 1.
 bool dcb3d_supported(int L, int T);

@@ -82,13 +82,70 @@ struct RowOut {
 
 // One segment: own row raw bytes, neighbours' raw bytes, the extra x
 // neighbour bit eb, the per-row bond arrays (EA), Philox block index h0.
+// Bonds of the eight own sites (bit 1 where J = -1, one byte per site, in
+// the order of the own array): b pairs with the other array of the row
+// unshifted, s with it shifted by one site (see segment_update), and the
+// bonds to y + 1, y - 1, z + 1, z - 1.
+struct Bonds3 {
+    uint2 b, s, yp, ym, zp, zm;
+};
+
+// From the int8 bond rows: +x bonds of the row (jx) and the bond entering
+// it from x0 - 1 (bit jeb), +y bonds of the row (jy) and of row y - 1
+// (jym), +z bonds of the row (jz) and of row z - 1 (jzm).
+__device__ __forceinline__ Bonds3 bonds_from_bytes(const uint4 &jx, uint32_t jeb, const uint4 &jy, const uint4 &jym,
+                                                   const uint4 &jz, const uint4 &jzm, int A) {
+    const uint32_t sa = A ? 0x07050301u : 0x06040200u, sb = A ? 0x06040200u : 0x07050301u;
+    const uint2 jxa = bits2(half_of(jx, sa)), jxb = bits2(half_of(jx, sb));
+    Bonds3 bd;
+    // paired with the unshifted other array: x -> x + 1 of even-x sites
+    // (array a), x - 1 -> x of odd-x sites (array b); with the shifted one:
+    // x + 1 of odd-x sites (array a), x - 1 of even-x sites (array b shifted
+    // up, x0 - 1 entering)
+    bd.b = A ? jxb : jxa;
+    bd.s.x = A ? jxa.x : ((jxb.x << 8) | jeb);
+    bd.s.y = A ? jxa.y : alignbyte(jxb.y, jxb.x, 3);
+    bd.yp = bits2(half_of(jy, sa));
+    bd.ym = bits2(half_of(jym, sa));
+    bd.zp = bits2(half_of(jz, sa));
+    bd.zm = bits2(half_of(jzm, sa));
+    return bd;
+}
+
+// Eight bits to eight 0/1 bytes.
+__device__ __forceinline__ uint2 spread8(uint32_t m) {
+    return make_uint2(((m & 15u) * 0x00204081u) & 0x01010101u, (((m >> 4) & 15u) * 0x00204081u) & 0x01010101u);
+}
+
+// From bit-packed bond masks of one direction and segment: bits 0..7 the
+// even-x sites, bits 8..15 the odd-x sites (bit 1 where J = -1).  jx, jy, jz
+// are the row's masks, jym and jzm those of rows y - 1 and z - 1, jeb the
+// bond entering the row from x0 - 1.
+__device__ __forceinline__ Bonds3 bonds_from_bits(uint32_t jx, uint32_t jeb, uint32_t jy, uint32_t jym, uint32_t jz,
+                                                  uint32_t jzm, int A) {
+    const int sh = A ? 8 : 0;
+    const uint32_t ax = (jx >> sh) & 0xFFu, bx = (jx >> (8 - sh)) & 0xFFu;
+    Bonds3 bd;
+    bd.b = spread8(A ? bx : ax);
+    bd.s = spread8(A ? ax : (((bx << 1) | jeb) & 0xFFu));
+    bd.yp = spread8((jy >> sh) & 0xFFu);
+    bd.ym = spread8((jym >> sh) & 0xFFu);
+    bd.zp = spread8((jz >> sh) & 0xFFu);
+    bd.zm = spread8((jzm >> sh) & 0xFFu);
+    return bd;
+}
+
+// Four 0/1 bytes to four bits.
+__device__ __forceinline__ uint32_t gather4(uint32_t w) { return (w * 0x01020408u) >> 24; }
+
+// One segment: own row raw bytes, the neighbour rows' raw bytes, the x
+// neighbour beyond the segment (bit eb: x0 + 16 for odd-x own sites, x0 - 1
+// for even-x), the bonds (EA), Philox block index h0 of the own sites.
 template <bool EA>
 __device__ __forceinline__ RowOut segment_update(const uint4 &own, const uint4 &rym, const uint4 &ryp,
                                                  const uint4 &rzm, const uint4 &rzp, uint32_t eb, int A,
-                                                 const uint4 &jx, uint32_t jeb, const uint4 &jy, const uint4 &jym,
-                                                 const uint4 &jz, const uint4 &jzm, const ThrRow &th, uint32_t h0,
-                                                 uint32_t c, uint32_t t, uint32_t r, Key key, uint32_t one2,
-                                                 uint32_t four) {
+                                                 const Bonds3 &bd, const ThrRow &th, uint32_t h0, uint32_t c,
+                                                 uint32_t t, uint32_t r, Key key, uint32_t one2, uint32_t four) {
     const uint32_t sa = A ? 0x07050301u : 0x06040200u, sb = A ? 0x06040200u : 0x07050301u;
     const uint2 Sa = bits2(half_of(own, sa));
     const uint2 Sb = bits2(half_of(own, sb));
@@ -103,20 +160,10 @@ __device__ __forceinline__ RowOut segment_update(const uint4 &own, const uint4 &
     sh.y = A ? ((Sb.y >> 8) | (eb << 24)) : alignbyte(Sb.y, Sb.x, 3);
     RowOut o;
     if constexpr (EA) {
-        const uint2 jxa = bits2(half_of(jx, sa)), jxb = bits2(half_of(jx, sb));
-        // bond paired with Sb: x -> x + 1 of even-x sites (array a), x - 1 -> x
-        // of odd-x sites (array b); bond paired with sh: x + 1 of odd-x sites
-        // (array a), x - 1 of even-x sites (array b shifted up, x0 - 1 entering)
-        const uint2 bB = A ? jxb : jxa;
-        uint2 bS;
-        bS.x = A ? jxa.x : ((jxb.x << 8) | jeb);
-        bS.y = A ? jxa.y : alignbyte(jxb.y, jxb.x, 3);
-        const uint2 jyp = bits2(half_of(jy, sa)), jymb = bits2(half_of(jym, sa));
-        const uint2 jzp = bits2(half_of(jz, sa)), jzmb = bits2(half_of(jzm, sa));
-        o.n0 = ((Sa.x ^ Sb.x ^ bB.x) + (Sa.x ^ sh.x ^ bS.x)) + ((Sa.x ^ yp.x ^ jyp.x) + (Sa.x ^ ym.x ^ jymb.x)) +
-               ((Sa.x ^ zp.x ^ jzp.x) + (Sa.x ^ zm.x ^ jzmb.x));
-        o.n1 = ((Sa.y ^ Sb.y ^ bB.y) + (Sa.y ^ sh.y ^ bS.y)) + ((Sa.y ^ yp.y ^ jyp.y) + (Sa.y ^ ym.y ^ jymb.y)) +
-               ((Sa.y ^ zp.y ^ jzp.y) + (Sa.y ^ zm.y ^ jzmb.y));
+        o.n0 = ((Sa.x ^ Sb.x ^ bd.b.x) + (Sa.x ^ sh.x ^ bd.s.x)) + ((Sa.x ^ yp.x ^ bd.yp.x) + (Sa.x ^ ym.x ^ bd.ym.x)) +
+               ((Sa.x ^ zp.x ^ bd.zp.x) + (Sa.x ^ zm.x ^ bd.zm.x));
+        o.n1 = ((Sa.y ^ Sb.y ^ bd.b.y) + (Sa.y ^ sh.y ^ bd.s.y)) + ((Sa.y ^ yp.y ^ bd.yp.y) + (Sa.y ^ ym.y ^ bd.ym.y)) +
+               ((Sa.y ^ zp.y ^ bd.zp.y) + (Sa.y ^ zm.y ^ bd.zm.y));
     } else {
         o.n0 = ((Sa.x ^ Sb.x) + (Sa.x ^ sh.x)) + ((Sa.x ^ yp.x) + (Sa.x ^ ym.x)) + ((Sa.x ^ zp.x) + (Sa.x ^ zm.x));
         o.n1 = ((Sa.y ^ Sb.y) + (Sa.y ^ sh.y)) + ((Sa.y ^ yp.y) + (Sa.y ^ ym.y)) + ((Sa.y ^ zp.y) + (Sa.y ^ zm.y));

@@ -32,6 +32,7 @@ struct Sweep3dArgs {
     const int8_t *coup;     // EA: [sample][3][L^3] (bond i -> i + mu at mu * L^3 + i), or nullptr
     int rep_per_sample;
     const ThrRow *thr;      // per replica (high halves <= 0xFFFF, checked on the host)
+    const uint2 *pbonds;    // EA bit-packed: [sample][L^3 / 16] (pack_bonds3d), or nullptr
     int64_t *dE;            // per replica, or nullptr
     Key key;
     uint32_t t;
@@ -43,8 +44,10 @@ struct Sweep3dArgs {
 
 // Z rows per thread: the segments (x0, y, z0 .. z0 + Z - 1), each row's
 // z + 1 neighbour becoming the next row, the row itself the next z - 1.
-template <bool EA, int Z, bool NT>
+// M: 0 Ising, 1 EA with the int8 bonds, 2 EA with bit-packed bonds.
+template <int M, int Z, bool NT>
 __global__ __launch_bounds__(kThreads) void k_ising3d_half(Sweep3dArgs a) {
+    constexpr bool EA = M != 0;
     __shared__ long long red[kThreads / 64];
     const int L = a.L;
     const int r = (int)blockIdx.x / a.blocks_per_rep;
@@ -58,7 +61,8 @@ __global__ __launch_bounds__(kThreads) void k_ising3d_half(Sweep3dArgs a) {
         const int x0 = (int)(g - rowq * segs) << 4;
         const int y = (int)(rowq % L), z0 = (int)(rowq / L) * Z;
         int8_t *S = a.spins + (int64_t)r * N;
-        const int8_t *J = EA ? a.coup + (int64_t)(r / a.rep_per_sample) * 3 * N : nullptr;
+        const int8_t *J = M == 1 ? a.coup + (int64_t)(r / a.rep_per_sample) * 3 * N : nullptr;
+        const uint2 *PB = M == 2 ? a.pbonds + (int64_t)(r / a.rep_per_sample) * (N >> 4) : nullptr;
         const int64_t dym = y == 0 ? (LL - 1) * LL : -LL, dyp = y == L - 1 ? -(LL - 1) * LL : LL;
         const int64_t xl = x0 == 0 ? L - 1 : x0 - 1, xr = x0 + 16 == L ? 0 : x0 + 16;
         const ThrRow th = a.thr[r];
@@ -66,9 +70,14 @@ __global__ __launch_bounds__(kThreads) void k_ising3d_half(Sweep3dArgs a) {
         uint4 rzm = *(const uint4 *)(S + (z0 == 0 ? i0 + (LL - 1) * P : i0 - P));
         uint4 own = *(const uint4 *)(S + i0);
         uint4 jzm = make_uint4(0u, 0u, 0u, 0u), jz = jzm;
-        if constexpr (EA) {
+        uint2 pzm = make_uint2(0u, 0u), pown = pzm;
+        if constexpr (M == 1) {
             jzm = *(const uint4 *)(J + 2 * N + (z0 == 0 ? i0 + (LL - 1) * P : i0 - P));
             jz = *(const uint4 *)(J + 2 * N + i0);
+        }
+        if constexpr (M == 2) {
+            pzm = PB[(z0 == 0 ? i0 + (LL - 1) * P : i0 - P) >> 4];
+            pown = PB[i0 >> 4];
         }
 #pragma unroll(Z < 4 ? Z : 4)
         for (int j = 0; j < Z; ++j) {
@@ -80,18 +89,27 @@ __global__ __launch_bounds__(kThreads) void k_ising3d_half(Sweep3dArgs a) {
             const int A = ((y + z) & 1) ^ a.c;
             const int64_t iex = i0 - x0 + (A ? xr : xl);
             const uint32_t eb = ((uint32_t)(uint8_t)S[iex] >> 1) & 1u;
-            uint4 jx = make_uint4(0u, 0u, 0u, 0u), jy = jx, jym = jx, jzn = jx;
-            uint32_t jeb = 0u;
-            if constexpr (EA) {
-                jx = *(const uint4 *)(J + i0);
-                jeb = ((uint32_t)(uint8_t)J[iex] >> 1) & 1u;
-                jy = *(const uint4 *)(J + N + i0);
-                jym = *(const uint4 *)(J + N + i0 + dym);
+            uint4 jzn = make_uint4(0u, 0u, 0u, 0u);
+            uint2 pnext = make_uint2(0u, 0u);
+            Bonds3 bd{};
+            if constexpr (M == 1) {
+                const uint4 jx = *(const uint4 *)(J + i0);
+                const uint32_t jeb = ((uint32_t)(uint8_t)J[i0 - x0 + xl] >> 1) & 1u;
+                const uint4 jy = *(const uint4 *)(J + N + i0);
+                const uint4 jym = *(const uint4 *)(J + N + i0 + dym);
                 if (j + 1 < Z) jzn = *(const uint4 *)(J + 2 * N + izp);
+                bd = bonds_from_bytes(jx, jeb, jy, jym, jz, jzm, A);
             }
-            const RowOut o = segment_update<EA>(own, rym, ryp, rzm, rzp, eb, A, jx, jeb, jy, jym, jz, jzm, th,
-                                                (uint32_t)(i0 >> 1), (uint32_t)a.c, a.t, (uint32_t)r, a.key,
-                                                a.one2, a.four);
+            if constexpr (M == 2) {
+                // the bond entering the row from x0 - 1: the last odd-x bit of
+                // the x mask of the segment to the left
+                const uint32_t jeb = (PB[(i0 - x0 + xl) >> 4].x >> 15) & 1u;
+                const uint2 pym = PB[(i0 + dym) >> 4];
+                if (j + 1 < Z) pnext = PB[izp >> 4];
+                bd = bonds_from_bits(pown.x & 0xFFFFu, jeb, pown.x >> 16, pym.x >> 16, pown.y, pzm.y, A);
+            }
+            const RowOut o = segment_update<EA>(own, rym, ryp, rzm, rzp, eb, A, bd, th, (uint32_t)(i0 >> 1),
+                                                (uint32_t)a.c, a.t, (uint32_t)r, a.key, a.one2, a.four);
             if (o.F0 | o.F1) {
                 const uint4 out = apply_flips(own, o, A);
                 if constexpr (NT)
@@ -104,9 +122,13 @@ __global__ __launch_bounds__(kThreads) void k_ising3d_half(Sweep3dArgs a) {
             // the other colour's bytes are read from it, which did not change)
             rzm = own;
             own = rzp;
-            if constexpr (EA) {
+            if constexpr (M == 1) {
                 jzm = jz;
                 jz = jzn;
+            }
+            if constexpr (M == 2) {
+                pzm = pown;
+                pown = pnext;
             }
             i0 = izp;
         }
@@ -123,7 +145,33 @@ __global__ __launch_bounds__(kThreads) void k_ising3d_half(Sweep3dArgs a) {
     }
 }
 
+// Bit-packed bonds: per sample and 16-site segment, x = (x mask) | (y mask
+// << 16), y = z mask; a mask holds the even-x sites in bits 0..7 and the
+// odd-x sites in bits 8..15, bit 1 where J = -1.
+__global__ __launch_bounds__(kThreads) void k_pack_bonds3d(const int8_t *coup, uint2 *out, int64_t N, int64_t total) {
+    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // sample * (N / 16) + segment
+    if (q >= total) return;
+    const int64_t sample = q / (N >> 4), seg = q - sample * (N >> 4);
+    const int8_t *J = coup + sample * 3 * N + (seg << 4);
+    uint32_t m[3];
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+        const uint4 w = *(const uint4 *)(J + mu * N);
+        const uint2 e = bits2(half_of(w, 0x06040200u)), o = bits2(half_of(w, 0x07050301u));
+        m[mu] = gather4(e.x) | (gather4(e.y) << 4) | (gather4(o.x) << 8) | (gather4(o.y) << 12);
+    }
+    out[q] = make_uint2(m[0] | (m[1] << 16), m[2]);
+}
+
 }  // namespace
+
+hipError_t launch_pack_bonds3d(const int8_t *coup, uint2 *out, int L, int n_samples, hipStream_t s) {
+    if (L % 16 || n_samples < 1) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)L * L * L, total = (int64_t)n_samples * (N >> 4);
+    hipLaunchKernelGGL(k_pack_bonds3d, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, coup,
+                       out, N, total);
+    return hipGetLastError();
+}
 
 bool sweep3d_supported(int L) { return L >= 16 && L % 16 == 0; }
 
@@ -149,32 +197,33 @@ bool sweep3d_nt() {
     return !(env && env[0] == '0');
 }
 
-template <bool EA, int Z>
+template <int M, int Z>
 void launch_rows(bool nt, unsigned blocks, const Sweep3dArgs &a, hipStream_t s) {
     if (nt)
-        hipLaunchKernelGGL((k_ising3d_half<EA, Z, true>), dim3(blocks), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((k_ising3d_half<M, Z, true>), dim3(blocks), dim3(kThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_ising3d_half<EA, Z, false>), dim3(blocks), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((k_ising3d_half<M, Z, false>), dim3(blocks), dim3(kThreads), 0, s, a);
 }
 
-template <bool EA>
+template <int M>
 void launch_model(int Z, bool nt, unsigned blocks, const Sweep3dArgs &a, hipStream_t s) {
     if (Z == 16)
-        launch_rows<EA, 16>(nt, blocks, a, s);
+        launch_rows<M, 16>(nt, blocks, a, s);
     else if (Z == 8)
-        launch_rows<EA, 8>(nt, blocks, a, s);
+        launch_rows<M, 8>(nt, blocks, a, s);
     else if (Z == 4)
-        launch_rows<EA, 4>(nt, blocks, a, s);
+        launch_rows<M, 4>(nt, blocks, a, s);
     else if (Z == 2)
-        launch_rows<EA, 2>(nt, blocks, a, s);
+        launch_rows<M, 2>(nt, blocks, a, s);
     else
-        launch_rows<EA, 1>(nt, blocks, a, s);
+        launch_rows<M, 1>(nt, blocks, a, s);
 }
 
 }  // namespace
 
-hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, int rep_per_sample, const ThrRow *thr,
-                               int64_t *dE, int n_rep, int L, Key key, uint32_t t, int c, hipStream_t s) {
+hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, const uint2 *pbonds, int rep_per_sample,
+                               const ThrRow *thr, int64_t *dE, int n_rep, int L, Key key, uint32_t t, int c,
+                               hipStream_t s) {
     if (!sweep3d_supported(L) || rep_per_sample < 1 || n_rep < 1) return hipErrorInvalidValue;
     // a replica's (L / 16)^3 workgroups of one-row threads regroup into whole
     // workgroups of Z-row threads when Z divides (L / 16)^3
@@ -185,6 +234,7 @@ hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, int rep_per_sa
     Sweep3dArgs a;
     a.spins = spins;
     a.coup = coup;
+    a.pbonds = pbonds;
     a.rep_per_sample = rep_per_sample;
     a.thr = thr;
     a.dE = dE;
@@ -197,10 +247,12 @@ hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, int rep_per_sa
     a.four = 4u;
     const int64_t blocks = (int64_t)n_rep * a.blocks_per_rep;
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
-    if (coup)
-        launch_model<true>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
+    if (pbonds)
+        launch_model<2>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
+    else if (coup)
+        launch_model<1>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
     else
-        launch_model<false>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
+        launch_model<0>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
     return hipGetLastError();
 }
 

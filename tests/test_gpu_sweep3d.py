@@ -87,3 +87,13 @@ def test_launch_shapes_bit_exact(monkeypatch, z, nt):
         betas = np.linspace(0.15, 0.9, n_rep)
         b, got, dE, ref, ref_dE = _run(model, L, n_rep, rps, betas, 3, 5, W.seed_for(44))
         assert np.array_equal(got, ref) and np.array_equal(dE, ref_dE)
+
+
+@pytest.mark.parametrize("pack", ["1", "0"])
+def test_ea_bond_forms_bit_exact(monkeypatch, pack):
+    """EA calls of four or more sweeps read bit-packed bonds (SPINMC_SWEEP3D_PACK=0:
+    the int8 bonds); both match the oracle, with samples shared by two replicas."""
+    monkeypatch.setenv("SPINMC_SWEEP3D_PACK", pack)
+    betas = np.linspace(0.2, 1.1, 4)
+    b, got, dE, ref, ref_dE = _run(S.EA, 48, 4, 2, betas, 9, 6, W.seed_for(45))
+    assert np.array_equal(got, ref) and np.array_equal(dE, ref_dE)
