@@ -295,7 +295,8 @@ int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t word_bits, int3
  *  desc:      uniform 2D or 3D batch (L > 0), model SMC_ISING or SMC_EA.
  *             In 3D the tiles are cubes and tile colour is (bx + by + bz) & 1.
  *  tile:      2D: a multiple of 16 in [16, 128] with L / tile even or 1;
- *             3D: 16, with L / 16 even or 1.
+ *             3D: 16, with L / 16 even or 1 (spins and couplings 16-byte
+ *             aligned).
  *  hits:      >= 1; (sweep0 + n_sweeps) * hits must not exceed 2^32.
  *  spins, couplings, beta (HOST [n_rep]), sweep0, n_sweeps, dE_accum,
  *  stream: as for smc_metropolis_sweep; every replica is updated in place.

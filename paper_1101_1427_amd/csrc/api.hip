@@ -1354,6 +1354,8 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     if (hits < 1) return fail(SMC_EINVAL, "hits must be >= 1");
     if (!spins) return fail(SMC_EINVAL, "spins is NULL");
     if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
+    if (desc->dim == 3 && (((uintptr_t)spins & 15u) || ((uintptr_t)couplings & 15u)))
+        return fail(SMC_EINVAL, "3D double checkerboard: spins and couplings must be 16-byte aligned");
     if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
     if ((sweep0 + (uint64_t)n_sweeps) * (uint64_t)hits > (1ull << 32))
         return fail(SMC_EINVAL, "(sweep0 + n_sweeps) * hits exceeds 2^32 (the hit index is one 32-bit word)");

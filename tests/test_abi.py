@@ -169,6 +169,9 @@ def test_dcb_arguments_are_validated():
     d3 = _desc(dim=3, L=32, n_rep=1, spins_len=32 ** 3)
     rc = L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 32, 1, 0, None, None, None)
     assert rc == S.EINVAL and b"16 x 16 x 16" in L.smc_last_error()
+    d3 = _desc(dim=3, L=32, n_rep=1, spins_len=32 ** 3)
+    rc = L.smc_dcb_sweep(C.byref(d3), C.c_void_p(FAKE.value + 1), None, beta, 0, 1, 16, 1, 0, None, None, None)
+    assert rc == S.EINVAL and b"16-byte aligned" in L.smc_last_error()
     d3 = _desc(dim=3, L=48, n_rep=1, spins_len=48 ** 3)
     assert L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 16, 1, 0, None, None, None) == S.EINVAL
     dh = _desc(model=S.HEISENBERG, dim=3, L=32, n_rep=1, spins_len=3 * 32 ** 3)
