@@ -70,6 +70,7 @@ def lib():
             "orc_pt_step": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, I, vp]),
             "orc_pt_run": (None, [I, I, vp, i8p, I, f64p, i32p, i64p, U64, U32, U32, U32, I, I, vp]),
             "orc_swap_u53": (D, [U64, U32, U32, U32]),
+            "orc_pt_audit": (None, [u64p, C.POINTER(C.c_double), I]),
             "orc_window_run": (None, [I, I, I, I, i8p, D, U64, U32, U32, I]),
             "orc_dcb_run": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
             "orc_dcb_run3": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
@@ -201,6 +202,16 @@ def pt_run(dim, L, J, spins, beta, slot_of_temp, E, seed, q, r0, t0, n_steps, sw
     n_temps = len(beta)
     lib().orc_pt_run(dim, L, _ptr(J), spins.reshape(-1), n_temps, np.ascontiguousarray(beta, np.float64),
                      slot_of_temp, E, seed, q, r0, t0, n_steps, sweeps_per_step, _ptr(swap_acc))
+
+
+def pt_audit(reset: bool = False) -> dict:
+    """Exchange attempts with x < 0 made by the oracle since the last reset,
+    how many had |u53 - exp(x)| < 2^-40 (a decision that a one-ulp difference
+    in exp could change), and the smallest gap |u53 - exp(x)| seen."""
+    counts = np.zeros(2, np.uint64)
+    gap = C.c_double(0.0)
+    lib().orc_pt_audit(counts, C.byref(gap), 1 if reset else 0)
+    return {"attempts": int(counts[0]), "near_ties": int(counts[1]), "min_gap": gap.value}
 
 
 def dcb_run(L, T, k, J, s, beta, seed, r, t0, n, palindromic=False, dim=2) -> int:

@@ -692,6 +692,26 @@ EXPORT void orc_heis_magnetisation(int dim, int L, const double *s, double m[3])
 /*   accept iff x >= 0 or u < exp(x), u the 53-bit uniform of (k, t, q, SWAP)*/
 /* and on acceptance the two slots exchange temperatures.                    */
 /* ------------------------------------------------------------------------ */
+/* Near-tie audit of the exchange decisions (test infrastructure): the
+ * device evaluates exp(x) with its own float64 exp, which may differ from
+ * libm by an ulp, so a decision is only shared when u is not within such a
+ * distance of exp(x).  Every attempt with x < 0 is counted, with those whose
+ * |u - exp(x)| < 2^-40 and the smallest gap seen.  Not thread-safe. */
+static uint64_t audit_attempts = 0, audit_near_ties = 0;
+static double audit_min_gap = 1.0;
+
+EXPORT void orc_pt_audit(uint64_t counts[2], double *min_gap, int reset)
+{
+    counts[0] = audit_attempts;
+    counts[1] = audit_near_ties;
+    *min_gap = audit_min_gap;
+    if (reset) {
+        audit_attempts = 0;
+        audit_near_ties = 0;
+        audit_min_gap = 1.0;
+    }
+}
+
 EXPORT void orc_pt_step(int dim, int L, const int8_t *J, int8_t *spins /* [n_temps][N] */,
                         int n_temps, const double *beta, int32_t *slot_of_temp, int64_t *E,
                         uint64_t seed, uint32_t q, uint32_t r0, uint32_t t, int m, uint64_t *swap_acc)
@@ -708,7 +728,15 @@ EXPORT void orc_pt_step(int dim, int L, const int8_t *J, int8_t *spins /* [n_tem
         double x = (beta[k + 1] - beta[k]) * (double)(E[B] - E[A]);
         uint32_t w[4];
         draw(seed, (uint32_t)k, t, q, TAG_SWAP * 2, w);
-        int accept = (x >= 0.0) || (unit53(w[0], w[1]) < exp(x));
+        int accept = 1;
+        if (!(x >= 0.0)) {
+            double u = unit53(w[0], w[1]), p = exp(x);
+            double gap = fabs(u - p);
+            audit_attempts += 1;
+            if (gap < 0x1p-40) audit_near_ties += 1;
+            if (gap < audit_min_gap) audit_min_gap = gap;
+            accept = u < p;
+        }
         if (accept) {
             slot_of_temp[k] = B;
             slot_of_temp[k + 1] = A;

@@ -111,3 +111,38 @@ def test_swap_uniform_is_53_bit_uniform():
     assert abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / len(u))
     # 53 significant bits: scaled by 2^53 every value is an integer
     assert np.all(np.floor(u * 2.0 ** 53) == u * 2.0 ** 53)
+
+
+@pytest.mark.planted_tie
+def test_near_tie_audit_counts_a_planted_tie():
+    """The audit sees an exchange whose exp(x) lies within 2^-40 of its
+    uniform: two frozen slots (all spins up at beta >= 8, where every
+    threshold is 0) with energies chosen so that x = ln(u53) up to rounding."""
+    n, L, t, q = 2, 4, 0, 5
+    u = O.swap_u53(SEED, 0, t, q)
+    D = 100
+    b0 = 8.0
+    b1 = b0 - math.log(u) / D                        # x = (b1 - b0) * (E_B - E_A) = ln(u) when E_B - E_A = -D
+    spins = np.ones((n, L * L), np.int8)
+    E = np.array([0, -D], np.int64)
+    sot = np.arange(n, dtype=np.int32)
+    O.pt_audit(reset=True)
+    O.pt_run(2, L, None, spins, np.array([b0, b1]), sot, E, SEED, q, 0, t, 1)
+    audit = O.pt_audit(reset=True)
+    assert audit["attempts"] == 1 and audit["near_ties"] == 1 and audit["min_gap"] < 2.0 ** -40
+    assert list(E) == [0, -D]                        # frozen: no flip was accepted
+    # one step later (odd step: no pair of two slots is attempted)
+    O.pt_run(2, L, None, spins, np.array([b0, b1]), sot, E, SEED, q, 0, t + 1, 1)
+    assert O.pt_audit(reset=True)["attempts"] == 0
+
+
+def test_near_tie_audit_on_a_ladder():
+    """A 4x4 ladder of 8 temperatures over 1000 steps: hundreds of attempts
+    with x < 0, none within 2^-40 (the audit fixture asserts that too)."""
+    n = 8
+    spins, E, sot = _chain(2, 4, n, 0)
+    beta = np.ascontiguousarray(W.geometric_ladder(0.5, 2.0, n))
+    O.pt_audit(reset=True)
+    O.pt_run(2, 4, None, spins, beta, sot, E, SEED, 0, 0, 0, 1000)
+    audit = O.pt_audit()
+    assert audit["attempts"] > 150 and audit["near_ties"] == 0 and audit["min_gap"] > 2.0 ** -40
