@@ -22,7 +22,20 @@
  *   asynchronous with respect to the host on that stream; its results are
  *   valid once the stream has reached the call.
  * - Arguments are validated on the host before anything is launched; on an
- *   argument error nothing is launched and nothing is modified.
+ *   argument error nothing is launched and nothing is modified.  Every kernel
+ *   launch configuration is checked on the host as well (at least one
+ *   workgroup, at most 2^31 - 1; 1 .. 1024 work-items per workgroup; dynamic
+ *   LDS within 160 KiB; fewer than 2^32 work-items): a configuration outside
+ *   these limits is not issued and the call returns SMC_EHIP with the
+ *   kernel and the broken limit in smc_last_error().
+ * - Calls on a stream that is capturing a graph return SMC_EINVAL and issue
+ *   nothing: they stage host tables through pinned buffers, may grow their
+ *   scratch and build graphs of their own, none of which can be recorded into
+ *   a caller's capture.
+ * - Inverse temperatures and uneven-batch tables are HOST arrays: the
+ *   acceptance thresholds floor(2^32 exp(-beta Delta E)) are computed from
+ *   them on the host in float64 with the C library's exp, so that every
+ *   integer decision is reproducible off the device.
  * - Results are a pure function of (inputs, seed, sweep/step index): they
  *   do not depend on launch shapes, streams or the device.  Every random
  *   number is a Philox4x32-10 draw keyed by the seed with a counter made of
@@ -185,7 +198,9 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins,
                       uint64_t step0, int32_t n_steps, uint64_t *swap_accepts, void *stream);
 
 /*
- * Energy and magnetisation of every replica (row "measure"):
+ * Energy and magnetisation of every replica (Sec. 3.5: energies as sums over
+ * bonds, tracked incrementally during sweeps and recomputed here; Sec. 4:
+ * measurements accumulated in double precision; Eqs. 1, 10, 11):
  *  E = -sum_i sum_mu J(i,mu) s_i . s_{i+e_mu},  M = sum_i s_i.
  *  energy:        DEVICE float64 [n_rep] (exact integers for Ising/EA).
  *  magnetisation: DEVICE float64 [n_rep] (Ising/EA) or [n_rep][3]

@@ -17,6 +17,23 @@
 #include "internal.hpp"
 
 namespace smc {
+
+thread_local std::string g_launch_rejection;
+
+hipError_t reject_launch(const char *kernel, uint64_t grid, uint64_t block, uint64_t lds, const char *why) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "launch of %s refused (%s): %llu workgroups of %llu, %llu bytes of LDS", kernel, why,
+             (unsigned long long)grid, (unsigned long long)block, (unsigned long long)lds);
+    g_launch_rejection = buf;
+    return hipErrorInvalidConfiguration;
+}
+
+std::string take_launch_rejection() {
+    std::string r;
+    r.swap(g_launch_rejection);
+    return r;
+}
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -31,10 +48,14 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define SMC_HIP(call)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess) return fail(SMC_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+#define SMC_HIP(call)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) {                                                                          \
+            const std::string why_ = take_launch_rejection();                                            \
+            return fail(SMC_EHIP, "%s: %s%s%s", #call, hipGetErrorString(e_), why_.empty() ? "" : ": ", \
+                        why_.c_str());                                                                   \
+        }                                                                                                \
     } while (0)
 
 // ------------------------------------------------------------------ scratch --
@@ -93,6 +114,7 @@ struct GraphCache {
 };
 
 struct StreamCtx {
+    hipStream_t stream = nullptr;  // the stream whose calls use this set
     Buffer dev[kNumSlots];
     GraphCache graphs[2];  // full chunk of steps, remainder
 };
@@ -104,16 +126,19 @@ StreamCtx &ctx_for(hipStream_t s) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_ctx_mutex);
-    return g_ctx[std::make_pair(dev, s)];
+    StreamCtx &c = g_ctx[std::make_pair(dev, s)];
+    c.stream = s;
+    return c;
 }
 
-// Device buffer of at least `bytes`; growing waits for the device first so
-// that no queued kernel still reads the old allocation.
+// Device buffer of at least `bytes`.  Only calls on this set's stream use
+// the buffer, so growing waits for that stream (not the whole device)
+// before the old allocation is freed.
 int ensure(StreamCtx &c, Slot slot, size_t bytes, void **out) {
     Buffer &b = c.dev[slot];
     if (b.bytes < bytes) {
         if (b.p) {
-            SMC_HIP(hipDeviceSynchronize());
+            SMC_HIP(hipStreamSynchronize(c.stream));
             SMC_HIP(hipFree(b.p));
             b.p = nullptr;
             b.bytes = 0;
@@ -162,6 +187,18 @@ int upload(StreamCtx &c, hipStream_t s, Slot slot, const void *src, size_t bytes
     SMC_HIP(hipMemcpyAsync(*dev_out, b.pinned, bytes, hipMemcpyHostToDevice, s));
     SMC_HIP(hipEventRecord(b.staged, s));
     b.staged_pending = true;
+    return SMC_OK;
+}
+
+// Calls stage host data (tables, instance lists) through pinned buffers,
+// grow their scratch on demand and build graphs of their own; none of that
+// can be recorded into a caller's stream capture, so a call on a capturing
+// stream is refused before anything is issued.
+int refuse_capture(hipStream_t s) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    SMC_HIP(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(SMC_EINVAL, "the stream is capturing a graph: this call cannot be captured");
     return SMC_OK;
 }
 
@@ -236,7 +273,7 @@ bool sweep3d_shape(const smc_desc *d) {
 
 bool use_sweep3d(const smc_desc *d, const void *spins, const int8_t *coup, const std::vector<ThrRow> &rows) {
     if (!sweep3d_shape(d)) return false;
-    if (((uintptr_t)spins & 15u) != 0 || ((uintptr_t)coup & 15u) != 0) return false;
+    if (((uintptr_t)spins & 15u) != 0 || (d->model == SMC_EA && ((uintptr_t)coup & 15u) != 0)) return false;
     for (const ThrRow &r : rows)
         if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu || r.m[3].x > 0xFFFFu) return false;
     return true;
@@ -412,9 +449,7 @@ int uneven2d_threads(StreamCtx &c, hipStream_t s, const Uneven2dArgs &a, int L, 
         }
     }
     const char *env = getenv("SPINMC_AUTOTUNE");
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    SMC_HIP(hipStreamIsCapturing(s, &cap));
-    if ((env && env[0] == '0') || cap != hipStreamCaptureStatusNone) {
+    if (env && env[0] == '0') {
         *out = uneven2d_threads_default(L);
         return SMC_OK;
     }
@@ -596,10 +631,8 @@ int run_uneven2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, const Plan &
     }
     a.sweeps = m;
 
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    SMC_HIP(hipStreamIsCapturing(s, &cap));
-    if (cap != hipStreamCaptureStatusNone || n_steps < 4) {
-        // inside a caller's capture (or a few steps): plain launches in step order
+    if (n_steps < 4) {
+        // a few steps: plain launches in step order
         for (int32_t k = 0; k < n_steps; ++k) {
             for (const EdgeClass &e : classes)
                 SMC_HIP(launch_uneven2d_sweep(a, wl + e.first, e.count, e.L, ea, e.threads, s));
@@ -1034,6 +1067,7 @@ int smc_spin_init(const smc_desc *desc, void *spins, int8_t *couplings, void *st
     if (rc) return rc;
     if (!spins) return fail(SMC_EINVAL, "spins is NULL");
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
     StreamCtx &c = ctx_for(s);
     if ((rc = upload_inst(c, s, desc, plan))) return rc;
     const Key key = make_key(desc->seed);
@@ -1092,6 +1126,7 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
     if (n_sweeps == 0) return SMC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
     StreamCtx &c = ctx_for(s);
     if ((rc = upload_inst(c, s, desc, plan))) return rc;
 
@@ -1231,6 +1266,7 @@ int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     }
     if (n_sweeps == 0) return SMC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
     StreamCtx &c = ctx_for(s);
     if ((rc = upload_inst(c, s, desc, plan))) return rc;
     const int G = desc->n_rep / 32;
@@ -1354,13 +1390,14 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
     if (hits < 1) return fail(SMC_EINVAL, "hits must be >= 1");
     if (!spins) return fail(SMC_EINVAL, "spins is NULL");
     if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
-    if (desc->dim == 3 && (((uintptr_t)spins & 15u) || ((uintptr_t)couplings & 15u)))
-        return fail(SMC_EINVAL, "3D double checkerboard: spins and couplings must be 16-byte aligned");
+    if (desc->dim == 3 && (((uintptr_t)spins & 15u) || (desc->model == SMC_EA && ((uintptr_t)couplings & 15u))))
+        return fail(SMC_EINVAL, "3D double checkerboard: spins (and EA couplings) must be 16-byte aligned");
     if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
     if ((sweep0 + (uint64_t)n_sweeps) * (uint64_t)hits > (1ull << 32))
         return fail(SMC_EINVAL, "(sweep0 + n_sweeps) * hits exceeds 2^32 (the hit index is one 32-bit word)");
     if (n_sweeps == 0) return SMC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
     StreamCtx &c = ctx_for(s);
     const std::vector<ThrRow> rows = dcb_rows(desc, beta);
     void *tp = nullptr, *sp = nullptr;
@@ -1424,6 +1461,7 @@ int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, ui
         if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
     if (n_sweeps == 0) return SMC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
     StreamCtx &c = ctx_for(s);
     void *bp = nullptr, *sp = nullptr;
     if (precision == SMC_HEIS_DOUBLE) {
@@ -1558,6 +1596,7 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, 
     }
     if (n_steps == 0) return SMC_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
     StreamCtx &c = ctx_for(s);
     if ((rc = upload_inst(c, s, desc, plan))) return rc;
 
@@ -1630,6 +1669,7 @@ int smc_measure_energy_magnetisation(const smc_desc *desc, const void *spins, co
     if (!spins || !energy) return fail(SMC_EINVAL, "spins and energy are required");
     if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
     StreamCtx &c = ctx_for(s);
     if ((rc = upload_inst(c, s, desc, plan))) return rc;
     const size_t bytes = measure_scratch_bytes(plan.b, plan.max_L);

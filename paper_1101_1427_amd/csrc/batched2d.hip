@@ -394,13 +394,13 @@ Uneven2dArgs make_uneven2d_args(int8_t *spins, const smc_inst *inst, const uint8
 hipError_t launch_coup_split2d(const int8_t *coup, uint8_t *out, const smc_inst *samples, int n_samples,
                                int64_t chunks_total, const int64_t *chunk_start, hipStream_t s) {
     if (chunks_total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coup_split2d, dim3((unsigned)((chunks_total + 255) / 256)), dim3(256), 0, s, coup, out,
+    SMC_LAUNCH(k_coup_split2d, dim3((unsigned)((chunks_total + 255) / 256)), dim3(256), 0, s, coup, out,
                        samples, n_samples, chunks_total, chunk_start);
     return hipGetLastError();
 }
 
 hipError_t launch_set_step(uint32_t *t_dev, uint32_t t, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, t_dev, t);
+    SMC_LAUNCH(k_set_step, dim3(1), dim3(1), 0, s, t_dev, t);
     return hipGetLastError();
 }
 
@@ -420,6 +420,9 @@ hipError_t add_uneven2d_sweep_node(hipGraph_t g, hipGraphNode_t *node, const hip
     p.sharedMemBytes = (unsigned)uneven2d_lds_bytes(L);
     p.kernelParams = params;
     p.extra = nullptr;
+    if (const char *why = launch_config_error((uint64_t)n_work, (uint64_t)threads, p.sharedMemBytes))
+        return reject_launch("k_uneven2d_sweep (graph node)", (uint64_t)n_work, (uint64_t)threads, p.sharedMemBytes,
+                             why);
     return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
 }
 
@@ -441,14 +444,14 @@ hipError_t launch_uneven2d_sweep(const Uneven2dArgs &a, const int32_t *work, int
                                  hipStream_t s) {
     const size_t lds = uneven2d_lds_bytes(L);
     if (ea)
-        hipLaunchKernelGGL(k_uneven2d_sweep<true>, dim3(n_work), dim3(threads), lds, s, a, work, L);
+        SMC_LAUNCH(k_uneven2d_sweep<true>, dim3(n_work), dim3(threads), lds, s, a, work, L);
     else
-        hipLaunchKernelGGL(k_uneven2d_sweep<false>, dim3(n_work), dim3(threads), lds, s, a, work, L);
+        SMC_LAUNCH(k_uneven2d_sweep<false>, dim3(n_work), dim3(threads), lds, s, a, work, L);
     return hipGetLastError();
 }
 
 hipError_t launch_advance_step(uint32_t *t_dev, hipStream_t s, uint32_t inc) {
-    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, s, t_dev, inc);
+    SMC_LAUNCH(k_advance_step, dim3(1), dim3(1), 0, s, t_dev, inc);
     return hipGetLastError();
 }
 

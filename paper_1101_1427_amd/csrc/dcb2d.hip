@@ -531,12 +531,12 @@ int dcb2d_tiles_per_colour(int L, int T) {
 
 hipError_t launch_dcb_zero(int64_t *p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dcb_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    SMC_LAUNCH(k_dcb_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
 hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int per_rep, bool assign, hipStream_t s) {
-    hipLaunchKernelGGL(k_dcb_collect, dim3((unsigned)n_rep), dim3(256), 0, s, slots, dE, per_rep, assign ? 1 : 0);
+    SMC_LAUNCH(k_dcb_collect, dim3((unsigned)n_rep), dim3(256), 0, s, slots, dE, per_rep, assign ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -545,9 +545,9 @@ hipError_t launch_packed(const DcbPackedArgs &a, bool ea, hipStream_t s) {
     using Gm = DcbGeom<T>;
     const unsigned blocks = (unsigned)((a.total + Gm::G - 1) / Gm::G);
     if (ea)
-        hipLaunchKernelGGL((k_dcb2d_packed<T, true>), dim3(blocks), dim3(Gm::THREADS), 0, s, a);
+        SMC_LAUNCH((k_dcb2d_packed<T, true>), dim3(blocks), dim3(Gm::THREADS), 0, s, a);
     else
-        hipLaunchKernelGGL((k_dcb2d_packed<T, false>), dim3(blocks), dim3(Gm::THREADS), 0, s, a);
+        SMC_LAUNCH((k_dcb2d_packed<T, false>), dim3(blocks), dim3(Gm::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -602,7 +602,7 @@ hipError_t launch_dcb2d(int8_t *spins, const int8_t *coup, int rep_per_sample, c
     const unsigned threads = (unsigned)(T * T / 16);
     const size_t lds = (size_t)3 * (T + 2) * (T + 2);
     const unsigned blocks = (unsigned)(n_rep * tpc);
-    hipLaunchKernelGGL(k_dcb2d, dim3(blocks), dim3(threads), lds, s, a);
+    SMC_LAUNCH(k_dcb2d, dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 

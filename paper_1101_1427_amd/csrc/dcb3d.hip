@@ -192,9 +192,9 @@ hipError_t launch_dcb3d(int8_t *spins, const int8_t *coup, int rep_per_sample, c
     a.tiles_per_colour = dcb3d_tiles_per_colour(L, T);
     const unsigned blocks = (unsigned)(n_rep * a.tiles_per_colour);
     if (coup)
-        hipLaunchKernelGGL(k_dcb3d<true>, dim3(blocks), dim3(kThreads3), 0, s, a);
+        SMC_LAUNCH(k_dcb3d<true>, dim3(blocks), dim3(kThreads3), 0, s, a);
     else
-        hipLaunchKernelGGL(k_dcb3d<false>, dim3(blocks), dim3(kThreads3), 0, s, a);
+        SMC_LAUNCH(k_dcb3d<false>, dim3(blocks), dim3(kThreads3), 0, s, a);
     return hipGetLastError();
 }
 

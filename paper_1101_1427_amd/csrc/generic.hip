@@ -408,39 +408,39 @@ int blocks_for(int64_t work) { return (int)((work + kBlock - 1) / kBlock); }
 
 hipError_t launch_init_spins(const Batch &b, int max_L, int8_t *spins, Key key, hipStream_t s) {
     const int bpr = blocks_for((sites_of(b.dim, max_L) + 3) / 4);
-    hipLaunchKernelGGL(k_init_spins, dim3(bpr * b.n_rep), dim3(kBlock), 0, s, b, spins, key, bpr);
+    SMC_LAUNCH(k_init_spins, dim3(bpr * b.n_rep), dim3(kBlock), 0, s, b, spins, key, bpr);
     return hipGetLastError();
 }
 
 hipError_t launch_init_heis(const Batch &b, int max_L, float *spins, Key key, hipStream_t s) {
     const int bpr = blocks_for(sites_of(b.dim, max_L));
-    hipLaunchKernelGGL(k_init_heis, dim3(bpr * b.n_rep), dim3(kBlock), 0, s, b, spins, key, bpr);
+    SMC_LAUNCH(k_init_heis, dim3(bpr * b.n_rep), dim3(kBlock), 0, s, b, spins, key, bpr);
     return hipGetLastError();
 }
 
 hipError_t launch_init_couplings(int dim, int n_samples, const smc_inst *samples_dev, int max_L, int8_t *coup,
                                  Key key, hipStream_t s) {
     const int bpr = blocks_for((dim * sites_of(dim, max_L) + 3) / 4);
-    hipLaunchKernelGGL(k_init_couplings, dim3(bpr * n_samples), dim3(kBlock), 0, s, dim, samples_dev, coup, key,
+    SMC_LAUNCH(k_init_couplings, dim3(bpr * n_samples), dim3(kBlock), 0, s, dim, samples_dev, coup, key,
                        bpr);
     return hipGetLastError();
 }
 
 hipError_t launch_half_sweep_generic(const SweepArgs &a, int c, hipStream_t s) {
     const int bpr = blocks_for(sites_of(a.b.dim, a.max_L) / 2);
-    hipLaunchKernelGGL(k_half_sweep_generic, dim3(bpr * a.b.n_rep), dim3(kBlock), 0, s, a, c, bpr);
+    SMC_LAUNCH(k_half_sweep_generic, dim3(bpr * a.b.n_rep), dim3(kBlock), 0, s, a, c, bpr);
     return hipGetLastError();
 }
 
 hipError_t launch_heis_half_sweep_generic(const SweepArgs &a, int c, hipStream_t s) {
     const int bpr = blocks_for(sites_of(a.b.dim, a.max_L) / 2);
-    hipLaunchKernelGGL(k_heis_half_sweep_generic, dim3(bpr * a.b.n_rep), dim3(kBlock), 0, s, a, c, bpr);
+    SMC_LAUNCH(k_heis_half_sweep_generic, dim3(bpr * a.b.n_rep), dim3(kBlock), 0, s, a, c, bpr);
     return hipGetLastError();
 }
 
 hipError_t launch_heis_renorm(const Batch &b, float *spins, int max_L, hipStream_t s) {
     const int bpr = blocks_for(sites_of(b.dim, max_L));
-    hipLaunchKernelGGL(k_heis_renorm, dim3(bpr * b.n_rep), dim3(kBlock), 0, s, b, spins, bpr);
+    SMC_LAUNCH(k_heis_renorm, dim3(bpr * b.n_rep), dim3(kBlock), 0, s, b, spins, bpr);
     return hipGetLastError();
 }
 
@@ -453,21 +453,21 @@ hipError_t launch_measure(const Batch &b, const void *spins, const int8_t *coup,
     const int nblk = measure_blocks(b, max_L);
     if (scratch_bytes < measure_scratch_bytes(b, max_L)) return hipErrorInvalidValue;
     Partial *part = (Partial *)scratch;
-    hipLaunchKernelGGL(k_measure_partials, dim3(nblk * b.n_rep), dim3(kBlock), 0, s, b, spins, coup, part, nblk);
+    SMC_LAUNCH(k_measure_partials, dim3(nblk * b.n_rep), dim3(kBlock), 0, s, b, spins, coup, part, nblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_measure_final, dim3((b.n_rep + 255) / 256), dim3(256), 0, s, b.n_rep, nblk,
+    SMC_LAUNCH(k_measure_final, dim3((b.n_rep + 255) / 256), dim3(256), 0, s, b.n_rep, nblk,
                        b.model == SMC_HEISENBERG ? 1 : 0, part, energy, magnet);
     return hipGetLastError();
 }
 
 hipError_t launch_pt_prepare(const SwapArgs &a, const double *energy_in, hipStream_t s) {
-    hipLaunchKernelGGL(k_pt_prepare, dim3((a.n_chains + 255) / 256), dim3(256), 0, s, a, energy_in);
+    SMC_LAUNCH(k_pt_prepare, dim3((a.n_chains + 255) / 256), dim3(256), 0, s, a, energy_in);
     return hipGetLastError();
 }
 
 hipError_t launch_pt_swap(const SwapArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_pt_swap, dim3((a.n_chains + 255) / 256), dim3(256), 0, s, a);
+    SMC_LAUNCH(k_pt_swap, dim3((a.n_chains + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -481,12 +481,14 @@ hipError_t add_pt_swap_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNo
     p.gridDim = dim3((unsigned)((a.n_chains + 255) / 256));
     p.blockDim = dim3(256);
     p.kernelParams = params;
+    if (const char *why = launch_config_error(p.gridDim.x, 256, 0))
+        return reject_launch("k_pt_swap (graph node)", p.gridDim.x, 256, 0, why);
     return hipGraphAddKernelNode(node, g, deps, n_deps, &p);
 }
 
 hipError_t launch_pt_finish(const SwapArgs &a, double *energy_out, hipStream_t s) {
     const int n = a.n_chains * a.n_temps;
-    hipLaunchKernelGGL(k_pt_finish, dim3((n + 255) / 256), dim3(256), 0, s, a, energy_out);
+    SMC_LAUNCH(k_pt_finish, dim3((n + 255) / 256), dim3(256), 0, s, a, energy_out);
     return hipGetLastError();
 }
 

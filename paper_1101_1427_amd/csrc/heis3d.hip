@@ -364,7 +364,7 @@ hipError_t launch_heis3d_half(float *spins, const float *beta, int64_t *acc, int
     while ((1 << a.lgL) < L) ++a.lgL;
     a.N = (int64_t)L * L * L;
     a.bpr = (int)((a.N / 2 + kThreads * kSitesPerThread - 1) / (kThreads * kSitesPerThread));
-    hipLaunchKernelGGL(k_heis3d_half, dim3((unsigned)(a.bpr * n_rep)), dim3(kThreads), 0, s, a, c);
+    SMC_LAUNCH(k_heis3d_half, dim3((unsigned)(a.bpr * n_rep)), dim3(kThreads), 0, s, a, c);
     return hipGetLastError();
 }
 
@@ -394,7 +394,7 @@ hipError_t launch_heis3d_tiled(const float *src, float *dst, const float *beta, 
     const size_t lds = heis3d_tiled_lds_bytes();
     (void)hipFuncSetAttribute((const void *)k_heis3d_tiled, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const unsigned blocks = (unsigned)(a.tiles * a.tiles * a.segs * n_rep);
-    hipLaunchKernelGGL(k_heis3d_tiled, dim3(blocks), dim3(kTiledThreads), lds, s, a);
+    SMC_LAUNCH(k_heis3d_tiled, dim3(blocks), dim3(kTiledThreads), lds, s, a);
     return hipGetLastError();
 }
 

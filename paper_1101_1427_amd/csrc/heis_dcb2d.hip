@@ -355,9 +355,9 @@ hipError_t launch_t(const HeisDcbArgs &a, int n_rep, hipStream_t s) {
     const unsigned blocks = (unsigned)(n_rep * a.tiles_per_colour);
     constexpr unsigned threads = HeisGeom<T, SPT>::THREADS;
     if (a.cap > 0.0)
-        hipLaunchKernelGGL((k_heis_dcb2d<T, SPT, MODE, true>), dim3(blocks), dim3(threads), 0, s, a);
+        SMC_LAUNCH((k_heis_dcb2d<T, SPT, MODE, true>), dim3(blocks), dim3(threads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_heis_dcb2d<T, SPT, MODE, false>), dim3(blocks), dim3(threads), 0, s, a);
+        SMC_LAUNCH((k_heis_dcb2d<T, SPT, MODE, false>), dim3(blocks), dim3(threads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -417,9 +417,9 @@ hipError_t launch_heis_dcb_renorm(void *spins, int64_t n_spins, int precision, h
     if (n_spins <= 0) return hipSuccess;
     const dim3 grid((unsigned)((n_spins + 255) / 256));
     switch (precision) {
-        case SMC_HEIS_FAST: hipLaunchKernelGGL(k_heis_dcb_renorm<SMC_HEIS_FAST>, grid, dim3(256), 0, s, spins, n_spins); break;
-        case SMC_HEIS_FLOAT: hipLaunchKernelGGL(k_heis_dcb_renorm<SMC_HEIS_FLOAT>, grid, dim3(256), 0, s, spins, n_spins); break;
-        case SMC_HEIS_DOUBLE: hipLaunchKernelGGL(k_heis_dcb_renorm<SMC_HEIS_DOUBLE>, grid, dim3(256), 0, s, spins, n_spins); break;
+        case SMC_HEIS_FAST: SMC_LAUNCH(k_heis_dcb_renorm<SMC_HEIS_FAST>, grid, dim3(256), 0, s, spins, n_spins); break;
+        case SMC_HEIS_FLOAT: SMC_LAUNCH(k_heis_dcb_renorm<SMC_HEIS_FLOAT>, grid, dim3(256), 0, s, spins, n_spins); break;
+        case SMC_HEIS_DOUBLE: SMC_LAUNCH(k_heis_dcb_renorm<SMC_HEIS_DOUBLE>, grid, dim3(256), 0, s, spins, n_spins); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -3,12 +3,35 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/spinmc.h"
 #include "lattice2d.hpp"
+#include "launch_check.hpp"
 #include "philox.hpp"
 #include "tables.hpp"
 
 namespace smc {
+
+// A launch whose configuration launch_config_error refuses is not issued:
+// the description (kernel, grid, workgroup, LDS, reason) is kept for the
+// calling thread's error message and hipErrorInvalidConfiguration returned.
+hipError_t reject_launch(const char *kernel, uint64_t grid, uint64_t block, uint64_t lds, const char *why);
+// The description of the last refused launch on this thread ("" if none),
+// cleared by reading it.
+std::string take_launch_rejection();
+
+// Every kernel launch of the library goes through this check (inside
+// functions that return hipError_t).
+#define SMC_LAUNCH(kernel, grid, block, lds, stream, ...)                                                   \
+    do {                                                                                                   \
+        const dim3 g_ = (grid), b_ = (block);                                                              \
+        const uint64_t ng_ = (uint64_t)g_.x * g_.y * g_.z, nb_ = (uint64_t)b_.x * b_.y * b_.z;             \
+        const uint64_t lds_ = (uint64_t)(lds);                                                             \
+        if (const char *why_ = ::smc::launch_config_error(ng_, nb_, lds_))                                 \
+            return ::smc::reject_launch(#kernel, ng_, nb_, lds_, why_);                                    \
+        hipLaunchKernelGGL(kernel, g_, b_, lds_, stream, __VA_ARGS__);                                     \
+    } while (0)
 
 // Geometry of a batch as the kernels see it.  Uniform batches use (L, N,
 // spin_stride, coup_stride, rep_per_sample); uneven ones the inst table.

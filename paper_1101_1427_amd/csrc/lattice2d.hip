@@ -28,6 +28,7 @@
 // that draws the 16-bit tail.
 #include <stdlib.h>
 
+#include "internal.hpp"
 #include "lattice2d.hpp"
 
 namespace smc {
@@ -620,14 +621,14 @@ size_t lattice2d_split_bytes(int L) { return (size_t)(2 * (int64_t)L * lattice2d
 
 hipError_t launch_to_split(const int8_t *src, uint8_t *dst, int L, int n_rep, hipStream_t s) {
     const int64_t cpr = (int64_t)L * L / 16, total = cpr * n_rep;
-    hipLaunchKernelGGL(k_to_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L,
+    SMC_LAUNCH(k_to_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L,
                        lattice2d_pitch(L), cpr, total);
     return hipGetLastError();
 }
 
 hipError_t launch_from_split(const uint8_t *src, int8_t *dst, int L, int n_rep, hipStream_t s) {
     const int64_t cpr = (int64_t)L * L / 16, total = cpr * n_rep;
-    hipLaunchKernelGGL(k_from_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L,
+    SMC_LAUNCH(k_from_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, L,
                        lattice2d_pitch(L), cpr, total);
     return hipGetLastError();
 }
@@ -681,7 +682,7 @@ size_t lattice2d_de_slots(int L, int n_rep) {
 hipError_t launch_lattice2d_de_collect(const int64_t *part, int64_t *dE, int L, int n_rep, hipStream_t s) {
     const size_t slots = lattice2d_de_slots(L, n_rep);
     if (slots == 0 || n_rep <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_de_collect, dim3((unsigned)n_rep), dim3(256), 0, s, part, dE, (int)(slots / n_rep));
+    SMC_LAUNCH(k_de_collect, dim3((unsigned)n_rep), dim3(256), 0, s, part, dE, (int)(slots / n_rep));
     return hipGetLastError();
 }
 
@@ -717,7 +718,7 @@ hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_r
         (void)hipFuncSetAttribute((const void *)k_ising2d_split<CC, NFF>,                                  \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
         const unsigned threads = compute_threads + 64u * LoaderShape<NFF>::NLW;                           \
-        hipLaunchKernelGGL((k_ising2d_split<CC, NFF>), dim3(blocks), dim3(threads), lds, s, a);            \
+        SMC_LAUNCH((k_ising2d_split<CC, NFF>), dim3(blocks), dim3(threads), lds, s, a);            \
         return hipGetLastError();                                                                          \
     }
     SMC_L2D(1, 2)

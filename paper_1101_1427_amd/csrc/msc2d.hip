@@ -346,14 +346,14 @@ bool msc2d_supported(int dim, int L) { return dim == 2 && (L == 16 || L == 32 ||
 hipError_t launch_msc_pack(const int8_t *spins, uint32_t *packed, int64_t N, int n_groups, hipStream_t s) {
     const int64_t quads = (int64_t)n_groups * N / 4;
     if (quads == 0 || N % 4) return quads == 0 ? hipSuccess : hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_msc_pack, dim3(blocks_for(quads)), dim3(256), 0, s, spins, packed, N, quads);
+    SMC_LAUNCH(k_msc_pack, dim3(blocks_for(quads)), dim3(256), 0, s, spins, packed, N, quads);
     return hipGetLastError();
 }
 
 hipError_t launch_msc_pack_coup(const int8_t *coup, uint32_t *packed, int64_t dN, int n_groups, hipStream_t s) {
     const int64_t quads = (int64_t)n_groups * dN / 4;
     if (quads == 0 || dN % 4) return quads == 0 ? hipSuccess : hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_msc_pack, dim3(blocks_for(quads)), dim3(256), 0, s, coup, packed, dN, quads);
+    SMC_LAUNCH(k_msc_pack, dim3(blocks_for(quads)), dim3(256), 0, s, coup, packed, dN, quads);
     return hipGetLastError();
 }
 
@@ -361,22 +361,22 @@ hipError_t launch_msc_unpack(const uint32_t *packed, const uint32_t *gauge, int8
                              hipStream_t s) {
     const int64_t quads = (int64_t)n_groups * N / 4;
     if (quads == 0 || N % 4) return quads == 0 ? hipSuccess : hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_msc_unpack, dim3(blocks_for(quads)), dim3(256), 0, s, packed, gauge, spins, N, quads);
+    SMC_LAUNCH(k_msc_unpack, dim3(blocks_for(quads)), dim3(256), 0, s, packed, gauge, spins, N, quads);
     return hipGetLastError();
 }
 
 hipError_t launch_msc_gauge2d(uint32_t *spins, uint32_t *coup, uint32_t *gauge, int L, int n_groups, hipStream_t s) {
     const int64_t rows = (int64_t)n_groups * L, words = rows * L;
     if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_msc_gauge_rows, dim3(blocks_for(rows)), dim3(256), 0, s, spins, coup, gauge, L, rows);
+    SMC_LAUNCH(k_msc_gauge_rows, dim3(blocks_for(rows)), dim3(256), 0, s, spins, coup, gauge, L, rows);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_msc_gauge_vertical, dim3(blocks_for(words)), dim3(256), 0, s, coup, gauge, L, words);
+    SMC_LAUNCH(k_msc_gauge_vertical, dim3(blocks_for(words)), dim3(256), 0, s, coup, gauge, L, words);
     return hipGetLastError();
 }
 
 hipError_t launch_msc_energy_diff(const double *E0, const double *E1, int64_t *dE, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_msc_energy_diff, dim3(blocks_for(n)), dim3(256), 0, s, E0, E1, dE, n);
+    SMC_LAUNCH(k_msc_energy_diff, dim3(blocks_for(n)), dim3(256), 0, s, E0, E1, dE, n);
     return hipGetLastError();
 }
 
@@ -386,9 +386,9 @@ hipError_t launch_msc2d_seg(const Msc2dArgs &a, int words_per_draw, hipStream_t 
     const int wpw = kMscBlock / tpg * words_per_draw;
     const unsigned blocks = (unsigned)((a.G + wpw - 1) / wpw);
     if (words_per_draw == 2)
-        hipLaunchKernelGGL((k_msc2d<SEG, 2>), dim3(blocks), dim3(kMscBlock), 0, s, a);
+        SMC_LAUNCH((k_msc2d<SEG, 2>), dim3(blocks), dim3(kMscBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((k_msc2d<SEG, 1>), dim3(blocks), dim3(kMscBlock), 0, s, a);
+        SMC_LAUNCH((k_msc2d<SEG, 1>), dim3(blocks), dim3(kMscBlock), 0, s, a);
     return hipGetLastError();
 }
 

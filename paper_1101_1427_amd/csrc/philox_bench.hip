@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBenchBlock) void k_philox_bench(Key key, uint32_t 
 hipError_t launch_philox_bench(Key key, uint32_t t, uint32_t r, uint32_t tag, uint32_t n_threads, int per_thread,
                                uint32_t *out, hipStream_t s) {
     const unsigned blocks = (n_threads + kBenchBlock - 1) / kBenchBlock;
-    hipLaunchKernelGGL(k_philox_bench, dim3(blocks), dim3(kBenchBlock), 0, s, key, t, r, tag, n_threads, per_thread,
+    SMC_LAUNCH(k_philox_bench, dim3(blocks), dim3(kBenchBlock), 0, s, key, t, r, tag, n_threads, per_thread,
                        out);
     return hipGetLastError();
 }

@@ -410,11 +410,11 @@ hipError_t launch_pt3d(int model, int8_t *spins, const int8_t *coup, int rep_per
     if (model == SMC_EA) {
         (void)hipFuncSetAttribute((const void *)k_pt3d_chain<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-        hipLaunchKernelGGL(k_pt3d_chain<true>, dim3(n_chains), dim3(kThreads), lds, s, a);
+        SMC_LAUNCH(k_pt3d_chain<true>, dim3(n_chains), dim3(kThreads), lds, s, a);
     } else {
         (void)hipFuncSetAttribute((const void *)k_pt3d_chain<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
-        hipLaunchKernelGGL(k_pt3d_chain<false>, dim3(n_chains), dim3(kThreads), lds, s, a);
+        SMC_LAUNCH(k_pt3d_chain<false>, dim3(n_chains), dim3(kThreads), lds, s, a);
     }
     return hipGetLastError();
 }

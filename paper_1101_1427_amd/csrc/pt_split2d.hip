@@ -54,26 +54,26 @@ unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_pt_gather_thr(const ThrRow *rows, const int32_t *row_of_rep, ThrRow *out, int n_rep,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_pt_gather_thr, dim3(blocks_of(n_rep)), dim3(256), 0, s, rows, row_of_rep, out, n_rep);
+    SMC_LAUNCH(k_pt_gather_thr, dim3(blocks_of(n_rep)), dim3(256), 0, s, rows, row_of_rep, out, n_rep);
     return hipGetLastError();
 }
 
 hipError_t launch_pt_add_masked(int64_t *d, int64_t *E, const int32_t *row_of_rep, int n_rep, hipStream_t s) {
-    hipLaunchKernelGGL(k_pt_add_masked, dim3(blocks_of(n_rep)), dim3(256), 0, s, d, E, row_of_rep, n_rep);
+    SMC_LAUNCH(k_pt_add_masked, dim3(blocks_of(n_rep)), dim3(256), 0, s, d, E, row_of_rep, n_rep);
     return hipGetLastError();
 }
 
 hipError_t launch_copy_valid(const int8_t *src, int8_t *dst, const int32_t *row_of_rep, int64_t N, int n_rep,
                              hipStream_t s) {
     if (N % 16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_copy_valid, dim3(blocks_of(N / 16 * n_rep)), dim3(256), 0, s, src, dst, row_of_rep, N,
+    SMC_LAUNCH(k_copy_valid, dim3(blocks_of(N / 16 * n_rep)), dim3(256), 0, s, src, dst, row_of_rep, N,
                        n_rep);
     return hipGetLastError();
 }
 
 hipError_t launch_zero64(int64_t *p, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero64, dim3(blocks_of(n)), dim3(256), 0, s, p, n);
+    SMC_LAUNCH(k_zero64, dim3(blocks_of(n)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_bonds3d(const int8_t *coup, u
 hipError_t launch_pack_bonds3d(const int8_t *coup, uint2 *out, int L, int n_samples, hipStream_t s) {
     if (L % 16 || n_samples < 1) return hipErrorInvalidValue;
     const int64_t N = (int64_t)L * L * L, total = (int64_t)n_samples * (N >> 4);
-    hipLaunchKernelGGL(k_pack_bonds3d, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, coup,
+    SMC_LAUNCH(k_pack_bonds3d, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, coup,
                        out, N, total);
     return hipGetLastError();
 }
@@ -198,25 +198,21 @@ bool sweep3d_nt() {
 }
 
 template <int M, int Z>
-void launch_rows(bool nt, unsigned blocks, const Sweep3dArgs &a, hipStream_t s) {
+hipError_t launch_rows(bool nt, unsigned blocks, const Sweep3dArgs &a, hipStream_t s) {
     if (nt)
-        hipLaunchKernelGGL((k_ising3d_half<M, Z, true>), dim3(blocks), dim3(kThreads), 0, s, a);
+        SMC_LAUNCH((k_ising3d_half<M, Z, true>), dim3(blocks), dim3(kThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_ising3d_half<M, Z, false>), dim3(blocks), dim3(kThreads), 0, s, a);
+        SMC_LAUNCH((k_ising3d_half<M, Z, false>), dim3(blocks), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
 }
 
 template <int M>
-void launch_model(int Z, bool nt, unsigned blocks, const Sweep3dArgs &a, hipStream_t s) {
-    if (Z == 16)
-        launch_rows<M, 16>(nt, blocks, a, s);
-    else if (Z == 8)
-        launch_rows<M, 8>(nt, blocks, a, s);
-    else if (Z == 4)
-        launch_rows<M, 4>(nt, blocks, a, s);
-    else if (Z == 2)
-        launch_rows<M, 2>(nt, blocks, a, s);
-    else
-        launch_rows<M, 1>(nt, blocks, a, s);
+hipError_t launch_model(int Z, bool nt, unsigned blocks, const Sweep3dArgs &a, hipStream_t s) {
+    if (Z == 16) return launch_rows<M, 16>(nt, blocks, a, s);
+    if (Z == 8) return launch_rows<M, 8>(nt, blocks, a, s);
+    if (Z == 4) return launch_rows<M, 4>(nt, blocks, a, s);
+    if (Z == 2) return launch_rows<M, 2>(nt, blocks, a, s);
+    return launch_rows<M, 1>(nt, blocks, a, s);
 }
 
 }  // namespace
@@ -247,13 +243,9 @@ hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, const uint2 *p
     a.four = 4u;
     const int64_t blocks = (int64_t)n_rep * a.blocks_per_rep;
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
-    if (pbonds)
-        launch_model<2>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
-    else if (coup)
-        launch_model<1>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
-    else
-        launch_model<0>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
-    return hipGetLastError();
+    if (pbonds) return launch_model<2>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
+    if (coup) return launch_model<1>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
+    return launch_model<0>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
 }
 
 }  // namespace smc

@@ -174,6 +174,14 @@ def test_dcb_arguments_are_validated():
     assert rc == S.EINVAL and b"16-byte aligned" in L.smc_last_error()
     d3 = _desc(dim=3, L=48, n_rep=1, spins_len=48 ** 3)
     assert L.smc_dcb_sweep(C.byref(d3), FAKE, None, beta, 0, 1, 16, 1, 0, None, None, None) == S.EINVAL
+    # only the pointers the kernel reads must be aligned: an Ising call ignores
+    # its couplings argument (a zero-sweep call returns after the checks)
+    d3 = _desc(dim=3, L=32, n_rep=1, spins_len=32 ** 3)
+    unaligned = C.c_void_p(FAKE.value + 3)
+    assert L.smc_dcb_sweep(C.byref(d3), FAKE, unaligned, beta, 0, 0, 16, 1, 0, None, None, None) == S.OK
+    d3ea = _desc(model=S.EA, dim=3, L=32, n_rep=1, spins_len=32 ** 3, coup_len=3 * 32 ** 3)
+    rc = L.smc_dcb_sweep(C.byref(d3ea), FAKE, unaligned, beta, 0, 0, 16, 1, 0, None, None, None)
+    assert rc == S.EINVAL and b"16-byte aligned" in L.smc_last_error()
     dh = _desc(model=S.HEISENBERG, dim=3, L=32, n_rep=1, spins_len=3 * 32 ** 3)
     assert L.smc_dcb_sweep(C.byref(dh), FAKE, None, beta, 0, 1, 16, 1, 0, None, None, None) == S.EUNSUPPORTED
 
