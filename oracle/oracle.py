@@ -63,6 +63,7 @@ def lib():
             "orc_run_series": (None, [I, I, vp, i8p, D, U64, U32, U32, I, i64p, i64p]),
             "orc_heis_half_sweep": (I64, [I, I, f64p, D, U64, U32, U32, I]),
             "orc_heis_renormalise": (None, [I, I, f64p]),
+            "orc_heis_half_sweep_gaps": (I64, [I, I, f64p, D, U64, U32, U32, I, f64p]),
             "orc_heis_sweep": (I64, [I, I, f64p, D, U64, U32, U32, I]),
             "orc_heis_run": (I64, [I, I, f64p, D, U64, U32, U32, I, I]),
             "orc_heis_energy": (D, [I, I, f64p]),
@@ -166,6 +167,18 @@ def init_heis(dim: int, L: int, seed: int, r: int) -> np.ndarray:
 
 def heis_half_sweep(dim, L, s, beta, seed, r, t, c) -> int:
     return int(lib().orc_heis_half_sweep(dim, L, s, beta, seed, r, t, c))
+
+
+def heis_sweep_gaps(dim, L, s, beta, seed, r, t, renorm_every=16):
+    """Sweep t (orc_heis_sweep's moves and renormalisation) that also returns,
+    per site, the acceptance margin u - exp(-beta Delta E) of its move (+inf
+    where Delta E <= 0): (accepted moves, gaps float64 [N])."""
+    gap = np.full(n_sites(dim, L), np.inf)
+    n = int(lib().orc_heis_half_sweep_gaps(dim, L, s, beta, seed, r, t, 0, gap))
+    n += int(lib().orc_heis_half_sweep_gaps(dim, L, s, beta, seed, r, t, 1, gap))
+    if renorm_every > 0 and (t + 1) % renorm_every == 0:
+        heis_renormalise(dim, L, s)
+    return n, gap
 
 
 def heis_sweep(dim, L, s, beta, seed, r, t, renorm_every=16) -> int:

@@ -519,8 +519,8 @@ static void cap_point(const double *s, double cap, double u0, double u1, double 
  * the cap of size cap around s (0 < cap <= 2) from words 0, 1 of
  * (i >> 1, t, r, HEIS+c) and accept iff Delta E = -(s' - s).h <= 0 or
  * u < exp(-beta Delta E), u from word 2.  Returns 1 if accepted. */
-static int heis_site_move_cap(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r, uint32_t t, int c,
-                              int64_t i, double cap)
+static int heis_site_move_gap(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r, uint32_t t, int c,
+                              int64_t i, double cap, double *gap)
 {
     int x[3];
     coords(dim, L, i, x);
@@ -540,9 +540,16 @@ static int heis_site_move_cap(int dim, int L, double *s, double beta, uint64_t s
     double dE = 0.0;
     for (int a = 0; a < 3; ++a) dE -= (sp[a] - s[3 * i + a]) * h[a];
     int accept = (dE <= 0.0) || (unit23(w[2]) < exp(-beta * dE));
+    if (gap) *gap = dE <= 0.0 ? INFINITY : unit23(w[2]) - exp(-beta * dE);
     if (accept)
         for (int a = 0; a < 3; ++a) s[3 * i + a] = sp[a];
     return accept;
+}
+
+static int heis_site_move_cap(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r, uint32_t t, int c,
+                              int64_t i, double cap)
+{
+    return heis_site_move_gap(dim, L, s, beta, seed, r, t, c, i, cap, NULL);
 }
 
 static int heis_site_move(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r, uint32_t t, int c,
@@ -563,6 +570,26 @@ EXPORT int64_t orc_heis_half_sweep(int dim, int L, double *s, double beta,
         coords(dim, L, i, x);
         if (colour_of(dim, x) != c) continue;
         n_acc += heis_site_move(dim, L, s, beta, seed, r, t, c, i);
+    }
+    return n_acc;
+}
+
+/* orc_heis_half_sweep that also reports, for every site i of colour c, the
+ * margin of its acceptance test: gap[i] = u - exp(-beta Delta E), or +inf
+ * where Delta E <= 0 decides alone (other entries untouched).  An
+ * implementation that evaluates the move in lower precision can only take
+ * the other decision where |gap| lies within its rounding (test
+ * infrastructure: the same moves as orc_heis_half_sweep). */
+EXPORT int64_t orc_heis_half_sweep_gaps(int dim, int L, double *s, double beta, uint64_t seed, uint32_t r,
+                                        uint32_t t, int c, double *gap)
+{
+    int64_t N = n_sites(dim, L);
+    int64_t n_acc = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int x[3];
+        coords(dim, L, i, x);
+        if (colour_of(dim, x) != c) continue;
+        n_acc += heis_site_move_gap(dim, L, s, beta, seed, r, t, c, i, 0.0, &gap[i]);
     }
     return n_acc;
 }

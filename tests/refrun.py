@@ -53,3 +53,50 @@ def sweep_msc(model, dim, L, spins, coup, betas, seed, t0, n, w=32):
         J = None if coup is None else coup[r]
         dE[r] = O.run(dim, L, J, spins[r], float(betas[r]), seed, r // w, t0, n)
     return dE
+
+
+def pt_chain(job):
+    """One tempering chain of a batch run by the oracle (module-level so that a
+    process pool can call it).  job: dict with dim, L, model, seed, q (chain
+    index), n_temps, sample, beta, perm, t0, steps and m.  Returns (spins
+    [n_temps][N], slot_of_temp, E, swap counts [n_temps-1], near-tie audit)."""
+    dim, L, n_temps, q = job["dim"], job["L"], job["n_temps"], job["q"]
+    r0 = q * n_temps
+    chain = np.stack([O.init_spins(dim, L, job["seed"], r0 + k) for k in range(n_temps)])
+    J = O.init_couplings(dim, L, job["seed"], job["sample"]) if job["model"] == EA else None
+    E = np.array([O.energy(dim, L, J, chain[k]) for k in range(n_temps)], np.int64)
+    sq = np.asarray(job["perm"], np.int32).copy()
+    aq = np.zeros(n_temps, np.uint64)
+    O.pt_audit(reset=True)
+    O.pt_run(dim, L, J, chain, np.asarray(job["beta"], np.float64), sq, E, job["seed"], q, r0, job["t0"],
+             job["steps"], aq, sweeps_per_step=job.get("m", 1))
+    return chain, sq, E, aq[:n_temps - 1], O.pt_audit(reset=True)
+
+
+def run_parallel(fn, jobs):
+    """fn over jobs in fresh worker processes (spawned, so that they never
+    inherit a GPU context), at most 16 at a time; results in job order."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    n = max(1, min(16, n, len(jobs)))
+    with cf.ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(fn, jobs))
+
+
+def sweeps_parallel(job):
+    """n sweeps of one 2D/3D replica by the oracle (for a process pool): job has
+    dim, L, seed, r, beta, t0, n and checkpoints (sweep counts after which the
+    spins are recorded).  Returns the list of recorded spin arrays."""
+    s = O.init_spins(job["dim"], job["L"], job["seed"], job["r"])
+    out, done = [], 0
+    for upto in job["checkpoints"]:
+        O.run(job["dim"], job["L"], None, s, job["beta"], job["seed"], job["r"], job["t0"] + done, upto - done)
+        done = upto
+        out.append(s.copy())
+    return out

@@ -32,10 +32,28 @@ def _binned_mean_err(x, n_bins=20):
     return bins.mean(), bins.std(ddof=1) / np.sqrt(n_bins)
 
 
+# A float32 decision can differ from the float64 oracle's only where the
+# uniform u lies within the float32 error of exp(-beta dE): spins and
+# proposals carry ~2^-23 relative error, the field of six neighbours and the
+# difference s' - s put at most ~2e-5 on dE, and beta = 0.693 scales that to
+# below 2^-16 on the acceptance probability (the hardware exp2 adds ~1e-7).
+NEAR_TIE = 2.0 ** -16
+
+
+def _neighbours_of(mask, L):
+    g = mask.reshape(L, L, L)
+    out = np.zeros_like(g)
+    for ax in range(3):
+        out |= np.roll(g, 1, axis=ax) | np.roll(g, -1, axis=ax)
+    return out.reshape(-1)
+
+
 def test_heisenberg_256_first_sweep_sitewise():
     """256^3 at beta = 0.693 (the Heisenberg workload): one sweep from each
-    side's own start; every component within 1e-5 except where an accept
-    decision sits within float32 rounding of exp(-beta dE)."""
+    side's own start; every component within 1e-5 except at sites whose
+    decision differs, and each such site is either a near tie of the oracle's
+    acceptance test (|u - exp(-beta dE)| < 2^-16) or a colour-1 neighbour of
+    a colour-0 near tie (whose field the tie changed)."""
     cfg = W.heisenberg_3d()
     L, beta = cfg.L, cfg.betas[0]
     N = L ** 3
@@ -45,13 +63,22 @@ def test_heisenberg_256_first_sweep_sitewise():
     n_acc = torch.zeros(1, dtype=torch.int64, device=DEV)
     S.metropolis_sweep(b, spins, [beta], 0, 1, dE_accum=n_acc)
     ref = O.init_heis(3, L, cfg.seed, 0)
-    ref_acc = O.heis_sweep(3, L, ref, beta, cfg.seed, 0, 0, cfg.renorm_every)
+    ref_acc, gap = O.heis_sweep_gaps(3, L, ref, beta, cfg.seed, 0, 0, cfg.renorm_every)
     got = _host(spins).astype(np.float64).reshape(-1, 3)
     dev = np.abs(got - ref).max(axis=1)
-    mismatches = int((dev > 1e-5).sum())
-    # a decision differs only where u is within ~2^-23 of exp(-beta dE): expected count ~ N * 2^-21
-    assert mismatches <= max(8, int(8 * N * 2.0 ** -21)), mismatches
-    assert abs(int(_host(n_acc)[0]) - ref_acc) <= mismatches
+    mis = dev > 1e-5
+    idx = np.arange(N)
+    colour = ((idx % L) + (idx // L) % L + idx // (L * L)) & 1
+    primary = mis & (np.abs(gap) < NEAR_TIE)
+    secondary = mis & (colour == 1) & _neighbours_of(primary & (colour == 0), L)
+    unexplained = int((mis & ~primary & ~secondary).sum())
+    print(f"256^3 first sweep: {int(mis.sum())} differing sites ({int(primary.sum())} near ties, "
+          f"{int((secondary & ~primary).sum())} neighbours of one); sites within 2^-16 of a tie: "
+          f"{int((np.abs(gap) < NEAR_TIE).sum())}")
+    assert unexplained == 0
+    # at most max(4, 16 N 2^-24) = 16 differing sites at 256^3 (1 observed)
+    assert mis.sum() <= max(4, int(16 * N * 2.0 ** -24)), int(mis.sum())
+    assert abs(int(_host(n_acc)[0]) - ref_acc) <= int(mis.sum())
     assert np.abs(np.linalg.norm(got, axis=1) - 1).max() < 2e-6
 
 
