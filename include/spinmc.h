@@ -213,6 +213,29 @@ int smc_measure_energy_magnetisation(const smc_desc *desc, const void *spins,
                                      double *magnetisation, void *stream);
 
 /*
+ * The same measurement for callers that cannot allocate device memory (code
+ * running under a stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc / hipFree and stages nothing from the
+ * host.  Its partial sums live in one fixed device array of the library
+ * (16 MiB on each GPU it runs on, held until the process ends) instead of the
+ * per-stream scratch; arguments, results and kernels are those of
+ * smc_measure_energy_magnetisation, so the results are identical.
+ *  desc:  a uniform batch (L > 0); SMC_EUNSUPPORTED for an uneven one.
+ *         The partial sums take 32 bytes x n_rep x min(2048, ceil(N / 4096));
+ *         a batch needing more than 16 MiB is refused with SMC_EINVAL before
+ *         anything is issued (e.g. up to 256 replicas of 16384^2, or 524288
+ *         replicas of up to 4096 sites).
+ *  spins, couplings, energy, magnetisation, stream: as above.
+ * Every call on one GPU shares that GPU's array, which keeps the previous
+ * call's contents (every entry a call reads it writes first): calls that
+ * overlap on one GPU (different streams, or host threads) race and must be
+ * ordered by the caller.
+ */
+int smc_measure_energy_magnetisation_noalloc(const smc_desc *desc, const void *spins,
+                                             const int8_t *couplings, double *energy,
+                                             double *magnetisation, void *stream);
+
+/*
  * Autotuning of launch shapes; it never changes results.  For a 2D Ising or
  * EA batch it measures the workgroup size of the LDS-resident 2D kernel
  * (small lattices, uneven tempering) for every edge of the batch that this

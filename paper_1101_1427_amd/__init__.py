@@ -57,7 +57,9 @@ def lib():
         L.smc_metropolis_sweep.argtypes = [P(Desc), vp, vp, P(C.c_double), C.c_uint64, C.c_int32, vp, vp]
         L.smc_pt_sweep_swap.argtypes = [P(Desc), P(PTDesc), vp, vp, vp, vp, C.c_uint64, C.c_int32, vp, vp]
         L.smc_measure_energy_magnetisation.argtypes = [P(Desc), vp, vp, vp, vp, vp]
-        for f in (L.smc_spin_init, L.smc_metropolis_sweep, L.smc_pt_sweep_swap, L.smc_measure_energy_magnetisation):
+        L.smc_measure_energy_magnetisation_noalloc.argtypes = [P(Desc), vp, vp, vp, vp, vp]
+        for f in (L.smc_spin_init, L.smc_metropolis_sweep, L.smc_pt_sweep_swap, L.smc_measure_energy_magnetisation,
+                  L.smc_measure_energy_magnetisation_noalloc):
             f.restype = C.c_int
         L.smc_sweep_plan.argtypes = [P(Desc), P(C.c_int32), P(C.c_char_p)]
         L.smc_sweep_plan.restype = C.c_int
@@ -271,6 +273,16 @@ def measure_energy_magnetisation(batch: Batch, spins, energy, magnetisation=None
     _check(lib().smc_measure_energy_magnetisation(C.byref(d), _ptr(spins), _ptr(couplings), _ptr(energy),
                                                   _ptr(magnetisation), _stream(stream)),
            "smc_measure_energy_magnetisation")
+
+
+def measure_energy_magnetisation_noalloc(batch: Batch, spins, energy, magnetisation=None, couplings=None,
+                                        stream=None):
+    """As measure_energy_magnetisation, with the library's fixed device array
+    for the partial sums (no allocation; uniform batches, bounded size)."""
+    d = _desc(batch, spins, couplings)
+    _check(lib().smc_measure_energy_magnetisation_noalloc(C.byref(d), _ptr(spins), _ptr(couplings), _ptr(energy),
+                                                          _ptr(magnetisation), _stream(stream)),
+           "smc_measure_energy_magnetisation_noalloc")
 
 
 def sweep_plan(batch: Batch):

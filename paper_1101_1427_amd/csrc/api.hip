@@ -1681,3 +1681,60 @@ int smc_measure_energy_magnetisation(const smc_desc *desc, const void *spins, co
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------ allocation-free call --
+// smc_measure_energy_magnetisation_noalloc keeps its partial sums in this
+// fixed array instead of the per-stream scratch.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the device
+// symbol): the device address of each GPU's copy is looked up once per device
+// with hipGetSymbolAddress and that address is what the kernels receive.
+namespace smc {
+constexpr size_t kNoAllocScratchBytes = 16u << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(void **out) {
+    int dev = 0;
+    SMC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SMC_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_noalloc_mutex);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        SMC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(SMC_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return SMC_OK;
+}
+}  // namespace
+}  // namespace smc
+
+extern "C" {
+
+int smc_measure_energy_magnetisation_noalloc(const smc_desc *desc, const void *spins, const int8_t *couplings,
+                                             double *energy, double *magnetisation, void *stream) {
+    using namespace smc;
+    g_last_error.clear();
+    Plan plan;
+    int rc = validate(desc, true, plan);
+    if (rc) return rc;
+    if (desc->L <= 0) return fail(SMC_EUNSUPPORTED, "the allocation-free measurement takes uniform batches only");
+    if (!spins || !energy) return fail(SMC_EINVAL, "spins and energy are required");
+    if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
+    const size_t bytes = measure_scratch_bytes(plan.b, plan.max_L);
+    if (bytes > kNoAllocScratchBytes)
+        return fail(SMC_EINVAL, "batch needs %zu bytes of partial sums; the allocation-free call holds at most %zu",
+                    bytes, kNoAllocScratchBytes);
+    void *p = nullptr;
+    if ((rc = noalloc_scratch(&p))) return rc;
+    SMC_HIP(launch_measure(plan.b, spins, desc->model == SMC_EA ? couplings : nullptr, plan.max_L, energy,
+                           magnetisation, p, bytes, (hipStream_t)stream));
+    return SMC_OK;
+}
+
+}  // extern "C"

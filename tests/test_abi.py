@@ -245,3 +245,15 @@ def test_sweep_plan_names_the_3d_kernel(monkeypatch):
     assert S.sweep_plan(S.Batch(S.HEISENBERG, 3, 32, 1, 1))[1] != "k_ising3d_half"
     monkeypatch.setenv("SPINMC_SWEEP3D", "0")
     assert S.sweep_plan(S.Batch(S.ISING, 3, 64, 1, 1)) == (2, "k_half_sweep_generic")
+
+
+def test_noalloc_measure_checks_before_any_device_work():
+    """The allocation-free measurement refuses uneven batches and batches whose
+    partial sums exceed its fixed 16 MiB array, on the host."""
+    L = S.lib()
+    d = _desc(L=16384, n_rep=257, spins_len=257 * 16384 * 16384)  # 257 x 2048 partials x 32 B > 16 MiB
+    rc = L.smc_measure_energy_magnetisation_noalloc(C.byref(d), FAKE, None, FAKE, None, None)
+    assert rc == S.EINVAL and b"16777216" in L.smc_last_error()
+    inst = (S.Inst * 2)(S.Inst(16, 0, 0, 0), S.Inst(32, 0, 256, 0))
+    d = _desc(L=0, n_rep=2, inst=C.cast(inst, C.POINTER(S.Inst)), spins_len=256 + 1024)
+    assert L.smc_measure_energy_magnetisation_noalloc(C.byref(d), FAKE, None, FAKE, None, None) == S.EUNSUPPORTED
