@@ -1202,16 +1202,37 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
             if ((rc = ensure(c, kL2dPart, slots * sizeof(int64_t), &q))) return rc;
             part = (int64_t *)q;
         }
-        SMC_HIP(launch_to_split((const int8_t *)spins, A, desc->L, desc->n_rep, s));
+        const char *fuse_env = getenv("SPINMC_L2D_FUSE");
+        if (fuse_env && fuse_env[0] == '0') {
+            // separate layout conversions around the sweeps (for comparison)
+            SMC_HIP(launch_to_split((const int8_t *)spins, A, desc->L, desc->n_rep, s));
+            SweepTimer timer(s, n_sweeps);
+            for (int32_t k = 0; k < n_sweeps; ++k) {
+                const uint32_t t = (uint32_t)(sweep0 + (uint64_t)k);
+                SMC_HIP(launch_ising2d_split(k & 1 ? B : A, false, k & 1 ? A : B, false, desc->L, desc->n_rep,
+                                             a.thr, part, k == 0, a.key, t, s));
+            }
+            timer.finish();
+            if (part) SMC_HIP(launch_lattice2d_de_collect(part, dE_accum, desc->L, desc->n_rep, s));
+            SMC_HIP(launch_from_split(n_sweeps & 1 ? B : A, (int8_t *)spins, desc->L, desc->n_rep, s));
+            return SMC_OK;
+        }
+        // The first sweep reads the caller's lattice, the last one writes it
+        // back; the sweeps between ping-pong on the split layout (sweep k
+        // leaves its result in A for even k, in B for odd k).  A single sweep
+        // ends in A and is converted back.
         SweepTimer timer(s, n_sweeps);
         for (int32_t k = 0; k < n_sweeps; ++k) {
             const uint32_t t = (uint32_t)(sweep0 + (uint64_t)k);
-            SMC_HIP(launch_ising2d_split(k & 1 ? B : A, k & 1 ? A : B, desc->L, desc->n_rep, a.thr, part, k == 0,
-                                         a.key, t, s));
+            const bool first = k == 0, last = k == n_sweeps - 1 && n_sweeps > 1;
+            const void *src = first ? spins : (k & 1 ? (const void *)A : (const void *)B);
+            void *dst = last ? spins : (k & 1 ? (void *)B : (void *)A);
+            SMC_HIP(launch_ising2d_split(src, first, dst, last, desc->L, desc->n_rep, a.thr, part, first, a.key, t,
+                                         s));
         }
         timer.finish();
         if (part) SMC_HIP(launch_lattice2d_de_collect(part, dE_accum, desc->L, desc->n_rep, s));
-        SMC_HIP(launch_from_split(n_sweeps & 1 ? B : A, (int8_t *)spins, desc->L, desc->n_rep, s));
+        if (n_sweeps == 1) SMC_HIP(launch_from_split(A, (int8_t *)spins, desc->L, desc->n_rep, s));
         return SMC_OK;
     }
     if (use_sweep3d(desc, spins, a.coup, rows)) {
@@ -1539,7 +1560,8 @@ int run_pt_split2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, void *spin
         sw.t = t;
         SMC_HIP(launch_pt_gather_thr(thr_rows, sw.row_of_rep, thr_rep, n_rep, s));
         for (int j = 0; j < m; ++j, ++done)
-            SMC_HIP(launch_ising2d_split(done & 1 ? B : A, done & 1 ? A : B, L, n_rep, thr_rep, part, j == 0, key,
+            SMC_HIP(launch_ising2d_split(done & 1 ? B : A, false, done & 1 ? A : B, false, L, n_rep, thr_rep, part,
+                                         j == 0, key,
                                          t * (uint32_t)m + (uint32_t)j, s));
         SMC_HIP(launch_lattice2d_de_collect(part, d, L, n_rep, s));
         SMC_HIP(launch_pt_add_masked(d, sw.E, sw.row_of_rep, n_rep, s));

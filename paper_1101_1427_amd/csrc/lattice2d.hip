@@ -19,6 +19,13 @@
 // spin read once and written once (plus 4 halo rows per band).  Rows are
 // stored in lattice order with a padded pitch.
 //
+// Caller's layout.  The first sweep of a call can read the caller's
+// row-major int8 +-1 lattice directly (a feed is then one whole row, split
+// into the two planes by the compute waves, whose plane-0 half is kept in
+// registers for the next step), and the last sweep can write it directly
+// (both planes of a finished row interleaved back into the row), so a call
+// moves no bytes beyond its sweeps.
+//
 // Decision (Eq. 2 with integer thresholds).  Per site the number n of
 // antiparallel neighbours gives dE = 8 - 4n; n >= 2 always flips.  The
 // 16-bit head of the site's uniform is compared with the 16-bit high part
@@ -164,10 +171,10 @@ __device__ __forceinline__ uint32_t decide4(uint32_t n, uint32_t wa, uint32_t wb
 }
 
 struct Lattice2dArgs {
-    const uint8_t *src;  // split planes of replica 0 (read)
-    uint8_t *dst;        // split planes of replica 0 (written)
-    int64_t rep_bytes;   // bytes per replica (2 planes of L rows at `pitch`)
-    int64_t pitch;       // bytes between consecutive physical rows of a plane (>= L/2)
+    const uint8_t *src;  // replica 0 read: split planes, or the caller's int8 rows (IO & kAbiIn)
+    uint8_t *dst;        // replica 0 written: split planes, or the caller's int8 rows (IO & kAbiOut)
+    int64_t src_rep, dst_rep;      // bytes per replica (split: 2 planes of L rows at the pitch; rows: L*L)
+    int64_t src_pitch, dst_pitch;  // bytes between consecutive rows (split plane: >= L/2; rows: L)
     const ThrRow *thr;   // per replica
     int64_t *dE_part;    // per compute wave of every workgroup (workgroup-major), or nullptr
     int dE_first;        // 1: this launch writes the partial sums, 0: adds to them
@@ -302,21 +309,54 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 
+// IO flags of a launch: the source / destination is the caller's row-major
+// int8 +-1 lattice instead of the split planes.
+constexpr int kAbiIn = 1, kAbiOut = 2;
+
 template <int C>
 struct Band {
-    const uint8_t *S0, *S1;
-    uint8_t *D0, *D1;
+    const uint8_t *S0, *S1;  // split source planes (S0 alone: the source rows when reading the caller's layout)
+    uint8_t *D0, *D1;        // split destination planes (D0 alone: the destination rows)
     int L, half, Y0, H, ncw;
-    int64_t pitch;
+    int64_t pin, pout;       // row pitch of source and destination
     int64_t lane_off;
     uint32_t gpr, lg0, r, t;
     Key key;
     Lut K;
-    __device__ __forceinline__ int64_t off(int y) const {
-        const int w = y < 0 ? y + L : (y >= L ? y - L : y);
-        return (int64_t)w * pitch;
-    }
+    __device__ __forceinline__ int wrap(int y) const { return y < 0 ? y + L : (y >= L ? y - L : y); }
+    __device__ __forceinline__ int64_t off(int y) const { return (int64_t)wrap(y) * pin; }
+    __device__ __forceinline__ int64_t off_out(int y) const { return (int64_t)wrap(y) * pout; }
 };
+
+// Caller's layout <-> split planes.  A row's 16C bytes x0 .. x0+16C-1 (x0 a
+// multiple of 16C) hold its sites as int8 +-1; the split rows hold the even-x
+// and the odd-x sites of that range as 0 (+1) / 1 (-1) bytes.  Plane p of row
+// y holds the sites with x = 2k + ((y + p) & 1).
+template <int C>
+__device__ __forceinline__ void split_row(const Row<2 * C> &v, Row<C> &even, Row<C> &odd) {
+    const uint32_t m = 0x01010101u;
+#pragma unroll
+    for (int i = 0; i < 2 * C; ++i) {
+        const uint32_t b0 = (v.d[2 * i] >> 1) & m, b1 = (v.d[2 * i + 1] >> 1) & m;
+        even.d[i] = perm(b1, b0, 0x06040200u);
+        odd.d[i] = perm(b1, b0, 0x07050301u);
+    }
+}
+
+__device__ __forceinline__ uint32_t to_pm1(uint32_t b) { return ((b << 8) - b) | 0x01010101u; }
+
+template <int C>
+__device__ __forceinline__ void store_joined_row(uint8_t *p, const Row<C> &even, const Row<C> &odd) {
+    typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const uint32_t e0 = to_pm1(even.d[2 * i]), o0 = to_pm1(odd.d[2 * i]);
+        const uint32_t e1 = to_pm1(even.d[2 * i + 1]), o1 = to_pm1(odd.d[2 * i + 1]);
+        const v4 x = {perm(o0, e0, 0x05010400u), perm(o0, e0, 0x07030602u), perm(o1, e1, 0x05010400u),
+                      perm(o1, e1, 0x07030602u)};
+        __builtin_nontemporal_store(x, (v4 *)p + i);
+    }
+}
 
 // Loader waves: the feed of step s (plane-1 row s+1, plane-0 row s) goes to
 // ring slot (s - Y0 + 1) % kSlots.  A feed is NF direct-load instructions,
@@ -329,7 +369,7 @@ struct LoaderShape {
     static constexpr int PER = NF / NLW;          // instructions per loader wave per feed
 };
 
-template <int C, int NF>
+template <int C, int NF, int IO>
 __device__ __forceinline__ void issue_feed(const Band<C> &B, int s, uint8_t *ring, int lw) {
     using SH = LoaderShape<NF>;
     const int slot = (s - B.Y0 + 1) % kSlots;
@@ -339,13 +379,23 @@ __device__ __forceinline__ void issue_feed(const Band<C> &B, int s, uint8_t *rin
 #pragma unroll
     for (int q = 0; q < SH::PER; ++q) {
         const int ins = lw + q * SH::NLW;  // instruction index within the feed
-        const int pl = ins / per_plane, k = ins % per_plane;
-        const int row = pl == 0 ? s + 1 : s;  // pl 0: plane 1, pl 1: plane 0
-        const uint8_t *src = (pl == 0 ? B.S1 : B.S0) + B.off(row);
-        uint8_t *dst = ring + (size_t)(pl * kSlots + slot) * (size_t)B.half;
-        if (active)
-            __builtin_amdgcn_global_load_lds(src + 1024 * k + 16 * lane, (lds_void_t *)(lds_u8_t *)(dst + 1024 * k), 16,
-                                             0, 0);
+        if constexpr (IO & kAbiIn) {
+            // the whole caller's row s+1 (L bytes) into slot `slot` (L bytes),
+            // instruction ins moving bytes [seg * ins, seg * (ins + 1))
+            const int seg = B.half < 1024 ? B.half : 1024;
+            const uint8_t *src = B.S0 + B.off(s + 1) + (int64_t)seg * ins;
+            uint8_t *dst = ring + (size_t)slot * (size_t)B.L + (size_t)seg * ins;
+            if (active)
+                __builtin_amdgcn_global_load_lds(src + 16 * lane, (lds_void_t *)(lds_u8_t *)dst, 16, 0, 0);
+        } else {
+            const int pl = ins / per_plane, k = ins % per_plane;
+            const int row = pl == 0 ? s + 1 : s;  // pl 0: plane 1, pl 1: plane 0
+            const uint8_t *src = (pl == 0 ? B.S1 : B.S0) + B.off(row);
+            uint8_t *dst = ring + (size_t)(pl * kSlots + slot) * (size_t)B.half;
+            if (active)
+                __builtin_amdgcn_global_load_lds(src + 1024 * k + 16 * lane,
+                                                 (lds_void_t *)(lds_u8_t *)(dst + 1024 * k), 16, 0, 0);
+        }
     }
 }
 
@@ -354,20 +404,20 @@ __device__ __forceinline__ void issue_feed(const Band<C> &B, int s, uint8_t *rin
 // loaders order their LDS writes explicitly (wait_vmcnt before the barrier).
 __device__ __forceinline__ void loader_barrier() { __builtin_amdgcn_s_barrier(); }
 
-template <int C, int NF>
+template <int C, int NF, int IO>
 __device__ void loader_loop(const Band<C> &B, uint8_t *ring, int lw) {
     using SH = LoaderShape<NF>;
     const int first = B.Y0 - 1, last = B.Y0 + B.H;  // steps
     // prologue: feeds of steps first .. first+kDepth-1, then the first one must land
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) issue_feed<C, NF>(B, first + d, ring, lw);
+    for (int d = 0; d < kDepth; ++d) issue_feed<C, NF, IO>(B, first + d, ring, lw);
     wait_vmcnt<SH::PER *(kDepth - 1)>();
     loader_barrier();  // (1) prologue
     loader_barrier();  // (2) initial edge exchange of the compute waves
     for (int s = first; s < last; ++s) {
         // step s is running on the compute waves; bring in step s+kDepth, make s+1 land
         if (s + kDepth <= last) {
-            issue_feed<C, NF>(B, s + kDepth, ring, lw);
+            issue_feed<C, NF, IO>(B, s + kDepth, ring, lw);
             wait_vmcnt<SH::PER *(kDepth - 1)>();
         } else {
             wait_vmcnt<0>();
@@ -382,19 +432,37 @@ __device__ void loader_loop(const Band<C> &B, uint8_t *ring, int lw) {
 template <int C>
 struct Pipe {
     Row<C> p1[4], n0[4];
+    Row<C> next0;  // reading the caller's layout: plane-0 half of the row fed last step
     uint32_t e1, e0;
     uint32_t de_total, counted;
 };
 
-template <int C, int PH>
+template <int C, int PH, int IO>
 __device__ __forceinline__ void step(Pipe<C> &S, const Band<C> &B, int j, const uint8_t *ring, uint32_t *xch) {
     constexpr int a_m1 = (PH + 3) & 3, a_0 = PH & 3, a_p1 = (PH + 1) & 3, a_m2 = (PH + 2) & 3;
     constexpr int P = PH & 1;
     __builtin_amdgcn_sched_barrier(0);
     // new rows from the ring: plane-1 row j+1, plane-0 row j
     const int slot = (j - B.Y0 + 1) % kSlots;
-    S.p1[a_p1] = lds_row<C>(ring + (size_t)slot * B.half + B.lane_off);
-    Row<C> own0 = lds_row<C>(ring + (size_t)(kSlots + slot) * B.half + B.lane_off);
+    Row<C> own0;
+    if constexpr (IO & kAbiIn) {
+        // the caller's row j+1: plane 1 now, plane 0 at the next step (row
+        // y = j+1 has parity (PH+1) & 1 since bands start at multiples of 4)
+        const Row<2 * C> full = lds_row<2 * C>(ring + (size_t)slot * B.L + 2 * B.lane_off);
+        Row<C> ev, od;
+        split_row<C>(full, ev, od);
+        own0 = S.next0;
+        if constexpr (((PH + 1) & 1) == 1) {
+            S.p1[a_p1] = ev;
+            S.next0 = od;
+        } else {
+            S.p1[a_p1] = od;
+            S.next0 = ev;
+        }
+    } else {
+        S.p1[a_p1] = lds_row<C>(ring + (size_t)slot * B.half + B.lane_off);
+        own0 = lds_row<C>(ring + (size_t)(kSlots + slot) * B.half + B.lane_off);
+    }
     const int jw = j < 0 ? j + B.L : (j >= B.L ? j - B.L : j);
     const uint32_t row0 = (uint32_t)jw;
     const uint32_t row1 = jw == 0 ? (uint32_t)B.L - 1u : (uint32_t)jw - 1u;
@@ -423,8 +491,16 @@ __device__ __forceinline__ void step(Pipe<C> &S, const Band<C> &B, int j, const 
         apply_row<C>(S.p1[a_m1], S.n0[a_m2], S.n0[a_0], S.n0[a_m1], S.e0, P, w1, g1, 1u, B.K, B.key, B.t, B.r, true,
                      S.de_total);
         S.counted += 1u;
-        store_row<C>(B.D0 + B.off(j - 1) + B.lane_off, S.n0[a_m1]);
-        store_row<C>(B.D1 + B.off(j - 1) + B.lane_off, S.p1[a_m1]);
+        if constexpr (IO & kAbiOut) {
+            // row j-1 (parity (PH+1) & 1): even x in plane (y & 1), odd x in the other
+            if constexpr (((PH + 1) & 1) == 1)
+                store_joined_row<C>(B.D0 + B.off_out(j - 1) + 2 * B.lane_off, S.p1[a_m1], S.n0[a_m1]);
+            else
+                store_joined_row<C>(B.D0 + B.off_out(j - 1) + 2 * B.lane_off, S.n0[a_m1], S.p1[a_m1]);
+        } else {
+            store_row<C>(B.D0 + B.off_out(j - 1) + B.lane_off, S.n0[a_m1]);
+            store_row<C>(B.D1 + B.off_out(j - 1) + B.lane_off, S.p1[a_m1]);
+        }
     }
     if (j < B.Y0 + B.H) {
         // edges for step j+1: plane-1 old row j+1 and plane-0 new row j
@@ -434,13 +510,24 @@ __device__ __forceinline__ void step(Pipe<C> &S, const Band<C> &B, int j, const 
     }
 }
 
-template <int C>
+template <int C, int IO>
 __device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xch, int64_t *dE_part, bool first) {
     Pipe<C> S;
     const int Y0 = B.Y0;  // a multiple of 4: step Y0-1 has phase 3
     // rows Y0-2 and Y0-1 of plane 1 (all later rows come through the ring)
-    S.p1[2] = load_row<C>(B.S1 + B.off(Y0 - 2) + B.lane_off);
-    S.p1[3] = load_row<C>(B.S1 + B.off(Y0 - 1) + B.lane_off);
+    if constexpr (IO & kAbiIn) {
+        // caller's rows Y0-2 (even: plane 1 holds its odd x) and Y0-1 (odd:
+        // plane 1 holds its even x, plane 0 its odd x, needed at step Y0-1)
+        Row<C> ev, od;
+        split_row<C>(load_row<2 * C>(B.S0 + B.off(Y0 - 2) + 2 * B.lane_off), ev, od);
+        S.p1[2] = od;
+        split_row<C>(load_row<2 * C>(B.S0 + B.off(Y0 - 1) + 2 * B.lane_off), ev, od);
+        S.p1[3] = ev;
+        S.next0 = od;
+    } else {
+        S.p1[2] = load_row<C>(B.S1 + B.off(Y0 - 2) + B.lane_off);
+        S.p1[3] = load_row<C>(B.S1 + B.off(Y0 - 1) + B.lane_off);
+    }
 #pragma unroll
     for (int i = 0; i < 2 * C; ++i) S.n0[0].d[i] = S.n0[1].d[i] = S.n0[2].d[i] = S.n0[3].d[i] = 0u;
     S.de_total = 0;
@@ -452,14 +539,14 @@ __device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xc
         uint32_t dummy;
         exchange2<1>(S.p1[3].d[0], 0u, xch, 0, S.e1, dummy, B.ncw);  // (2)
     }
-    step<C, 3>(S, B, Y0 - 1, ring, xch);
+    step<C, 3, IO>(S, B, Y0 - 1, ring, xch);
     for (int j = Y0; j < Y0 + B.H; j += 4) {
-        step<C, 0>(S, B, j, ring, xch);
-        step<C, 1>(S, B, j + 1, ring, xch);
-        step<C, 2>(S, B, j + 2, ring, xch);
-        step<C, 3>(S, B, j + 3, ring, xch);
+        step<C, 0, IO>(S, B, j, ring, xch);
+        step<C, 1, IO>(S, B, j + 1, ring, xch);
+        step<C, 2, IO>(S, B, j + 2, ring, xch);
+        step<C, 3, IO>(S, B, j + 3, ring, xch);
     }
-    step<C, 0>(S, B, Y0 + B.H, ring, xch);
+    step<C, 0, IO>(S, B, Y0 + B.H, ring, xch);
     if (dE_part) {
         // sum over sites of (dE/4 + 2) minus 2 per counted site, into this
         // wave's own slot (no other wave touches it, so no atomics)
@@ -473,9 +560,10 @@ __device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xc
     }
 }
 
-template <int C, int NF>
+template <int C, int NF, int IO>
 __global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];  // [2 planes][kSlots][L/2] ring, then the edge words
+    // ring: [2 planes][kSlots][L/2] (split source) or [kSlots][L] (caller's rows), then the edge words
+    extern __shared__ __align__(16) uint8_t smem[];
     const int ncw = (int)(blockDim.x >> 6) - LoaderShape<NF>::NLW;  // compute waves; the last NLW waves load
     uint8_t *ring = smem;
     uint32_t *xch = (uint32_t *)(smem + (size_t)2 * kSlots * (a.L >> 1));
@@ -486,12 +574,13 @@ __global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
     B.half = a.L >> 1;
     B.H = band < a.nb1 ? a.H : a.H2;
     B.Y0 = band < a.nb1 ? band * a.H : a.nb1 * a.H + (band - a.nb1) * a.H2;
-    B.pitch = a.pitch;
+    B.pin = a.src_pitch;
+    B.pout = a.dst_pitch;
     B.ncw = ncw;
-    B.S0 = a.src + (int64_t)r * a.rep_bytes;
-    B.S1 = B.S0 + B.pitch * a.L;
-    B.D0 = a.dst + (int64_t)r * a.rep_bytes;
-    B.D1 = B.D0 + B.pitch * a.L;
+    B.S0 = a.src + (int64_t)r * a.src_rep;
+    B.S1 = B.S0 + B.pin * a.L;
+    B.D0 = a.dst + (int64_t)r * a.dst_rep;
+    B.D1 = B.D0 + B.pout * a.L;
     B.lane_off = (int64_t)threadIdx.x * 8 * C;
     B.gpr = (uint32_t)a.L >> 4;  // draw groups per row (8 sites each)
     B.lg0 = threadIdx.x * C;     // this lane's first group in a row
@@ -499,10 +588,10 @@ __global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
     B.t = a.t;
     B.key = a.key;
     if ((int)(threadIdx.x >> 6) >= ncw) {
-        loader_loop<C, NF>(B, ring, (int)(threadIdx.x >> 6) - ncw);
+        loader_loop<C, NF, IO>(B, ring, (int)(threadIdx.x >> 6) - ncw);
     } else {
         B.K = make_lut(a.thr[r], a.one2, a.four);
-        compute_loop<C>(B, ring, xch, a.dE_part, a.dE_first != 0);
+        compute_loop<C, IO>(B, ring, xch, a.dE_part, a.dE_first != 0);
     }
 }
 
@@ -686,16 +775,22 @@ hipError_t launch_lattice2d_de_collect(const int64_t *part, int64_t *dE, int L, 
     return hipGetLastError();
 }
 
-hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_rep, const ThrRow *thr,
-                                int64_t *dE_part, bool dE_first, Key key, uint32_t t, hipStream_t s) {
+hipError_t launch_ising2d_split(const void *src, bool src_rows, void *dst, bool dst_rows, int L, int n_rep,
+                                const ThrRow *thr, int64_t *dE_part, bool dE_first, Key key, uint32_t t,
+                                hipStream_t s) {
     BandShape g;
     if (!band_shape(L, n_rep, g)) return hipErrorInvalidValue;
+    if (src == dst) return hipErrorInvalidValue;  // bands read only the source: never in place
     const int C = g.C;
+    const int IO = (src_rows ? kAbiIn : 0) | (dst_rows ? kAbiOut : 0);
     Lattice2dArgs a;
-    a.src = src;
-    a.dst = dst;
-    a.pitch = lattice2d_pitch(L);
-    a.rep_bytes = 2 * (int64_t)L * a.pitch;
+    a.src = (const uint8_t *)src;
+    a.dst = (uint8_t *)dst;
+    const int64_t pitch = lattice2d_pitch(L);
+    a.src_pitch = src_rows ? (int64_t)L : pitch;
+    a.dst_pitch = dst_rows ? (int64_t)L : pitch;
+    a.src_rep = src_rows ? (int64_t)L * L : 2 * (int64_t)L * pitch;
+    a.dst_rep = dst_rows ? (int64_t)L * L : 2 * (int64_t)L * pitch;
     a.thr = thr;
     a.dE_part = dE_part;
     a.dE_first = dE_first ? 1 : 0;
@@ -713,20 +808,25 @@ hipError_t launch_ising2d_split(const uint8_t *src, uint8_t *dst, int L, int n_r
     const unsigned blocks = (unsigned)(a.bands * n_rep);
     const size_t lds = (size_t)2 * kSlots * (L / 2) + 2 * 16 * 2 * sizeof(uint32_t);
     const int NF = L >= 2048 ? L / 1024 : 2;  // direct-load instructions per feed (two planes of L/2 bytes)
-#define SMC_L2D(CC, NFF)                                                                                   \
-    if (C == CC && NF == NFF) {                                                                            \
-        (void)hipFuncSetAttribute((const void *)k_ising2d_split<CC, NFF>,                                  \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
-        const unsigned threads = compute_threads + 64u * LoaderShape<NFF>::NLW;                           \
-        SMC_LAUNCH((k_ising2d_split<CC, NFF>), dim3(blocks), dim3(threads), lds, s, a);            \
-        return hipGetLastError();                                                                          \
+#define SMC_L2D_IO(CC, NFF, IOO)                                                                            \
+    if (C == CC && NF == NFF && IO == IOO) {                                                                \
+        (void)hipFuncSetAttribute((const void *)k_ising2d_split<CC, NFF, IOO>,                              \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
+        const unsigned threads = compute_threads + 64u * LoaderShape<NFF>::NLW;                            \
+        SMC_LAUNCH((k_ising2d_split<CC, NFF, IOO>), dim3(blocks), dim3(threads), lds, s, a);                \
+        return hipGetLastError();                                                                           \
     }
+#define SMC_L2D(CC, NFF)     \
+    SMC_L2D_IO(CC, NFF, 0)   \
+    SMC_L2D_IO(CC, NFF, 1)   \
+    SMC_L2D_IO(CC, NFF, 2)
     SMC_L2D(1, 2)
     SMC_L2D(1, 4)
     SMC_L2D(1, 8)
     SMC_L2D(2, 8)
     SMC_L2D(2, 16)
 #undef SMC_L2D
+#undef SMC_L2D_IO
     return hipErrorInvalidValue;
 }
 

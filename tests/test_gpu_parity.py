@@ -245,7 +245,8 @@ def test_pt_ising_equal_betas_walk():
 
 
 # ------------------------------------------- one-pass split-layout 2D kernel --
-@pytest.mark.parametrize("L,n_rep,n,sweep0", [(1024, 2, 5, 0), (2048, 1, 4, 33), (1024, 3, 1, 7)])
+@pytest.mark.parametrize("L,n_rep,n,sweep0", [(1024, 2, 5, 0), (2048, 1, 4, 33), (1024, 3, 1, 7), (1024, 1, 2, 3),
+                                               (4096, 2, 3, 0), (2048, 3, 2, 11)])
 def test_split_kernel_bit_exact(L, n_rep, n, sweep0):
     """Uniform 2D Ising batches served by the one-pass kernel: odd and even
     sweep counts, nonzero first sweep index, per-replica beta, dE tracking."""
@@ -281,6 +282,25 @@ def test_split_kernel_launch_shape_invariance(monkeypatch):
         outs.append((_host(spins).copy(), int(_host(dE)[0])))
     for s, d in outs[1:]:
         assert np.array_equal(s, outs[0][0]) and d == outs[0][1]
+
+
+@pytest.mark.parametrize("L,n_rep", [(1024, 3), (2048, 1), (8192, 1)])
+def test_split_kernel_fused_layout_equals_separate_conversions(monkeypatch, L, n_rep):
+    """The first sweep reading the caller's rows and the last writing them
+    back give the same spins and energy changes as converting to the split
+    layout before the sweeps and back after them, for 1 to 4 sweeps."""
+    seed = W.seed_for(24)
+    b = S.Batch(S.ISING, 2, L, n_rep, seed)
+    betas = [0.30, W.BETA_C_2D, 0.55][:n_rep]
+    for n in (1, 2, 3, 4):
+        outs = []
+        for fuse in ("1", "0"):
+            monkeypatch.setenv("SPINMC_L2D_FUSE", fuse)
+            spins, _ = gpu_init(b)
+            dE = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
+            S.metropolis_sweep(b, spins, betas, 5, n, dE_accum=dE)
+            outs.append((_host(spins).copy(), _host(dE).copy()))
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1]), n
 
 
 # ------------------------------------------------- LDS-resident small lattices --
