@@ -76,6 +76,9 @@ def lib():
             "orc_dcb_run": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
             "orc_dcb_run3": (I64, [I, I, I, vp, i8p, D, U64, U32, U32, I, I]),
             "orc_heis_dcb_run": (I64, [I, I, I, f64p, D, U64, U32, U32, I, I, I, D]),
+            "orc_rng_state_words": (I64, [I, I, I]),
+            "orc_rng_init": (None, [I, I, I, U64, U32, u64p]),
+            "orc_dcb_run_rng": (I64, [I, I, I, vp, i8p, D, I, u64p, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -232,6 +235,24 @@ def dcb_run(L, T, k, J, s, beta, seed, r, t0, n, palindromic=False, dim=2) -> in
     3D lattice in place; returns the summed Delta E (orc_dcb_run, orc_dcb_run3)."""
     f = lib().orc_dcb_run if dim == 2 else lib().orc_dcb_run3
     return int(f(L, T, k, _ptr(J), s, beta, seed & 0xFFFFFFFFFFFFFFFF, r, t0, n, 1 if palindromic else 0))
+
+
+# Generators of the random-number study (Table 1): codes of orc_dcb_run_rng.
+GEN_LCG32, GEN_LCG32_RANDOM, GEN_LCG64, GEN_LCG64_RANDOM, GEN_FIB521, GEN_FIB1279 = 1, 2, 3, 4, 5, 6
+
+
+def rng_init(gen, L, T, seed, rep) -> np.ndarray:
+    """Initial state (uint64 words) of a study generator for one replica."""
+    n = int(lib().orc_rng_state_words(gen, L, T))
+    st = np.zeros(max(n, 1), np.uint64)
+    lib().orc_rng_init(gen, L, T, seed & 0xFFFFFFFFFFFFFFFF, rep, st)
+    return st
+
+
+def dcb_run_rng(L, T, k, J, s, beta, gen, state, n) -> int:
+    """n double-checkerboard sweeps (T x T tiles, k hits) drawing from a study
+    generator whose state advances in place (orc_dcb_run_rng)."""
+    return int(lib().orc_dcb_run_rng(L, T, k, _ptr(J), s, beta, gen, state, n))
 
 
 def heis_dcb_run(L, T, k, s, beta, seed, r, t0, n, palindromic=False, renorm_every=16, cap=0.0) -> int:

@@ -352,6 +352,174 @@ EXPORT int64_t orc_dcb_run(int L, int T, int k, const int8_t *J, int8_t *s, doub
     return dE_sum;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The generators of the paper's random-number study (Sec. 3.3, Table 1),    */
+/* driving the double checkerboard of orc_dcb_run (tile colour 0 then 1, k   */
+/* hits, colour 0 then colour 1 sites, no palindrome):                       */
+/*   LCG32: x' = (1664525 x + 1013904223) mod 2^32 (Eq. 3, m = 2^32);        */
+/*   LCG64: x' = (2862933555777941757 x + 1442695040888963407) mod 2^64,     */
+/*          the uniform being its top 32 bits;                               */
+/*   lagged Fibonacci: x_n = x_{n-r} + x_{n-s} mod 2^32 (Eq. 6 with unit     */
+/*          multipliers, i.e. Eq. 7 on 32-bit fixed point), (r, s) =         */
+/*          (521, 353) or (1279, 861).                                       */
+/* Streams.  With tiles of edge T (B = L / T per direction), the tiles of one */
+/* tile colour are numbered q = by (B/2) + bx/2 and the colour-c sites of a  */
+/* tile p = v (T/2) + u/2 (site (u, v) of the tile), so that (q, p) runs     */
+/* over L^2/4 positions, the threads of the paper's GPU code.  An LCG stream */
+/* j = q T^2/2 + p serves position (q, p) of both tile colours and both site */
+/* colours, one number per attempt, in the order of the sweep: per sweep     */
+/* tile colour 0 (k hits, each colour 0 then 1), then tile colour 1.  With   */
+/* skip-ahead (Eqs. 4, 5) stream j delivers x_j, x_{j+M}, x_{j+2M}, ... of   */
+/* one global sequence (M = L^2/4 streams); the "random" variants instead   */
+/* start each stream at an independent seed and step it by Eq. 3 itself.     */
+/* A lagged-Fibonacci generator serves tile q (both tile colours): each      */
+/* round of a tile (one colour of one hit) consumes T^2/2 consecutive        */
+/* numbers, position p taking the p-th.  Every attempt consumes its number,  */
+/* also when Delta E <= 0 accepts without it.                                */
+/* Seeds come from Philox draws with counter word 3 = 16: the start x_0 of   */
+/* the global sequence of replica r from (0, 0, r, 16) (word 0, LCG64: words */
+/* 0 and 1 as low and high half), stream j's seed from (j, 1, r, 16), word   */
+/* i of Fibonacci generator q's initial ring from word 0 of                  */
+/* (q r_lag + i, 2, r, 16).                                                  */
+/* ------------------------------------------------------------------------ */
+enum { GEN_LCG32 = 1, GEN_LCG32_RANDOM = 2, GEN_LCG64 = 3, GEN_LCG64_RANDOM = 4, GEN_FIB521 = 5, GEN_FIB1279 = 6 };
+static const uint32_t LCG32_A = 1664525u, LCG32_C = 1013904223u;
+static const uint64_t LCG64_A = 2862933555777941757ull, LCG64_C = 1442695040888963407ull;
+enum { TAG_GEN = 8 };
+
+static int fib_lags(int gen, int *r, int *s)
+{
+    if (gen == GEN_FIB521) { *r = 521; *s = 353; return 1; }
+    if (gen == GEN_FIB1279) { *r = 1279; *s = 861; return 1; }
+    return 0;
+}
+
+/* uint64 words of the state of one replica: the M stream values (LCG), or
+ * per tile q its r ring words followed by the count n mod r (Fibonacci);
+ * 0 for an unknown generator. */
+EXPORT int64_t orc_rng_state_words(int gen, int L, int T)
+{
+    int64_t M = (int64_t)L * L / 4, Q = (int64_t)(L / T) * (L / T) / 2;
+    int r, sl;
+    if (gen >= GEN_LCG32 && gen <= GEN_LCG64_RANDOM) return M;
+    if (fib_lags(gen, &r, &sl)) return Q * (r + 1);
+    return 0;
+}
+
+EXPORT void orc_rng_init(int gen, int L, int T, uint64_t seed, uint32_t rep, uint64_t *state)
+{
+    int64_t M = (int64_t)L * L / 4, Q = (int64_t)(L / T) * (L / T) / 2;
+    uint32_t w[4];
+    int r, sl;
+    if (gen == GEN_LCG32 || gen == GEN_LCG64) {
+        /* x_0 .. x_{M-1} of the global sequence, by plain iteration */
+        draw(seed, 0, 0, rep, TAG_GEN * 2, w);
+        uint64_t x = gen == GEN_LCG32 ? (uint64_t)w[0] : ((uint64_t)w[1] << 32 | w[0]);
+        for (int64_t j = 0; j < M; ++j) {
+            state[j] = x;
+            x = gen == GEN_LCG32 ? (uint64_t)(uint32_t)(LCG32_A * (uint32_t)x + LCG32_C) : LCG64_A * x + LCG64_C;
+        }
+    } else if (gen == GEN_LCG32_RANDOM || gen == GEN_LCG64_RANDOM) {
+        for (int64_t j = 0; j < M; ++j) {
+            draw(seed, (uint32_t)j, 1, rep, TAG_GEN * 2, w);
+            state[j] = gen == GEN_LCG32_RANDOM ? (uint64_t)w[0] : ((uint64_t)w[1] << 32 | w[0]);
+        }
+    } else if (fib_lags(gen, &r, &sl)) {
+        for (int64_t q = 0; q < Q; ++q) {
+            for (int i = 0; i < r; ++i) {
+                draw(seed, (uint32_t)(q * r + i), 2, rep, TAG_GEN * 2, w);
+                state[q * (r + 1) + i] = w[0];
+            }
+            state[q * (r + 1) + r] = 0;  /* x_n is written to ring word n mod r */
+        }
+    }
+}
+
+/* The step that moves a skip-ahead stream on by M numbers of the global
+ * sequence, x -> A x + C, composed from M plain steps (Eqs. 4, 5). */
+static void lcg_power(int gen, int64_t M, uint64_t *A, uint64_t *C)
+{
+    uint64_t a = 1, c = 0;
+    for (int64_t i = 0; i < M; ++i) {
+        if (gen == GEN_LCG32) {
+            a = (uint32_t)(LCG32_A * (uint32_t)a);
+            c = (uint32_t)(LCG32_A * (uint32_t)c + LCG32_C);
+        } else {
+            a = LCG64_A * a;
+            c = LCG64_A * c + LCG64_C;
+        }
+    }
+    *A = a;
+    *C = c;
+}
+
+/* n double-checkerboard sweeps of a 2D Ising / EA lattice with the
+ * uniforms taken from the study's generators (layout above); the state
+ * advances.  Tiles T x T with B = L / T even; the Fibonacci generators need
+ * T^2/2 <= min(s, r - s) (a round then reads no number of its own round).
+ * Returns the summed Delta E of accepted flips. */
+EXPORT int64_t orc_dcb_run_rng(int L, int T, int k, const int8_t *J, int8_t *s, double beta, int gen,
+                               uint64_t *state, int n)
+{
+    uint64_t thr[4];
+    orc_thresholds(beta, 2, thr);
+    const int B = L / T, P = T * T / 2;
+    const int64_t M = (int64_t)L * L / 4;
+    uint64_t A = 1, C = 0;
+    int r = 0, sl = 0;
+    const int fib = fib_lags(gen, &r, &sl);
+    if (gen == GEN_LCG32 || gen == GEN_LCG64) lcg_power(gen, M, &A, &C);
+    if (gen == GEN_LCG32_RANDOM) { A = LCG32_A; C = LCG32_C; }
+    if (gen == GEN_LCG64_RANDOM) { A = LCG64_A; C = LCG64_C; }
+    int64_t dE_sum = 0;
+    for (int m = 0; m < n; ++m) {
+        for (int tile_colour = 0; tile_colour < 2; ++tile_colour) {
+            for (int by = 0; by < B; ++by) {
+                for (int bx = 0; bx < B; ++bx) {
+                    if (((bx + by) & 1) != tile_colour) continue;
+                    const int64_t q = (int64_t)by * (B / 2) + bx / 2;
+                    for (int j = 0; j < k; ++j) {
+                        for (int c = 0; c < 2; ++c) {
+                            for (int v = 0; v < T; ++v) {
+                                for (int u = 0; u < T; ++u) {
+                                    const int x = bx * T + u, y = by * T + v;
+                                    if (((x + y) & 1) != c) continue;
+                                    const int64_t p = (int64_t)v * (T / 2) + u / 2;
+                                    uint32_t uu;
+                                    if (fib) {
+                                        uint64_t *ring = state + q * (r + 1);
+                                        const uint64_t nn = ring[r];
+                                        const uint64_t back = (nn + (uint64_t)r - (uint64_t)sl) % (uint64_t)r;
+                                        uu = (uint32_t)(ring[nn] + ring[back]);
+                                        ring[nn] = uu;
+                                        ring[r] = (nn + 1) % (uint64_t)r;
+                                    } else {
+                                        uint64_t *xs = &state[q * P + p];
+                                        uu = (gen == GEN_LCG32 || gen == GEN_LCG32_RANDOM) ? (uint32_t)*xs
+                                                                                            : (uint32_t)(*xs >> 32);
+                                        *xs = (gen == GEN_LCG32 || gen == GEN_LCG32_RANDOM)
+                                                  ? (uint64_t)(uint32_t)((uint32_t)A * (uint32_t)*xs + (uint32_t)C)
+                                                  : A * *xs + C;
+                                    }
+                                    const int64_t i = (int64_t)y * L + x;
+                                    const int h = local_field(2, L, J, s, i);
+                                    const int dE = 2 * s[i] * h;
+                                    const int accept = dE <= 0 || (uint64_t)uu < thr[dE / 4];
+                                    if (accept) {
+                                        s[i] = (int8_t)(-s[i]);
+                                        dE_sum += dE;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return dE_sum;
+}
+
 /* The same in three dimensions (the paper carries the tiled update over to
  * 3D): T x T x T tiles, tile colour (bx + by + bz) & 1, tile colour 0 first,
  * colour-0 sites (x + y + z even) of a tile before its colour-1 sites, the
