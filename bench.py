@@ -828,6 +828,58 @@ def table1(S, W, updates=10_000_000, n_rep=64, L=1024, beta=0.4, therm=2000, eve
             "exact": TABLE1_EXACT, "rows": rows}
 
 
+RNG_STUDY = (("LCG32", 1), ("LCG32, random", 2), ("LCG64", 3), ("LCG64, random", 4), ("Fibonacci, r=521", 5),
+             ("Fibonacci, r=1279", 6))
+
+
+def table1_generators(S, W, updates=10_000_000, n_rep=64, L=1024, beta=0.4, therm=2000, tile=16, k=1,
+                      chunk=256):
+    """Table 1's generator rows on the GPU: the 1024^2 Ising model at beta =
+    0.4 with the double checkerboard (16 x 16 tiles, one hit) drawing from the
+    paper's generators (LCG32 / LCG64 with skip-ahead over one global
+    sequence or independently seeded per stream, lagged Fibonacci with
+    r = 521 and 1279), `updates` attempts per spin in total over n_rep
+    replicas, the energy recorded after every sweep; Delta_rel against the
+    printed exact values."""
+    import torch
+
+    N = L * L
+    per_rep = updates // n_rep
+    rows = []
+    for name, gen in RNG_STUDY:
+        b = S.Batch(S.ISING, 2, L, n_rep, W.seed_for(98))
+        spins = torch.empty(n_rep * N, dtype=torch.int8, device="cuda")
+        S.spin_init(b, spins)
+        state = torch.zeros(S.rng_study_state_bytes(b, tile, gen), dtype=torch.uint8, device="cuda")
+        S.rng_study_init(b, tile, gen, state)
+        S.rng_study_sweep(b, spins, [beta] * n_rep, therm, tile, k, gen, state)
+        E0 = torch.empty(n_rep, dtype=torch.float64, device="cuda")
+        S.measure_energy_magnetisation(b, spins, E0)
+        trace = torch.empty(per_rep, n_rep, dtype=torch.int64, device="cuda")
+        dE = torch.zeros(n_rep, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(per_rep):
+            S.rng_study_sweep(b, spins, [beta] * n_rep, 1, tile, k, gen, state, dE_accum=dE)
+            trace[i].copy_(dE)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        E = (E0.cpu().numpy()[None, :] + trace.cpu().numpy()).T
+        e, de, c, dc = _e_and_c(E, N, beta)
+        rows.append({"method": f"double checkerboard {tile}x{tile}, k = {k}, {name}",
+                     "measurements_per_replica": int(E.shape[1]),
+                     "e": round(e, 9), "e_err": float(f"{de:.2g}"),
+                     "e_delta_rel": round((e - TABLE1_EXACT["e"]) / de, 2),
+                     "C": round(c, 7), "C_err": float(f"{dc:.2g}"),
+                     "C_delta_rel": round((c - TABLE1_EXACT["C"]) / dc, 2), "seconds": round(secs, 2),
+                     "ps_per_flip": round(secs * 1e12 / (per_rep * n_rep * N), 3)})
+        print(f"[bench] table1 {name}: e = {e:.7f} ({rows[-1]['e_delta_rel']} sd), C = {c:.5f} "
+              f"({rows[-1]['C_delta_rel']} sd)", file=sys.stderr, flush=True)
+        del spins, trace, state
+        torch.cuda.empty_cache()
+    return rows
+
+
 def tau_int(series, c=6.0):
     """Integrated autocorrelation time of equilibrium series (rows =
     independent replicas, columns = measurement times), in units of the
@@ -1139,6 +1191,8 @@ def main():
                     help="only the 2D Ising tempering benchmark of 20 replicas (L = 64 .. 2048)")
     ap.add_argument("--table1-only", action="store_true",
                     help="only Table 1 with the Philox streams (1024^2, beta = 0.4, 1e7 attempts per spin)")
+    ap.add_argument("--table1-updates", type=float, default=1e7,
+                    help="attempts per spin in total for each Table 1 row (the paper: 1e7)")
     ap.add_argument("--tau-only", action="store_true",
                     help="only the double-checkerboard autocorrelation study (128^2, 16x16 tiles)")
     ap.add_argument("--tau-updates", type=int, default=1 << 15, help="attempts per site per (beta, k) series")
@@ -1210,7 +1264,9 @@ def main():
         print(json.dumps({"ising2d_paper": tempering_ising2d(S, W, sizes=sizes, flips=args.paper_pt_flips)}))
         return
     if args.table1_only:
-        print(json.dumps({"table1": table1(S, W)}))
+        t1 = table1(S, W, updates=int(args.table1_updates))
+        t1["rows"] += table1_generators(S, W, updates=int(args.table1_updates))
+        print(json.dumps({"table1": t1}))
         return
     if args.tau_only:
         print(json.dumps({"tau_dcb": tau_dcb(S, W, n_rep=args.tau_replicas, updates=args.tau_updates)}))

@@ -106,6 +106,19 @@ typedef enum {
     SMC_HEIS_DOUBLE = 2  /* float64 spins and arithmetic                          */
 } smc_heis_precision;
 
+/* Generators of the random-number study (Sec. 3.3, Table 1). */
+typedef enum {
+    SMC_RNG_LCG32 = 1,         /* x' = 1664525 x + 1013904223 mod 2^32, one global
+                                  sequence shared by all streams with skip-ahead */
+    SMC_RNG_LCG32_RANDOM = 2,  /* the same map, every stream seeded independently */
+    SMC_RNG_LCG64 = 3,         /* x' = 2862933555777941757 x + 1442695040888963407
+                                  mod 2^64 (top 32 bits used), skip-ahead          */
+    SMC_RNG_LCG64_RANDOM = 4,  /* the same map, independent stream seeds          */
+    SMC_RNG_FIB521 = 5,        /* lagged Fibonacci x_n = x_{n-521} + x_{n-353}
+                                  mod 2^32, one generator per tile                 */
+    SMC_RNG_FIB1279 = 6        /* lagged Fibonacci with lags 1279 and 861          */
+} smc_rng_generator;
+
 /* One replica of an uneven batch. */
 typedef struct smc_inst {
     int32_t L;        /* even edge length >= 4                                  */
@@ -409,6 +422,48 @@ int smc_dcb_plan(const smc_desc *desc, const double *beta, int32_t tile, const c
  */
 int smc_philox_bench(uint64_t seed, uint32_t t, uint32_t r, uint32_t tag, int32_t n_threads, int32_t per_thread,
                      uint32_t *out, void *stream);
+
+/*
+ * The random-number study of Sec. 3.3 (Table 1): double-checkerboard sweeps
+ * (tile colour 0 then 1, `hits` hits per tile, each colour 0 then colour 1;
+ * no palindrome) of a uniform 2D Ising or EA batch whose uniforms come from
+ * one of the paper's generators instead of the Philox streams.  Not the
+ * method's sampler (its results depend on the generator, which is the point
+ * of the study): the sampler is smc_dcb_sweep.
+ *  Streams.  Tiles of edge T = tile (B = L / T per direction, B even); the
+ *  tiles of one tile colour are numbered q = by (B/2) + bx/2 and the sites
+ *  of one colour inside a tile p = v (T/2) + u/2 (site (u, v) of the tile),
+ *  the L^2/4 positions (q, p) being the threads of the paper's code.  An LCG
+ *  stream j = q T^2/2 + p serves position (q, p) of both tile colours and
+ *  both site colours, one number per attempt in sweep order; with
+ *  skip-ahead (Eqs. 4-5) stream j delivers x_j, x_{j+M}, x_{j+2M}, ... of
+ *  one global sequence (M = L^2/4), otherwise it steps its own seed by the
+ *  map.  A lagged Fibonacci generator serves tile q; each round (one colour
+ *  of one hit of the tile) takes T^2/2 consecutive numbers, position p the
+ *  p-th.  Every attempt consumes a number (also when Delta E <= 0).  The
+ *  acceptance is u < floor(2^32 exp(-beta Delta E)) with u the 32-bit number
+ *  (LCG64: the top 32 bits).
+ *  Seeds (smc_rng_study_init) are Philox4x32-10 draws under desc.seed with
+ *  counter word 3 = 16: x_0 of replica r's global sequence from (0, 0, r,
+ *  16), stream j's seed from (j, 1, r, 16), word i of tile q's Fibonacci
+ *  ring from (q * r_lag + i, 2, r, 16) (word 0; 64-bit values: word 1 above
+ *  word 0).
+ *  desc:    uniform 2D batch, SMC_ISING or SMC_EA (EA couplings as usual).
+ *  tile:    16 or 32 with L / tile even (Fibonacci generators: 16, so that a
+ *           round of T^2/2 numbers reads none of its own).
+ *  state:   DEVICE, owned by the caller, smc_rng_study_state_bytes bytes
+ *           (8-byte aligned); replica-major; written by smc_rng_study_init,
+ *           advanced by every sweep (a run split over calls equals one call).
+ *  beta:    HOST [n_rep]; hits >= 1; dE_accum: DEVICE int64 [n_rep] or NULL
+ *           (+= the energy change).
+ * SMC_EINVAL for other tiles, generators, models or a too small state.
+ */
+int smc_rng_study_state_bytes(const smc_desc *desc, int32_t tile, int32_t generator, int64_t *bytes);
+int smc_rng_study_init(const smc_desc *desc, int32_t tile, int32_t generator, void *state, int64_t state_bytes,
+                       void *stream);
+int smc_rng_study_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta,
+                        int32_t n_sweeps, int32_t tile, int32_t hits, int32_t generator, void *state,
+                        int64_t state_bytes, int64_t *dE_accum, void *stream);
 
 /* Static description of a status code. */
 const char *smc_strerror(int status);

@@ -84,6 +84,13 @@ def lib():
         L.smc_autotune.restype = C.c_int
         L.smc_dcb_plan.argtypes = [P(Desc), P(C.c_double), C.c_int32, P(C.c_char_p)]
         L.smc_dcb_plan.restype = C.c_int
+        L.smc_rng_study_state_bytes.argtypes = [P(Desc), C.c_int32, C.c_int32, P(C.c_int64)]
+        L.smc_rng_study_state_bytes.restype = C.c_int
+        L.smc_rng_study_init.argtypes = [P(Desc), C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]
+        L.smc_rng_study_init.restype = C.c_int
+        L.smc_rng_study_sweep.argtypes = [P(Desc), C.c_void_p, C.c_void_p, P(C.c_double), C.c_int32, C.c_int32,
+                                          C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.smc_rng_study_sweep.restype = C.c_int
         L.smc_philox_bench.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32,
                                        C.c_void_p, C.c_void_p]
         L.smc_philox_bench.restype = C.c_int
@@ -283,6 +290,36 @@ def measure_energy_magnetisation_noalloc(batch: Batch, spins, energy, magnetisat
     _check(lib().smc_measure_energy_magnetisation_noalloc(C.byref(d), _ptr(spins), _ptr(couplings), _ptr(energy),
                                                           _ptr(magnetisation), _stream(stream)),
            "smc_measure_energy_magnetisation_noalloc")
+
+
+# Generators of the random-number study (smc_rng_generator).
+RNG_LCG32, RNG_LCG32_RANDOM, RNG_LCG64, RNG_LCG64_RANDOM, RNG_FIB521, RNG_FIB1279 = 1, 2, 3, 4, 5, 6
+
+
+def rng_study_state_bytes(batch: Batch, tile: int, generator: int) -> int:
+    """Bytes of generator state the study needs for this batch (smc_rng_study_state_bytes)."""
+    d = batch.desc(batch.spins_shape()[0], batch.coup_len())
+    n = C.c_int64(0)
+    _check(lib().smc_rng_study_state_bytes(C.byref(d), tile, generator, C.byref(n)), "smc_rng_study_state_bytes")
+    return int(n.value)
+
+
+def rng_study_init(batch: Batch, tile: int, generator: int, state, stream=None):
+    """Seed a study generator's state (a device tensor of rng_study_state_bytes bytes)."""
+    d = batch.desc(batch.spins_shape()[0], batch.coup_len())
+    _check(lib().smc_rng_study_init(C.byref(d), tile, generator, _ptr(state), state.numel() * state.element_size(),
+                                    _stream(stream)), "smc_rng_study_init")
+
+
+def rng_study_sweep(batch: Batch, spins, beta, n_sweeps: int, tile: int, hits: int, generator: int, state,
+                    couplings=None, dE_accum=None, stream=None):
+    """n_sweeps double-checkerboard sweeps drawing from a study generator (smc_rng_study_sweep)."""
+    d = _desc(batch, spins, couplings)
+    b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (batch.n_rep,)))
+    _check(lib().smc_rng_study_sweep(C.byref(d), _ptr(spins), _ptr(couplings), b.ctypes.data_as(C.POINTER(C.c_double)),
+                                     n_sweeps, tile, hits, generator, _ptr(state),
+                                     state.numel() * state.element_size(), _ptr(dE_accum), _stream(stream)),
+           "smc_rng_study_sweep")
 
 
 def sweep_plan(batch: Batch):

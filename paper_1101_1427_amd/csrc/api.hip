@@ -1513,6 +1513,88 @@ int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, ui
     return SMC_OK;
 }
 
+// Checks shared by the random-number study calls; per-replica state bytes.
+static int rng_study_check(const smc_desc *desc, int32_t tile, int32_t generator, int64_t *per_rep) {
+    if (!desc) return fail(SMC_EINVAL, "desc is NULL");
+    if (desc->dim != 2 || desc->L <= 0 || (desc->model != SMC_ISING && desc->model != SMC_EA))
+        return fail(SMC_EINVAL, "the random-number study takes uniform 2D Ising or EA batches");
+    if (generator < SMC_RNG_LCG32 || generator > SMC_RNG_FIB1279)
+        return fail(SMC_EINVAL, "unknown generator %d", generator);
+    if (tile != 16 && tile != 32) return fail(SMC_EINVAL, "tile must be 16 or 32 (got %d)", tile);
+    int r = 0, s = 0;
+    if (rng_study_lags(generator, &r, &s) && tile != 16)
+        return fail(SMC_EINVAL, "the lagged Fibonacci generators take tile 16 (a round of T^2/2 numbers must "
+                                "not exceed min(s, r - s))");
+    if (desc->L % tile || (desc->L / tile) % 2)
+        return fail(SMC_EINVAL, "L / tile must be an even integer (L=%d, tile=%d)", desc->L, tile);
+    *per_rep = rng_study_state_bytes(generator, desc->L, tile);
+    return SMC_OK;
+}
+
+int smc_rng_study_state_bytes(const smc_desc *desc, int32_t tile, int32_t generator, int64_t *bytes) {
+    g_last_error.clear();
+    int64_t per = 0;
+    int rc = rng_study_check(desc, tile, generator, &per);
+    if (rc) return rc;
+    if (!bytes) return fail(SMC_EINVAL, "bytes is NULL");
+    if (desc->n_rep < 1) return fail(SMC_EINVAL, "n_rep must be >= 1");
+    *bytes = per * desc->n_rep;
+    return SMC_OK;
+}
+
+int smc_rng_study_init(const smc_desc *desc, int32_t tile, int32_t generator, void *state, int64_t state_bytes,
+                       void *stream) {
+    g_last_error.clear();
+    int64_t per = 0;
+    int rc = rng_study_check(desc, tile, generator, &per);
+    if (rc) return rc;
+    if (desc->n_rep < 1) return fail(SMC_EINVAL, "n_rep must be >= 1");
+    if (!state || ((uintptr_t)state & 7u)) return fail(SMC_EINVAL, "state must be a non-NULL 8-byte aligned pointer");
+    if (state_bytes < per * desc->n_rep)
+        return fail(SMC_EINVAL, "state holds %lld bytes, needs %lld", (long long)state_bytes,
+                    (long long)(per * desc->n_rep));
+    hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
+    SMC_HIP(launch_rng_init(generator, desc->L, tile, desc->n_rep, state, make_key(desc->seed), s));
+    return SMC_OK;
+}
+
+int smc_rng_study_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta,
+                        int32_t n_sweeps, int32_t tile, int32_t hits, int32_t generator, void *state,
+                        int64_t state_bytes, int64_t *dE_accum, void *stream) {
+    g_last_error.clear();
+    int64_t per = 0;
+    int rc = rng_study_check(desc, tile, generator, &per);
+    if (rc) return rc;
+    Plan plan;
+    if ((rc = validate(desc, desc->model == SMC_EA, plan))) return rc;
+    if (!spins) return fail(SMC_EINVAL, "spins is NULL");
+    if (desc->model == SMC_EA && !couplings) return fail(SMC_EINVAL, "couplings are required for EA");
+    if (!beta) return fail(SMC_EINVAL, "beta is NULL");
+    for (int r = 0; r < desc->n_rep; ++r)
+        if (!(beta[r] >= 0.0) || !isfinite(beta[r])) return fail(SMC_EINVAL, "beta[%d] must be finite and >= 0", r);
+    if (hits < 1) return fail(SMC_EINVAL, "hits must be >= 1");
+    if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+    if (!state || ((uintptr_t)state & 7u)) return fail(SMC_EINVAL, "state must be a non-NULL 8-byte aligned pointer");
+    if (state_bytes < per * desc->n_rep)
+        return fail(SMC_EINVAL, "state holds %lld bytes, needs %lld", (long long)state_bytes,
+                    (long long)(per * desc->n_rep));
+    if (n_sweeps == 0) return SMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (int rc_cap = refuse_capture(s)) return rc_cap;
+    StreamCtx &c = ctx_for(s);
+    std::vector<ThrRow> rows((size_t)desc->n_rep);
+    for (int r = 0; r < desc->n_rep; ++r) rows[r] = threshold_row(beta[r], 2);
+    void *p = nullptr;
+    if ((rc = upload(c, s, kTables, rows.data(), sizeof(ThrRow) * rows.size(), &p))) return rc;
+    const int rps = desc->model == SMC_EA ? desc->rep_per_sample : 1;
+    for (int32_t t = 0; t < n_sweeps; ++t)
+        for (int tc = 0; tc < 2; ++tc)
+            SMC_HIP(launch_dcb_rng(generator, (int8_t *)spins, desc->model == SMC_EA ? couplings : nullptr, rps,
+                                   (const ThrRow *)p, state, dE_accum, desc->n_rep, desc->L, tile, hits, tc, s));
+    return SMC_OK;
+}
+
 int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t word_bits, int32_t *launches,
                  const char **kernel_name) {
     g_last_error.clear();

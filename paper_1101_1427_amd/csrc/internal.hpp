@@ -228,4 +228,11 @@ hipError_t launch_pt_prepare(const SwapArgs &a, const double *energy_in, hipStre
 hipError_t launch_pt_swap(const SwapArgs &a, hipStream_t s);
 hipError_t launch_pt_finish(const SwapArgs &a, double *energy_out, hipStream_t s);
 
+// ---- random-number study (rngstudy.hip) ----
+bool rng_study_lags(int gen, int *r, int *s);
+int64_t rng_study_state_bytes(int gen, int L, int T);  // per replica; 0 for an unknown generator
+hipError_t launch_rng_init(int gen, int L, int T, int n_rep, void *state, Key key, hipStream_t s);
+hipError_t launch_dcb_rng(int gen, int8_t *spins, const int8_t *coup, int rep_per_sample, const ThrRow *thr,
+                          void *state, int64_t *dE, int n_rep, int L, int T, int k, int tile_colour, hipStream_t s);
+
 }  // namespace smc

@@ -1,0 +1,95 @@
+"""GPU parity of the random-number study (Sec. 3.3, Table 1): the double
+checkerboard driven by the paper's LCGs and lagged Fibonacci generators,
+bit-exact against the oracle (spins, energy changes and generator state),
+over calls split in two (the state carries the streams across calls)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1101_1427_amd as S
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+GENS = [S.RNG_LCG32, S.RNG_LCG32_RANDOM, S.RNG_LCG64, S.RNG_LCG64_RANDOM, S.RNG_FIB521, S.RNG_FIB1279]
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _gpu_state_words(gen, st):
+    """The GPU state of one replica as the oracle's uint64 words."""
+    if gen in (S.RNG_LCG64, S.RNG_LCG64_RANDOM):
+        return st.view(np.uint64).astype(np.uint64)
+    return st.view(np.uint32).astype(np.uint64)
+
+
+@pytest.mark.parametrize("gen", GENS)
+@pytest.mark.parametrize("model,L,tile,k", [(S.ISING, 64, 16, 1), (S.EA, 64, 16, 3), (S.ISING, 128, 32, 2)])
+def test_study_sweep_bit_exact(gen, model, L, tile, k):
+    if gen in (S.RNG_FIB521, S.RNG_FIB1279) and tile != 16:
+        pytest.skip("lagged Fibonacci generators take tile 16")
+    seed, n_rep, rps = W.seed_for(91), 3, 1
+    betas = [0.35, 0.42, 0.5]
+    b = S.Batch(model, 2, L, n_rep, seed, rep_per_sample=rps)
+    spins = torch.zeros(n_rep * L * L, dtype=torch.int8, device=DEV)
+    coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV) if model == S.EA else None
+    S.spin_init(b, spins, coup)
+    nbytes = S.rng_study_state_bytes(b, tile, gen)
+    state = torch.zeros(nbytes, dtype=torch.uint8, device=DEV)
+    S.rng_study_init(b, tile, gen, state)
+    dE = torch.zeros(n_rep, dtype=torch.int64, device=DEV)
+    init_state = _host(state).copy()
+    S.rng_study_sweep(b, spins, betas, 2, tile, k, gen, state, couplings=coup, dE_accum=dE)
+    S.rng_study_sweep(b, spins, betas, 3, tile, k, gen, state, couplings=coup, dE_accum=dE)
+    got_s, got_dE, got_st = _host(spins).reshape(n_rep, -1), _host(dE), _host(state).reshape(n_rep, -1)
+    init_state = init_state.reshape(n_rep, -1)
+    for r in range(n_rep):
+        J = O.init_couplings(2, L, seed, r // rps) if model == S.EA else None
+        s = O.init_spins(2, L, seed, r)
+        st = O.rng_init(gen, L, tile, seed, r)
+        assert np.array_equal(_gpu_state_words(gen, init_state[r]), st), f"initial state of replica {r}"
+        d = O.dcb_run_rng(L, tile, k, J, s, betas[r], gen, st, 5)
+        assert np.array_equal(got_s[r], s), f"spins of replica {r}"
+        assert got_dE[r] == d
+        assert np.array_equal(_gpu_state_words(gen, got_st[r]), st), f"state of replica {r}"
+
+
+def test_skip_ahead_lcg32_is_visibly_biased():
+    """The paper's negative control at its own size: 1024^2 Ising at beta =
+    0.4, tiles 16, one hit: after 300 sweeps the energy over 2000 more from
+    the skip-ahead LCG32 streams is far from the exact e = 1.106079207
+    (Table 1), while the independently seeded LCG32 streams and the lagged
+    Fibonacci generator agree with it."""
+    from tests.conftest import read_golden
+
+    (_, _, e_exact, _), = read_golden("table1_exact.txt")
+    e_exact = float(e_exact)
+    L, tile, beta, n_rep = 1024, 16, 0.4, 4
+    out = {}
+    for gen in (S.RNG_LCG32, S.RNG_LCG32_RANDOM, S.RNG_FIB521):
+        b = S.Batch(S.ISING, 2, L, n_rep, W.seed_for(92))
+        spins = torch.zeros(n_rep * L * L, dtype=torch.int8, device=DEV)
+        S.spin_init(b, spins)
+        state = torch.zeros(S.rng_study_state_bytes(b, tile, gen), dtype=torch.uint8, device=DEV)
+        S.rng_study_init(b, tile, gen, state)
+        S.rng_study_sweep(b, spins, [beta] * n_rep, 300, tile, 1, gen, state)
+        E = torch.zeros(n_rep, dtype=torch.float64, device=DEV)
+        es = []
+        for _ in range(40):
+            S.rng_study_sweep(b, spins, [beta] * n_rep, 50, tile, 1, gen, state)
+            S.measure_energy_magnetisation(b, spins, E)
+            es.append(-_host(E) / (L * L))
+        es = np.array(es)
+        out[gen] = (float(es.mean()), float(es.mean(axis=0).std(ddof=1) / np.sqrt(n_rep)))
+    print("e from the study generators (LCG32 skip-ahead, LCG32 random, Fibonacci 521):", out)
+    m, err = out[S.RNG_LCG32]
+    assert abs(m - e_exact) > 1e-3 and abs(m - e_exact) > 20 * err, out
+    for gen in (S.RNG_LCG32_RANDOM, S.RNG_FIB521):
+        m, err = out[gen]
+        assert abs(m - e_exact) < 5 * err + 5e-5, out
