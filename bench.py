@@ -109,6 +109,14 @@ def kt_summary(db: str, log: str, kernel: str, L: int, command: str):
                                         "where name like ? group by grid_x order by grid_x desc",
                                         (f"%{kernel}%",)):
         lines.append(f"grid_{grid}: {calls} {avg:.3f}")
+    lines.append(f"# {kernel} per instantiation and grid size: dispatches, mean duration in microseconds")
+    for name, grid, calls, avg in con.execute("select name, grid_x, count(*), avg(duration) / 1000.0 from kernels "
+                                              "where name like ? group by name, grid_x order by grid_x desc, name",
+                                              (f"%{kernel}%",)):
+        import re
+
+        inst = re.search(r"<[^>]*>", name)
+        lines.append(f"{kernel}{inst.group(0) if inst else ''} grid_{grid}: {calls} {avg:.3f}")
     if bench_line:
         import json
 
@@ -125,38 +133,66 @@ def kt_summary(db: str, log: str, kernel: str, L: int, command: str):
 
 
 def valu_summary(db: str, command: str):
-    """VALU issue utilisation of the hot kernels from a rocprofv3 --pmc run
-    with SQ_INSTS_VALU and GRBM_GUI_ACTIVE: wave-instructions per dispatch over
-    (GPU-busy cycles per XCD x 256 CUs x one wave64 VALU instruction per CU
-    per cycle)."""
+    """VALU use of the hot kernels from a rocprofv3 --pmc run with
+    SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_VALU2,
+    SQ_BUSY_CU_CYCLES and GRBM_GUI_ACTIVE, per dispatch of each kernel's
+    largest grid, against C = CU_NUM x GRBM_GUI_ACTIVE (CU-cycles of the
+    dispatch; GRBM_GUI_ACTIVE is summed over the 8 XCDs in the database and
+    taken as that sum / 8):
+      issue = SQ_INSTS_VALU / C: wave64 VALU instructions per CU per cycle;
+              1.0 when each of the four SIMDs issues one per quad-cycle;
+              gfx950 can issue two per quad-cycle, so this can exceed 1;
+      dual  = SQ_ACTIVE_INST_VALU2 / SQ_ACTIVE_INST_VALU: the share of VALU
+              instructions issued in a quad-cycle that issued two;
+      busy  = (SQ_ACTIVE_INST_VALU - SQ_ACTIVE_INST_VALU2) / C: the share of
+              SIMD quad-cycles that issued at least one VALU instruction
+              (SQ_ACTIVE_INST_VALU counts one quad-cycle per instruction, so
+              dual-issued quad-cycles are counted twice; the profiler's
+              VALUBusy is SQ_ACTIVE_INST_VALU / C);
+      cu    = SQ_BUSY_CU_CYCLES / C: the share of CU-cycles with work."""
     import sqlite3
 
+    cu_num = 256
     con = sqlite3.connect(db)
-    # per kernel, the dispatches of its largest grid (the batched launch, not
-    # the one-chain launches of the per-instance comparison)
     rows = con.execute("select kernel_name, counter_name, value, grid_size from counters_collection").fetchall()
-    biggest = {}
-    for name, _, _, grid in rows:
-        k = short_name(name)
-        biggest[k] = max(biggest.get(k, 0), grid)
+    # per kernel: its largest grid, and of that grid the instantiation with
+    # the most dispatches (the 2D sweep: the split-to-split launches)
+    count = {}
+    for name, cname, _, grid in rows:
+        if cname == "SQ_INSTS_VALU":
+            count[(short_name(name), grid, name)] = count.get((short_name(name), grid, name), 0) + 1
+    pick = {}
+    for (k, grid, name), n in count.items():
+        if k not in pick or (grid, n) > (pick[k][0], pick[k][1]):
+            pick[k] = (grid, n, name)
     acc = {}
     for name, cname, val, grid in rows:
         k = short_name(name)
-        if grid == biggest[k]:
+        if k in pick and (grid, name) == (pick[k][0], pick[k][2]):
             acc.setdefault(k, {}).setdefault(cname, []).append(val)
-    lines = ["# VALU issue utilisation per dispatch of each kernel's largest grid (rocprofv3 --pmc)",
+    lines = ["# VALU use per dispatch of each kernel's largest grid, most frequent instantiation (rocprofv3 --pmc)",
              f"# command: {command}",
-             "# util = SQ_INSTS_VALU / (GRBM_GUI_ACTIVE / 8 XCDs * 256 CUs); peak is one wave64 VALU",
-             "# instruction per CU per cycle (four SIMD16 units, four cycles each)",
-             f"{'kernel':28s} {'dispatches':>10s} {'VALU_insts':>14s} {'busy_cycles':>12s} {'util':>6s}"]
-    for k in ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_tiled", "k_heis3d_half",
-              "k_half_sweep_generic", "k_msc2d", "k_dcb2d_packed", "k_dcb2d", "k_heis_dcb2d", "k_philox_bench", "k_to_split", "k_from_split"):
-        if k not in acc or "SQ_INSTS_VALU" not in acc[k] or "GRBM_GUI_ACTIVE" not in acc[k]:
+             "# C = CU_NUM (256) x GRBM_GUI_ACTIVE (8-XCD sum / 8): CU-cycles of the dispatch",
+             "# issue = SQ_INSTS_VALU / C: wave64 VALU instructions per CU per cycle (1.0 = one per SIMD per",
+             "#         quad-cycle; gfx950 dual-issues, so up to 2)",
+             "# dual  = SQ_ACTIVE_INST_VALU2 / SQ_ACTIVE_INST_VALU (share of instructions issued two at a time)",
+             "# busy  = (SQ_ACTIVE_INST_VALU - SQ_ACTIVE_INST_VALU2) / C: SIMD quad-cycles issuing >= 1 VALU op",
+             "# cu    = SQ_BUSY_CU_CYCLES / C",
+             f"{'kernel':24s} {'disp':>5s} {'VALU_insts':>11s} {'gui_cycles':>11s} {'issue':>6s} {'dual':>6s} "
+             f"{'busy':>6s} {'cu':>6s}"]
+    names = ("k_ising2d_split", "k_pt3d_chain", "k_uneven2d_sweep", "k_heis3d_tiled", "k_heis3d_half",
+             "k_ising3d_half", "k_ising3d_pass", "k_half_sweep_generic", "k_msc2d", "k_dcb2d_packed", "k_dcb2d",
+             "k_dcb3d", "k_heis_dcb2d", "k_philox_bench", "k_dcb_rng")
+    for k in names:
+        a = acc.get(k, {})
+        if "SQ_INSTS_VALU" not in a or "GRBM_GUI_ACTIVE" not in a:
             continue
-        v = acc[k]["SQ_INSTS_VALU"]
-        g = acc[k]["GRBM_GUI_ACTIVE"]
-        vi, gi = sum(v) / len(v), sum(g) / len(g) / 8.0
-        lines.append(f"{k:28s} {len(v):10d} {vi:14.4g} {gi:12.4g} {vi / (gi * 256):6.3f}")
+        mean = lambda key: sum(a[key]) / len(a[key]) if key in a else float("nan")
+        vi, gui = mean("SQ_INSTS_VALU"), mean("GRBM_GUI_ACTIVE") / 8.0
+        act, act2, cub = mean("SQ_ACTIVE_INST_VALU"), mean("SQ_ACTIVE_INST_VALU2"), mean("SQ_BUSY_CU_CYCLES")
+        C = cu_num * gui
+        lines.append(f"{k:24s} {len(a['SQ_INSTS_VALU']):5d} {vi:11.4g} {gui:11.4g} {vi / C:6.3f} "
+                     f"{(act2 / act if act > 0 else float('nan')):6.3f} {(act - act2) / C:6.3f} {cub / C:6.3f}")
     os.makedirs(PROFILES, exist_ok=True)
     with open(os.path.join(PROFILES, "valu_utilisation.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -195,7 +231,10 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
         return acc
 
     def mean_of(acc, key):
-        name = max((n for n in acc if key in n), key=lambda n: sum(acc[n]) / len(acc[n]))
+        # the variant of the kernel with the most dispatches: for the 2D sweep
+        # the split-to-split launches, not the first and last sweeps of a call
+        # (which read and write the caller's rows)
+        name = max((n for n in acc if key in n), key=lambda n: (len(acc[n]), sum(acc[n]) / len(acc[n])))
         return name, sum(acc[name]) / len(acc[name])
 
     kf, kfv = mean_of(per_kernel(fetch_db, "FETCH_SIZE", True), kernel)
@@ -395,16 +434,25 @@ def under_profiler() -> bool:
 
 # Profiled runs (rocprofv3 with hardware counters) have stopped with a
 # malformed-packet queue error while thousands of small kernels were queued
-# back to back without a host synchronisation; runs of about a thousand
-# dispatches per section completed.  Under a profiler a section that would
-# queue more than this many dispatches is refused instead of run.
-PROFILED_DISPATCH_LIMIT = 2000
+# back to back without a host synchronisation (the autotuner's replica copies;
+# dcb_scan's double-checkerboard launches at L = 64 with a budget of 2e8
+# flips).  Under a profiler the sections that queue many small launches are
+# held to the sizes with which profiled runs have completed.
+PROFILED_LIMITS = {
+    "dcb_scan": ("flips", 2e6),
+    "dcb3d": ("flips", 2e6),
+    "tempering.ising2d_paper": ("flips", 2e8),
+    "tempering.ea2d_uneven": ("steps", 40),
+}
 
 
-def profiler_guard(section: str, dispatches: int) -> None:
-    if under_profiler() and dispatches > PROFILED_DISPATCH_LIMIT:
-        raise RuntimeError(f"{section}: about {dispatches} kernel dispatches would be queued under a profiler "
-                           f"(limit {PROFILED_DISPATCH_LIMIT}); reduce its size options for profiled runs")
+def profiler_guard(section: str, value: float) -> None:
+    if not under_profiler() or section not in PROFILED_LIMITS:
+        return
+    what, limit = PROFILED_LIMITS[section]
+    if value > limit:
+        raise RuntimeError(f"{section}: {what} = {value:g} under a profiler (limit {limit:g}, the largest size with "
+                           f"which profiled runs have completed); reduce it for profiled runs")
 
 
 def _events():
@@ -457,12 +505,7 @@ def tempering_ising2d(S, W, sizes=(64, 128, 256, 1024, 2048), n_temps=20, every=
     import numpy as np
 
     beta = np.linspace(0.10, 0.15, n_temps)
-    est = 0
-    for L in sizes:
-        for m in every:
-            steps = max(2, int(flips // (n_temps * L * L * m)))
-            est += 4 * (steps + 1) * (2 * m if L >= 1024 else 1) + 8
-    profiler_guard("tempering.ising2d_paper", est)
+    profiler_guard("tempering.ising2d_paper", flips)
     rows = []
     for L in sizes:
         for m in every:
@@ -622,12 +665,7 @@ def dcb_scan(S, W, sizes=(64, 256, 1024, 4096, 16384), hits=(1, 100), beta=0.4, 
     64 above)."""
     import torch
 
-    # plain sweeps: at most two launches per sweep; double checkerboard: two per sweep and a collect
-    est = 0
-    for L in sizes:
-        n = max(2, min(20000, int(flips // (L * L))))
-        est += 2 * (n + 2) + sum(2 * (max(2, n // k) + 1) + 2 for k in hits)
-    profiler_guard("dcb_scan", est)
+    profiler_guard("dcb_scan", flips)
     rows = []
     for L in sizes:
         b = S.Batch(S.ISING, 2, L, 1, W.seed_for(100))
@@ -656,6 +694,7 @@ def dcb3d(S, W, L=256, hits=(1, 10, 100), beta=0.22, flips=4e9):
     attempted flip against k, and the plain 3D checkerboard sweep."""
     import torch
 
+    profiler_guard("dcb3d", flips)
     b = S.Batch(S.ISING, 3, L, 1, W.seed_for(102))
     spins = torch.empty(L ** 3, dtype=torch.int8, device="cuda")
     S.spin_init(b, spins)
@@ -976,9 +1015,7 @@ def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):
     if under_profiler() and os.environ.get("SPINMC_AUTOTUNE", "") != "0":
         raise RuntimeError("tempering.ea2d_uneven: the workgroup-size autotuner queues thousands of small copies; "
                            "set SPINMC_AUTOTUNE=0 for profiled runs")
-    n_edges = len(set(int(L) for L in cfg.sizes))
-    profiler_guard("tempering.ea2d_uneven",
-                   (n_edges + 3) * (2 * cfg.steps + 64) + per_inst_chains * 2 * (per_inst_steps * 3 + 4))
+    profiler_guard("tempering.ea2d_uneven", cfg.steps)
     inst = W.uneven_table(2, cfg.sizes, nt, S.EA)
     b, spins, coup, E, sot = _pt_batch(S, S.EA, 2, 0, nc, nt, cfg.seed, inst=inst)
     sites = int(sum(int(r[0]) ** 2 for r in inst))
@@ -1024,9 +1061,13 @@ def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):
         for st in streams:
             cur.wait_stream(st)
 
-    per_instance_4()
-    ms_pi4 = _timed(per_instance_4)
-    rate_pi4 = per_inst_steps * sample_sites / (ms_pi4 * 1e-3) / (sites / (nc * nt))
+    pi4 = None  # not run under a profiler (counters, not times, are wanted there)
+    if not under_profiler():
+        per_instance_4()
+        ms_pi4 = _timed(per_instance_4)
+        rate_pi4 = per_inst_steps * sample_sites / (ms_pi4 * 1e-3) / (sites / (nc * nt))
+        pi4 = {"replica_sweeps_per_s": round(rate_pi4, 1), "speedup": round(rate / rate_pi4, 2),
+               "sample": "the same calls, round-robin over four streams"}
     del spins, coup, E, sot
     torch.cuda.empty_cache()
     return {"workload": f"uneven 2D +-J EA, {nc} instances (L from {{32,48,64,96,128,192,256}}) x {nt} "
@@ -1037,9 +1078,7 @@ def tempering_ea2d_uneven(S, W, steps, per_inst_chains=64, per_inst_steps=3):
                              "sample": f"{per_inst_chains} instances spread over the batch, {per_inst_steps} "
                                        "steps, one call per instance, rate scaled by lattice size"},
             "speedup_vs_per_instance": round(rate / rate_pi, 2),
-            "per_instance_4_streams": {"replica_sweeps_per_s": round(rate_pi4, 1),
-                                       "speedup": round(rate / rate_pi4, 2),
-                                       "sample": "the same calls, round-robin over four streams"}}
+            "per_instance_4_streams": pi4}
 
 
 def heisenberg3d(S, W, sweeps):
@@ -1134,7 +1173,7 @@ def summary(out: dict) -> dict:
             r[f"{short}_replica_sweeps_per_s"] = t["replica_sweeps_per_s"]
             r[f"{short}_per_instance_replica_sweeps_per_s"] = t["per_instance"]["replica_sweeps_per_s"]
             r[f"{short}_speedup_vs_per_instance"] = t["speedup_vs_per_instance"]
-            if "per_instance_4_streams" in t:
+            if t.get("per_instance_4_streams"):
                 r[f"{short}_speedup_vs_per_instance_4_streams"] = t["per_instance_4_streams"]["speedup"]
     h = out.get("heisenberg")
     if isinstance(h, dict) and "hbm_roof_at_24B_per_flip" in h:
