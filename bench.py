@@ -35,6 +35,7 @@ KERNEL_SOURCES = {
     "k_ising2d_split": ("lattice2d.hip", "lattice2d.hpp", "philox.hpp", "tables.hpp"),
     "k_heis3d_tiled": ("heis3d.hip", "heis_math.hpp", "philox.hpp"),
     "k_ising3d_half": ("sweep3d.hip", "segment3d.hpp", "philox.hpp", "tables.hpp"),
+    "k_ising3d_pass": ("pass3d.hip", "segment3d.hpp", "philox.hpp", "tables.hpp"),
 }
 
 
@@ -83,6 +84,14 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 4):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
 
 
+KT_WORKLOADS = {
+    "k_ising2d_split": "2D Ising {L}x{L}, the headline batch of three lattices",
+    "k_heis3d_tiled": "3D Heisenberg {L}^3, one lattice",
+    "k_ising3d_pass": "3D Ising and EA (one +-J sample), one L^3 lattice per model, L up to {L}",
+    "k_ising3d_half": "3D Ising and EA (one +-J sample), one L^3 lattice per model, L up to {L}",
+}
+
+
 def kt_summary(db: str, log: str, kernel: str, L: int, command: str):
     """Per-kernel totals of a rocprofv3 --kernel-trace --stats run, beside the
     bench line the same run printed; written next to the traffic summary."""
@@ -95,10 +104,10 @@ def kt_summary(db: str, log: str, kernel: str, L: int, command: str):
         for line in fh:
             if line.startswith("{") and '"metric"' in line:
                 bench_line = line.strip()
-    lines = [f"# rocprofv3 --kernel-trace --stats summary: {kernel}, 2D Ising {L}x{L}",
+    lines = [f"# rocprofv3 --kernel-trace --stats summary: {kernel}, {KT_WORKLOADS[kernel].format(L=L)}",
              f"# command: {command}",
              "# durations in microseconds (top_kernels view of the results database)",
-             f"kernel_source_sha256: {kernel_source_hash()}",
+             f"kernel_source_sha256: {kernel_source_hash(kernel)}",
              f"{'kernel':40s} {'calls':>7s} {'total_us':>12s} {'avg_us':>10s} {'pct':>7s}"]
     for name, calls, total, avg, pct in rows:
         lines.append(f"{short_name(name):40s} {calls:7d} {total:12.1f} {avg:10.3f} {pct:7.2f}")
@@ -252,6 +261,10 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
     if kernel == "k_heis3d_tiled":
         algorithmic = 24.0 * L ** 3
         what = f"one launch = one sweep of a 3D Heisenberg {L}^3 lattice (24 B per site)"
+    elif kernel == "k_ising3d_pass":
+        algorithmic = BYTES_PER_FLIP * L ** 3
+        what = (f"one launch = one sweep of a 3D Ising {L}^3 lattice; algorithmic bytes = one read and one write "
+                f"of every spin (2 B per site)")
     elif kernel == "k_ising3d_half":
         algorithmic = 1.0 * L ** 3
         what = (f"one launch = one half-sweep of a 3D Ising {L}^3 lattice; algorithmic bytes = half of the "
@@ -715,9 +728,9 @@ def dcb3d(S, W, L=256, hits=(1, 10, 100), beta=0.22, flips=4e9):
 
 def sweep3d(S, W, sizes=(256, 512, 1024), beta=0.2216, flips=8e9, models=("ising", "ea")):
     """Plain 3D checkerboard sweeps (Ising, and EA with one coupling sample)
-    on one L^3 lattice: ps per attempted flip for the segment-per-thread
-    kernel and the per-site kernels, and the rate at 2 B/flip (one read and
-    one write of every spin per sweep) against 8 TB/s."""
+    on one L^3 lattice: ps per attempted flip for the one-pass segment sweep,
+    the two half-sweep launches and the per-site kernels, and the rate at
+    2 B/flip (one read and one write of every spin per sweep) against 8 TB/s."""
     import os
     import torch
 
@@ -738,17 +751,23 @@ def sweep3d(S, W, sizes=(256, 512, 1024), beta=0.2216, flips=8e9, models=("ising
             spins = torch.empty(L ** 3, dtype=torch.int8, device="cuda")
             coup = torch.empty(3 * L ** 3, dtype=torch.int8, device="cuda") if model == S.EA else None
             S.spin_init(b, spins, coup)
-            n = max(2, int(flips // L ** 3))
-            row = {"model": "EA" if model == S.EA else "Ising", "L": L}
-            for flag in ("1", "0"):
-                os.environ["SPINMC_SWEEP3D"] = flag
+            n = max(2, int(flips // L ** 3) // 2 * 2)  # even: the one-pass sweeps end in the caller's buffer
+            row = {"model": "EA" if model == S.EA else "Ising", "L": L, "default": S.sweep_plan(b)[1]}
+            for key, env in (("pass", {"SPINMC_SWEEP3D_PASS": "1"}), ("half", {"SPINMC_SWEEP3D_PASS": "0"}),
+                             ("per_site", {"SPINMC_SWEEP3D": "0"})):
+                os.environ.update(env)
                 S.metropolis_sweep(b, spins, [beta], 0, 2, couplings=coup)
+                S.kernel_timing_read()
+                S.kernel_timing_enable(True)
                 ms = _timed(lambda: S.metropolis_sweep(b, spins, [beta], 2, n, couplings=coup))
+                kernel_ms, launches = S.kernel_timing_read()
+                S.kernel_timing_enable(False)
+                for k in env:
+                    os.environ.pop(k, None)
                 ps = ms * 1e9 / (n * L ** 3)
-                key = "segment" if flag == "1" else "per_site"
                 row[key] = {"kernel": S.sweep_plan(b)[1], "ps_per_flip": round(ps, 4),
-                            "hbm_frac_2B": round(2.0 / (ps * 1e-12) / 8e12, 4)}
-            os.environ.pop("SPINMC_SWEEP3D", None)
+                            "hbm_frac_2B": round(2.0 / (ps * 1e-12) / 8e12, 4),
+                            "kernel_us_per_sweep": round(kernel_ms * 1e3 / n, 3) if launches else None}
             rows.append(row)
             del spins, coup
             torch.cuda.empty_cache()
@@ -1181,10 +1200,13 @@ def summary(out: dict) -> dict:
         r["heis3d_hbm_frac"] = h["hbm_roof_at_24B_per_flip"]["frac"]
     s3 = out.get("sweep3d")
     if isinstance(s3, dict):
+        # the kernel the library takes by default at each edge
         for row in s3.get("rows", []):
-            if row.get("model") == "Ising" and "segment" in row:
-                r[f"ising3d_L{row['L']}_ps_per_flip"] = row["segment"]["ps_per_flip"]
-                r[f"ising3d_L{row['L']}_hbm_frac_2B"] = row["segment"]["hbm_frac_2B"]
+            key = "pass" if row.get("default") == "k_ising3d_pass" else "half"
+            if key in row:
+                name = f"{row['model'].lower()}3d_L{row['L']}"
+                r[f"{name}_ps_per_flip"] = row[key]["ps_per_flip"]
+                r[f"{name}_hbm_frac_2B"] = row[key]["hbm_frac_2B"]
     cb = out.get("cpu_baseline")
     if isinstance(cb, dict):
         r["oracle_ns_per_flip_2d"] = cb["value"]
@@ -1238,7 +1260,7 @@ def main():
     ap.add_argument("--tau-replicas", type=int, default=256)
     ap.add_argument("--msc-only", action="store_true", help="only the multi-spin-coded measurement (for profiling)")
     ap.add_argument("--pmc-kernel", default="k_ising2d_split", choices=sorted(KERNEL_SOURCES),
-                    help="kernel of the --pmc-summary")
+                    help="kernel of the --pmc-summary and --kt-summary")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter scale for the traffic figure)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
@@ -1260,11 +1282,13 @@ def main():
     if args.valu_summary:
         valu_summary(args.valu_summary, args.pmc_command[0] if args.pmc_command else "")
         return
+    kernel_L = {"k_heis3d_tiled": 256, "k_ising3d_half": max(args.sweep3d_sizes),
+                "k_ising3d_pass": max(args.sweep3d_sizes)}.get(args.pmc_kernel, args.L)
     if args.kt_summary:
-        kt_summary(*args.kt_summary, kernel="k_ising2d_split", L=args.L, command=args.kt_command)
+        kt_summary(*args.kt_summary, kernel=args.pmc_kernel, L=kernel_L, command=args.kt_command)
         return
     if args.pmc_summary:
-        pmc_L = {"k_heis3d_tiled": 256, "k_ising3d_half": max(args.sweep3d_sizes)}.get(args.pmc_kernel, args.L)
+        pmc_L = kernel_L
         pmc_summary(*args.pmc_summary, kernel=args.pmc_kernel, L=pmc_L,
                     commands=args.pmc_command)
         return

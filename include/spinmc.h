@@ -60,14 +60,20 @@
  *   runs all steps of a call in one launch; 2D tempering with edges in
  *   {16, 32, ..., 256} runs one workgroup per replica per step (a graph of
  *   steps); uniform 3D Ising / EA batches with L a multiple of 16 sweep
- *   16-site row segments per thread (two launches per sweep, in place);
+ *   16-site row segments per thread: for L in [512, 1024] in one launch per
+ *   sweep that alternates between the caller's lattice and a library-held
+ *   second lattice of the same size (an odd sweep count ends with one
+ *   device copy back), below in two launches per sweep, in place;
  *   everything else takes generic per-site kernels.  All paths give
  *   identical results.  Environment variables for comparisons and tuning
  *   (read at each call): SPINMC_PT3D=0, SPINMC_UNEVEN2D=0 and
  *   SPINMC_PT_SPLIT2D=0 send tempering to the generic kernels,
  *   SPINMC_SWEEP_LDS2D=0 small 2D sweeps, SPINMC_SWEEP3D=0 3D Ising / EA
- *   sweeps (SPINMC_SWEEP3D_Z = 1 .. 16 rows per thread and
- *   SPINMC_SWEEP3D_NT=0, plain stores, set their launch shape);
+ *   sweeps; SPINMC_SWEEP3D_PASS=0 keeps the two launches per sweep for
+ *   every edge, =1 takes the one launch from edge 32 (SPINMC_PASS3D_TY,
+ *   _SEGS and _D set its rows per strip, segments per thread and planes
+ *   per z segment; SPINMC_SWEEP3D_Z = 1 .. 16 rows per thread and
+ *   SPINMC_SWEEP3D_NT=0, plain stores, the two-launch shape);
  *   SPINMC_L2D_CHUNKS (1 or 2),
  *   SPINMC_L2D_H (band height, a multiple of 4), SPINMC_L2D_H1 /
  *   SPINMC_L2D_H2 (heights of the bands of the first and second half of

@@ -103,6 +103,7 @@ enum Slot {
     kPtDelta,
     kPtOut,
     kBonds3d,    // bit-packed 3D EA bonds of the segment sweep
+    kPass3d,     // second lattice buffer of the one-pass 3D sweep
     kNumSlots
 };
 
@@ -269,6 +270,17 @@ bool sweep3d_shape(const smc_desc *d) {
     const char *env = getenv("SPINMC_SWEEP3D");
     if (env && env[0] == '0') return false;
     return d->dim == 3 && d->L > 0 && (d->model == SMC_ISING || d->model == SMC_EA) && sweep3d_supported(d->L);
+}
+
+// ... and, with an edge of 512 .. 1024, the one-pass sweep (below 512 its
+// strips are too few to fill the chip and the two half-sweep launches are
+// faster; SPINMC_SWEEP3D_PASS=1 takes it for every edge of 32 .. 1024 it
+// supports, SPINMC_SWEEP3D_PASS=0 never).
+bool pass3d_enabled(const smc_desc *d) {
+    const char *env = getenv("SPINMC_SWEEP3D_PASS");
+    if (env && env[0] == '0') return false;
+    if (!(env && env[0] == '1') && d->L < 512) return false;
+    return pass3d_supported(d->L);
 }
 
 bool use_sweep3d(const smc_desc *d, const void *spins, const int8_t *coup, const std::vector<ThrRow> &rows) {
@@ -896,8 +908,9 @@ int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char
         *launches_per_sweep = 1;
         *kernel_name = "k_ising2d_split";
     } else if (sweep3d_shape(desc)) {
-        *launches_per_sweep = 2;
-        *kernel_name = "k_ising3d_half";
+        const bool pass = pass3d_enabled(desc);
+        *launches_per_sweep = pass ? 1 : 2;
+        *kernel_name = pass ? "k_ising3d_pass" : "k_ising3d_half";
     } else if (lds2d_sweep_shape(desc) && !(getenv("SPINMC_UNEVEN2D") && getenv("SPINMC_UNEVEN2D")[0] == '0')) {
         *launches_per_sweep = 1;  // at most: up to 256 sweeps per launch
         *kernel_name = "k_uneven2d_sweep";
@@ -1242,13 +1255,31 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
         const int8_t *coup8 = a.coup;
         const uint2 *packed = nullptr;
         const char *env = getenv("SPINMC_SWEEP3D_PACK");
-        if (a.coup && n_sweeps >= 4 && !(env && env[0] == '0')) {
+        const bool pass = pass3d_enabled(desc);
+        if (a.coup && (pass || (n_sweeps >= 4 && !(env && env[0] == '0')))) {
             void *q = nullptr;
             if ((rc = ensure(c, kBonds3d, (size_t)plan.n_samples * (size_t)(plan.b.N / 16) * sizeof(uint2), &q)))
                 return rc;
             packed = (const uint2 *)q;
             coup8 = nullptr;
             SMC_HIP(launch_pack_bonds3d(a.coup, (uint2 *)q, desc->L, (int)plan.n_samples, s));
+        }
+        if (pass) {
+            // one launch per sweep, ping-pong between the caller's lattice and
+            // a second buffer; an odd count ends with one copy back
+            const size_t bytes = (size_t)desc->n_rep * (size_t)plan.b.N;
+            void *q = nullptr;
+            if ((rc = ensure(c, kPass3d, bytes, &q))) return rc;
+            int8_t *A = (int8_t *)spins, *B = (int8_t *)q;
+            SweepTimer timer(s, n_sweeps);
+            for (int32_t k = 0; k < n_sweeps; ++k) {
+                const uint32_t t = (uint32_t)(sweep0 + (uint64_t)k);
+                SMC_HIP(launch_ising3d_pass(k & 1 ? B : A, k & 1 ? A : B, packed, plan.b.rep_per_sample, a.thr,
+                                            dE_accum, desc->n_rep, desc->L, a.key, t, s));
+            }
+            timer.finish();
+            if (n_sweeps & 1) SMC_HIP(hipMemcpyAsync(A, B, bytes, hipMemcpyDeviceToDevice, s));
+            return SMC_OK;
         }
         SweepTimer timer(s, 2 * (int64_t)n_sweeps);
         for (int32_t k = 0; k < n_sweeps; ++k) {

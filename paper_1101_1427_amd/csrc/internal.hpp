@@ -228,6 +228,12 @@ hipError_t launch_pt_prepare(const SwapArgs &a, const double *energy_in, hipStre
 hipError_t launch_pt_swap(const SwapArgs &a, hipStream_t s);
 hipError_t launch_pt_finish(const SwapArgs &a, double *energy_out, hipStream_t s);
 
+// ---- one-pass 3D Ising / EA sweep (pass3d.hip): src and dst distinct ----
+bool pass3d_supported(int L);
+hipError_t launch_ising3d_pass(const int8_t *src, int8_t *dst, const uint2 *pbonds, int rep_per_sample,
+                               const ThrRow *thr, int64_t *dE, int n_rep, int L, Key key, uint32_t t,
+                               hipStream_t s);
+
 // ---- random-number study (rngstudy.hip) ----
 bool rng_study_lags(int gen, int *r, int *s);
 int64_t rng_study_state_bytes(int gen, int L, int T);  // per replica; 0 for an unknown generator

@@ -80,6 +80,40 @@ struct RowOut {
     uint32_t F0, F1, n0, n1;
 };
 
+// True where a 16-bit lane of eq is zero (a head equal to its high half).
+__device__ __forceinline__ bool has_tie(uint32_t eq) { return ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u); }
+
+// Exact decisions of the eight sites of o (heads w, in-colour indices h0 ..
+// h0 + 7) on the lanes with tie set: a head equal to the high half of its
+// threshold (probability 2^-16 per site) compares the tail draw with the low
+// half.
+__device__ __forceinline__ void exact_decisions(RowOut &o, const uint4 &w, const ThrRow &th, uint32_t h0, uint32_t c,
+                                                uint32_t t, uint32_t r, Key key, uint32_t four, bool tie) {
+    if (!tie) return;
+    // the heads as two 64-bit words and the three thresholds as values, so
+    // that the selections below stay in registers
+    const uint64_t wlo = ((uint64_t)w.y << 32) | w.x, whi = ((uint64_t)w.w << 32) | w.z;
+    const uint64_t T3 = ((uint64_t)th.m[3].y << 32) | th.m[3].x, T2 = ((uint64_t)th.m[2].y << 32) | th.m[2].x,
+                   T1 = ((uint64_t)th.m[1].y << 32) | th.m[1].x;
+    uint32_t f0 = 0u, f1 = 0u;
+#pragma unroll 1
+    for (uint32_t i = 0; i < 2u * four; ++i) {
+        const uint32_t ns = ((i < 4u ? o.n0 : o.n1) >> (8u * (i & 3u))) & 0xFFu;
+        const uint32_t head = (uint32_t)((i < 4u ? wlo : whi) >> (16u * (i & 3u))) & 0xFFFFu;
+        uint32_t flip = 1u;
+        if (ns < 3u) {
+            const uint64_t T = ns == 0u ? T3 : ns == 1u ? T2 : T1;  // Delta E = 12 - 4 ns
+            flip = metropolis_accept(head, make_uint2((uint32_t)T, (uint32_t)(T >> 32)), h0 + i, t, r, c, key);
+        }
+        if (i < 4u)
+            f0 |= flip << (8u * (i & 3u));
+        else
+            f1 |= flip << (8u * (i & 3u));
+    }
+    o.F0 = f0;
+    o.F1 = f1;
+}
+
 // One segment: own row raw bytes, neighbours' raw bytes, the extra x
 // neighbour bit eb, the per-row bond arrays (EA), Philox block index h0.
 // Bonds of the eight own sites (bit 1 where J = -1, one byte per site, in
@@ -173,32 +207,7 @@ __device__ __forceinline__ RowOut segment_update(const uint4 &own, const uint4 &
     uint32_t eq = 0xFFFFFFFFu;
     o.F0 = decide4(o.n0, w.x, w.y, K, one2, eq);
     o.F1 = decide4(o.n1, w.z, w.w, K, one2, eq);
-    const bool tie = ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u);
-    if (__builtin_expect(__any(tie), 0)) {
-        if (tie) {
-            // exact decisions of the eight sites (a head equal to the high
-            // half of its threshold: probability 2^-16 per site)
-            uint32_t f0 = 0u, f1 = 0u;
-#pragma unroll 1
-            for (uint32_t i = 0; i < 2u * four; ++i) {
-                const uint32_t ns = ((i < 4u ? o.n0 : o.n1) >> (8u * (i & 3u))) & 0xFFu;
-                const uint32_t j = i >> 1;
-                const uint32_t word = (j & 2u) ? ((j & 1u) ? w.w : w.z) : ((j & 1u) ? w.y : w.x);
-                const uint32_t head = (i & 1u) ? (word >> 16) : (word & 0xFFFFu);
-                uint32_t flip = 1u;
-                if (ns < 3u) {
-                    const uint2 tv = ns == 0u ? th.m[3] : ns == 1u ? th.m[2] : th.m[1];  // Delta E = 12 - 4 ns
-                    flip = metropolis_accept(head, tv, h0 + i, t, r, c, key);
-                }
-                if (i < 4u)
-                    f0 |= flip << (8u * (i & 3u));
-                else
-                    f1 |= flip << (8u * (i & 3u));
-            }
-            o.F0 = f0;
-            o.F1 = f1;
-        }
-    }
+    if (__builtin_expect(__any(has_tie(eq)), 0)) exact_decisions(o, w, th, h0, c, t, r, key, four, has_tie(eq));
     return o;
 }
 

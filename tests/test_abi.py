@@ -237,12 +237,22 @@ def test_autotune_has_nothing_to_tune_for_other_batches(tmp_path):
 
 def test_sweep_plan_names_the_3d_kernel(monkeypatch):
     """smc_sweep_plan: uniform 3D Ising / EA batches with an edge that is a
-    multiple of 16 take the segment-per-thread half-sweeps; other edges,
-    Heisenberg batches and SPINMC_SWEEP3D=0 the generic kernels."""
-    for model, L, want in ((S.ISING, 16, "k_ising3d_half"), (S.EA, 48, "k_ising3d_half"),
-                           (S.ISING, 20, "k_half_sweep_generic"), (S.EA, 8, "k_half_sweep_generic")):
-        assert S.sweep_plan(S.Batch(model, 3, L, 2, 1)) == (2, want)
-    assert S.sweep_plan(S.Batch(S.HEISENBERG, 3, 32, 1, 1))[1] != "k_ising3d_half"
+    multiple of 16 take the one-pass segment sweep (edges 512 .. 1024 by
+    default, 32 .. 1024 with SPINMC_SWEEP3D_PASS=1; one launch) or the
+    segment half-sweeps (smaller edges, or SPINMC_SWEEP3D_PASS=0); other
+    edges, Heisenberg batches and SPINMC_SWEEP3D=0 the generic kernels."""
+    for model, L, want in ((S.ISING, 16, (2, "k_ising3d_half")), (S.EA, 48, (2, "k_ising3d_half")),
+                           (S.ISING, 256, (2, "k_ising3d_half")), (S.EA, 512, (1, "k_ising3d_pass")),
+                           (S.ISING, 1024, (1, "k_ising3d_pass")),
+                           (S.ISING, 20, (2, "k_half_sweep_generic")), (S.EA, 8, (2, "k_half_sweep_generic"))):
+        assert S.sweep_plan(S.Batch(model, 3, L, 2, 1)) == want
+    assert S.sweep_plan(S.Batch(S.HEISENBERG, 3, 32, 1, 1))[1] not in ("k_ising3d_half", "k_ising3d_pass")
+    monkeypatch.setenv("SPINMC_SWEEP3D_PASS", "1")
+    assert S.sweep_plan(S.Batch(S.EA, 3, 48, 2, 1)) == (1, "k_ising3d_pass")
+    assert S.sweep_plan(S.Batch(S.ISING, 3, 16, 2, 1)) == (2, "k_ising3d_half")
+    monkeypatch.setenv("SPINMC_SWEEP3D_PASS", "0")
+    assert S.sweep_plan(S.Batch(S.EA, 3, 48, 2, 1)) == (2, "k_ising3d_half")
+    assert S.sweep_plan(S.Batch(S.ISING, 3, 1024, 1, 1)) == (2, "k_ising3d_half")
     monkeypatch.setenv("SPINMC_SWEEP3D", "0")
     assert S.sweep_plan(S.Batch(S.ISING, 3, 64, 1, 1)) == (2, "k_half_sweep_generic")
 
