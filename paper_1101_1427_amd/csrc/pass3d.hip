@@ -75,7 +75,7 @@ struct Pass3dArgs {
     int L, D;              // edge; planes per z segment
     int strips, zsegs;     // per replica
     int np;                // threads per row-parity class (a multiple of 64)
-    uint32_t one2, four, m2;  // 0x00010001, 4, 0x02020202: opaque to the compiler
+    uint32_t one2, four;   // 0x00010001 and 4, opaque to the compiler
 };
 
 __device__ __forceinline__ int wrapi(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
@@ -117,47 +117,6 @@ __device__ __forceinline__ void set_half(uint4 &q, uint2 h) {
     }
 }
 
-// Bits o .. o + 7 of m to eight bytes whose bit 1 is the bit (four bits per
-// 24-bit product: bit i of a nibble lands on bits i + 1, i + 8, i + 15 and
-// i + 22, so bit 8 i + 1 holds it and no two land on one position).  The
-// other bits of each byte are left as they come: every use masks bit 1.
-__device__ __forceinline__ uint2 spread8b(uint32_t m, uint32_t o) {
-    return make_uint2(__umul24(__builtin_amdgcn_ubfe(m, o, 4), 0x00408102u),
-                      __umul24(__builtin_amdgcn_ubfe(m, o + 4, 4), 0x00408102u));
-}
-
-// Bonds of the eight own sites (parity A in x), bit 1 of a byte set where
-// J = -1 (the byte's other bits are arbitrary), in the order of the own half: b to the other half unshifted, s to it shifted by
-// one site, then +y, -y, +z, -z.  jxy: the row's x mask (bits 0-7 even-x,
-// 8-15 odd-x sites) and y mask (bits 16-31); jeb the bond entering the row
-// from x0 - 1; jym_xy the masks of row y - 1; jz, jzm the z masks of the row
-// and of the row in plane z - 1.
-struct BondsB {
-    uint2 b, s, yp, ym, zp, zm;
-};
-
-template <int A>
-__device__ __forceinline__ BondsB bonds_b(uint32_t jxy, uint32_t jeb, uint32_t jym_xy, uint32_t jz, uint32_t jzm) {
-    constexpr uint32_t sh = A ? 8u : 0u;
-    BondsB bd;
-    // the unshifted pairs are joined by the even-x sites' +x bonds (bits
-    // 0-7) for either parity; the shifted pairs by the odd-x sites' bonds
-    // (bits 8-15), which the even-x sites see moved up by one site with the
-    // bond from x0 - 1 entering at the bottom
-    bd.b = spread8b(jxy, 0u);
-    bd.s = A ? spread8b(jxy, 8u) : spread8b(((jxy >> 7) & 0xFEu) | jeb, 0u);
-    bd.yp = spread8b(jxy, 16u + sh);
-    bd.ym = spread8b(jym_xy, 16u + sh);
-    bd.zp = spread8b(jz, sh);
-    bd.zm = spread8b(jzm, sh);
-    return bd;
-}
-
-// (a ^ b) & m in one instruction: 2 per byte where two +-1 spin bytes differ.
-__device__ __forceinline__ uint32_t unsat(uint32_t a, uint32_t b, uint32_t m) {
-    return __builtin_amdgcn_bitop3_b32(a, b, m, 0x28);
-}
-
 // The eight sites of parity A of a split segment q, colour c: neighbours in
 // the other half (x +- 1, with eb the raw byte of the site beyond the
 // segment: x0 + 16 for odd-x sites, x0 - 1 for even-x), in rows y -+ 1 (ym,
@@ -165,7 +124,7 @@ __device__ __forceinline__ uint32_t unsat(uint32_t a, uint32_t b, uint32_t m) {
 // new own half; adds the energy change to dE where count is set.
 template <bool EA, int A, bool DE>
 __device__ __forceinline__ uint2 update_half(const uint4 &q, uint2 ym, uint2 yp, uint2 zm, uint2 zp, uint32_t eb,
-                                             const BondsB &bd, const Lut3 &K, const ThrRow &th, uint32_t h0,
+                                             const Bonds3 &bd, const Lut3 &K, const ThrRow &th, uint32_t h0,
                                              uint32_t c, uint32_t r, const Pass3dArgs &a, bool count, long long &dE) {
     const uint2 Sa = half<A>(q), Sb = half<1 - A>(q);
     uint2 sh;
@@ -176,23 +135,8 @@ __device__ __forceinline__ uint2 update_half(const uint4 &q, uint2 ym, uint2 yp,
         sh.x = (Sb.x << 8) | eb;
         sh.y = alignbyte(Sb.y, Sb.x, 3);
     }
-    const uint32_t m2 = a.m2;
     RowOut o;
-    if constexpr (EA) {
-        o.n0 = (unsat(Sa.x ^ bd.b.x, Sb.x, m2) + unsat(Sa.x ^ bd.s.x, sh.x, m2) + unsat(Sa.x ^ bd.yp.x, yp.x, m2) +
-                unsat(Sa.x ^ bd.ym.x, ym.x, m2) + unsat(Sa.x ^ bd.zp.x, zp.x, m2) + unsat(Sa.x ^ bd.zm.x, zm.x, m2)) >>
-               1;
-        o.n1 = (unsat(Sa.y ^ bd.b.y, Sb.y, m2) + unsat(Sa.y ^ bd.s.y, sh.y, m2) + unsat(Sa.y ^ bd.yp.y, yp.y, m2) +
-                unsat(Sa.y ^ bd.ym.y, ym.y, m2) + unsat(Sa.y ^ bd.zp.y, zp.y, m2) + unsat(Sa.y ^ bd.zm.y, zm.y, m2)) >>
-               1;
-    } else {
-        o.n0 = (unsat(Sa.x, Sb.x, m2) + unsat(Sa.x, sh.x, m2) + unsat(Sa.x, yp.x, m2) + unsat(Sa.x, ym.x, m2) +
-                unsat(Sa.x, zp.x, m2) + unsat(Sa.x, zm.x, m2)) >>
-               1;
-        o.n1 = (unsat(Sa.y, Sb.y, m2) + unsat(Sa.y, sh.y, m2) + unsat(Sa.y, yp.y, m2) + unsat(Sa.y, ym.y, m2) +
-                unsat(Sa.y, zp.y, m2) + unsat(Sa.y, zm.y, m2)) >>
-               1;
-    }
+    count_unsat<EA>(Sa, Sb, sh, ym, yp, zm, zp, bd, o.n0, o.n1);
     const uint4 w = philox4x32_10(make_uint4(h0 >> 3, a.t, r, 2 * kTagHead + c), a.key);
     uint32_t eq = 0xFFFFFFFFu;
     o.F0 = decide4(o.n0, w.x, w.y, K, a.one2, eq);
@@ -321,10 +265,13 @@ __global__ __launch_bounds__(pass3d_max_threads(TY, SEGS)) void k_ising3d_pass(P
         // x0 + 16 (even, first byte of the next segment) or x0 - 1 (odd, last
         // byte of the previous segment)
         const uint32_t eb = A ? S[8 * segn] : S[(L >> 1) + 8 * segp + 7];
-        BondsB bd{};
+        Bonds3 bd{};
         if constexpr (EA) {
+            // masks: x (bits 0-15) and y (16-31) of the row and of row y - 1,
+            // z of the row and of the row in plane z - 1, the bond entering
+            // from x0 - 1 (last odd-x bit of the x mask to the left)
             const uint32_t jeb = (bmask(s, ry, segp) >> 15) & 1u;
-            bd = bonds_b<A>(bo.x, jeb, bmask(s, ry - 1, seg), bo.y, bzm);
+            bd = bonds_from_bits(bo.x, jeb, bo.x >> 16, bmask(s, ry - 1, seg) >> 16, bo.y, bzm, A);
         }
         const uint32_t h0 = (poff(z) + row_off + 16u * (uint32_t)seg) >> 1;
         return update_half<EA, A, DE>(q, ym, yp, half<A>(qzm), half<A>(qzp), eb, bd, K, th, h0, c, (uint32_t)r, a,
@@ -474,7 +421,6 @@ hipError_t launch_ising3d_pass(const int8_t *src, int8_t *dst, const uint2 *pbon
     a.np = threads / 2;
     a.one2 = 0x00010001u;
     a.four = 4u;
-    a.m2 = 0x02020202u;
     const size_t lds = (size_t)kRing * (size_t)(ty + 4) * (size_t)L * (pbonds ? 5 : 4) / 4;
     const dim3 grid((unsigned)((int64_t)n_rep * a.strips * a.zsegs));
 #define SMC_PASS3D(MM, TT, SS, DD)                                                                          \

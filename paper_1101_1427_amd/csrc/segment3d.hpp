@@ -7,9 +7,11 @@
 // sites (A = 1) or even-x sites (A = 0); they are the in-colour indices
 // h0 .. h0 + 7 (h0 = first site / 2, a multiple of 8), whose 16-bit heads
 // are the eight halves of the Philox block (h0 / 8, t, r, 2*HEAD + c) in
-// order.  Unsatisfied bonds are counted four sites to a word, the flip
-// decision compares heads with the thresholds' high halves in packed 16-bit
-// lanes, and a head equal to a high half takes the exact (tail) decision.
+// order.  Unsatisfied bonds are counted four sites to a word ((a ^ b) & 2
+// per byte of two +-1 spin bytes, one v_bitop3 per neighbour word), the
+// flip decision compares heads with the thresholds' high halves in packed
+// 16-bit lanes, and a head equal to a high half takes the exact (tail)
+// decision.
 #pragma once
 #include "internal.hpp"
 
@@ -34,9 +36,25 @@ __device__ __forceinline__ uint32_t min16(uint32_t a, uint32_t b) {
     return as_u32(__builtin_elementwise_min(as_u16x2(a), as_u16x2(b)));
 }
 
-// Spin bytes +1 / -1 (0x01 / 0xFF) to bits 0 / 1, four per word.
+// +-1 bytes (0x01 / 0xFF) to bits 0 / 1, four per word (bond packing).
 __device__ __forceinline__ uint32_t bits(uint32_t v) { return (v >> 1) & 0x01010101u; }
 __device__ __forceinline__ uint2 bits2(uint2 v) { return make_uint2(bits(v.x), bits(v.y)); }
+
+// (a ^ b) & m in one instruction: with m = 0x02020202, 2 in each byte where
+// two +-1 spin bytes (0x01 / 0xFF) differ, or where bit 1 of the xor of
+// three such bytes or bond bytes is set.
+__device__ __forceinline__ uint32_t unsat(uint32_t a, uint32_t b, uint32_t m) {
+    return __builtin_amdgcn_bitop3_b32(a, b, m, 0x28);
+}
+
+// Bits o .. o + 7 of m to eight bytes whose bit 1 is the bit (four bits per
+// 24-bit product: bit i of a nibble lands on bits i + 1, i + 8, i + 15 and
+// i + 22, so bit 8 i + 1 holds it and no two land on one position).  The
+// other bits of each byte are left as they come: every use masks bit 1.
+__device__ __forceinline__ uint2 spread8b(uint32_t m, uint32_t o) {
+    return make_uint2(__umul24(__builtin_amdgcn_ubfe(m, o, 4), 0x00408102u),
+                      __umul24(__builtin_amdgcn_ubfe(m, o + 4, 4), 0x00408102u));
+}
 
 // Even-x (sel 0x06040200) or odd-x (sel 0x07050301) bytes of a segment.
 __device__ __forceinline__ uint2 half_of(uint4 w, uint32_t sel) {
@@ -114,12 +132,11 @@ __device__ __forceinline__ void exact_decisions(RowOut &o, const uint4 &w, const
     o.F1 = f1;
 }
 
-// One segment: own row raw bytes, neighbours' raw bytes, the extra x
-// neighbour bit eb, the per-row bond arrays (EA), Philox block index h0.
-// Bonds of the eight own sites (bit 1 where J = -1, one byte per site, in
-// the order of the own array): b pairs with the other array of the row
-// unshifted, s with it shifted by one site (see segment_update), and the
-// bonds to y + 1, y - 1, z + 1, z - 1.
+// Bonds of the eight own sites (bit 1 of a byte set where J = -1, the
+// byte's other bits arbitrary, one byte per site in the order of the own
+// array): b pairs with the other array of the row unshifted, s with it
+// shifted by one site (see segment_update), and the bonds to y + 1, y - 1,
+// z + 1, z - 1.
 struct Bonds3 {
     uint2 b, s, yp, ym, zp, zm;
 };
@@ -127,28 +144,25 @@ struct Bonds3 {
 // From the int8 bond rows: +x bonds of the row (jx) and the bond entering
 // it from x0 - 1 (bit jeb), +y bonds of the row (jy) and of row y - 1
 // (jym), +z bonds of the row (jz) and of row z - 1 (jzm).
+// (int8 +-1 bonds have bit 1 set exactly where J = -1, so their bytes are
+// used as they are.)
 __device__ __forceinline__ Bonds3 bonds_from_bytes(const uint4 &jx, uint32_t jeb, const uint4 &jy, const uint4 &jym,
                                                    const uint4 &jz, const uint4 &jzm, int A) {
     const uint32_t sa = A ? 0x07050301u : 0x06040200u, sb = A ? 0x06040200u : 0x07050301u;
-    const uint2 jxa = bits2(half_of(jx, sa)), jxb = bits2(half_of(jx, sb));
+    const uint2 jxa = half_of(jx, sa), jxb = half_of(jx, sb);
     Bonds3 bd;
     // paired with the unshifted other array: x -> x + 1 of even-x sites
     // (array a), x - 1 -> x of odd-x sites (array b); with the shifted one:
     // x + 1 of odd-x sites (array a), x - 1 of even-x sites (array b shifted
     // up, x0 - 1 entering)
     bd.b = A ? jxb : jxa;
-    bd.s.x = A ? jxa.x : ((jxb.x << 8) | jeb);
+    bd.s.x = A ? jxa.x : ((jxb.x << 8) | (jeb << 1));
     bd.s.y = A ? jxa.y : alignbyte(jxb.y, jxb.x, 3);
-    bd.yp = bits2(half_of(jy, sa));
-    bd.ym = bits2(half_of(jym, sa));
-    bd.zp = bits2(half_of(jz, sa));
-    bd.zm = bits2(half_of(jzm, sa));
+    bd.yp = half_of(jy, sa);
+    bd.ym = half_of(jym, sa);
+    bd.zp = half_of(jz, sa);
+    bd.zm = half_of(jzm, sa);
     return bd;
-}
-
-// Eight bits to eight 0/1 bytes.
-__device__ __forceinline__ uint2 spread8(uint32_t m) {
-    return make_uint2(((m & 15u) * 0x00204081u) & 0x01010101u, (((m >> 4) & 15u) * 0x00204081u) & 0x01010101u);
 }
 
 // From bit-packed bond masks of one direction and segment: bits 0..7 the
@@ -157,51 +171,69 @@ __device__ __forceinline__ uint2 spread8(uint32_t m) {
 // bond entering the row from x0 - 1.
 __device__ __forceinline__ Bonds3 bonds_from_bits(uint32_t jx, uint32_t jeb, uint32_t jy, uint32_t jym, uint32_t jz,
                                                   uint32_t jzm, int A) {
-    const int sh = A ? 8 : 0;
-    const uint32_t ax = (jx >> sh) & 0xFFu, bx = (jx >> (8 - sh)) & 0xFFu;
+    const uint32_t sh = A ? 8u : 0u;
     Bonds3 bd;
-    bd.b = spread8(A ? bx : ax);
-    bd.s = spread8(A ? ax : (((bx << 1) | jeb) & 0xFFu));
-    bd.yp = spread8((jy >> sh) & 0xFFu);
-    bd.ym = spread8((jym >> sh) & 0xFFu);
-    bd.zp = spread8((jz >> sh) & 0xFFu);
-    bd.zm = spread8((jzm >> sh) & 0xFFu);
+    // the unshifted pairs are joined by the even-x sites' +x bonds (bits
+    // 0-7) for either parity; the shifted pairs by the odd-x sites' bonds
+    // (bits 8-15), which the even-x sites see moved up by one site with the
+    // bond from x0 - 1 entering at the bottom
+    bd.b = spread8b(jx, 0u);
+    bd.s = A ? spread8b(jx, 8u) : spread8b(((jx >> 7) & 0xFEu) | jeb, 0u);
+    bd.yp = spread8b(jy, sh);
+    bd.ym = spread8b(jym, sh);
+    bd.zp = spread8b(jz, sh);
+    bd.zm = spread8b(jzm, sh);
     return bd;
 }
 
 // Four 0/1 bytes to four bits.
 __device__ __forceinline__ uint32_t gather4(uint32_t w) { return (w * 0x01020408u) >> 24; }
 
+// Bond counts of the eight own sites (bytes 0 .. 6) from the own array Sa,
+// the other array Sb, the other array shifted by one site (sh) and the y
+// and z neighbour arrays, all raw spin bytes in the order of the own sites.
+template <bool EA>
+__device__ __forceinline__ void count_unsat(const uint2 &Sa, const uint2 &Sb, const uint2 &sh, const uint2 &ym,
+                                            const uint2 &yp, const uint2 &zm, const uint2 &zp, const Bonds3 &bd,
+                                            uint32_t &n0, uint32_t &n1) {
+    const uint32_t m2 = 0x02020202u;
+    if constexpr (EA) {
+        n0 = (unsat(Sa.x ^ bd.b.x, Sb.x, m2) + unsat(Sa.x ^ bd.s.x, sh.x, m2) + unsat(Sa.x ^ bd.yp.x, yp.x, m2) +
+              unsat(Sa.x ^ bd.ym.x, ym.x, m2) + unsat(Sa.x ^ bd.zp.x, zp.x, m2) + unsat(Sa.x ^ bd.zm.x, zm.x, m2)) >>
+             1;
+        n1 = (unsat(Sa.y ^ bd.b.y, Sb.y, m2) + unsat(Sa.y ^ bd.s.y, sh.y, m2) + unsat(Sa.y ^ bd.yp.y, yp.y, m2) +
+              unsat(Sa.y ^ bd.ym.y, ym.y, m2) + unsat(Sa.y ^ bd.zp.y, zp.y, m2) + unsat(Sa.y ^ bd.zm.y, zm.y, m2)) >>
+             1;
+    } else {
+        n0 = (unsat(Sa.x, Sb.x, m2) + unsat(Sa.x, sh.x, m2) + unsat(Sa.x, yp.x, m2) + unsat(Sa.x, ym.x, m2) +
+              unsat(Sa.x, zp.x, m2) + unsat(Sa.x, zm.x, m2)) >>
+             1;
+        n1 = (unsat(Sa.y, Sb.y, m2) + unsat(Sa.y, sh.y, m2) + unsat(Sa.y, yp.y, m2) + unsat(Sa.y, ym.y, m2) +
+              unsat(Sa.y, zp.y, m2) + unsat(Sa.y, zm.y, m2)) >>
+             1;
+    }
+}
+
 // One segment: own row raw bytes, the neighbour rows' raw bytes, the x
-// neighbour beyond the segment (bit eb: x0 + 16 for odd-x own sites, x0 - 1
-// for even-x), the bonds (EA), Philox block index h0 of the own sites.
+// neighbour beyond the segment (eb, its raw byte: x0 + 16 for odd-x own
+// sites, x0 - 1 for even-x), the bonds (EA), Philox block index h0 of the
+// own sites.
 template <bool EA>
 __device__ __forceinline__ RowOut segment_update(const uint4 &own, const uint4 &rym, const uint4 &ryp,
                                                  const uint4 &rzm, const uint4 &rzp, uint32_t eb, int A,
                                                  const Bonds3 &bd, const ThrRow &th, uint32_t h0, uint32_t c,
                                                  uint32_t t, uint32_t r, Key key, uint32_t one2, uint32_t four) {
     const uint32_t sa = A ? 0x07050301u : 0x06040200u, sb = A ? 0x06040200u : 0x07050301u;
-    const uint2 Sa = bits2(half_of(own, sa));
-    const uint2 Sb = bits2(half_of(own, sb));
-    const uint2 ym = bits2(half_of(rym, sa));
-    const uint2 yp = bits2(half_of(ryp, sa));
-    const uint2 zm = bits2(half_of(rzm, sa));
-    const uint2 zp = bits2(half_of(rzp, sa));
+    const uint2 Sa = half_of(own, sa);
+    const uint2 Sb = half_of(own, sb);
     // the other array shifted by one site: odd-x sites see x + 1 (down by a
     // byte, x0 + 16 entering at the top), even-x sites x - 1 (up by a byte)
     uint2 sh;
     sh.x = A ? alignbyte(Sb.y, Sb.x, 1) : ((Sb.x << 8) | eb);
     sh.y = A ? ((Sb.y >> 8) | (eb << 24)) : alignbyte(Sb.y, Sb.x, 3);
     RowOut o;
-    if constexpr (EA) {
-        o.n0 = ((Sa.x ^ Sb.x ^ bd.b.x) + (Sa.x ^ sh.x ^ bd.s.x)) + ((Sa.x ^ yp.x ^ bd.yp.x) + (Sa.x ^ ym.x ^ bd.ym.x)) +
-               ((Sa.x ^ zp.x ^ bd.zp.x) + (Sa.x ^ zm.x ^ bd.zm.x));
-        o.n1 = ((Sa.y ^ Sb.y ^ bd.b.y) + (Sa.y ^ sh.y ^ bd.s.y)) + ((Sa.y ^ yp.y ^ bd.yp.y) + (Sa.y ^ ym.y ^ bd.ym.y)) +
-               ((Sa.y ^ zp.y ^ bd.zp.y) + (Sa.y ^ zm.y ^ bd.zm.y));
-    } else {
-        o.n0 = ((Sa.x ^ Sb.x) + (Sa.x ^ sh.x)) + ((Sa.x ^ yp.x) + (Sa.x ^ ym.x)) + ((Sa.x ^ zp.x) + (Sa.x ^ zm.x));
-        o.n1 = ((Sa.y ^ Sb.y) + (Sa.y ^ sh.y)) + ((Sa.y ^ yp.y) + (Sa.y ^ ym.y)) + ((Sa.y ^ zp.y) + (Sa.y ^ zm.y));
-    }
+    count_unsat<EA>(Sa, Sb, sh, half_of(rym, sa), half_of(ryp, sa), half_of(rzm, sa), half_of(rzp, sa), bd, o.n0,
+                    o.n1);
     const uint4 w = philox4x32_10(make_uint4(h0 >> 3, t, r, 2 * kTagHead + c), key);
     const Lut3 K = lut_of(th);
     uint32_t eq = 0xFFFFFFFFu;

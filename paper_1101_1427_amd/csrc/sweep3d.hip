@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_ising3d_half(Sweep3dArgs a) {
             const uint4 ryp = *(const uint4 *)(S + i0 + dyp);
             const int A = ((y + z) & 1) ^ a.c;
             const int64_t iex = i0 - x0 + (A ? xr : xl);
-            const uint32_t eb = ((uint32_t)(uint8_t)S[iex] >> 1) & 1u;
+            const uint32_t eb = (uint8_t)S[iex];
             uint4 jzn = make_uint4(0u, 0u, 0u, 0u);
             uint2 pnext = make_uint2(0u, 0u);
             Bonds3 bd{};
