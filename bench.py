@@ -468,6 +468,32 @@ def profiler_guard(section: str, value: float) -> None:
                            f"which profiled runs have completed); reduce it for profiled runs")
 
 
+def autotune_report(S, b, envs=({},)):
+    """smc_autotune for batch b (once under each environment of envs) and the
+    shapes it recorded for b's edge: kind, model, replicas, values."""
+    import tempfile
+
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        for env in envs:
+            old = {k: os.environ.get(k) for k in env}
+            os.environ.update(env)
+            try:
+                S.autotune(b, path)
+            finally:
+                for k, v in old.items():
+                    if v is None:
+                        os.environ.pop(k, None)
+                    else:
+                        os.environ[k] = v
+        lines = []
+        if os.path.exists(path):
+            with open(path) as fh:
+                lines = [l.split() for l in fh if not l.startswith("#")]
+    return [{"kind": l[1], "model": "EA" if l[3] == "1" else "Ising", "replicas": int(l[4]),
+             "values": [int(x) for x in l[5:8]]} for l in lines if len(l) == 8 and int(l[2]) == b.L]
+
+
 def _events():
     import torch
 
@@ -726,11 +752,13 @@ def dcb3d(S, W, L=256, hits=(1, 10, 100), beta=0.22, flips=4e9):
     return {"workload": f"3D Ising {L}^3, beta = {beta}, one lattice, 16^3 tiles", "rows": rows}
 
 
-def sweep3d(S, W, sizes=(256, 512, 1024), beta=0.2216, flips=8e9, models=("ising", "ea")):
+def sweep3d(S, W, sizes=(256, 512, 1024), beta=0.2216, flips=8e9, models=("ising", "ea"), tune=True):
     """Plain 3D checkerboard sweeps (Ising, and EA with one coupling sample)
     on one L^3 lattice: ps per attempted flip for the one-pass segment sweep,
     the two half-sweep launches and the per-site kernels, and the rate at
-    2 B/flip (one read and one write of every spin per sweep) against 8 TB/s."""
+    2 B/flip (one read and one write of every spin per sweep) against 8 TB/s.
+    With tune, smc_autotune first measures the launch shapes of both 3D
+    paths for each lattice (the rows report them)."""
     import os
     import torch
 
@@ -753,6 +781,10 @@ def sweep3d(S, W, sizes=(256, 512, 1024), beta=0.2216, flips=8e9, models=("ising
             S.spin_init(b, spins, coup)
             n = max(2, int(flips // L ** 3) // 2 * 2)  # even: the one-pass sweeps end in the caller's buffer
             row = {"model": "EA" if model == S.EA else "Ising", "L": L, "default": S.sweep_plan(b)[1]}
+            if tune:
+                row["tuned"] = [t for t in autotune_report(S, b, envs=({"SPINMC_SWEEP3D_PASS": "1"},
+                                                                      {"SPINMC_SWEEP3D_PASS": "0"}))
+                                if t["model"] == row["model"] and t["replicas"] == 1]
             for key, env in (("pass", {"SPINMC_SWEEP3D_PASS": "1"}), ("half", {"SPINMC_SWEEP3D_PASS": "0"}),
                              ("per_site", {"SPINMC_SWEEP3D": "0"})):
                 os.environ.update(env)
@@ -1271,6 +1303,8 @@ def main():
                     help="write the kernel-trace summary from a rocprofv3 database and the run's output")
     ap.add_argument("--kt-command", default="", help="command line recorded in the kernel-trace summary")
     ap.add_argument("--valu-summary", metavar="DB", help="write the VALU utilisation summary from a --pmc database")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (no smc_autotune before the measurements)")
     ap.add_argument("--preheat-s", type=float, default=1.0,
                     help="seconds of untimed sweeps of the headline batch before the warm-up sweeps")
     ap.add_argument("--oracle-job", nargs=3, metavar=("KIND", "SECONDS", "INDEX"), help=argparse.SUPPRESS)
@@ -1317,7 +1351,8 @@ def main():
                           "dcb3d": dcb3d(S, W, flips=args.dcb_scan_flips)}))
         return
     if args.sweep3d_only:
-        print(json.dumps({"sweep3d": sweep3d(S, W, sizes=tuple(args.sweep3d_sizes), models=tuple(args.sweep3d_models))}))
+        print(json.dumps({"sweep3d": sweep3d(S, W, sizes=tuple(args.sweep3d_sizes), models=tuple(args.sweep3d_models),
+                                             tune=not args.no_autotune)}))
         return
     if args.heis_dcb_only:
         print(json.dumps({"heis_dcb2d": heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps)}))
@@ -1343,6 +1378,11 @@ def main():
     # replicas: a step is one sweep of all three (one launch).
     nb = len(cfg.betas)
     b = S.Batch(S.ISING, 2, L, nb, cfg.seed)
+    # launch shapes measured for this batch first (untimed; the band height
+    # of the one-pass kernel)
+    t_tune = time.perf_counter()
+    tuned = [] if args.no_autotune else autotune_report(S, b)
+    tune_s = time.perf_counter() - t_tune
     spins = torch.empty(nb * N, dtype=torch.int8, device=dev)
     S.spin_init(b, spins)
     dE = torch.zeros(nb, dtype=torch.int64, device=dev)
@@ -1417,7 +1457,8 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel_us_per_launch": round(launch_ms * 1e3, 3),
                      "conversion_us_per_call": round(conversion_ms * 1e3, 3),
-                     "single_lattice": single, "rng_floor": rng},
+                     "single_lattice": single, "rng_floor": rng,
+                     "autotune": {"seconds": round(tune_s, 3), "shapes": tuned}},
         "wall_s": round(wall, 4),
         "preheat_s": round(preheat_s, 3),
         "preheat_sweeps": pre,
@@ -1434,7 +1475,7 @@ def main():
         out["dcb2d"] = _section("dcb2d", lambda: dcb2d(S, W, args.dcb_sweeps))
         out["dcb_scan"] = _section("dcb_scan", lambda: dcb_scan(S, W, flips=args.dcb_scan_flips))
         out["dcb3d"] = _section("dcb3d", lambda: dcb3d(S, W, flips=args.dcb_scan_flips))
-        out["sweep3d"] = _section("sweep3d", lambda: sweep3d(S, W))
+        out["sweep3d"] = _section("sweep3d", lambda: sweep3d(S, W, tune=not args.no_autotune))
         out["heis_dcb2d"] = _section("heis_dcb2d", lambda: heis_dcb2d(S, W, sweeps=args.heis_dcb_sweeps))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _section("cpu_baseline", cpu_baseline)

@@ -255,12 +255,27 @@ int smc_measure_energy_magnetisation_noalloc(const smc_desc *desc, const void *s
                                              double *magnetisation, void *stream);
 
 /*
- * Autotuning of launch shapes; it never changes results.  For a 2D Ising or
- * EA batch it measures the workgroup size of the LDS-resident 2D kernel
- * (small lattices, uneven tempering) for every edge of the batch that this
- * kernel takes and keeps the choice for later calls in the process (calls
- * that meet an edge first measure it themselves, on copies of their own
- * replicas).  Other batches have nothing to tune (SMC_OK).
+ * Autotuning of launch shapes; it never changes results.  It measures, on
+ * scratch lattices of the batch's shape with random spins, and keeps for
+ * later calls in the process on this device:
+ *  - 2D Ising / EA: the workgroup size of the LDS-resident 2D kernel
+ *    (small lattices, uneven tempering) for every edge of the batch that
+ *    this kernel takes (calls that meet an edge first measure it
+ *    themselves, on copies of their own replicas);
+ *  - uniform 2D Ising with L a power of two in [1024, 16384]: the band
+ *    height of the one-pass sweep (rows per workgroup, 4 .. 128), per edge
+ *    and replica count;
+ *  - uniform 3D Ising / EA with L a multiple of 16: the strip shape of the
+ *    one-pass sweep (rows per strip, segments per thread, planes per z
+ *    segment) where that sweep is taken, else the rows per thread of the
+ *    half-sweeps, per edge, model and replica count.
+ * Each candidate is timed over about 5 ms after an untimed round; a shape
+ * other than the default is kept only if it is more than 2 % faster.
+ * Environment overrides of a shape (SPINMC_L2D_H, SPINMC_PASS3D_*,
+ * SPINMC_SWEEP3D_Z, SPINMC_U2D_THREADS) take precedence, and that shape is
+ * then not measured.  The double checkerboard's tile is an argument of
+ * smc_dcb_sweep (it changes the chain), never a tuned shape.  Other batches
+ * have nothing to tune (SMC_OK, no device work).
  *  cache_path: NULL, or a text file read first (choices recorded for this
  *              device, identified by its architecture name and compute
  *              units, are not measured again) and written afterwards (lines

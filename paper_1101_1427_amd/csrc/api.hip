@@ -15,397 +15,10 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "runtime.hpp"
 
 namespace smc {
-
-thread_local std::string g_launch_rejection;
-
-hipError_t reject_launch(const char *kernel, uint64_t grid, uint64_t block, uint64_t lds, const char *why) {
-    char buf[256];
-    snprintf(buf, sizeof buf, "launch of %s refused (%s): %llu workgroups of %llu, %llu bytes of LDS", kernel, why,
-             (unsigned long long)grid, (unsigned long long)block, (unsigned long long)lds);
-    g_launch_rejection = buf;
-    return hipErrorInvalidConfiguration;
-}
-
-std::string take_launch_rejection() {
-    std::string r;
-    r.swap(g_launch_rejection);
-    return r;
-}
-
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
-
-#define SMC_HIP(call)                                                                                    \
-    do {                                                                                                 \
-        hipError_t e_ = (call);                                                                          \
-        if (e_ != hipSuccess) {                                                                          \
-            const std::string why_ = take_launch_rejection();                                            \
-            return fail(SMC_EHIP, "%s: %s%s%s", #call, hipGetErrorString(e_), why_.empty() ? "" : ": ", \
-                        why_.c_str());                                                                   \
-        }                                                                                                \
-    } while (0)
-
-// ------------------------------------------------------------------ scratch --
-// Device scratch and a pinned staging area, one set per (device, stream):
-// calls on one stream are ordered, so reusing the set between them is safe;
-// calls on different streams never share a set.
-struct Buffer {
-    void *p = nullptr;
-    size_t bytes = 0;
-    // uploaded slots: pinned staging, the event of its last copy, and the
-    // bytes last uploaded (an identical upload is skipped)
-    void *pinned = nullptr;
-    size_t pinned_bytes = 0;
-    hipEvent_t staged = nullptr;
-    bool staged_pending = false;
-    std::vector<unsigned char> last;
-};
-
-enum Slot {
-    kTables = 0,
-    kInst,
-    kSamples,
-    kMeasure,
-    kEnergy64,
-    kRows,
-    kBeta,
-    kPingPong,
-    kCoupSplit,
-    kChunks,
-    kWork,
-    kStep,
-    kTuneSpins,
-    kTuneInst,
-    kTuneWork,
-    kTuneRows,
-    kTuneE,
-    kHeisPing,
-    kL2dPart,
-    kMscSpins,
-    kMscCoup,
-    kMscEnergy,
-    kMscGauge,
-    kDcbSlots,
-    kPtThr,
-    kPtDelta,
-    kPtOut,
-    kBonds3d,    // bit-packed 3D EA bonds of the segment sweep
-    kPass3d,     // second lattice buffer of the one-pass 3D sweep
-    kNumSlots
-};
-
-// An instantiated tempering graph of `steps` steps and the launch arguments
-// it was built from (rebuilt when they change).
-struct GraphCache {
-    std::vector<uint64_t> sig;
-    hipGraphExec_t exec = nullptr;
-};
-
-struct StreamCtx {
-    hipStream_t stream = nullptr;  // the stream whose calls use this set
-    Buffer dev[kNumSlots];
-    GraphCache graphs[2];  // full chunk of steps, remainder
-};
-
-std::mutex g_ctx_mutex;
-std::map<std::pair<int, hipStream_t>, StreamCtx> g_ctx;
-
-StreamCtx &ctx_for(hipStream_t s) {
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    std::lock_guard<std::mutex> lk(g_ctx_mutex);
-    StreamCtx &c = g_ctx[std::make_pair(dev, s)];
-    c.stream = s;
-    return c;
-}
-
-// Device buffer of at least `bytes`.  Only calls on this set's stream use
-// the buffer, so growing waits for that stream (not the whole device)
-// before the old allocation is freed.
-int ensure(StreamCtx &c, Slot slot, size_t bytes, void **out) {
-    Buffer &b = c.dev[slot];
-    if (b.bytes < bytes) {
-        if (b.p) {
-            SMC_HIP(hipStreamSynchronize(c.stream));
-            SMC_HIP(hipFree(b.p));
-            b.p = nullptr;
-            b.bytes = 0;
-        }
-        b.last.clear();
-        size_t want = bytes < 256 ? 256 : bytes;
-        if (hipMalloc(&b.p, want) != hipSuccess) {
-            (void)hipGetLastError();
-            b.p = nullptr;
-            return fail(SMC_ENOMEM, "could not allocate %zu bytes of scratch", want);
-        }
-        b.bytes = want;
-    }
-    *out = b.p;
-    return SMC_OK;
-}
-
-// Copy host bytes into a device scratch slot through that slot's pinned
-// staging area.  The staging area is reused only after its previous copy has
-// completed; an upload identical to the slot's previous one is skipped (the
-// device copy is only ever written by uploads, in stream order).
-int upload(StreamCtx &c, hipStream_t s, Slot slot, const void *src, size_t bytes, void **dev_out) {
-    int rc = ensure(c, slot, bytes, dev_out);
-    if (rc) return rc;
-    Buffer &b = c.dev[slot];
-    if (b.last.size() == bytes && memcmp(b.last.data(), src, bytes) == 0) return SMC_OK;
-    if (b.staged_pending) {
-        SMC_HIP(hipEventSynchronize(b.staged));
-        b.staged_pending = false;
-    }
-    if (b.pinned_bytes < bytes) {
-        if (b.pinned) SMC_HIP(hipHostFree(b.pinned));
-        b.pinned = nullptr;
-        b.pinned_bytes = 0;
-        size_t want = bytes < 4096 ? 4096 : bytes;
-        if (hipHostMalloc(&b.pinned, want, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            b.pinned = nullptr;
-            return fail(SMC_ENOMEM, "could not allocate %zu bytes of pinned staging", want);
-        }
-        b.pinned_bytes = want;
-    }
-    if (!b.staged) SMC_HIP(hipEventCreateWithFlags(&b.staged, hipEventDisableTiming));
-    memcpy(b.pinned, src, bytes);
-    b.last.assign((const unsigned char *)src, (const unsigned char *)src + bytes);
-    SMC_HIP(hipMemcpyAsync(*dev_out, b.pinned, bytes, hipMemcpyHostToDevice, s));
-    SMC_HIP(hipEventRecord(b.staged, s));
-    b.staged_pending = true;
-    return SMC_OK;
-}
-
-// Calls stage host data (tables, instance lists) through pinned buffers,
-// grow their scratch on demand and build graphs of their own; none of that
-// can be recorded into a caller's stream capture, so a call on a capturing
-// stream is refused before anything is issued.
-int refuse_capture(hipStream_t s) {
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    SMC_HIP(hipStreamIsCapturing(s, &cap));
-    if (cap != hipStreamCaptureStatusNone)
-        return fail(SMC_EINVAL, "the stream is capturing a graph: this call cannot be captured");
-    return SMC_OK;
-}
-
-// ----------------------------------------------------------------- tables ----
-// thr[m] = floor(2^32 exp(-4 m beta)) for Delta E = 4m > 0, computed in
-// float64 with the C library's exp and split as (thr >> 16, thr & 0xffff).
-ThrRow threshold_row(double beta, int dim) {
-    ThrRow row;
-    row.m[0] = make_uint2(65536u, 0u);
-    for (int m = 1; m <= 3; ++m) {
-        uint64_t thr = 0;
-        if (m <= dim) {
-            const double p = exp(-beta * (4.0 * m));
-            thr = (uint64_t)floor(4294967296.0 * p);
-        }
-        row.m[m] = make_uint2((uint32_t)(thr >> 16), (uint32_t)(thr & 0xFFFFu));
-    }
-    return row;
-}
-
-// The chain-resident tempering kernel serves 3D edge-16 batches of at most
-// 32 temperatures with 16-byte aligned spins and thresholds below 2^32.
-// Uniform 3D Heisenberg batches with a power-of-two edge take the indexed
-// kernel (SPINMC_HEIS3D=0 sends them to the generic one).
-bool use_heis3d(const smc_desc *d) {
-    const char *env = getenv("SPINMC_HEIS3D");
-    if (env && env[0] == '0') return false;
-    return d->model == SMC_HEISENBERG && d->L > 0 && heis3d_supported(d->dim, d->L);
-}
-
-// ... and with an edge of at least 32 the one-pass tiled kernel
-// (SPINMC_HEIS_TILED=0 keeps the two half-sweep launches).
-bool use_heis3d_tiled(const smc_desc *d) {
-    const char *env = getenv("SPINMC_HEIS_TILED");
-    if (env && env[0] == '0') return false;
-    return use_heis3d(d) && heis3d_tiled_supported(d->dim, d->L);
-}
-
-bool pt3d_enabled() {
-    const char *env = getenv("SPINMC_PT3D");
-    return !(env && env[0] == '0');
-}
-
-bool use_pt3d(const smc_desc *d, const smc_pt_desc *pt, const void *spins, const std::vector<ThrRow> &rows) {
-    if (!pt3d_enabled() || !pt3d_supported(d, pt->n_temps)) return false;
-    if (((uintptr_t)spins & 15u) != 0) return false;
-    for (const ThrRow &r : rows)
-        if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu || r.m[3].x > 0xFFFFu) return false;
-    return true;
-}
-
-// The one-pass split-layout kernel serves uniform 2D Ising batches whose
-// edge it supports, with 16-byte aligned spins and thresholds below 2^32
-// (beta > 0 up to rounding; the generic kernels cover the rest).
-bool use_lattice2d(const smc_desc *d, const void *spins, const std::vector<ThrRow> &rows) {
-    if (d->model != SMC_ISING || d->dim != 2 || d->L <= 0 || !lattice2d_supported(d->L)) return false;
-    if (((uintptr_t)spins & 15u) != 0) return false;
-    for (const ThrRow &r : rows)
-        if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu) return false;
-    return true;
-}
-
-// Uniform 3D Ising / EA batches with an edge that is a multiple of 16 take
-// the segment-per-thread half-sweeps when spins (and couplings) are 16-byte
-// aligned and every threshold has a 16-bit high half; SPINMC_SWEEP3D=0 keeps
-// them on the generic kernels (same results).
-bool sweep3d_shape(const smc_desc *d) {
-    const char *env = getenv("SPINMC_SWEEP3D");
-    if (env && env[0] == '0') return false;
-    return d->dim == 3 && d->L > 0 && (d->model == SMC_ISING || d->model == SMC_EA) && sweep3d_supported(d->L);
-}
-
-// ... and, with an edge of 512 .. 1024, the one-pass sweep (below 512 its
-// strips are too few to fill the chip and the two half-sweep launches are
-// faster; SPINMC_SWEEP3D_PASS=1 takes it for every edge of 32 .. 1024 it
-// supports, SPINMC_SWEEP3D_PASS=0 never).
-bool pass3d_enabled(const smc_desc *d) {
-    const char *env = getenv("SPINMC_SWEEP3D_PASS");
-    if (env && env[0] == '0') return false;
-    if (!(env && env[0] == '1') && d->L < 512) return false;
-    return pass3d_supported(d->L);
-}
-
-bool use_sweep3d(const smc_desc *d, const void *spins, const int8_t *coup, const std::vector<ThrRow> &rows) {
-    if (!sweep3d_shape(d)) return false;
-    if (((uintptr_t)spins & 15u) != 0 || (d->model == SMC_EA && ((uintptr_t)coup & 15u) != 0)) return false;
-    for (const ThrRow &r : rows)
-        if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu || r.m[3].x > 0xFFFFu) return false;
-    return true;
-}
-
-// Tempering of a uniform 2D Ising batch on the one-pass colour-split sweep:
-// L a power of two in [1024, 16384], aligned spins, thresholds of every
-// temperature with 16-bit high halves; SPINMC_PT_SPLIT2D=0 sends such
-// batches to the generic kernels (same results).
-bool use_pt_split2d(const smc_desc *d, const void *spins, const std::vector<ThrRow> &rows) {
-    const char *env = getenv("SPINMC_PT_SPLIT2D");
-    if (env && env[0] == '0') return false;
-    return use_lattice2d(d, spins, rows);
-}
-
-// --------------------------------------------------------------- validation --
-struct Plan {
-    Batch b;
-    int max_L = 0;
-    int64_t n_samples = 0;
-    std::vector<smc_inst> samples;  // distinct samples (EA): L, sample, -, coup_off
-};
-
-int64_t sites(int dim, int L) { return dim == 3 ? (int64_t)L * L * L : (int64_t)L * L; }
-
-// The coupling samples of a uniform EA batch: sample q at q * d * N.
-void fill_uniform_samples(const smc_desc *d, Plan &plan) {
-    if (d->L <= 0 || d->model != SMC_EA || !plan.samples.empty()) return;
-    plan.samples.resize((size_t)plan.n_samples);
-    for (int64_t q = 0; q < plan.n_samples; ++q) {
-        smc_inst &g = plan.samples[(size_t)q];
-        g.L = d->L;
-        g.sample = (int32_t)q;
-        g.spin_off = 0;
-        g.coup_off = q * d->dim * plan.b.N;
-    }
-}
-
-int validate(const smc_desc *d, bool need_coup, Plan &plan) {
-    if (!d) return fail(SMC_EINVAL, "desc is NULL");
-    if (d->model < SMC_ISING || d->model > SMC_HEISENBERG) return fail(SMC_EINVAL, "unknown model %d", d->model);
-    if (d->dim != 2 && d->dim != 3) return fail(SMC_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
-    if (d->n_rep < 1) return fail(SMC_EINVAL, "n_rep must be >= 1 (got %d)", d->n_rep);
-    if (d->spins_len <= 0) return fail(SMC_EINVAL, "spins_len must be > 0");
-    if (d->model == SMC_HEISENBERG && d->renorm_every < 0) return fail(SMC_EINVAL, "renorm_every must be >= 0");
-    const bool ea = d->model == SMC_EA;
-    const int per_site = d->model == SMC_HEISENBERG ? 3 : 1;
-    Batch &b = plan.b;
-    b.dim = d->dim;
-    b.model = d->model;
-    b.n_rep = d->n_rep;
-    b.L = d->L;
-    b.rep_per_sample = 1;
-    b.inst = nullptr;
-    b.N = 0;
-    plan.samples.clear();
-    if (d->L > 0) {
-        if (d->inst) return fail(SMC_EINVAL, "inst must be NULL for a uniform batch (L > 0)");
-        if (d->L % 2 || d->L < 4) return fail(SMC_EINVAL, "L must be even and >= 4 (got %d)", d->L);
-        if (d->L > (d->dim == 3 ? 1024 : 65536)) return fail(SMC_EINVAL, "L too large (got %d)", d->L);
-        b.N = sites(d->dim, d->L);
-        if (b.N / 2 > 0xFFFFFFFFll) return fail(SMC_EINVAL, "lattice too large for 32-bit site counters");
-        plan.max_L = d->L;
-        if ((int64_t)d->n_rep * b.N * per_site > d->spins_len)
-            return fail(SMC_EINVAL, "spin buffer too small: need %lld elements, have %lld",
-                        (long long)((int64_t)d->n_rep * b.N * per_site), (long long)d->spins_len);
-        if (ea) {
-            if (d->rep_per_sample < 1) return fail(SMC_EINVAL, "rep_per_sample must be >= 1 for EA");
-            b.rep_per_sample = d->rep_per_sample;
-            plan.n_samples = (d->n_rep + d->rep_per_sample - 1) / d->rep_per_sample;
-            // the sample table is built only where a path needs it (fill_uniform_samples)
-            if (need_coup) {
-                if (d->coup_len <= 0) return fail(SMC_EINVAL, "coup_len must be > 0 for EA");
-                if (plan.n_samples * d->dim * b.N > d->coup_len)
-                    return fail(SMC_EINVAL, "couplings of sample %lld lie outside the coupling buffer",
-                                (long long)(d->coup_len / (d->dim * b.N)));
-            }
-        }
-    } else {
-        if (!d->inst) return fail(SMC_EINVAL, "inst is required when L == 0");
-        std::map<int32_t, smc_inst> seen;
-        for (int r = 0; r < d->n_rep; ++r) {
-            const smc_inst &g = d->inst[r];
-            if (g.L % 2 || g.L < 4 || g.L > (d->dim == 3 ? 1024 : 65536))
-                return fail(SMC_EINVAL, "inst[%d].L must be even and in [4, limit] (got %d)", r, g.L);
-            const int64_t N = sites(d->dim, g.L);
-            if (g.spin_off < 0 || g.spin_off > d->spins_len / per_site - N)
-                return fail(SMC_EINVAL, "inst[%d] spins lie outside the spin buffer", r);
-            if (ea) {
-                if (g.sample < 0) return fail(SMC_EINVAL, "inst[%d].sample must be >= 0", r);
-                auto it = seen.find(g.sample);
-                if (it == seen.end()) {
-                    seen[g.sample] = g;
-                } else if (it->second.L != g.L || it->second.coup_off != g.coup_off) {
-                    return fail(SMC_EINVAL, "inst[%d]: sample %d used with two geometries", r, g.sample);
-                }
-            }
-            if (g.L > plan.max_L) plan.max_L = g.L;
-        }
-        for (auto &kv : seen) plan.samples.push_back(kv.second);
-        plan.n_samples = (int64_t)plan.samples.size();
-    }
-    if (ea && need_coup && d->L == 0) {
-        if (d->coup_len <= 0) return fail(SMC_EINVAL, "coup_len must be > 0 for EA");
-        for (const smc_inst &g : plan.samples) {
-            const int64_t need = (int64_t)d->dim * sites(d->dim, g.L);
-            if (g.coup_off < 0 || g.coup_off > d->coup_len - need)
-                return fail(SMC_EINVAL, "couplings of sample %d lie outside the coupling buffer", g.sample);
-        }
-    }
-    return SMC_OK;
-}
-
-int upload_inst(StreamCtx &c, hipStream_t s, const smc_desc *d, Plan &plan) {
-    if (d->L > 0) return SMC_OK;
-    void *p = nullptr;
-    int rc = upload(c, s, kInst, d->inst, sizeof(smc_inst) * (size_t)d->n_rep, &p);
-    plan.b.inst = (const smc_inst *)p;
-    return rc;
-}
 
 // ------------------------------------------------ uneven 2D tempering ----
 // Batches of 2D lattices with edges in {16, 32, ..., 256} (uniform or uneven)
@@ -431,110 +44,6 @@ bool use_uneven2d(const smc_desc *d, const void *spins, const int8_t *coup, cons
         if (d->model == SMC_EA && g.coup_off % 16) return false;
     }
     return true;
-}
-
-// Threads per workgroup for an edge, without measurement: about four draw
-// groups per thread and colour, between one and eight waves.
-int uneven2d_threads_default(int L) {
-    const int groups = L * L / 16;
-    int t = 64;
-    while (t < 512 && 4 * t < groups) t <<= 1;
-    return t;
-}
-
-// Autotuned workgroup size per (device, edge, model), measured once per
-// process: the sweep kernel runs on scratch copies of up to 4096 replicas of
-// the edge (enough workgroups to fill the chip) with every candidate size and
-// the fastest is kept.  The choice changes
-// the schedule only, never the results.  SPINMC_U2D_THREADS=n forces n;
-// SPINMC_AUTOTUNE=0 takes the default without measuring.
-std::mutex g_tune_mutex;
-std::map<std::tuple<int, int, int>, int> g_tuned;
-
-int uneven2d_threads(StreamCtx &c, hipStream_t s, const Uneven2dArgs &a, int L, bool ea,
-                     const std::vector<int32_t> &reps, const std::vector<smc_inst> &rows, int *out) {
-    if (const char *f = getenv("SPINMC_U2D_THREADS")) {
-        const int v = atoi(f);
-        if (v == 64 || v == 128 || v == 256 || v == 512) {
-            *out = v;
-            return SMC_OK;
-        }
-    }
-    const char *env = getenv("SPINMC_AUTOTUNE");
-    if (env && env[0] == '0') {
-        *out = uneven2d_threads_default(L);
-        return SMC_OK;
-    }
-    int dev = 0;
-    SMC_HIP(hipGetDevice(&dev));
-    const auto key = std::make_tuple(dev, L, ea ? 1 : 0);
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mutex);
-        auto it = g_tuned.find(key);
-        if (it != g_tuned.end()) {
-            *out = it->second;
-            return SMC_OK;
-        }
-    }
-    // scratch copies of the first replicas of the edge (couplings are read in place)
-    int rc;
-    const int M = (int)std::min<size_t>(reps.size(), 4096);
-    const int64_t N = (int64_t)L * L;
-    void *sp = nullptr, *ip = nullptr, *wp = nullptr, *rp = nullptr, *ep = nullptr;
-    if ((rc = ensure(c, kTuneSpins, (size_t)(M * N), &sp))) return rc;
-    std::vector<smc_inst> tinst(M);
-    std::vector<int32_t> twork(M), trows(M, 0);
-    for (int m = 0; m < M; ++m) {
-        tinst[m] = rows[reps[m]];
-        tinst[m].spin_off = (int64_t)m * N;
-        twork[m] = m;
-    }
-    // one copy per run of replicas that sit back to back in the caller's
-    // array (the temperatures of a chain usually do)
-    for (int m = 0; m < M;) {
-        int e = m + 1;
-        while (e < M && rows[reps[e]].spin_off == rows[reps[e - 1]].spin_off + N) ++e;
-        SMC_HIP(hipMemcpyAsync((int8_t *)sp + (int64_t)m * N, a.spins + rows[reps[m]].spin_off,
-                               (size_t)((int64_t)(e - m) * N), hipMemcpyDeviceToDevice, s));
-        m = e;
-    }
-    if ((rc = upload(c, s, kTuneInst, tinst.data(), sizeof(smc_inst) * M, &ip))) return rc;
-    if ((rc = upload(c, s, kTuneWork, twork.data(), sizeof(int32_t) * M, &wp))) return rc;
-    if ((rc = upload(c, s, kTuneRows, trows.data(), sizeof(int32_t) * M, &rp))) return rc;
-    if ((rc = ensure(c, kTuneE, sizeof(int64_t) * M, &ep))) return rc;
-    Uneven2dArgs t = a;
-    t.spins = (int8_t *)sp;
-    t.inst = (const smc_inst *)ip;
-    t.row_of_rep = (const int32_t *)rp;
-    t.E = (int64_t *)ep;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    SMC_HIP(hipEventCreate(&e0));
-    SMC_HIP(hipEventCreate(&e1));
-    int best = uneven2d_threads_default(L);
-    float best_ms = 1e30f;
-    hipError_t err = hipSuccess;
-    for (int th = 64; th <= 512 && err == hipSuccess; th <<= 1) {
-        err = launch_uneven2d_sweep(t, (const int32_t *)wp, M, L, ea, th, s);  // warm-up
-        if (err == hipSuccess) err = hipEventRecord(e0, s);
-        for (int k = 0; k < 3 && err == hipSuccess; ++k) err = launch_uneven2d_sweep(t, (const int32_t *)wp, M, L, ea, th, s);
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = th;
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (err != hipSuccess) return fail(SMC_EHIP, "autotuning the 2D sweep: %s", hipGetErrorString(err));
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mutex);
-        g_tuned[key] = best;
-    }
-    *out = best;
-    return SMC_OK;
 }
 
 std::vector<smc_inst> inst_rows(const smc_desc *d) {
@@ -845,7 +354,7 @@ const char *smc_strerror(int status) {
     }
 }
 
-const char *smc_last_error(void) { return g_last_error.c_str(); }
+const char *smc_last_error(void) { return last_error().c_str(); }
 
 int smc_kernel_timing_enable(int enable) {
     std::lock_guard<std::mutex> lk(g_timing_mutex);
@@ -856,7 +365,7 @@ int smc_kernel_timing_enable(int enable) {
 
 int smc_philox_bench(uint64_t seed, uint32_t t, uint32_t r, uint32_t tag, int32_t n_threads, int32_t per_thread,
                      uint32_t *out, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     if (!out) return fail(SMC_EINVAL, "out is NULL");
     if (n_threads <= 0 || per_thread <= 0) return fail(SMC_EINVAL, "n_threads and per_thread must be positive");
     if ((int64_t)n_threads * per_thread > (int64_t)1 << 32)
@@ -867,7 +376,7 @@ int smc_philox_bench(uint64_t seed, uint32_t t, uint32_t r, uint32_t tag, int32_
 }
 
 int smc_kernel_timing_read(double *elapsed_ms, int64_t *launches) {
-    g_last_error.clear();
+    last_error().clear();
     if (!elapsed_ms || !launches) return fail(SMC_EINVAL, "output pointers are required");
     std::lock_guard<std::mutex> lk(g_timing_mutex);
     double ms = 0.0;
@@ -891,7 +400,7 @@ int smc_kernel_timing_read(double *elapsed_ms, int64_t *launches) {
 }
 
 int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char **kernel_name) {
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     int rc = validate(desc, false, plan);
     if (rc) return rc;
@@ -923,7 +432,7 @@ int smc_sweep_plan(const smc_desc *desc, int32_t *launches_per_sweep, const char
 
 int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, int32_t *launches,
                 const char **kernel_name) {
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     int rc = validate(desc, false, plan);
     if (rc) return rc;
@@ -974,106 +483,8 @@ int smc_pt_plan(const smc_desc *desc, const smc_pt_desc *pt, int32_t n_steps, in
     return SMC_OK;
 }
 
-// The device's identity in the autotune cache file: architecture and CUs.
-static std::string device_tag(int dev) {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "";
-    std::string arch(p.gcnArchName);
-    for (char &ch : arch)
-        if (ch == ' ') ch = '_';
-    return arch + ":" + std::to_string(p.multiProcessorCount);
-}
-
-int smc_autotune(const smc_desc *desc, const char *cache_path, void *stream) {
-    g_last_error.clear();
-    Plan plan;
-    int rc = validate(desc, false, plan);
-    if (rc) return rc;
-    // the tuned shape: the workgroup size of the LDS-resident 2D kernel per edge
-    if (desc->dim != 2 || (desc->model != SMC_ISING && desc->model != SMC_EA)) return SMC_OK;
-    std::map<int, int> count;  // edge -> replicas
-    for (int r = 0; r < desc->n_rep; ++r) {
-        const int L = desc->L > 0 ? desc->L : desc->inst[r].L;
-        if (uneven2d_edge_supported(L)) ++count[L];
-    }
-    if (count.empty()) return SMC_OK;
-    const bool ea = desc->model == SMC_EA;
-    int dev = 0;
-    SMC_HIP(hipGetDevice(&dev));
-    const std::string tag = device_tag(dev);
-    std::vector<std::string> keep;  // lines of other devices
-    if (cache_path) {
-        FILE *f = fopen(cache_path, "r");
-        if (f) {
-            char line[256];
-            while (fgets(line, sizeof line, f)) {
-                char t[160];
-                int L = 0, e = 0, th = 0;
-                if (line[0] == '#' || sscanf(line, "%159s %d %d %d", t, &L, &e, &th) != 4) continue;
-                if (tag != t) {
-                    keep.emplace_back(line);
-                    continue;
-                }
-                if (uneven2d_edge_supported(L) && (e == 0 || e == 1) &&
-                    (th == 64 || th == 128 || th == 256 || th == 512)) {
-                    std::lock_guard<std::mutex> lk(g_tune_mutex);
-                    g_tuned[std::make_tuple(dev, L, e)] = th;
-                }
-            }
-            fclose(f);
-        }
-    }
-    // measure the edges not known yet, on scratch lattices (all spins up,
-    // ferromagnetic couplings: the sweep's time does not depend on them)
-    hipStream_t s = (hipStream_t)stream;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    SMC_HIP(hipStreamIsCapturing(s, &cap));
-    if (cap != hipStreamCaptureStatusNone) return fail(SMC_EINVAL, "smc_autotune cannot run under stream capture");
-    StreamCtx &c = ctx_for(s);
-    const ThrRow row = threshold_row(0.44, 2);
-    void *tp = nullptr, *st = nullptr;
-    if ((rc = upload(c, s, kTables, &row, sizeof row, &tp))) return rc;
-    if ((rc = ensure(c, kStep, 2 * sizeof(uint32_t), &st))) return rc;
-    SMC_HIP(launch_set_step((uint32_t *)st, 0u, s));
-    for (auto &kv : count) {
-        const int L = kv.first, M = std::min(kv.second, 4096);
-        const int64_t N = (int64_t)L * L;
-        void *sp = nullptr, *cp = nullptr;
-        if ((rc = ensure(c, kPingPong, (size_t)(M * N), &sp))) return rc;
-        SMC_HIP(hipMemsetAsync(sp, 0x01, (size_t)(M * N), s));
-        if (ea) {
-            if ((rc = ensure(c, kCoupSplit, (size_t)(2 * N), &cp))) return rc;
-            SMC_HIP(hipMemsetAsync(cp, 0, (size_t)(2 * N), s));
-        }
-        std::vector<smc_inst> rows(M);
-        std::vector<int32_t> reps(M);
-        for (int m = 0; m < M; ++m) {
-            rows[m] = smc_inst{L, 0, (int64_t)m * N, 0};
-            reps[m] = m;
-        }
-        SMC_HIP(uneven2d_prepare_kernel(ea, L));
-        const Uneven2dArgs a = make_uneven2d_args((int8_t *)sp, nullptr, (const uint8_t *)cp, nullptr,
-                                                  (const ThrRow *)tp, nullptr, (const uint32_t *)st,
-                                                  make_key(desc->seed));
-        int th = 0;
-        if ((rc = uneven2d_threads(c, s, a, L, ea, reps, rows, &th))) return rc;
-    }
-    if (cache_path) {
-        FILE *f = fopen(cache_path, "w");
-        if (!f) return fail(SMC_EINVAL, "cannot write the autotune cache %s", cache_path);
-        fprintf(f, "# spinmc autotune cache: device edge ea threads (workgroup size of the LDS-resident 2D sweep)\n");
-        for (const std::string &l : keep) fputs(l.c_str(), f);
-        std::lock_guard<std::mutex> lk(g_tune_mutex);
-        for (const auto &kv : g_tuned)
-            if (std::get<0>(kv.first) == dev)
-                fprintf(f, "%s %d %d %d\n", tag.c_str(), std::get<1>(kv.first), std::get<2>(kv.first), kv.second);
-        fclose(f);
-    }
-    return SMC_OK;
-}
-
 int smc_spin_init(const smc_desc *desc, void *spins, int8_t *couplings, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     const bool want_coup = desc && desc->model == SMC_EA && couplings;
     int rc = validate(desc, want_coup, plan);
@@ -1126,7 +537,7 @@ bool use_msc2d(const smc_desc *d, const void *spins, const void *coup) {
 
 int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta,
                          uint64_t sweep0, int32_t n_sweeps, int64_t *dE_accum, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     int rc = validate(desc, true, plan);
     if (rc) return rc;
@@ -1301,7 +712,7 @@ int smc_metropolis_sweep(const smc_desc *desc, void *spins, const int8_t *coupli
 
 int smc_msc_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
                   int32_t n_sweeps, int32_t word_bits, int64_t *dE_accum, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     int rc = validate(desc, true, plan);
     if (rc) return rc;
@@ -1423,7 +834,7 @@ static std::vector<ThrRow> dcb_rows(const smc_desc *desc, const double *beta) {
 }
 
 int smc_dcb_plan(const smc_desc *desc, const double *beta, int32_t tile, const char **kernel_name) {
-    g_last_error.clear();
+    last_error().clear();
     if (!kernel_name) return fail(SMC_EINVAL, "kernel_name is NULL");
     int rc = dcb_check(desc, beta, tile);
     if (rc) return rc;
@@ -1436,7 +847,7 @@ int smc_dcb_plan(const smc_desc *desc, const double *beta, int32_t tile, const c
 int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta, uint64_t sweep0,
                   int32_t n_sweeps, int32_t tile, int32_t hits, int32_t palindromic, int64_t *dE_accum,
                   int64_t *dE_trace, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     int rc = dcb_check(desc, beta, tile);
     if (rc) return rc;
     if (hits < 1) return fail(SMC_EINVAL, "hits must be >= 1");
@@ -1488,7 +899,7 @@ int smc_dcb_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, co
 int smc_heis_dcb_sweep(const smc_desc *desc, void *spins, const double *beta, uint64_t sweep0, int32_t n_sweeps,
                        int32_t tile, int32_t hits, int32_t precision, int32_t palindromic, double cap,
                        int64_t *accepts, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     int rc = validate(desc, false, plan);
     if (rc) return rc;
@@ -1563,7 +974,7 @@ static int rng_study_check(const smc_desc *desc, int32_t tile, int32_t generator
 }
 
 int smc_rng_study_state_bytes(const smc_desc *desc, int32_t tile, int32_t generator, int64_t *bytes) {
-    g_last_error.clear();
+    last_error().clear();
     int64_t per = 0;
     int rc = rng_study_check(desc, tile, generator, &per);
     if (rc) return rc;
@@ -1575,7 +986,7 @@ int smc_rng_study_state_bytes(const smc_desc *desc, int32_t tile, int32_t genera
 
 int smc_rng_study_init(const smc_desc *desc, int32_t tile, int32_t generator, void *state, int64_t state_bytes,
                        void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     int64_t per = 0;
     int rc = rng_study_check(desc, tile, generator, &per);
     if (rc) return rc;
@@ -1593,7 +1004,7 @@ int smc_rng_study_init(const smc_desc *desc, int32_t tile, int32_t generator, vo
 int smc_rng_study_sweep(const smc_desc *desc, void *spins, const int8_t *couplings, const double *beta,
                         int32_t n_sweeps, int32_t tile, int32_t hits, int32_t generator, void *state,
                         int64_t state_bytes, int64_t *dE_accum, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     int64_t per = 0;
     int rc = rng_study_check(desc, tile, generator, &per);
     if (rc) return rc;
@@ -1628,7 +1039,7 @@ int smc_rng_study_sweep(const smc_desc *desc, void *spins, const int8_t *couplin
 
 int smc_msc_plan(const smc_desc *desc, int32_t n_sweeps, int32_t word_bits, int32_t *launches,
                  const char **kernel_name) {
-    g_last_error.clear();
+    last_error().clear();
     if (!launches || !kernel_name) return fail(SMC_EINVAL, "output pointers are required");
     Plan plan;
     int rc = validate(desc, false, plan);
@@ -1691,7 +1102,7 @@ int run_pt_split2d(StreamCtx &c, hipStream_t s, const smc_desc *desc, void *spin
 int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, const int8_t *couplings,
                       int32_t *slot_of_temp, double *energy, uint64_t step0, int32_t n_steps,
                       uint64_t *swap_accepts, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     int rc = validate(desc, true, plan);
     if (rc) return rc;
@@ -1797,7 +1208,7 @@ int smc_pt_sweep_swap(const smc_desc *desc, const smc_pt_desc *pt, void *spins, 
 
 int smc_measure_energy_magnetisation(const smc_desc *desc, const void *spins, const int8_t *couplings,
                                      double *energy, double *magnetisation, void *stream) {
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     int rc = validate(desc, true, plan);
     if (rc) return rc;
@@ -1854,7 +1265,7 @@ extern "C" {
 int smc_measure_energy_magnetisation_noalloc(const smc_desc *desc, const void *spins, const int8_t *couplings,
                                              double *energy, double *magnetisation, void *stream) {
     using namespace smc;
-    g_last_error.clear();
+    last_error().clear();
     Plan plan;
     int rc = validate(desc, true, plan);
     if (rc) return rc;

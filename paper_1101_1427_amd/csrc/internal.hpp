@@ -182,6 +182,8 @@ hipError_t launch_dcb_collect(const int64_t *slots, int64_t *dE, int n_rep, int 
 // launch_pack_bonds3d: [sample][L^3 / 16] uint2), the other nullptr.
 bool sweep3d_supported(int L);
 hipError_t launch_pack_bonds3d(const int8_t *coup, uint2 *out, int L, int n_samples, hipStream_t s);
+// Rows per thread along z of the next half-sweep of this batch.
+int sweep3d_rows(int L, bool ea, int n_rep);
 hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, const uint2 *pbonds, int rep_per_sample,
                                const ThrRow *thr, int64_t *dE, int n_rep, int L, Key key, uint32_t t, int c,
                                hipStream_t s);
@@ -228,8 +230,26 @@ hipError_t launch_pt_prepare(const SwapArgs &a, const double *energy_in, hipStre
 hipError_t launch_pt_swap(const SwapArgs &a, hipStream_t s);
 hipError_t launch_pt_finish(const SwapArgs &a, double *energy_out, hipStream_t s);
 
+// ---- tuned launch shapes (tune.hip) ----
+// Launch shapes measured by smc_autotune, per device (the current one),
+// kind, edge, model (0 Ising, 1 EA) and replica count.  The launchers take
+// an environment override first, then a tuned shape, then their default;
+// no shape changes results.
+enum ShapeKind { kShapeBand2d = 0, kShapePass3d = 1, kShapeHalf3d = 2 };
+struct Shape {
+    int v[3];  // band2d: rows per band; pass3d: rows per strip, segments per thread, planes per z segment; half3d: rows per thread
+};
+bool tuned_shape(int kind, int L, int model, int n_rep, Shape *out);
+void set_tuned_shape(int kind, int L, int model, int n_rep, const Shape &s);
+
 // ---- one-pass 3D Ising / EA sweep (pass3d.hip): src and dst distinct ----
 bool pass3d_supported(int L);
+// Whether (rows per strip, segments per thread, planes per z segment) is a
+// launch shape of the one-pass sweep for this edge and model.
+bool pass3d_shape_valid(int L, bool ea, int ty, int segs, int D);
+// The launch shape the next one-pass sweep of this batch takes (false if
+// the edge has none).
+bool pass3d_launch_shape(int L, bool ea, int n_rep, Shape *out);
 hipError_t launch_ising3d_pass(const int8_t *src, int8_t *dst, const uint2 *pbonds, int rep_per_sample,
                                const ThrRow *thr, int64_t *dE, int n_rep, int L, Key key, uint32_t t,
                                hipStream_t s);

@@ -682,9 +682,12 @@ bool lattice2d_supported(int L) { return lattice2d_chunks(L) > 0; }
 // 32 rows per band; a batch with fewer than two such bands per compute unit
 // (a single lattice of L <= 4096) takes lower bands, down to 4 rows, so
 // that every compute unit has work (the halo rows then cost relatively
-// more).  SPINMC_L2D_H forces a height.
+// more).  SPINMC_L2D_H forces a height; a height smc_autotune measured for
+// the edge and replica count comes next.
 int lattice2d_band_height(int L, int n_rep) {
     int H = env_int("SPINMC_L2D_H", 0);
+    Shape tuned;
+    if ((H < 4 || H % 4 || L % H) && tuned_shape(kShapeBand2d, L, 0, n_rep, &tuned)) H = tuned.v[0];
     if (H < 4 || H % 4 || L % H) {
         int cus = 0, dev = 0;
         (void)hipGetDevice(&dev);

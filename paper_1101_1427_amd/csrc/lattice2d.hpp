@@ -11,6 +11,7 @@ namespace smc {
 
 bool lattice2d_supported(int L);
 size_t lattice2d_split_bytes(int L);  // bytes of one replica in the split layout
+int lattice2d_band_height(int L, int n_rep);  // rows per band of the next sweep of this batch
 hipError_t launch_to_split(const int8_t *src, uint8_t *dst, int L, int n_rep, hipStream_t s);
 hipError_t launch_from_split(const uint8_t *src, int8_t *dst, int L, int n_rep, hipStream_t s);
 // One sweep from src to dst (distinct buffers).  Each is either the split

@@ -370,40 +370,70 @@ int pass3d_threads(int L, int ty, int segs) {
     return 2 * ((per_class + 63) / 64 * 64);
 }
 
+// Whether a launch shape fits: ty and D divide L, at most two segments per
+// thread dividing the row's segments, the workgroup within the kernel's
+// bound, and no EA kernel of 16 rows with two segments (it would not fit its
+// registers).
+bool shape_fits(int L, bool ea, int ty, int segs, int D, int *threads) {
+    if (L < 32 || L > 1024 || L % 16 || (ty != 8 && ty != 16) || (segs != 1 && segs != 2)) return false;
+    if ((L / 16) % segs || (ea && ty == 16 && segs == 2)) return false;
+    if ((D != 16 && D != 32 && D != 64 && D != 128) || D > L || L % D || L % ty) return false;
+    *threads = pass3d_threads(L, ty, segs);
+    return *threads <= pass3d_max_threads(ty, segs);
+}
+
 // Launch shape for an edge: rows per strip, segments per thread, planes per
 // z segment, workgroup size; false if the edge has none.  SPINMC_PASS3D_TY
 // (8 or 16), SPINMC_PASS3D_SEGS (1 or 2) and SPINMC_PASS3D_D (16, 32, 64 or
-// 128) override the first three; results never depend on them.
-bool pass3d_shape(int L, bool ea, int *ty, int *segs, int *D, int *threads) {
+// 128) override the first three; without them a shape smc_autotune
+// measured for the edge, model and replica count is taken.  Results never
+// depend on the shape.
+bool pass3d_shape(int L, bool ea, int n_rep, int *ty, int *segs, int *D, int *threads) {
     if (L < 32 || L > 1024 || L % 16) return false;
+    const char *ety = getenv("SPINMC_PASS3D_TY"), *esegs = getenv("SPINMC_PASS3D_SEGS"),
+               *ed = getenv("SPINMC_PASS3D_D");
+    Shape t;
+    if (!(ety || esegs || ed) && tuned_shape(kShapePass3d, L, ea ? 1 : 0, n_rep, &t) &&
+        shape_fits(L, ea, t.v[0], t.v[1], t.v[2], threads)) {
+        *ty = t.v[0];
+        *segs = t.v[1];
+        *D = t.v[2];
+        return true;
+    }
     *ty = L >= 1024 ? 8 : 16;
     *segs = 1;
-    const char *e = getenv("SPINMC_PASS3D_TY");
-    if (e && (atoi(e) == 8 || atoi(e) == 16)) *ty = atoi(e);
-    e = getenv("SPINMC_PASS3D_SEGS");
-    if (e && (atoi(e) == 1 || atoi(e) == 2)) *segs = atoi(e);
+    if (ety && (atoi(ety) == 8 || atoi(ety) == 16)) *ty = atoi(ety);
+    if (esegs && (atoi(esegs) == 1 || atoi(esegs) == 2)) *segs = atoi(esegs);
     if ((L / 16) % *segs) *segs = 1;
     if (*segs == 1 && pass3d_threads(L, *ty, 1) > pass3d_max_threads(*ty, 1) && (L / 16) % 2 == 0) *segs = 2;
     if (ea && *ty == 16 && *segs == 2) *ty = 8;  // the EA kernel of that shape would not fit its registers
     *D = L >= 1024 ? 128 : L >= 512 ? 32 : 16;
-    e = getenv("SPINMC_PASS3D_D");
-    if (e && (atoi(e) == 16 || atoi(e) == 32 || atoi(e) == 64 || atoi(e) == 128)) *D = atoi(e);
-    *threads = pass3d_threads(L, *ty, *segs);
-    return L % *D == 0 && L % *ty == 0 && *threads <= pass3d_max_threads(*ty, *segs);
+    if (ed && (atoi(ed) == 16 || atoi(ed) == 32 || atoi(ed) == 64 || atoi(ed) == 128)) *D = atoi(ed);
+    return shape_fits(L, ea, *ty, *segs, *D, threads);
 }
 
 }  // namespace
 
 bool pass3d_supported(int L) {
     int ty, segs, D, threads;
-    return pass3d_shape(L, false, &ty, &segs, &D, &threads) && pass3d_shape(L, true, &ty, &segs, &D, &threads);
+    return pass3d_shape(L, false, 1, &ty, &segs, &D, &threads) && pass3d_shape(L, true, 1, &ty, &segs, &D, &threads);
+}
+
+bool pass3d_launch_shape(int L, bool ea, int n_rep, Shape *out) {
+    int threads;
+    return pass3d_shape(L, ea, n_rep, &out->v[0], &out->v[1], &out->v[2], &threads);
+}
+
+bool pass3d_shape_valid(int L, bool ea, int ty, int segs, int D) {
+    int threads;
+    return shape_fits(L, ea, ty, segs, D, &threads);
 }
 
 hipError_t launch_ising3d_pass(const int8_t *src, int8_t *dst, const uint2 *pbonds, int rep_per_sample,
                                const ThrRow *thr, int64_t *dE, int n_rep, int L, Key key, uint32_t t,
                                hipStream_t s) {
     int ty, segs, D, threads;
-    if (n_rep < 1 || src == dst || !pass3d_shape(L, pbonds != nullptr, &ty, &segs, &D, &threads))
+    if (n_rep < 1 || src == dst || !pass3d_shape(L, pbonds != nullptr, n_rep, &ty, &segs, &D, &threads))
         return hipErrorInvalidValue;
     Pass3dArgs a;
     a.src = src;

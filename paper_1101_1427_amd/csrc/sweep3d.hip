@@ -177,21 +177,6 @@ bool sweep3d_supported(int L) { return L >= 16 && L % 16 == 0; }
 
 namespace {
 
-// Rows per thread along z: Z rows fetch Z + 2 row segments of every column
-// instead of 3 Z, so a launch reads the lattice (Z + 2) / Z times.  Z = 4
-// (the default) runs the Ising sweep at 512^3 and 1024^3 about 20 % faster
-// than Z = 1; 8 and 16 fetch less but leave fewer threads and are no
-// faster.  SPINMC_SWEEP3D_Z = 1, 2, 4, 8 or 16 sets it; non-temporal stores
-// of the updated segments are on unless SPINMC_SWEEP3D_NT = 0.
-int sweep3d_rows() {
-    const char *env = getenv("SPINMC_SWEEP3D_Z");
-    if (env && env[0]) {
-        const int z = atoi(env);
-        if (z == 1 || z == 2 || z == 4 || z == 8 || z == 16) return z;
-    }
-    return 4;
-}
-
 bool sweep3d_nt() {
     const char *env = getenv("SPINMC_SWEEP3D_NT");
     return !(env && env[0] == '0');
@@ -217,6 +202,27 @@ hipError_t launch_model(int Z, bool nt, unsigned blocks, const Sweep3dArgs &a, h
 
 }  // namespace
 
+// Rows per thread along z: Z rows fetch Z + 2 row segments of every column
+// instead of 3 Z, so a launch reads the lattice (Z + 2) / Z times.  Z = 4
+// (the default) runs the Ising sweep at 512^3 and 1024^3 about 20 % faster
+// than Z = 1; 8 and 16 fetch less but leave fewer threads and are no
+// faster.  SPINMC_SWEEP3D_Z = 1, 2, 4, 8 or 16 sets it, else a value
+// smc_autotune measured for the edge, model and replica count; non-temporal
+// stores of the updated segments are on unless SPINMC_SWEEP3D_NT = 0.
+int sweep3d_rows(int L, bool ea, int n_rep) {
+    const char *env = getenv("SPINMC_SWEEP3D_Z");
+    if (env && env[0]) {
+        const int z = atoi(env);
+        if (z == 1 || z == 2 || z == 4 || z == 8 || z == 16) return z;
+    }
+    Shape t;
+    if (tuned_shape(kShapeHalf3d, L, ea ? 1 : 0, n_rep, &t)) {
+        const int z = t.v[0];
+        if (z == 1 || z == 2 || z == 4 || z == 8 || z == 16) return z;
+    }
+    return 4;
+}
+
 hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, const uint2 *pbonds, int rep_per_sample,
                                const ThrRow *thr, int64_t *dE, int n_rep, int L, Key key, uint32_t t, int c,
                                hipStream_t s) {
@@ -224,7 +230,7 @@ hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, const uint2 *p
     // a replica's (L / 16)^3 workgroups of one-row threads regroup into whole
     // workgroups of Z-row threads when Z divides (L / 16)^3
     const int B = L / 16;
-    int Z = sweep3d_rows();
+    int Z = sweep3d_rows(L, coup != nullptr || pbonds != nullptr, n_rep);
     while ((B * B * B) % Z) Z >>= 1;
     const int64_t threads = (int64_t)L * L * L / (16 * Z);  // per replica
     Sweep3dArgs a;

@@ -224,12 +224,15 @@ def test_heis_dcb_arguments_are_validated():
 
 
 def test_autotune_has_nothing_to_tune_for_other_batches(tmp_path):
-    """3D, Heisenberg and large-edge batches: SMC_OK, no device work, no file."""
+    """Batches none of whose kernels has a launch shape to tune (Heisenberg,
+    edges that take the generic kernels, the 2D Ising edge 1000 between the
+    LDS-resident and the one-pass kernels): SMC_OK, no device work, no file."""
     L = S.lib()
     path = str(tmp_path / "tune.txt").encode()
-    for d in (_desc(dim=3, L=16, n_rep=2, spins_len=2 * 16 ** 3),
+    for d in (_desc(dim=3, L=20, n_rep=2, spins_len=2 * 20 ** 3),
               _desc(model=S.HEISENBERG, L=32, n_rep=1, spins_len=3 * 32 * 32),
-              _desc(L=1024, n_rep=1, spins_len=1024 * 1024)):
+              _desc(model=S.HEISENBERG, dim=3, L=64, n_rep=1, spins_len=3 * 64 ** 3),
+              _desc(L=1000, n_rep=1, spins_len=1000 * 1000)):
         assert L.smc_autotune(C.byref(d), path, None) == S.OK
     assert not (tmp_path / "tune.txt").exists()
     assert L.smc_autotune(None, path, None) == S.EINVAL
