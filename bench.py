@@ -32,10 +32,10 @@ BYTES_PER_FLIP = 2.0  # int8 spin read once and written once per sweep
 
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = {
-    "k_ising2d_split": ("lattice2d.hip", "lattice2d.hpp", "philox.hpp", "tables.hpp"),
+    "k_ising2d_split": ("lattice2d.hip", "lattice2d.hpp", "intrin.hpp", "philox.hpp", "tables.hpp"),
     "k_heis3d_tiled": ("heis3d.hip", "heis_math.hpp", "philox.hpp"),
-    "k_ising3d_half": ("sweep3d.hip", "segment3d.hpp", "philox.hpp", "tables.hpp"),
-    "k_ising3d_pass": ("pass3d.hip", "segment3d.hpp", "philox.hpp", "tables.hpp"),
+    "k_ising3d_half": ("sweep3d.hip", "segment3d.hpp", "intrin.hpp", "philox.hpp", "tables.hpp"),
+    "k_ising3d_pass": ("pass3d.hip", "segment3d.hpp", "intrin.hpp", "philox.hpp", "tables.hpp"),
 }
 
 

@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include "internal.hpp"
+#include "intrin.hpp"
 
 namespace smc {
 namespace {
@@ -28,22 +29,6 @@ namespace {
 constexpr int kMaxThreads = 512;
 constexpr int kBatch = 8;  // 16-byte spin loads in flight per thread while staging a replica
 
-__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
-    return __builtin_amdgcn_perm(hi, lo, sel);
-}
-__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) {
-    return __builtin_amdgcn_alignbyte(hi, lo, s);
-}
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
-__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
-__device__ __forceinline__ uint32_t sub_sat16(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_sub_sat(as_u16x2(a), as_u16x2(b)));
-}
-__device__ __forceinline__ uint32_t sub16(uint32_t a, uint32_t b) { return as_u32(as_u16x2(a) - as_u16x2(b)); }
-__device__ __forceinline__ uint32_t min16(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_min(as_u16x2(a), as_u16x2(b)));
-}
 
 // Thresholds by the number n of unsatisfied bonds (Delta E = 8 - 4n): n = 0
 // and 1 take the high halves of thr[2] and thr[1]; n >= 2 is always accepted

@@ -16,6 +16,7 @@
 // eight in-colour sites of one such block (16 consecutive columns of a tile
 // row), so T is a multiple of 16.
 #include "internal.hpp"
+#include "intrin.hpp"
 
 namespace smc {
 namespace {
@@ -153,24 +154,6 @@ __global__ __launch_bounds__(kDcbMaxThreads) void k_dcb2d(DcbArgs a) {
 // number n of unsatisfied bonds gives dE = 8 - 4n; the head is compared with
 // the high half of thr(n) by packed 16-bit saturating subtraction; heads
 // equal to it take the exact path with the 16-bit tail.
-typedef unsigned short dcb_u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint32_t dcb_pk_sub_sat(uint32_t a, uint32_t b) {
-    return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(dcb_u16x2, a),
-                                                                      __builtin_bit_cast(dcb_u16x2, b)));
-}
-__device__ __forceinline__ uint32_t dcb_pk_sub(uint32_t a, uint32_t b) {
-    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(dcb_u16x2, a) - __builtin_bit_cast(dcb_u16x2, b));
-}
-__device__ __forceinline__ uint32_t dcb_pk_min(uint32_t a, uint32_t b) {
-    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(dcb_u16x2, a),
-                                                                  __builtin_bit_cast(dcb_u16x2, b)));
-}
-__device__ __forceinline__ uint32_t dcb_perm(uint32_t hi, uint32_t lo, uint32_t sel) {
-    return __builtin_amdgcn_perm(hi, lo, sel);
-}
-__device__ __forceinline__ uint32_t dcb_align(uint32_t hi, uint32_t lo, uint32_t sh) {
-    return __builtin_amdgcn_alignbyte(hi, lo, sh);
-}
 
 template <int T>
 struct DcbGeom {
@@ -197,19 +180,19 @@ struct DcbLut {
 // heads wa (sites 0, 1), wb (sites 2, 3); eq collects head - T(n).
 __device__ __forceinline__ uint32_t dcb_decide4(uint32_t n, uint32_t wa, uint32_t wb, const DcbLut &K,
                                                 uint32_t &eq) {
-    const uint32_t tl = dcb_perm(0xFFFFFFFFu, K.tlo, n);
-    const uint32_t th = dcb_perm(0xFFFFFFFFu, K.thi, n);
-    const uint32_t ta = dcb_perm(th, tl, 0x05010400u);
-    const uint32_t tb = dcb_perm(th, tl, 0x07030602u);
-    const uint32_t ra = dcb_pk_min(dcb_pk_sub_sat(ta, wa), K.one2);
-    const uint32_t rb = dcb_pk_min(dcb_pk_sub_sat(tb, wb), K.one2);
-    eq = dcb_pk_min(eq, dcb_pk_min(dcb_pk_sub(ta, wa), dcb_pk_sub(tb, wb)));
-    return dcb_perm(rb, ra, 0x06040200u);
+    const uint32_t tl = perm(0xFFFFFFFFu, K.tlo, n);
+    const uint32_t th = perm(0xFFFFFFFFu, K.thi, n);
+    const uint32_t ta = perm(th, tl, 0x05010400u);
+    const uint32_t tb = perm(th, tl, 0x07030602u);
+    const uint32_t ra = min16(sub_sat16(ta, wa), K.one2);
+    const uint32_t rb = min16(sub_sat16(tb, wb), K.one2);
+    eq = min16(eq, min16(sub16(ta, wa), sub16(tb, wb)));
+    return perm(rb, ra, 0x06040200u);
 }
 
 // Bytes 0, 2 (sel 0x06040200) or 1, 3 (sel 0x07050301) of two words.
 __device__ __forceinline__ uint32_t dcb_pick(uint32_t hi, uint32_t lo, int odd) {
-    return dcb_perm(hi, lo, odd ? 0x07050301u : 0x06040200u);
+    return perm(hi, lo, odd ? 0x07050301u : 0x06040200u);
 }
 // +1 / -1 bytes to 0 / 1 bytes.
 __device__ __forceinline__ uint32_t dcb_bits(uint32_t w) { return (w >> 7) & 0x01010101u; }
@@ -326,7 +309,7 @@ __global__ __launch_bounds__(DcbGeom<T>::THREADS) void k_dcb2d_packed(DcbPackedA
             const uint32_t xe[2] = {dcb_pick(x1b, x0b, 0), dcb_pick(x3b, x2b, 0)};
             const uint32_t xo[2] = {dcb_pick(x1b, x0b, 1), dcb_pick(x3b, x2b, 1)};
             // bonds to x - 1 of the even columns: bytes -1, 1, 3, ... of the +x bonds
-            const uint32_t xl[2] = {dcb_align(xo[0], prev, 3), dcb_align(xo[1], xo[0], 3)};
+            const uint32_t xl[2] = {alignbyte(xo[0], prev, 3), alignbyte(xo[1], xo[0], 3)};
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const int p = (v + c) & 1;  // own sites at odd columns of the segment
@@ -374,14 +357,14 @@ __global__ __launch_bounds__(DcbGeom<T>::THREADS) void k_dcb2d_packed(DcbPackedA
         const uint32_t E = *(const uint32_t *)(pl + ((P == 2 ? p : P) ? re_off : le_off));
         uint32_t s0, s1;
         if constexpr (P == 0) {
-            s0 = dcb_align(hz[0], E, 3);
-            s1 = dcb_align(hz[1], hz[0], 3);
+            s0 = alignbyte(hz[0], E, 3);
+            s1 = alignbyte(hz[1], hz[0], 3);
         } else if constexpr (P == 1) {
-            s0 = dcb_align(hz[1], hz[0], 1);
-            s1 = dcb_align(E, hz[1], 1);
+            s0 = alignbyte(hz[1], hz[0], 1);
+            s1 = alignbyte(E, hz[1], 1);
         } else {
-            s0 = p ? dcb_align(hz[1], hz[0], 1) : dcb_align(hz[0], E, 3);
-            s1 = p ? dcb_align(E, hz[1], 1) : dcb_align(hz[1], hz[0], 3);
+            s0 = p ? alignbyte(hz[1], hz[0], 1) : alignbyte(hz[0], E, 3);
+            s1 = p ? alignbyte(E, hz[1], 1) : alignbyte(hz[1], hz[0], 3);
         }
         const uint32_t uu[2] = {U.x, U.y}, dd[2] = {D.x, D.y}, ss[2] = {s0, s1};
         uint32_t n[2], F[2];
@@ -429,7 +412,7 @@ __global__ __launch_bounds__(DcbGeom<T>::THREADS) void k_dcb2d_packed(DcbPackedA
         for (int i = 0; i < 2; ++i) {
             own[i] ^= F[i];
             // per site dE/4 + 2: 2 when kept, 4 - n when flipped (n >= 2 always flips)
-            de += dcb_perm(0x01020304u, 0x02020202u, (F[i] << 2) + n[i]);
+            de += perm(0x01020304u, 0x02020202u, (F[i] << 2) + n[i]);
         }
         de_bytes = __builtin_amdgcn_sad_u8(de, 0u, de_bytes);
         *(uint2 *)(tl + C * PLANE + row_off + 8 * seg) = make_uint2(own[0], own[1]);
@@ -467,10 +450,10 @@ __global__ __launch_bounds__(DcbGeom<T>::THREADS) void k_dcb2d_packed(DcbPackedA
         const uint32_t e0 = pe ? sp1[0] : sp0[0], e1 = pe ? sp1[1] : sp0[1];
         const uint32_t o0 = pe ? sp0[0] : sp1[0], o1 = pe ? sp0[1] : sp1[1];
         uint4 q;
-        q.x = dcb_perm(0u, 0x0000FF01u, dcb_perm(o0, e0, 0x05010400u));
-        q.y = dcb_perm(0u, 0x0000FF01u, dcb_perm(o0, e0, 0x07030602u));
-        q.z = dcb_perm(0u, 0x0000FF01u, dcb_perm(o1, e1, 0x05010400u));
-        q.w = dcb_perm(0u, 0x0000FF01u, dcb_perm(o1, e1, 0x07030602u));
+        q.x = perm(0u, 0x0000FF01u, perm(o0, e0, 0x05010400u));
+        q.y = perm(0u, 0x0000FF01u, perm(o0, e0, 0x07030602u));
+        q.z = perm(0u, 0x0000FF01u, perm(o1, e1, 0x05010400u));
+        q.w = perm(0u, 0x0000FF01u, perm(o1, e1, 0x07030602u));
         *(uint4 *)(S + (int64_t)y * L + x) = q;
     }
     if (a.dE_slots) {

@@ -36,33 +36,17 @@
 #include <stdlib.h>
 
 #include "internal.hpp"
+#include "intrin.hpp"
 #include "lattice2d.hpp"
 
 namespace smc {
 namespace {
 
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
-__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
-// packed 16-bit helpers (v_pk_sub_u16 clamp, v_pk_sub_u16, v_pk_min_u16)
-__device__ __forceinline__ uint32_t pk_sub_sat_u16(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_sub_sat(as_u16x2(a), as_u16x2(b)));
-}
-__device__ __forceinline__ uint32_t pk_sub_u16(uint32_t a, uint32_t b) { return as_u32(as_u16x2(a) - as_u16x2(b)); }
-__device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_min(as_u16x2(a), as_u16x2(b)));
-}
-__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
-    return __builtin_amdgcn_perm(hi, lo, sel);
-}
 // (a ^ b) + c in one v_xad_u32 (register operands only, no memory access).
 __device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) {
     uint32_t d;
     asm("v_xad_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
     return d;
-}
-__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) {
-    return __builtin_amdgcn_alignbyte(hi, lo, s);
 }
 
 // Per-replica constants of the decision.
@@ -164,9 +148,9 @@ __device__ __forceinline__ uint32_t decide4(uint32_t n, uint32_t wa, uint32_t wb
     const uint32_t th = perm(K.thi_hi, K.thi_lo, n);
     const uint32_t ta = perm(th, tl, 0x05010400u);
     const uint32_t tb = perm(th, tl, 0x07030602u);
-    const uint32_t ra = pk_min_u16(pk_sub_sat_u16(ta, wa), K.one2);
-    const uint32_t rb = pk_min_u16(pk_sub_sat_u16(tb, wb), K.one2);
-    eq = pk_min_u16(eq, pk_min_u16(pk_sub_u16(ta, wa), pk_sub_u16(tb, wb)));
+    const uint32_t ra = min16(sub_sat16(ta, wa), K.one2);
+    const uint32_t rb = min16(sub_sat16(tb, wb), K.one2);
+    eq = min16(eq, min16(sub16(ta, wa), sub16(tb, wb)));
     return perm(rb, ra, 0x06040200u);
 }
 

@@ -61,8 +61,6 @@ using namespace seg3d;
 constexpr int kRing = 3;                // staged planes
 constexpr uint32_t kOob = 0x40000000u;  // a byte offset past every lattice (L^3 <= 2^30)
 
-typedef uint32_t v2u __attribute__((ext_vector_type(2)));
-
 struct Pass3dArgs {
     const int8_t *src;     // replica r at r * L^3 (read)
     int8_t *dst;           // replica r at r * L^3 (written)

@@ -18,6 +18,7 @@
 // other array of the same row (shifted by one byte with wrap-around), its y
 // and z neighbours the same array of the four adjacent rows.
 #include "internal.hpp"
+#include "intrin.hpp"
 
 namespace smc {
 namespace {
@@ -49,22 +50,6 @@ struct Pt3dArgs {
     uint32_t four;  // 4 (opaque trip count of the rarely taken exact-decision loop)
 };
 
-__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
-    return __builtin_amdgcn_perm(hi, lo, sel);
-}
-__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) {
-    return __builtin_amdgcn_alignbyte(hi, lo, s);
-}
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
-__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
-__device__ __forceinline__ uint32_t sub_sat16(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_sub_sat(as_u16x2(a), as_u16x2(b)));
-}
-__device__ __forceinline__ uint32_t sub16(uint32_t a, uint32_t b) { return as_u32(as_u16x2(a) - as_u16x2(b)); }
-__device__ __forceinline__ uint32_t min16(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_min(as_u16x2(a), as_u16x2(b)));
-}
 
 // Threshold table of one temperature for the byte-parallel decision: the
 // high 16 bits of the threshold for n unsatisfied bonds (n = 0, 1, 2 give

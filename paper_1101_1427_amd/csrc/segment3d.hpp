@@ -14,27 +14,10 @@
 // decision.
 #pragma once
 #include "internal.hpp"
+#include "intrin.hpp"
 
 namespace smc {
 namespace seg3d {
-
-__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
-    return __builtin_amdgcn_perm(hi, lo, sel);
-}
-__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) {
-    return __builtin_amdgcn_alignbyte(hi, lo, s);
-}
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
-__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
-__device__ __forceinline__ uint32_t sub_sat16(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_sub_sat(as_u16x2(a), as_u16x2(b)));
-}
-__device__ __forceinline__ uint32_t sub16(uint32_t a, uint32_t b) { return as_u32(as_u16x2(a) - as_u16x2(b)); }
-__device__ __forceinline__ uint32_t min16(uint32_t a, uint32_t b) {
-    return as_u32(__builtin_elementwise_min(as_u16x2(a), as_u16x2(b)));
-}
 
 // +-1 bytes (0x01 / 0xFF) to bits 0 / 1, four per word (bond packing).
 __device__ __forceinline__ uint32_t bits(uint32_t v) { return (v >> 1) & 0x01010101u; }
