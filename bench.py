@@ -216,7 +216,7 @@ def short_name(name: str) -> str:
 
 
 def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, kernel: str, L: int,
-                commands: list[str]):
+                commands: list[str], grid_rule: str = "most"):
     """kernel k_ising2d_split: one launch sweeps the bench's batch of three
     L x L lattices; k_heis3d_tiled: one launch sweeps one L^3 lattice."""
     """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the sweep kernel and
@@ -224,19 +224,30 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
     that traffic_per_launch reads."""
     import sqlite3
 
-    def per_kernel(db, counter, largest_grid=False):
+    def per_kernel(db, counter, main_grid=False):
         con = sqlite3.connect(db)
         rows = con.execute("select kernel_name, value, grid_size from counters_collection where counter_name=?",
                            (counter,)).fetchall()
-        biggest = {}
+        # per kernel instantiation, its grid with the most dispatches (the
+        # timed batch's launches, not the single-lattice launches the same
+        # run makes afterwards nor the launch shapes the autotuner tries), or
+        # with grid_rule "largest" its largest grid (the largest lattice of a
+        # run that sweeps several)
+        count = {}
         for name, _, grid in rows:
-            biggest[name] = max(biggest.get(name, 0), grid)
+            count[(name, grid)] = count.get((name, grid), 0) + 1
+        main = {}
+        for (name, grid), n in count.items():
+            if grid_rule == "largest":
+                if name not in main or grid > main[name]:
+                    main[name] = grid
+            elif name not in main or n > count[(name, main[name])]:
+                main[name] = grid
         acc = {}
         for name, val, grid in rows:
-            # the batched launch only, not the single-lattice launches the
-            # same run makes afterwards
-            if not largest_grid or grid == biggest[name]:
+            if not main_grid or grid == main[name]:
                 acc.setdefault(name, []).append(val)
+        per_kernel.grids = main
         return acc
 
     def mean_of(acc, key):
@@ -247,7 +258,9 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
         return name, sum(acc[name]) / len(acc[name])
 
     kf, kfv = mean_of(per_kernel(fetch_db, "FETCH_SIZE", True), kernel)
+    fetch_grid = per_kernel.grids[kf]
     kw, kwv = mean_of(per_kernel(write_db, "WRITE_SIZE", True), kernel)
+    write_grid = per_kernel.grids[kw]
     # the copy kernel: the one that fetched the most; its sums over the run
     # divided by the number of 1 GiB copies
     cf_all, cw_all = per_kernel(cfetch_db, "FETCH_SIZE"), per_kernel(cwrite_db, "WRITE_SIZE")
@@ -273,10 +286,13 @@ def pmc_summary(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str, ke
         algorithmic = BYTES_PER_FLIP * L * L * 3
         what = f"one launch = one sweep of a batch of three 2D Ising {L}x{L} lattices"
     lines = [f"# rocprofv3 --pmc summary: {kernel}, {what}",
-             "# figures are means per dispatch of the counter over the kernel's dispatches of its largest grid "
-             "(the batched launch) in the run"]
+             "# figures are means per dispatch of the counter over the dispatches of the kernel's instantiation and "
+             + ("grid with the most dispatches in the run (the timed batch)" if grid_rule == "most" else
+                "largest grid in the run (the largest lattice)")]
     lines += [f"# command: {c}" for c in commands]
     lines += [f"kernel_source_sha256: {kernel_source_hash(kernel)}",
+              f"kernel_dispatches: {short_name(kf)} grid {fetch_grid} (FETCH_SIZE run), grid {write_grid} "
+              f"(WRITE_SIZE run)",
               f"kernel_FETCH_SIZE_KiB_per_dispatch: {kfv:.1f}",
               f"kernel_WRITE_SIZE_KiB_per_dispatch: {kwv:.1f}",
               f"copy_kernel: {short_name(copy_name)}",
@@ -1144,6 +1160,14 @@ def heisenberg3d(S, W, sweeps):
     b = S.Batch(S.HEISENBERG, 3, L, 1, cfg.seed, renorm_every=cfg.renorm_every)
     spins = torch.zeros(3 * N, dtype=torch.float32, device="cuda")
     S.spin_init(b, spins)
+    # half a second of untimed sweeps of a scratch copy first, so that the
+    # timed sweeps do not start on a cold chip (this section can run alone)
+    warm = spins.clone()
+    t_end = time.perf_counter() + 0.5
+    while time.perf_counter() < t_end:
+        S.metropolis_sweep(b, warm, [cfg.betas[0]], 0, 16)
+        torch.cuda.synchronize()
+    del warm
     S.metropolis_sweep(b, spins, [cfg.betas[0]], 0, 2)
     S.kernel_timing_read()
     S.kernel_timing_enable(True)
@@ -1297,6 +1321,8 @@ def main():
                     help="only run a plain 1 GiB device copy (counter scale for the traffic figure)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
                     help="write the traffic summary of the sweep kernel from rocprofv3 counter databases")
+    ap.add_argument("--pmc-grid", choices=["most", "largest"], default="most",
+                    help="dispatches of the --pmc-summary: the grid with the most dispatches, or the largest grid")
     ap.add_argument("--pmc-command", action="append", default=[],
                     help="command line recorded in the traffic summary (repeatable)")
     ap.add_argument("--kt-summary", nargs=2, metavar=("KT_DB", "KT_LOG"),
@@ -1324,7 +1350,7 @@ def main():
     if args.pmc_summary:
         pmc_L = kernel_L
         pmc_summary(*args.pmc_summary, kernel=args.pmc_kernel, L=pmc_L,
-                    commands=args.pmc_command)
+                    commands=args.pmc_command, grid_rule=args.pmc_grid)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",

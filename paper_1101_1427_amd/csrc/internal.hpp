@@ -1,4 +1,4 @@
-// Internal interfaces between the C-ABI layer (api.hip) and the kernels.
+// Internal interfaces between the C-ABI layer (api.hip, runtime.hip, tune.hip) and the kernels.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
