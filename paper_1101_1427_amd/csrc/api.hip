@@ -800,7 +800,7 @@ static bool use_dcb_packed(const smc_desc *d, const std::vector<ThrRow> &rows, c
     const char *env = getenv("SPINMC_DCB_PACKED");
     if (env && env[0] == '0') return false;
     if (d->dim != 2 || !dcb2d_packed_supported(d->L, tile)) return false;
-    if (((uintptr_t)spins & 15u) || ((uintptr_t)coup & 15u)) return false;
+    if (((uintptr_t)spins & 15u) || (d->model == SMC_EA && ((uintptr_t)coup & 15u))) return false;
     for (const ThrRow &r : rows)
         if (r.m[1].x > 0xFFFFu || r.m[2].x > 0xFFFFu) return false;
     return true;

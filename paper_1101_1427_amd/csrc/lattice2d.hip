@@ -327,18 +327,24 @@ __device__ __forceinline__ void split_row(const Row<2 * C> &v, Row<C> &even, Row
     }
 }
 
-__device__ __forceinline__ uint32_t to_pm1(uint32_t b) { return ((b << 8) - b) | 0x01010101u; }
+// 0/1 bytes to int8 +1 / -1 (0x01 / 0xFF): each byte selects byte 0 or 1
+// of the table 0xFF01.
+__device__ __forceinline__ uint32_t to_pm1(uint32_t b) { return perm(0u, 0x0000FF01u, b); }
 
+// A lane writes 32 consecutive bytes of the row as two 16-byte stores, so
+// one store instruction covers every other 16 bytes of a 2 KB span.  These
+// stores go through the caches, which join the two halves of every line
+// before it reaches memory: non-temporal stores wrote 1.38 times the row
+// bytes (partial lines) and made the last sweep of a call 16 % slower.
 template <int C>
 __device__ __forceinline__ void store_joined_row(uint8_t *p, const Row<C> &even, const Row<C> &odd) {
     typedef uint32_t v4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int i = 0; i < C; ++i) {
-        const uint32_t e0 = to_pm1(even.d[2 * i]), o0 = to_pm1(odd.d[2 * i]);
-        const uint32_t e1 = to_pm1(even.d[2 * i + 1]), o1 = to_pm1(odd.d[2 * i + 1]);
-        const v4 x = {perm(o0, e0, 0x05010400u), perm(o0, e0, 0x07030602u), perm(o1, e1, 0x05010400u),
-                      perm(o1, e1, 0x07030602u)};
-        __builtin_nontemporal_store(x, (v4 *)p + i);
+        const uint32_t e0 = even.d[2 * i], o0 = odd.d[2 * i], e1 = even.d[2 * i + 1], o1 = odd.d[2 * i + 1];
+        const v4 x = {to_pm1(perm(o0, e0, 0x05010400u)), to_pm1(perm(o0, e0, 0x07030602u)),
+                      to_pm1(perm(o1, e1, 0x05010400u)), to_pm1(perm(o1, e1, 0x07030602u))};
+        ((v4 *)p)[i] = x;
     }
 }
 
@@ -544,8 +550,12 @@ __device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xc
     }
 }
 
+// At least six waves per SIMD: two workgroups of eight compute and four
+// loader waves per compute unit.  The variant that reads the caller's rows
+// would otherwise take 84 registers and run one workgroup per compute unit
+// (it keeps a 16-byte constant in scratch, reloaded only on the tie path).
 template <int C, int NF, int IO>
-__global__ __launch_bounds__(1024) void k_ising2d_split(Lattice2dArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void k_ising2d_split(Lattice2dArgs a) {
     // ring: [2 planes][kSlots][L/2] (split source) or [kSlots][L] (caller's rows), then the edge words
     extern __shared__ __align__(16) uint8_t smem[];
     const int ncw = (int)(blockDim.x >> 6) - LoaderShape<NF>::NLW;  // compute waves; the last NLW waves load
@@ -663,11 +673,13 @@ int lattice2d_chunks(int L) {
 
 bool lattice2d_supported(int L) { return lattice2d_chunks(L) > 0; }
 
-// 32 rows per band; a batch with fewer than two such bands per compute unit
-// (a single lattice of L <= 4096) takes lower bands, down to 4 rows, so
-// that every compute unit has work (the halo rows then cost relatively
-// more).  SPINMC_L2D_H forces a height; a height smc_autotune measured for
-// the edge and replica count comes next.
+// 32 rows per band (16 at L = 16384, where the extra halo reads cost less
+// than the shorter bands gain: 325 against 331 us per sweep of three
+// lattices); a batch with fewer than two bands per compute unit (a single
+// lattice of L <= 4096) takes lower bands, down to 4 rows, so that every
+// compute unit has work (the halo rows then cost relatively more).
+// SPINMC_L2D_H forces a height; a height smc_autotune measured for the edge
+// and replica count comes next.
 int lattice2d_band_height(int L, int n_rep) {
     int H = env_int("SPINMC_L2D_H", 0);
     Shape tuned;
@@ -676,7 +688,7 @@ int lattice2d_band_height(int L, int n_rep) {
         int cus = 0, dev = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        H = 32;
+        H = L >= 16384 ? 16 : 32;
         while (H > 4 && cus > 0 && (int64_t)n_rep * (L / H) < 2 * (int64_t)cus) H >>= 1;
     }
     while (H > 4 && L % H) H >>= 1;
