@@ -10,7 +10,10 @@ tens of CPU-minutes for these; the GPU seconds).
     after every call;
   * the uneven 2D +-J tempering batch in full (4096 instances x 16
     temperatures), 5000 steps in five calls, 64 chains (every edge) checked
-    after every call."""
+    after every call;
+  * the 3D Heisenberg workload in full (256^3, 1000 sweeps): the float32
+    chain's mean energy over the second half against the float64 oracle's
+    (tests/golden/heis3d_L256_energy.txt, written by make_heis_series.py)."""
 import hashlib
 import os
 
@@ -140,3 +143,42 @@ def test_uneven2d_full_workload_5000_steps():
                   lambda q: int(inst[q * nt][2]), lambda q: int(cfg.sizes[q]) ** 2)
     assert done == cfg.steps
 
+
+
+def _blocked_mean_err(x, block=50):
+    x = np.asarray(x, np.float64)
+    n = len(x) // block
+    bins = x[:n * block].reshape(n, block).mean(axis=1)
+    return bins.mean(), bins.std(ddof=1) / np.sqrt(n)
+
+
+def test_heisenberg_256_long_run_against_the_oracle_series():
+    """The 3D Heisenberg workload at full size and length (256^3, beta =
+    0.693, renormalisation every 16 sweeps, 1000 sweeps) on the one-pass
+    kernel: the mean energy per site over sweeps 500 .. 999 agrees with the
+    float64 oracle's (tests/golden/heis3d_L256_energy.txt) within three
+    combined standard errors, each from ten blocks of 50 sweeps."""
+    cfg = W.heisenberg_3d()
+    L, N = cfg.L, cfg.L ** 3
+    ref = []
+    with open(os.path.join(os.path.dirname(GOLDEN), "heis3d_L256_energy.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                t, e = line.split()
+                assert int(t) == len(ref)
+                ref.append(float(e))
+    assert len(ref) == cfg.sweeps
+    b = S.Batch(S.HEISENBERG, 3, L, 1, cfg.seed, renorm_every=cfg.renorm_every)
+    assert S.sweep_plan(b)[1] == "k_heis3d_tiled"
+    spins = torch.zeros(3 * N, dtype=torch.float32, device=DEV)
+    S.spin_init(b, spins)
+    series = torch.zeros(cfg.sweeps, dtype=torch.float64, device=DEV)
+    for t in range(cfg.sweeps):
+        S.metropolis_sweep(b, spins, cfg.betas, t, 1)
+        S.measure_energy_magnetisation(b, spins, series[t:t + 1])
+    e_gpu = _host(series) / N
+    mg, sg = _blocked_mean_err(e_gpu[500:])
+    mo, so = _blocked_mean_err(np.asarray(ref[500:]))
+    print(f"heisenberg 256^3 <e> over sweeps 500..999: gpu {mg:.8f} +- {sg:.2e}, oracle {mo:.8f} +- {so:.2e}, "
+          f"first sweep {e_gpu[0]:.8f} vs {ref[0]:.8f}")
+    assert abs(mg - mo) <= 3.0 * np.hypot(sg, so), (mg, sg, mo, so)
