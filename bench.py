@@ -810,10 +810,11 @@ def sweep3d(S, W, sizes=(256, 512, 1024), beta=0.2216, flips=8e9, models=("ising
                 ms = _timed(lambda: S.metropolis_sweep(b, spins, [beta], 2, n, couplings=coup))
                 kernel_ms, launches = S.kernel_timing_read()
                 S.kernel_timing_enable(False)
+                kernel = S.sweep_plan(b)[1]  # the path taken under this row's environment
                 for k in env:
                     os.environ.pop(k, None)
                 ps = ms * 1e9 / (n * L ** 3)
-                row[key] = {"kernel": S.sweep_plan(b)[1], "ps_per_flip": round(ps, 4),
+                row[key] = {"kernel": kernel, "ps_per_flip": round(ps, 4),
                             "hbm_frac_2B": round(2.0 / (ps * 1e-12) / 8e12, 4),
                             "kernel_us_per_sweep": round(kernel_ms * 1e3 / n, 3) if launches else None}
             rows.append(row)

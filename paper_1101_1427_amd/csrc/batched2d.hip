@@ -171,7 +171,7 @@ __device__ __forceinline__ void group(uint8_t *S, const GroupAt &o, const GroupC
     }
     *(uint2 *)(S + o_own) = make_uint2(own.x ^ F0, own.y ^ F1);
     // Delta E of a flip with n unsatisfied bonds is 4 (2 - n)
-    const uint32_t m0 = (F0 << 8) - F0, m1 = (F1 << 8) - F1;
+    const uint32_t m0 = bytes_ff(F0), m1 = bytes_ff(F1);
     cnt = __builtin_amdgcn_sad_u8(F0, 0u, __builtin_amdgcn_sad_u8(F1, 0u, cnt));
     nsum = __builtin_amdgcn_sad_u8(n0 & m0, 0u, __builtin_amdgcn_sad_u8(n1 & m1, 0u, nsum));
 }
@@ -292,8 +292,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
         const uint2 o = *(const uint2 *)(S + y * L + half + 8 * m);
         const uint32_t w0 = perm(o.x, e.x, 0x05010400u), w1 = perm(o.x, e.x, 0x07030602u);
         const uint32_t w2 = perm(o.y, e.y, 0x05010400u), w3 = perm(o.y, e.y, 0x07030602u);
-        auto pm1 = [](uint32_t v) { return ((v << 8) - v) | 0x01010101u; };
-        *(uint4 *)(gs + (int64_t)i * 16) = make_uint4(pm1(w0), pm1(w1), pm1(w2), pm1(w3));
+        *(uint4 *)(gs + (int64_t)i * 16) = make_uint4(bytes_pm1(w0), bytes_pm1(w1), bytes_pm1(w2), bytes_pm1(w3));
         y += dy;
         m += dk;
         if (m >= G) {

@@ -217,7 +217,7 @@ __device__ __forceinline__ bool update_cell(float *ring, int sm, int sz, int sp,
     hf.x += nz1.x; hf.y += nz1.y; hf.z += nz1.z;
     hf.x += nz0.x; hf.y += nz0.y; hf.z += nz0.z;
     const uint32_t i = (((zz << a.lgL) + y) << a.lgL) + x;
-    const uint4 w = philox4x32_10(make_uint4(i >> 1, a.t, (uint32_t)r, 2 * kTagHeis + (uint32_t)c), a.key);
+    const uint4 w = philox4x32_10_wide(make_uint4(i >> 1, a.t, (uint32_t)r, 2 * kTagHeis + (uint32_t)c), a.key);
     const float3 sp3 = heis_proposal(unit23f(w.x), unit23f(w.y));
     const float dE = -((sp3.x - so.x) * hf.x + (sp3.y - so.y) * hf.y + (sp3.z - so.z) * hf.z);
     if (dE <= 0.0f || unit23f(w.z) < heis_boltzmann(beta, dE)) {

@@ -32,4 +32,12 @@ __device__ __forceinline__ uint32_t min16(uint32_t a, uint32_t b) {
     return as_u32(__builtin_elementwise_min(as_u16x2(a), as_u16x2(b)));
 }
 
+// 0/1 bytes mapped through a two-entry byte table (each byte selects byte 0
+// or 1 of the table): one byte-permute, where the equivalent shifts and
+// subtraction ((b << 8) - b and the like) are combined by the compiler into
+// a 32-bit multiply.
+__device__ __forceinline__ uint32_t bytes_ff(uint32_t b) { return perm(0u, 0x0000FF00u, b); }   // 0x00 / 0xFF
+__device__ __forceinline__ uint32_t bytes_fe(uint32_t b) { return perm(0u, 0x0000FE00u, b); }   // 0x00 / 0xFE
+__device__ __forceinline__ uint32_t bytes_pm1(uint32_t b) { return perm(0u, 0x0000FF01u, b); }  // +1 / -1
+
 }  // namespace smc

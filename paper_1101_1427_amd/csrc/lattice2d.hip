@@ -327,9 +327,6 @@ __device__ __forceinline__ void split_row(const Row<2 * C> &v, Row<C> &even, Row
     }
 }
 
-// 0/1 bytes to int8 +1 / -1 (0x01 / 0xFF): each byte selects byte 0 or 1
-// of the table 0xFF01.
-__device__ __forceinline__ uint32_t to_pm1(uint32_t b) { return perm(0u, 0x0000FF01u, b); }
 
 // A lane writes 32 consecutive bytes of the row as two 16-byte stores, so
 // one store instruction covers every other 16 bytes of a 2 KB span.  These
@@ -342,8 +339,8 @@ __device__ __forceinline__ void store_joined_row(uint8_t *p, const Row<C> &even,
 #pragma unroll
     for (int i = 0; i < C; ++i) {
         const uint32_t e0 = even.d[2 * i], o0 = odd.d[2 * i], e1 = even.d[2 * i + 1], o1 = odd.d[2 * i + 1];
-        const v4 x = {to_pm1(perm(o0, e0, 0x05010400u)), to_pm1(perm(o0, e0, 0x07030602u)),
-                      to_pm1(perm(o1, e1, 0x05010400u)), to_pm1(perm(o1, e1, 0x07030602u))};
+        const v4 x = {bytes_pm1(perm(o0, e0, 0x05010400u)), bytes_pm1(perm(o0, e0, 0x07030602u)),
+                      bytes_pm1(perm(o1, e1, 0x05010400u)), bytes_pm1(perm(o1, e1, 0x07030602u))};
         ((v4 *)p)[i] = x;
     }
 }
@@ -612,8 +609,6 @@ __global__ __launch_bounds__(256) void k_to_split(const int8_t *src, uint8_t *ds
     *(uint2 *)(base + po * P + off) = od;
 }
 
-__device__ __forceinline__ uint32_t pm1(uint32_t b) { return ((b << 8) - b) | 0x01010101u; }
-
 __global__ __launch_bounds__(256) void k_from_split(const uint8_t *src, int8_t *dst, int L, int64_t pitch,
                                                     int64_t chunks_per_rep, int64_t total) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -627,7 +622,7 @@ __global__ __launch_bounds__(256) void k_from_split(const uint8_t *src, int8_t *
     const int pe = y & 1, po = (y + 1) & 1;
     const uint2 ev = *(const uint2 *)(base + pe * P + off);
     const uint2 od = *(const uint2 *)(base + po * P + off);
-    const uint32_t e0 = pm1(ev.x), e1 = pm1(ev.y), o0 = pm1(od.x), o1 = pm1(od.y);
+    const uint32_t e0 = bytes_pm1(ev.x), e1 = bytes_pm1(ev.y), o0 = bytes_pm1(od.x), o1 = bytes_pm1(od.y);
     uint4 v;
     v.x = perm(o0, e0, 0x05010400u);
     v.y = perm(o0, e0, 0x07030602u);

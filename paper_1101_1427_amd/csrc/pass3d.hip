@@ -135,7 +135,7 @@ __device__ __forceinline__ uint2 update_half(const uint4 &q, uint2 ym, uint2 yp,
     }
     RowOut o;
     count_unsat<EA>(Sa, Sb, sh, ym, yp, zm, zp, bd, o.n0, o.n1);
-    const uint4 w = philox4x32_10(make_uint4(h0 >> 3, a.t, r, 2 * kTagHead + c), a.key);
+    const uint4 w = philox4x32_10_wide(make_uint4(h0 >> 3, a.t, r, 2 * kTagHead + c), a.key);
     uint32_t eq = 0xFFFFFFFFu;
     o.F0 = decide4(o.n0, w.x, w.y, K, a.one2, eq);
     o.F1 = decide4(o.n1, w.z, w.w, K, a.one2, eq);
@@ -143,7 +143,7 @@ __device__ __forceinline__ uint2 update_half(const uint4 &q, uint2 ym, uint2 yp,
     if constexpr (DE) {
         if (count) dE += flip_energy(o);
     }
-    return make_uint2(Sa.x ^ ((o.F0 << 8) - (o.F0 << 1)), Sa.y ^ ((o.F1 << 8) - (o.F1 << 1)));
+    return make_uint2(Sa.x ^ bytes_fe(o.F0), Sa.y ^ bytes_fe(o.F1));
 }
 
 // Largest workgroup of a launch shape (edges up to 1024).

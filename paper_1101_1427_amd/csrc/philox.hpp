@@ -72,6 +72,40 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, Key key) {
     return x;
 }
 
+// 32 x 32 -> 64-bit product of a per-lane word and a constant as one
+// v_mad_u64_u32.  The compiler selects the same instruction from the plain
+// product in most places but splits the last round's products of a single
+// draw into separate low and high multiplies where the draw feeds packed
+// 16-bit code; this form keeps the one instruction.  Register operands only.
+__device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t m) {
+    uint64_t p, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(p), "=s"(carry) : "v"(a), "s"(m));
+    (void)carry;
+    return p;
+}
+
+// philox4x32_10 with the products of rounds 3 to 10 as mul_wide (for
+// kernels whose code is inlined in full: the asm statements raise the
+// compiler's inlining cost, so callers that rely on inlining of large
+// device functions keep the plain form).
+__device__ __forceinline__ uint4 philox4x32_10_wide(uint4 x, Key key) {
+    uint32_t k0 = key.k0, k1 = key.k1;
+    x = philox_round(x, k0, k1);
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+    x = philox_round(x, k0, k1);
+#pragma unroll
+    for (int round = 2; round < 10; ++round) {
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+        const uint64_t p0 = mul_wide(x.x, kPhiloxM0);
+        const uint64_t p1 = mul_wide(x.z, kPhiloxM1);
+        x = make_uint4(xor3_key((uint32_t)(p1 >> 32), x.y, k0), (uint32_t)p1, xor3_key((uint32_t)(p0 >> 32), x.w, k1),
+                       (uint32_t)p0);
+    }
+    return x;
+}
+
 // N independent draws advanced round by round together (independent
 // dependency chains interleave in the instruction stream).
 template <int NC>

@@ -206,7 +206,7 @@ __device__ __forceinline__ void half_pass(uint32_t *S, const uint32_t *Cb, const
             }
             *(uint2 *)(R + row * 4 + 2 * a) = make_uint2(own.x ^ F0, own.y ^ F1);
             // Delta E of a flip with n unsatisfied bonds is 4 (3 - n)
-            const uint32_t m0 = (F0 << 8) - F0, m1 = (F1 << 8) - F1;  // 0xFF where flipped
+            const uint32_t m0 = bytes_ff(F0), m1 = bytes_ff(F1);  // 0xFF where flipped
             cnt[q] = __builtin_amdgcn_sad_u8(F0, 0u, __builtin_amdgcn_sad_u8(F1, 0u, cnt[q]));
             nsum[q] = __builtin_amdgcn_sad_u8(n0 & m0, 0u, __builtin_amdgcn_sad_u8(n1 & m1, 0u, nsum[q]));
         }
@@ -345,8 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_pt3d_chain(Pt3dArgs a) {
         const uint4 v = *(const uint4 *)(S + i * 4);  // E0..3, E4..7, O0..3, O4..7
         const uint32_t b0 = perm(v.z, v.x, 0x05010400u), b1 = perm(v.z, v.x, 0x07030602u);
         const uint32_t b2 = perm(v.w, v.y, 0x05010400u), b3 = perm(v.w, v.y, 0x07030602u);
-        auto pm1 = [](uint32_t b) { return ((b << 8) - b) | 0x01010101u; };
-        *(uint4 *)(osp + (int64_t)i * 16) = make_uint4(pm1(b0), pm1(b1), pm1(b2), pm1(b3));
+        *(uint4 *)(osp + (int64_t)i * 16) = make_uint4(bytes_pm1(b0), bytes_pm1(b1), bytes_pm1(b2), bytes_pm1(b3));
     }
     if (tid < n) {
         a.slot_of_temp[(int64_t)q * n + tid] = cs.slot_of_temp[tid];

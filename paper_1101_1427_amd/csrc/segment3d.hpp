@@ -217,7 +217,7 @@ __device__ __forceinline__ RowOut segment_update(const uint4 &own, const uint4 &
     RowOut o;
     count_unsat<EA>(Sa, Sb, sh, half_of(rym, sa), half_of(ryp, sa), half_of(rzm, sa), half_of(rzp, sa), bd, o.n0,
                     o.n1);
-    const uint4 w = philox4x32_10(make_uint4(h0 >> 3, t, r, 2 * kTagHead + c), key);
+    const uint4 w = philox4x32_10_wide(make_uint4(h0 >> 3, t, r, 2 * kTagHead + c), key);
     const Lut3 K = lut_of(th);
     uint32_t eq = 0xFFFFFFFFu;
     o.F0 = decide4(o.n0, w.x, w.y, K, one2, eq);
@@ -228,7 +228,7 @@ __device__ __forceinline__ RowOut segment_update(const uint4 &own, const uint4 &
 
 // The segment with the flagged own sites flipped (+1 <-> -1: byte ^ 0xFE).
 __device__ __forceinline__ uint4 apply_flips(const uint4 &own, const RowOut &o, int A) {
-    const uint32_t m0 = (o.F0 << 8) - (o.F0 << 1), m1 = (o.F1 << 8) - (o.F1 << 1);  // 0xFE where flipped
+    const uint32_t m0 = bytes_fe(o.F0), m1 = bytes_fe(o.F1);  // 0xFE where flipped
     const uint32_t slo = A ? 0x01040004u : 0x04010400u, shi = A ? 0x03040204u : 0x04030402u;
     return make_uint4(own.x ^ perm(0u, m0, slo), own.y ^ perm(0u, m0, shi), own.z ^ perm(0u, m1, slo),
                       own.w ^ perm(0u, m1, shi));
@@ -237,7 +237,7 @@ __device__ __forceinline__ uint4 apply_flips(const uint4 &own, const RowOut &o, 
 // Energy change of the segment's flips: 12 - 4n for a site with n
 // unsatisfied bonds.
 __device__ __forceinline__ long long flip_energy(const RowOut &o) {
-    const uint32_t f0 = (o.F0 << 8) - o.F0, f1 = (o.F1 << 8) - o.F1;  // 0xFF where flipped
+    const uint32_t f0 = bytes_ff(o.F0), f1 = bytes_ff(o.F1);  // 0xFF where flipped
     const uint32_t cnt = __builtin_amdgcn_sad_u8(o.F0, 0u, __builtin_amdgcn_sad_u8(o.F1, 0u, 0u));
     const uint32_t nsum = __builtin_amdgcn_sad_u8(o.n0 & f0, 0u, __builtin_amdgcn_sad_u8(o.n1 & f1, 0u, 0u));
     return 12 * (long long)cnt - 4 * (long long)nsum;
