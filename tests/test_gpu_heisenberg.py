@@ -134,3 +134,29 @@ def test_gpu_heisenberg_kernels_agree(monkeypatch, L, n_rep, n):
     for o in out[1:]:
         assert np.array_equal(out[0][0], o[0])
         assert np.array_equal(out[0][1], o[1])
+
+
+def test_gpu_heisenberg_kernels_agree_at_the_largest_edge(monkeypatch):
+    """At the largest edge the one-pass kernel supports (1024^3, 2^30 sites,
+    32-bit site indices up to 2^30 - 1) it gives the same spins and
+    acceptance counts as the two-launch kernel after two sweeps (compared on
+    the device: 12.9 GB per copy)."""
+    L, n = 1024, 2
+    b = S.Batch(S.HEISENBERG, 3, L, 1, W.seed_for(33), renorm_every=16)
+    assert S.sweep_plan(b)[1] == "k_heis3d_tiled"
+    out = []
+    for tiled in ("1", "0"):
+        monkeypatch.setenv("SPINMC_HEIS_TILED", tiled)
+        spins = torch.zeros(3 * L ** 3, dtype=torch.float32, device=DEV)
+        S.spin_init(b, spins)
+        acc = torch.zeros(1, dtype=torch.int64, device=DEV)
+        S.metropolis_sweep(b, spins, [0.693], 14, n, dE_accum=acc)  # sweep 15 renormalises
+        torch.cuda.synchronize()
+        out.append((spins, int(acc.cpu()[0])))
+    assert out[0][1] == out[1][1] and out[0][1] > 0
+    assert torch.equal(out[0][0], out[1][0])
+    # unit vectors after the renormalisation of sweep 15
+    norms = out[0][0].view(-1, 3).norm(dim=1)
+    assert float((norms - 1.0).abs().max()) < 1e-6
+    del out
+    torch.cuda.empty_cache()
