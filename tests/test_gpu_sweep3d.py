@@ -64,7 +64,7 @@ def test_pass_launch_shapes_bit_exact(monkeypatch, ty, segs):
         assert np.array_equal(got, ref) and np.array_equal(dE, ref_dE)
 
 
-@pytest.mark.parametrize("model,L", [(S.ISING, 512), (S.EA, 512), (S.ISING, 1024)])
+@pytest.mark.parametrize("model,L", [(S.ISING, 512), (S.EA, 512), (S.ISING, 1024), (S.EA, 1024)])
 def test_pass_equals_half_sweeps_at_bench_sizes(monkeypatch, model, L):
     """At the bench's large edges the one-pass kernel (its default launch
     shape) and the two half-sweep launches give the same spins and energy
