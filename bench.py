@@ -36,6 +36,8 @@ KERNEL_SOURCES = {
     "k_heis3d_tiled": ("heis3d.hip", "heis_math.hpp", "philox.hpp"),
     "k_ising3d_half": ("sweep3d.hip", "segment3d.hpp", "intrin.hpp", "philox.hpp", "tables.hpp"),
     "k_ising3d_pass": ("pass3d.hip", "segment3d.hpp", "intrin.hpp", "philox.hpp", "tables.hpp"),
+    "k_pt3d_chain": ("pt3d.hip", "intrin.hpp", "philox.hpp", "tables.hpp"),
+    "k_uneven2d_sweep": ("batched2d.hip", "intrin.hpp", "philox.hpp", "tables.hpp"),
 }
 
 
@@ -89,6 +91,8 @@ KT_WORKLOADS = {
     "k_heis3d_tiled": "3D Heisenberg {L}^3, one lattice",
     "k_ising3d_pass": "3D Ising and EA (one +-J sample), one L^3 lattice per model, L up to {L}",
     "k_ising3d_half": "3D Ising and EA (one +-J sample), one L^3 lattice per model, L up to {L}",
+    "k_pt3d_chain": "3D +-J tempering, L = {L}: 512 samples x 2 replicas x 32 temperatures, chain-resident",
+    "k_uneven2d_sweep": "uneven 2D +-J tempering batch: 4096 instances x 16 temperatures, edges 32 .. {L}",
 }
 
 
@@ -130,10 +134,16 @@ def kt_summary(db: str, log: str, kernel: str, L: int, command: str):
         import json
 
         d = json.loads(bench_line)
-        r = d["roofline"]
-        lines.append(f"bench_line_kernel_us_per_launch: {r['kernel_us_per_launch']}")
-        lines.append(f"bench_line_roofline_frac: {r['frac']}")
-        lines.append(f"bench_line_ns_per_flip: {d['value']}")
+        if kernel in ("k_pt3d_chain", "k_uneven2d_sweep"):
+            t = d.get("tempering", {}).get("ea3d_L16" if kernel == "k_pt3d_chain" else "ea2d_uneven", {})
+            for key in ("steps", "ms", "replica_sweeps_per_s", "speedup_vs_per_instance"):
+                if key in t:
+                    lines.append(f"bench_line_{key}: {t[key]}")
+        else:
+            r = d["roofline"]
+            lines.append(f"bench_line_kernel_us_per_launch: {r['kernel_us_per_launch']}")
+            lines.append(f"bench_line_roofline_frac: {r['frac']}")
+            lines.append(f"bench_line_ns_per_flip: {d['value']}")
     os.makedirs(PROFILES, exist_ok=True)
     path = os.path.join(PROFILES, f"{kernel}_L{L}_kernel_trace.txt")
     with open(path, "w") as fh:
@@ -1344,7 +1354,8 @@ def main():
         valu_summary(args.valu_summary, args.pmc_command[0] if args.pmc_command else "")
         return
     kernel_L = {"k_heis3d_tiled": 256, "k_ising3d_half": max(args.sweep3d_sizes),
-                "k_ising3d_pass": max(args.sweep3d_sizes)}.get(args.pmc_kernel, args.L)
+                "k_ising3d_pass": max(args.sweep3d_sizes), "k_pt3d_chain": 16,
+                "k_uneven2d_sweep": 256}.get(args.pmc_kernel, args.L)
     if args.kt_summary:
         kt_summary(*args.kt_summary, kernel=args.pmc_kernel, L=kernel_L, command=args.kt_command)
         return
