@@ -58,7 +58,19 @@ struct Lut {
     uint2 thr1, thr2;                         // exact thresholds of dE = 4 and dE = 8
 };
 
-__device__ __forceinline__ Lut make_lut(const ThrRow &row, uint32_t one2, uint32_t four) {
+// The row is the workgroup's (one replica per band).  Its words are moved
+// to scalar registers: the compiler loads it with a vector load (the kernel
+// also writes global memory) and would hold the exact thresholds of the tie
+// path in vector registers, which the variant reading the caller's rows
+// then spilled to scratch, reloading them from memory at every tie while
+// the rest of the workgroup waited at the next barrier (about 50 us more
+// for that sweep at 3 x 16384^2).
+__device__ __forceinline__ Lut make_lut(const ThrRow &row_in, uint32_t one2, uint32_t four) {
+    ThrRow row;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        row.m[i] = make_uint2(__builtin_amdgcn_readfirstlane(row_in.m[i].x),
+                              __builtin_amdgcn_readfirstlane(row_in.m[i].y));
     Lut k;
     const uint32_t t2 = row.m[2].x, t1 = row.m[1].x;  // both <= 0xFFFF (checked on the host)
     k.tlo_lo = (t2 & 0xFFu) | ((t1 & 0xFFu) << 8) | 0xFFFF0000u;
@@ -548,9 +560,7 @@ __device__ void compute_loop(const Band<C> &B, const uint8_t *ring, uint32_t *xc
 }
 
 // At least six waves per SIMD: two workgroups of eight compute and four
-// loader waves per compute unit.  The variant that reads the caller's rows
-// would otherwise take 84 registers and run one workgroup per compute unit
-// (it keeps a 16-byte constant in scratch, reloaded only on the tie path).
+// loader waves per compute unit (at most 80 registers).
 template <int C, int NF, int IO>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void k_ising2d_split(Lattice2dArgs a) {
     // ring: [2 planes][kSlots][L/2] (split source) or [kSlots][L] (caller's rows), then the edge words
