@@ -58,19 +58,23 @@ struct Lut {
     uint2 thr1, thr2;                         // exact thresholds of dE = 4 and dE = 8
 };
 
-// The row is the workgroup's (one replica per band).  Its words are moved
-// to scalar registers: the compiler loads it with a vector load (the kernel
-// also writes global memory) and would hold the exact thresholds of the tie
-// path in vector registers, which the variant reading the caller's rows
-// then spilled to scratch, reloading them from memory at every tie while
-// the rest of the workgroup waited at the next barrier (about 50 us more
-// for that sweep at 3 x 16384^2).
+// The row is the workgroup's (one replica per band).  With SCALAR its
+// words are moved to scalar registers: the compiler loads the row with a
+// vector load (the kernel also writes global memory) and holds the exact
+// thresholds of the tie path in vector registers, which the variant reading
+// the caller's rows spilled to scratch, reloading them from memory at every
+// tie while the rest of the workgroup waited at the next barrier (about 50
+// us more for that sweep at 3 x 16384^2).  The other variants do not spill
+// and run 0.5 % faster with the vector copy.
+template <bool SCALAR>
 __device__ __forceinline__ Lut make_lut(const ThrRow &row_in, uint32_t one2, uint32_t four) {
-    ThrRow row;
+    ThrRow row = row_in;
+    if constexpr (SCALAR) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        row.m[i] = make_uint2(__builtin_amdgcn_readfirstlane(row_in.m[i].x),
-                              __builtin_amdgcn_readfirstlane(row_in.m[i].y));
+        for (int i = 0; i < 4; ++i)
+            row.m[i] = make_uint2(__builtin_amdgcn_readfirstlane(row_in.m[i].x),
+                                  __builtin_amdgcn_readfirstlane(row_in.m[i].y));
+    }
     Lut k;
     const uint32_t t2 = row.m[2].x, t1 = row.m[1].x;  // both <= 0xFFFF (checked on the host)
     k.tlo_lo = (t2 & 0xFFu) | ((t1 & 0xFFu) << 8) | 0xFFFF0000u;
@@ -591,7 +595,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     if ((int)(threadIdx.x >> 6) >= ncw) {
         loader_loop<C, NF, IO>(B, ring, (int)(threadIdx.x >> 6) - ncw);
     } else {
-        B.K = make_lut(a.thr[r], a.one2, a.four);
+        B.K = make_lut<(IO & kAbiIn) != 0>(a.thr[r], a.one2, a.four);
         compute_loop<C, IO>(B, ring, xch, a.dE_part, a.dE_first != 0);
     }
 }
