@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kThreads3) void k_dcb3d(Dcb3dArgs a) {
             if constexpr (EA) bd = bonds_from_bytes(jx, jeb, jy, jym, jz, jzm, A);
             const RowOut o = segment_update<EA>(own, R[q - 1], R[q + 1], R[q - kW3], R[q + kW3],
                                                 A ? XR[threadIdx.x] : XL[threadIdx.x], A, bd, th,
-                                                h0, (uint32_t)c, tj, (uint32_t)r, a.key, 0x00010001u, 4u);
+                                                h0, (uint32_t)c, tj, (uint32_t)r, a.key, 0x00010001u);
             if (o.F0 | o.F1) R[q] = apply_flips(own, o, A);
             dE += flip_energy(o);
             __syncthreads();

@@ -54,7 +54,6 @@ struct Lut {
     uint32_t tlo_lo, tlo_hi, thi_lo, thi_hi;  // T(n): low / high bytes, selectors n = 0..7
     uint32_t de_lo, de_hi;                    // dE/4 + 2 for index n + 4F
     uint32_t one2;                            // 0x00010001
-    uint32_t four;                            // 4 (trip count of the tie loop, kept opaque)
     uint2 thr1, thr2;                         // exact thresholds of dE = 4 and dE = 8
 };
 
@@ -67,7 +66,7 @@ struct Lut {
 // us more for that sweep at 3 x 16384^2).  The other variants do not spill
 // and run 0.5 % faster with the vector copy.
 template <bool SCALAR>
-__device__ __forceinline__ Lut make_lut(const ThrRow &row_in, uint32_t one2, uint32_t four) {
+__device__ __forceinline__ Lut make_lut(const ThrRow &row_in, uint32_t one2) {
     ThrRow row = row_in;
     if constexpr (SCALAR) {
 #pragma unroll
@@ -86,7 +85,6 @@ __device__ __forceinline__ Lut make_lut(const ThrRow &row_in, uint32_t one2, uin
     k.de_lo = 0x02020202u;
     k.de_hi = 0x01020304u;
     k.one2 = one2;
-    k.four = four;
     k.thr1 = row.m[1];
     k.thr2 = row.m[2];
     return k;
@@ -183,7 +181,6 @@ struct Lattice2dArgs {
     int L, H, bands, n_rep;
     int H2, nb1;    // bands 0 .. nb1-1 of a replica have H rows, the others H2 rows
     uint32_t one2;  // 0x00010001, passed in so that the compiler keeps the packed ops
-    uint32_t four;  // 4, passed in so that the compiler keeps the tie loop rolled
 };
 
 // Decide and apply colour c of one lane-row: own (updated in place),
@@ -206,32 +203,40 @@ __device__ __forceinline__ void apply_row(Row<C> &own, const Row<C> &va, const R
     // a head equal to the high half of its threshold: decide those sites exactly
     const bool tie = ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u);
     if (__builtin_expect(__any(tie), 0)) {
-        if (tie) {
-            // Exact decisions of all 8C sites, word by word with a rolled
-            // loop over the four sites of a word (ties are rare, probability
-            // 2^-16 per site, so this path is kept compact).
+        // Ties are rare (probability 2^-16 per site), but a wavefront that
+        // meets one holds up its workgroup at the next barrier, so this path
+        // is kept short: a mask of the tied sites (bit 4 i + s for site s of
+        // word i), then one pass per tied site of the lane with most of them
+        // (almost always one), each drawing the single tail it needs.
+        uint32_t tm = 0;
 #pragma unroll
-            for (int i = 0; i < 2 * C; ++i) {
-                const uint4 wq = w[i >> 1];
-                const uint32_t wlo = (i & 1) ? wq.z : wq.x, whi = (i & 1) ? wq.w : wq.y;
-                uint32_t f = 0;
-#pragma unroll 1
-                for (uint32_t s4 = 0; s4 < K.four; ++s4) {
-                    const uint32_t word = s4 < 2u ? wlo : whi;
-                    const uint32_t head = (s4 & 1u) ? (word >> 16) : (word & 0xFFFFu);
-                    const uint32_t ns = (n[i] >> (8u * s4)) & 0xFFu;
-                    uint32_t flip = 1u;
-                    if (ns < 2u) {
-                        const uint2 th = ns == 0u ? K.thr2 : K.thr1;
-                        flip = head < th.x ? 1u : 0u;
-                        if (head == th.x) {
-                            const uint32_t h = (g0 + (uint32_t)(i >> 1)) * 8u + 4u * (uint32_t)(i & 1) + s4;
-                            flip = tail16(h, t, r, c, key) < th.y ? 1u : 0u;
-                        }
-                    }
-                    f |= flip << (8u * s4);
+        for (int i = 0; i < 2 * C; ++i) {
+            const uint4 &wq = w[i >> 1];
+            const uint32_t tl = perm(K.tlo_hi, K.tlo_lo, n[i]), th = perm(K.thi_hi, K.thi_lo, n[i]);
+            const uint32_t da = perm(th, tl, 0x05010400u) ^ ((i & 1) ? wq.z : wq.x);
+            const uint32_t db = perm(th, tl, 0x07030602u) ^ ((i & 1) ? wq.w : wq.y);
+            const uint32_t m4 = ((da & 0xFFFFu) == 0u ? 1u : 0u) | ((da >> 16) == 0u ? 2u : 0u) |
+                                ((db & 0xFFFFu) == 0u ? 4u : 0u) | ((db >> 16) == 0u ? 8u : 0u);
+            tm |= m4 << (4 * i);
+        }
+        while (__any(tm != 0u)) {
+            if (tm != 0u) {
+                const uint32_t s = __builtin_ctz(tm), wi = s >> 2, s4 = s & 3u;
+                tm &= tm - 1u;
+                uint32_t nw = n[0];
+#pragma unroll
+                for (int i = 1; i < 2 * C; ++i) nw = wi == (uint32_t)i ? n[i] : nw;
+                const uint32_t ns = (nw >> (8u * s4)) & 0xFFu;
+                uint32_t flip = 1u;  // a head of 0xFFFF at a site with Delta E <= 0
+                if (ns < 2u) {
+                    // the head equals the threshold's high half: compare the tail
+                    const uint2 th = ns == 0u ? K.thr2 : K.thr1;
+                    const uint32_t h = (g0 + (s >> 3)) * 8u + (s & 7u);
+                    flip = tail16(h, t, r, c, key) < th.y ? 1u : 0u;
                 }
-                F[i] = f;
+                const uint32_t keep = ~(0xFFu << (8u * s4)), set = flip << (8u * s4);
+#pragma unroll
+                for (int i = 0; i < 2 * C; ++i) F[i] = wi == (uint32_t)i ? (F[i] & keep) | set : F[i];
             }
         }
     }
@@ -595,7 +600,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     if ((int)(threadIdx.x >> 6) >= ncw) {
         loader_loop<C, NF, IO>(B, ring, (int)(threadIdx.x >> 6) - ncw);
     } else {
-        B.K = make_lut<(IO & kAbiIn) != 0>(a.thr[r], a.one2, a.four);
+        B.K = make_lut<(IO & kAbiIn) != 0>(a.thr[r], a.one2);
         compute_loop<C, IO>(B, ring, xch, a.dE_part, a.dE_first != 0);
     }
 }
@@ -811,7 +816,6 @@ hipError_t launch_ising2d_split(const void *src, bool src_rows, void *dst, bool 
     a.nb1 = g.nb1;
     a.n_rep = n_rep;
     a.one2 = 0x00010001u;
-    a.four = 4u;
     const unsigned compute_threads = (unsigned)(L / (16 * C));
     const unsigned blocks = (unsigned)(a.bands * n_rep);
     const size_t lds = (size_t)2 * kSlots * (L / 2) + 2 * 16 * 2 * sizeof(uint32_t);

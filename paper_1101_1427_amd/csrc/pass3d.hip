@@ -73,7 +73,7 @@ struct Pass3dArgs {
     int L, D;              // edge; planes per z segment
     int strips, zsegs;     // per replica
     int np;                // threads per row-parity class (a multiple of 64)
-    uint32_t one2, four;   // 0x00010001 and 4, opaque to the compiler
+    uint32_t one2;         // 0x00010001, opaque to the compiler
 };
 
 __device__ __forceinline__ int wrapi(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
@@ -139,7 +139,7 @@ __device__ __forceinline__ uint2 update_half(const uint4 &q, uint2 ym, uint2 yp,
     uint32_t eq = 0xFFFFFFFFu;
     o.F0 = decide4(o.n0, w.x, w.y, K, a.one2, eq);
     o.F1 = decide4(o.n1, w.z, w.w, K, a.one2, eq);
-    if (__builtin_expect(__any(has_tie(eq)), 0)) exact_decisions(o, w, th, h0, c, a.t, r, a.key, a.four, has_tie(eq));
+    if (__builtin_expect(__any(has_tie(eq)), 0)) exact_decisions(o, w, th, K, h0, c, a.t, r, a.key, has_tie(eq));
     if constexpr (DE) {
         if (count) dE += flip_energy(o);
     }
@@ -448,7 +448,6 @@ hipError_t launch_ising3d_pass(const int8_t *src, int8_t *dst, const uint2 *pbon
     a.zsegs = L / D;
     a.np = threads / 2;
     a.one2 = 0x00010001u;
-    a.four = 4u;
     const size_t lds = (size_t)kRing * (size_t)(ty + 4) * (size_t)L * (pbonds ? 5 : 4) / 4;
     const dim3 grid((unsigned)((int64_t)n_rep * a.strips * a.zsegs));
 #define SMC_PASS3D(MM, TT, SS, DD)                                                                          \

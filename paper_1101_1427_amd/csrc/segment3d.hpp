@@ -84,35 +84,54 @@ struct RowOut {
 // True where a 16-bit lane of eq is zero (a head equal to its high half).
 __device__ __forceinline__ bool has_tie(uint32_t eq) { return ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u); }
 
-// Exact decisions of the eight sites of o (heads w, in-colour indices h0 ..
-// h0 + 7) on the lanes with tie set: a head equal to the high half of its
-// threshold (probability 2^-16 per site) compares the tail draw with the low
-// half.
-__device__ __forceinline__ void exact_decisions(RowOut &o, const uint4 &w, const ThrRow &th, uint32_t h0, uint32_t c,
-                                                uint32_t t, uint32_t r, Key key, uint32_t four, bool tie) {
-    if (!tie) return;
-    // the heads as two 64-bit words and the three thresholds as values, so
-    // that the selections below stay in registers
-    const uint64_t wlo = ((uint64_t)w.y << 32) | w.x, whi = ((uint64_t)w.w << 32) | w.z;
-    const uint64_t T3 = ((uint64_t)th.m[3].y << 32) | th.m[3].x, T2 = ((uint64_t)th.m[2].y << 32) | th.m[2].x,
-                   T1 = ((uint64_t)th.m[1].y << 32) | th.m[1].x;
-    uint32_t f0 = 0u, f1 = 0u;
-#pragma unroll 1
-    for (uint32_t i = 0; i < 2u * four; ++i) {
-        const uint32_t ns = ((i < 4u ? o.n0 : o.n1) >> (8u * (i & 3u))) & 0xFFu;
-        const uint32_t head = (uint32_t)((i < 4u ? wlo : whi) >> (16u * (i & 3u))) & 0xFFFFu;
-        uint32_t flip = 1u;
-        if (ns < 3u) {
-            const uint64_t T = ns == 0u ? T3 : ns == 1u ? T2 : T1;  // Delta E = 12 - 4 ns
-            flip = metropolis_accept(head, make_uint2((uint32_t)T, (uint32_t)(T >> 32)), h0 + i, t, r, c, key);
+// Exact decisions of the sites of o (heads w, in-colour indices h0 .. h0 + 7,
+// counts in o.n0 / o.n1) whose head equals the high half of the table entry
+// (probability 2^-16 per site), on the lanes with tie set.  A wavefront that
+// meets a tie holds up its workgroup at the next barrier, so the path is
+// short: a mask of the tied sites, then one pass per tied site of the lane
+// with most of them (almost always one), each drawing the single tail it
+// needs.
+__device__ __forceinline__ void exact_decisions(RowOut &o, const uint4 &w, const ThrRow &th, const Lut3 &K,
+                                                uint32_t h0, uint32_t c, uint32_t t, uint32_t r, Key key, bool tie) {
+    uint32_t tm = 0;  // bit s: site s (0 .. 7) is tied
+    if (tie) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint32_t n = q ? o.n1 : o.n0;
+            const uint32_t tl = perm(0xFFFFFFFFu, K.lo, n), thh = perm(0xFFFFFFFFu, K.hi, n);
+            const uint32_t da = perm(thh, tl, 0x05010400u) ^ (q ? w.z : w.x);
+            const uint32_t db = perm(thh, tl, 0x07030602u) ^ (q ? w.w : w.y);
+            const uint32_t m4 = ((da & 0xFFFFu) == 0u ? 1u : 0u) | ((da >> 16) == 0u ? 2u : 0u) |
+                                ((db & 0xFFFFu) == 0u ? 4u : 0u) | ((db >> 16) == 0u ? 8u : 0u);
+            tm |= m4 << (4 * q);
         }
-        if (i < 4u)
-            f0 |= flip << (8u * (i & 3u));
-        else
-            f1 |= flip << (8u * (i & 3u));
     }
-    o.F0 = f0;
-    o.F1 = f1;
+    // values, not references, below: a selected reference would put the
+    // structure it points into in scratch memory
+    const uint32_t n0 = o.n0, n1 = o.n1, w0 = w.x, w1 = w.y, w2 = w.z, w3 = w.w;
+    const uint32_t t3x = th.m[3].x, t3y = th.m[3].y, t2x = th.m[2].x, t2y = th.m[2].y, t1x = th.m[1].x,
+                   t1y = th.m[1].y;
+    while (__any(tm != 0u)) {
+        if (tm != 0u) {
+            const uint32_t s = __builtin_ctz(tm), b = 8u * (s & 3u);
+            tm &= tm - 1u;
+            const uint32_t ns = ((s < 4u ? n0 : n1) >> b) & 0xFFu;
+            const uint32_t word = s < 2u ? w0 : s < 4u ? w1 : s < 6u ? w2 : w3;
+            const uint32_t head = (s & 1u) ? (word >> 16) : (word & 0xFFFFu);
+            uint32_t flip = 1u;  // Delta E <= 0
+            if (ns < 3u) {
+                // Delta E = 12 - 4 ns
+                const uint32_t tx = ns == 0u ? t3x : ns == 1u ? t2x : t1x;
+                const uint32_t ty = ns == 0u ? t3y : ns == 1u ? t2y : t1y;
+                flip = metropolis_accept(head, make_uint2(tx, ty), h0 + s, t, r, c, key) ? 1u : 0u;
+            }
+            const uint32_t keep = ~(0xFFu << b), set = flip << b;
+            if (s < 4u)
+                o.F0 = (o.F0 & keep) | set;
+            else
+                o.F1 = (o.F1 & keep) | set;
+        }
+    }
 }
 
 // Bonds of the eight own sites (bit 1 of a byte set where J = -1, the
@@ -205,7 +224,7 @@ template <bool EA>
 __device__ __forceinline__ RowOut segment_update(const uint4 &own, const uint4 &rym, const uint4 &ryp,
                                                  const uint4 &rzm, const uint4 &rzp, uint32_t eb, int A,
                                                  const Bonds3 &bd, const ThrRow &th, uint32_t h0, uint32_t c,
-                                                 uint32_t t, uint32_t r, Key key, uint32_t one2, uint32_t four) {
+                                                 uint32_t t, uint32_t r, Key key, uint32_t one2) {
     const uint32_t sa = A ? 0x07050301u : 0x06040200u, sb = A ? 0x06040200u : 0x07050301u;
     const uint2 Sa = half_of(own, sa);
     const uint2 Sb = half_of(own, sb);
@@ -222,7 +241,7 @@ __device__ __forceinline__ RowOut segment_update(const uint4 &own, const uint4 &
     uint32_t eq = 0xFFFFFFFFu;
     o.F0 = decide4(o.n0, w.x, w.y, K, one2, eq);
     o.F1 = decide4(o.n1, w.z, w.w, K, one2, eq);
-    if (__builtin_expect(__any(has_tie(eq)), 0)) exact_decisions(o, w, th, h0, c, t, r, key, four, has_tie(eq));
+    if (__builtin_expect(__any(has_tie(eq)), 0)) exact_decisions(o, w, th, K, h0, c, t, r, key, has_tie(eq));
     return o;
 }
 

@@ -39,7 +39,6 @@ struct Sweep3dArgs {
     int L, c;
     int blocks_per_rep;
     uint32_t one2;  // 0x00010001 (opaque to the compiler, keeps the packed 16-bit ops)
-    uint32_t four;  // 4 (opaque trip count of the rarely taken exact-decision loop)
 };
 
 // Z rows per thread: the segments (x0, y, z0 .. z0 + Z - 1), each row's
@@ -109,7 +108,7 @@ __global__ __launch_bounds__(kThreads) void k_ising3d_half(Sweep3dArgs a) {
                 bd = bonds_from_bits(pown.x & 0xFFFFu, jeb, pown.x >> 16, pym.x >> 16, pown.y, pzm.y, A);
             }
             const RowOut o = segment_update<EA>(own, rym, ryp, rzm, rzp, eb, A, bd, th, (uint32_t)(i0 >> 1),
-                                                (uint32_t)a.c, a.t, (uint32_t)r, a.key, a.one2, a.four);
+                                                (uint32_t)a.c, a.t, (uint32_t)r, a.key, a.one2);
             if (o.F0 | o.F1) {
                 const uint4 out = apply_flips(own, o, A);
                 if constexpr (NT)
@@ -246,7 +245,6 @@ hipError_t launch_ising3d_half(int8_t *spins, const int8_t *coup, const uint2 *p
     a.c = c;
     a.blocks_per_rep = (int)((threads + kThreads - 1) / kThreads);
     a.one2 = 0x00010001u;
-    a.four = 4u;
     const int64_t blocks = (int64_t)n_rep * a.blocks_per_rep;
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
     if (pbonds) return launch_model<2>(Z, sweep3d_nt(), (unsigned)blocks, a, s);
