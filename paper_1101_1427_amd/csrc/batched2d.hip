@@ -104,7 +104,7 @@ __device__ __forceinline__ GroupCoup group_coup(const uint8_t *X, const uint8_t 
 template <bool EA>
 __device__ __forceinline__ void group(uint8_t *S, const GroupAt &o, const GroupCoup &J, int L, int y, int k, int c,
                                       uint32_t t, uint32_t r, Key key, Lut2 K, const ThrRow &th, uint32_t one2,
-                                      uint32_t four, uint32_t &cnt, uint32_t &nsum) {
+                                      uint32_t &cnt, uint32_t &nsum) {
     const int a = (y & 1) == c ? 0 : 1;
     const int o_own = o.own;
     const uint2 own = *(const uint2 *)(S + o.own);
@@ -145,28 +145,42 @@ __device__ __forceinline__ void group(uint8_t *S, const GroupAt &o, const GroupC
     uint32_t F1 = decide4(n1, w.z, w.w, K, one2, eq);
     const bool tie = ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u);
     if (__builtin_expect(__any(tie), 0)) {
+        // Exact decisions of the sites whose head equals the high half of the
+        // threshold (probability 2^-16 each).  A wavefront that meets one
+        // holds up its workgroup at the next barrier, so the path is short: a
+        // mask of the tied sites, then one pass per tied site of the lane with
+        // most of them (almost always one), each drawing the single tail it
+        // needs.
+        uint32_t tm = 0;  // bit s: site s (0 .. 7) is tied
         if (tie) {
-            uint32_t f0 = 0u, f1 = 0u;
-#pragma unroll 1
-            for (uint32_t i = 0; i < 2u * four; ++i) {
-                const uint32_t nw = i < 4u ? n0 : n1;
-                const uint32_t ns = (nw >> (8u * (i & 3u))) & 0xFFu;
-                const uint32_t j = i >> 1;
-                const uint32_t word = (j & 2u) ? ((j & 1u) ? w.w : w.z) : ((j & 1u) ? w.y : w.x);
-                const uint32_t head = (i & 1u) ? (word >> 16) : (word & 0xFFFFu);
-                uint32_t flip = 1u;
-                if (ns < 2u) {
-                    const uint2 tv = th.m[2u - ns];
-                    flip = head < tv.x ? 1u : 0u;
-                    if (head == tv.x) flip = tail16(g * 8u + i, t, r, (uint32_t)c, key) < tv.y ? 1u : 0u;
-                }
-                if (i < 4u)
-                    f0 |= flip << (8u * (i & 3u));
-                else
-                    f1 |= flip << (8u * (i & 3u));
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t n = q ? n1 : n0;
+                const uint32_t tl = perm(0xFFFFFFFFu, K.lo, n), thh = perm(0xFFFFFFFFu, K.hi, n);
+                const uint32_t da = perm(thh, tl, 0x05010400u) ^ (q ? w.z : w.x);
+                const uint32_t db = perm(thh, tl, 0x07030602u) ^ (q ? w.w : w.y);
+                const uint32_t m4 = ((da & 0xFFFFu) == 0u ? 1u : 0u) | ((da >> 16) == 0u ? 2u : 0u) |
+                                    ((db & 0xFFFFu) == 0u ? 4u : 0u) | ((db >> 16) == 0u ? 8u : 0u);
+                tm |= m4 << (4 * q);
             }
-            F0 = f0;
-            F1 = f1;
+        }
+        while (__any(tm != 0u)) {
+            if (tm != 0u) {
+                const uint32_t s = __builtin_ctz(tm), b = 8u * (s & 3u);
+                tm &= tm - 1u;
+                const uint32_t ns = ((s < 4u ? n0 : n1) >> b) & 0xFFu;
+                uint32_t flip = 1u;  // a head of 0xFFFF at a site with Delta E <= 0
+                if (ns < 2u) {
+                    // the head equals the threshold's high half: compare the tail
+                    const uint32_t lo = ns == 0u ? th.m[2].y : th.m[1].y;
+                    flip = tail16(g * 8u + s, t, r, (uint32_t)c, key) < lo ? 1u : 0u;
+                }
+                const uint32_t keep = ~(0xFFu << b), set = flip << b;
+                if (s < 4u)
+                    F0 = (F0 & keep) | set;
+                else
+                    F1 = (F1 & keep) | set;
+            }
         }
     }
     *(uint2 *)(S + o_own) = make_uint2(own.x ^ F0, own.y ^ F1);
@@ -272,14 +286,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_uneven2d_sweep(Uneven2dArgs a, 
                 const GroupAt atb = group_at(L, hb ? pb.yL : 0, hb ? pb.y : 0, pb.k, c);
                 GroupCoup Jb{};
                 if (EA) Jb = group_coup(X, Yp, atb);
-                group<EA>(S, ata, Ja, L, pa.y, pa.k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+                group<EA>(S, ata, Ja, L, pa.y, pa.k, c, t, (uint32_t)r, a.key, K, th, a.one2, cnt, nsum);
                 q += nt;
                 if (!hb) break;
                 pa = advance(pb);
                 const bool ha = q + nt < groups;
                 ata = group_at(L, ha ? pa.yL : 0, ha ? pa.y : 0, pa.k, c);
                 if (EA) Ja = group_coup(X, Yp, ata);
-                group<EA>(S, atb, Jb, L, pb.y, pb.k, c, t, (uint32_t)r, a.key, K, th, a.one2, a.four, cnt, nsum);
+                group<EA>(S, atb, Jb, L, pb.y, pb.k, c, t, (uint32_t)r, a.key, K, th, a.one2, cnt, nsum);
                 q += nt;
             }
             __syncthreads();
@@ -371,7 +385,6 @@ Uneven2dArgs make_uneven2d_args(int8_t *spins, const smc_inst *inst, const uint8
     a.sweeps = 1;
     a.key = key;
     a.one2 = 0x00010001u;
-    a.four = 4u;
     return a;
 }
 

@@ -172,7 +172,7 @@ struct DcbGeom {
 
 struct DcbLut {
     uint32_t tlo, thi;   // low / high bytes of the head thresholds T(n), n = 0, 1 (0xFF for n >= 2)
-    uint32_t one2, four;
+    uint32_t one2;
     uint2 thr1, thr2;    // exact thresholds of dE = 4 and dE = 8
 };
 
@@ -208,7 +208,7 @@ struct DcbPackedArgs {
     int k;
     int L, B;
     int tile_colour, rev, tiles_per_colour, total;  // total = n_rep * tiles_per_colour
-    uint32_t one2, four;                            // 0x00010001 and 4, opaque to the compiler
+    uint32_t one2;                                  // 0x00010001, opaque to the compiler
 };
 
 // Tile of a tile colour: the ti-th in row-major tile order.
@@ -329,7 +329,6 @@ __global__ __launch_bounds__(DcbGeom<T>::THREADS) void k_dcb2d_packed(DcbPackedA
     K.tlo = (th.m[2].x & 0xFFu) | ((th.m[1].x & 0xFFu) << 8) | 0xFFFF0000u;
     K.thi = (th.m[2].x >> 8) | ((th.m[1].x >> 8) << 8) | 0xFFFF0000u;
     K.one2 = a.one2;
-    K.four = a.four;
     K.thr1 = th.m[1];
     K.thr2 = th.m[2];
 
@@ -383,27 +382,40 @@ __global__ __launch_bounds__(DcbGeom<T>::THREADS) void k_dcb2d_packed(DcbPackedA
         }
         const bool tie = ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u);
         if (__builtin_expect(__any(tie), 0)) {
+            // Exact decisions of the sites whose head equals the high half of
+            // the threshold (probability 2^-16 each).  A wavefront that meets
+            // one holds up the workgroup at the next barrier, so the path is
+            // short: a mask of the tied sites, then one pass per tied site of
+            // the lane with most of them (almost always one), each drawing the
+            // single tail it needs.
+            uint32_t tm = 0;  // bit 4 i + s4: site s4 of word i is tied
             if (tie) {
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    const uint32_t wlo = i ? w.z : w.x, whi = i ? w.w : w.y;
-                    uint32_t f = 0;
-#pragma unroll 1
-                    for (uint32_t s4 = 0; s4 < K.four; ++s4) {
-                        const uint32_t word = s4 < 2u ? wlo : whi;
-                        const uint32_t head = (s4 & 1u) ? (word >> 16) : (word & 0xFFFFu);
-                        const uint32_t ns = (n[i] >> (8u * s4)) & 0xFFu;
-                        uint32_t flip = 1u;
-                        if (ns < 2u) {
-                            const uint2 thr = ns == 0u ? K.thr2 : K.thr1;
-                            flip = head < thr.x ? 1u : 0u;
-                            if (head == thr.x)
-                                flip = tail16(h0 + 4u * (uint32_t)i + s4, tj, (uint32_t)r, (uint32_t)C, a.key) < thr.y
-                                           ? 1u : 0u;
-                        }
-                        f |= flip << (8u * s4);
+                    const uint32_t tl = perm(0xFFFFFFFFu, K.tlo, n[i]), th = perm(0xFFFFFFFFu, K.thi, n[i]);
+                    const uint32_t da = perm(th, tl, 0x05010400u) ^ (i ? w.z : w.x);
+                    const uint32_t db = perm(th, tl, 0x07030602u) ^ (i ? w.w : w.y);
+                    const uint32_t m4 = ((da & 0xFFFFu) == 0u ? 1u : 0u) | ((da >> 16) == 0u ? 2u : 0u) |
+                                        ((db & 0xFFFFu) == 0u ? 4u : 0u) | ((db >> 16) == 0u ? 8u : 0u);
+                    tm |= m4 << (4 * i);
+                }
+            }
+            const uint32_t n0 = n[0], n1 = n[1], t2y = K.thr2.y, t1y = K.thr1.y;
+            while (__any(tm != 0u)) {
+                if (tm != 0u) {
+                    const uint32_t s = __builtin_ctz(tm), b = 8u * (s & 3u);
+                    tm &= tm - 1u;
+                    const uint32_t ns = ((s < 4u ? n0 : n1) >> b) & 0xFFu;
+                    uint32_t flip = 1u;  // a head of 0xFFFF at a site with Delta E <= 0
+                    if (ns < 2u) {
+                        // the head equals the threshold's high half: compare the tail
+                        flip = tail16(h0 + s, tj, (uint32_t)r, (uint32_t)C, a.key) < (ns == 0u ? t2y : t1y) ? 1u : 0u;
                     }
-                    F[i] = f;
+                    const uint32_t keep = ~(0xFFu << b), set = flip << b;
+                    if (s < 4u)
+                        F[0] = (F[0] & keep) | set;
+                    else
+                        F[1] = (F[1] & keep) | set;
                 }
             }
         }
@@ -558,7 +570,6 @@ hipError_t launch_dcb2d(int8_t *spins, const int8_t *coup, int rep_per_sample, c
         a.tiles_per_colour = tpc;
         a.total = n_rep * tpc;
         a.one2 = 0x00010001u;
-        a.four = 4u;
         switch (T) {
             case 16: return launch_packed<16>(a, coup != nullptr, s);
             case 32: return launch_packed<32>(a, coup != nullptr, s);

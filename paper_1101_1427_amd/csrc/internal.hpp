@@ -124,7 +124,6 @@ struct Uneven2dArgs {
     int sweeps;                // sweeps per launch (indices *t_dev .. *t_dev + sweeps - 1), the replica kept in LDS
     Key key;
     uint32_t one2;  // 0x00010001 (opaque to the compiler)
-    uint32_t four;  // 4 (opaque trip count of the exact-decision loop)
 };
 bool uneven2d_edge_supported(int L);
 size_t uneven2d_lds_bytes(int L);

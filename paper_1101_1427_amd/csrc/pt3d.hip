@@ -47,7 +47,6 @@ struct Pt3dArgs {
     int n_steps;
     int m;          // sweeps per step
     uint32_t one2;  // 0x00010001 (opaque to the compiler, keeps the packed 16-bit ops)
-    uint32_t four;  // 4 (opaque trip count of the rarely taken exact-decision loop)
 };
 
 
@@ -107,7 +106,7 @@ __device__ __forceinline__ int row_of(int idx, int P) {
 template <bool EA>
 __device__ __forceinline__ void half_pass(uint32_t *S, const uint32_t *Cb, const ChainState &cs, int a, int P, int c,
                                           int s0, int n, uint32_t rbase, uint32_t t, Key key, uint32_t one2,
-                                          uint32_t four, uint32_t (&cnt)[2], uint32_t (&nsum)[2]) {
+                                          uint32_t (&cnt)[2], uint32_t (&nsum)[2]) {
     const int lane = threadIdx.x & 63;
     const bool has1 = s0 + kWaves < n;
     const int s1 = has1 ? s0 + kWaves : s0;
@@ -173,35 +172,43 @@ __device__ __forceinline__ void half_pass(uint32_t *S, const uint32_t *Cb, const
             uint32_t F1 = decide4(n1, w[q].z, w[q].w, K, one2, eq);
             const bool tie = ((eq & 0xFFFFu) == 0u) || ((eq >> 16) == 0u);
             if (__builtin_expect(__any(tie), 0)) {
+                // Exact decisions of the sites whose head equals the high half
+                // of the threshold (probability 2^-16 each).  A wavefront that
+                // meets one holds up the workgroup at the next barrier, so the
+                // path is short: a mask of the tied sites, then one pass per
+                // tied site of the lane with most of them (almost always one),
+                // each drawing the single tail it needs.
+                uint32_t tm = 0;  // bit i: site i (0 .. 7) is tied
                 if (tie) {
-                    // exact decisions of the eight sites (a head equal to the
-                    // high half of its threshold: probability 2^-16 per site)
-                    const ThrRow &th = cs.thr[cs.temp_of_slot[s]];
-                    const uint32_t wx = w[q].x, wy = w[q].y, wz = w[q].z, ww = w[q].w;
-                    uint32_t f0 = 0u, f1 = 0u;
-#pragma unroll 1
-                    for (uint32_t i = 0; i < 2u * four; ++i) {
-                        const uint32_t nw = i < 4u ? n0 : n1;
-                        const uint32_t ns = (nw >> (8u * (i & 3u))) & 0xFFu;
-                        const uint32_t j = i >> 1;
-                        const uint32_t word = (j & 2u) ? ((j & 1u) ? ww : wz) : ((j & 1u) ? wy : wx);
-                        const uint32_t head = (i & 1u) ? (word >> 16) : (word & 0xFFFFu);
-                        uint32_t flip = 1u;
-                        if (ns < 3u) {
-                            const uint2 tv = th.m[3u - ns];
-                            flip = head < tv.x ? 1u : 0u;
-                            if (head == tv.x) {
-                                const uint32_t h = (uint32_t)row * 8u + i;
-                                flip = tail16(h, t, rbase + (uint32_t)s, (uint32_t)c, key) < tv.y ? 1u : 0u;
-                            }
-                        }
-                        if (i < 4u)
-                            f0 |= flip << (8u * (i & 3u));
-                        else
-                            f1 |= flip << (8u * (i & 3u));
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t nn = h ? n1 : n0;
+                        const uint32_t tl = perm(0xFFFFFFFFu, K.lo, nn), thh = perm(0xFFFFFFFFu, K.hi, nn);
+                        const uint32_t da = perm(thh, tl, 0x05010400u) ^ (h ? w[q].z : w[q].x);
+                        const uint32_t db = perm(thh, tl, 0x07030602u) ^ (h ? w[q].w : w[q].y);
+                        const uint32_t m4 = ((da & 0xFFFFu) == 0u ? 1u : 0u) | ((da >> 16) == 0u ? 2u : 0u) |
+                                            ((db & 0xFFFFu) == 0u ? 4u : 0u) | ((db >> 16) == 0u ? 8u : 0u);
+                        tm |= m4 << (4 * h);
                     }
-                    F0 = f0;
-                    F1 = f1;
+                }
+                const ThrRow &th = cs.thr[cs.temp_of_slot[s]];
+                while (__any(tm != 0u)) {
+                    if (tm != 0u) {
+                        const uint32_t i = __builtin_ctz(tm), b = 8u * (i & 3u);
+                        tm &= tm - 1u;
+                        const uint32_t ns = ((i < 4u ? n0 : n1) >> b) & 0xFFu;
+                        uint32_t flip = 1u;  // a head of 0xFFFF at a site with Delta E <= 0
+                        if (ns < 3u) {
+                            // the head equals the threshold's high half: compare the tail
+                            const uint32_t h = (uint32_t)row * 8u + i;
+                            flip = tail16(h, t, rbase + (uint32_t)s, (uint32_t)c, key) < th.m[3u - ns].y ? 1u : 0u;
+                        }
+                        const uint32_t keep = ~(0xFFu << b), set = flip << b;
+                        if (i < 4u)
+                            F0 = (F0 & keep) | set;
+                        else
+                            F1 = (F1 & keep) | set;
+                    }
                 }
             }
             *(uint2 *)(R + row * 4 + 2 * a) = make_uint2(own.x ^ F0, own.y ^ F1);
@@ -302,8 +309,8 @@ __global__ __launch_bounds__(kThreads) void k_pt3d_chain(Pt3dArgs a) {
             for (int c = 0; c < 2; ++c) {
                 if (active) {
                     // rows with (y+z)&1 == c update array E, the others array O
-                    half_pass<EA>(S, Cb, cs, 0, c, c, s0, n, rbase, ts, a.key, a.one2, a.four, cnt, nsum);
-                    half_pass<EA>(S, Cb, cs, 1, 1 - c, c, s0, n, rbase, ts, a.key, a.one2, a.four, cnt, nsum);
+                    half_pass<EA>(S, Cb, cs, 0, c, c, s0, n, rbase, ts, a.key, a.one2, cnt, nsum);
+                    half_pass<EA>(S, Cb, cs, 1, 1 - c, c, s0, n, rbase, ts, a.key, a.one2, cnt, nsum);
                 }
                 __syncthreads();
             }
@@ -389,7 +396,6 @@ hipError_t launch_pt3d(int model, int8_t *spins, const int8_t *coup, int rep_per
     a.n_steps = n_steps;
     a.m = m;
     a.one2 = 0x00010001u;
-    a.four = 4u;
     const size_t lds = pt3d_lds_bytes(model, n_temps);
     if (model == SMC_EA) {
         (void)hipFuncSetAttribute((const void *)k_pt3d_chain<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
