@@ -375,15 +375,15 @@ int pass3d_threads(int L, int ty, int segs) {
 bool shape_fits(int L, bool ea, int ty, int segs, int D, int *threads) {
     if (L < 32 || L > 1024 || L % 16 || (ty != 8 && ty != 16) || (segs != 1 && segs != 2)) return false;
     if ((L / 16) % segs || (ea && ty == 16 && segs == 2)) return false;
-    if ((D != 16 && D != 32 && D != 64 && D != 128) || D > L || L % D || L % ty) return false;
+    if ((D != 16 && D != 32 && D != 64 && D != 128 && D != 256 && D != 512) || D > L || L % D || L % ty) return false;
     *threads = pass3d_threads(L, ty, segs);
     return *threads <= pass3d_max_threads(ty, segs);
 }
 
 // Launch shape for an edge: rows per strip, segments per thread, planes per
 // z segment, workgroup size; false if the edge has none.  SPINMC_PASS3D_TY
-// (8 or 16), SPINMC_PASS3D_SEGS (1 or 2) and SPINMC_PASS3D_D (16, 32, 64 or
-// 128) override the first three; without them a shape smc_autotune
+// (8 or 16), SPINMC_PASS3D_SEGS (1 or 2) and SPINMC_PASS3D_D (16, 32, 64,
+// 128, 256 or 512) override the first three; without them a shape smc_autotune
 // measured for the edge, model and replica count is taken.  Results never
 // depend on the shape.
 bool pass3d_shape(int L, bool ea, int n_rep, int *ty, int *segs, int *D, int *threads) {
@@ -406,7 +406,9 @@ bool pass3d_shape(int L, bool ea, int n_rep, int *ty, int *segs, int *D, int *th
     if (*segs == 1 && pass3d_threads(L, *ty, 1) > pass3d_max_threads(*ty, 1) && (L / 16) % 2 == 0) *segs = 2;
     if (ea && *ty == 16 && *segs == 2) *ty = 8;  // the EA kernel of that shape would not fit its registers
     *D = L >= 1024 ? 128 : L >= 512 ? 32 : 16;
-    if (ed && (atoi(ed) == 16 || atoi(ed) == 32 || atoi(ed) == 64 || atoi(ed) == 128)) *D = atoi(ed);
+    if (ed && (atoi(ed) == 16 || atoi(ed) == 32 || atoi(ed) == 64 || atoi(ed) == 128 || atoi(ed) == 256 ||
+               atoi(ed) == 512))
+        *D = atoi(ed);
     return shape_fits(L, ea, *ty, *segs, *D, threads);
 }
 

@@ -161,7 +161,7 @@ int tune_pass3d(StreamCtx &c, hipStream_t s, const Batch &b, bool ea, int64_t n_
     std::vector<Shape> cands;
     for (int ty : {8, 16})
         for (int segs : {1, 2})
-            for (int D : {16, 32, 64, 128})
+            for (int D : {16, 32, 64, 128, 256, 512})
                 if (pass3d_shape_valid(L, ea, ty, segs, D)) cands.push_back(Shape{{ty, segs, D}});
     return pick_shape(kShapePass3d, L, ea ? 1 : 0, n_rep, cands, dflt, s, [&](int k) {
         return launch_ising3d_pass((const int8_t *)(k & 1 ? B : A), (int8_t *)(k & 1 ? A : B), (const uint2 *)pb, rps,

@@ -87,6 +87,35 @@ def test_pass_equals_half_sweeps_at_bench_sizes(monkeypatch, model, L):
     assert np.array_equal(outs[0][0], outs[1][0])
 
 
+@pytest.mark.parametrize("model,L,D", [(S.ISING, 256, 256), (S.EA, 512, 256), (S.ISING, 512, 512),
+                                         (S.EA, 1024, 512)])
+def test_pass_long_z_segments_equal_half_sweeps(monkeypatch, model, L, D):
+    """z segments of 256 and 512 planes (one segment per strip when D = L,
+    whose halo planes wrap onto the strip itself) give the same spins and
+    energy changes as the two half-sweep launches, over three sweeps from an
+    odd start."""
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("SPINMC_SWEEP3D_PASS", flag)
+        if flag == "1":
+            monkeypatch.setenv("SPINMC_PASS3D_D", str(D))
+        else:
+            monkeypatch.delenv("SPINMC_PASS3D_D", raising=False)
+        b = S.Batch(model, 3, L, 1, W.seed_for(49))
+        spins = torch.zeros(L ** 3, dtype=torch.int8, device=DEV)
+        coup = torch.zeros(b.coup_len(), dtype=torch.int8, device=DEV) if model == S.EA else None
+        S.spin_init(b, spins, coup)
+        dE = torch.zeros(1, dtype=torch.int64, device=DEV)
+        assert S.sweep_plan(b)[1] == ("k_ising3d_pass" if flag == "1" else "k_ising3d_half")
+        S.metropolis_sweep(b, spins, [0.2216], 7, 3, couplings=coup, dE_accum=dE)
+        torch.cuda.synchronize()
+        outs.append((spins.cpu().numpy(), int(dE.cpu()[0])))
+        del spins, coup
+        torch.cuda.empty_cache()
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
 @pytest.mark.parametrize("model,n,t0", [(S.ISING, 2, 5), (S.EA, 1, 2)])
 def test_pass_bit_exact_at_512(model, n, t0):
     """The one-pass kernel in its default launch shape at the bench's 512^3
